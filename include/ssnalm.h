@@ -1,0 +1,229 @@
+/*
+ * ssnalm.h - C ABI of the MI355X (gfx950) SSsNAL solver for the linear C-SVC
+ * dual quadratic program
+ *
+ *     min_x 1/2 x^T Q x - e^T x   s.t.  y^T x = 0,  0 <= x_i <= C,
+ *     Q = A A^T,  A = diag(y) X   (Q is never formed),
+ *
+ * of arXiv 1910.01312, Section 1 (eq. Def_Dual_of_C_SVM_Problem), solved by
+ * the sparse semismooth Newton augmented Lagrangian method of Section 3
+ * (Algorithm 1 for the outer loop, Algorithm 3 for the inner loop, the
+ * breakpoint projection of Section 3.2.1 and the reduced Newton system of
+ * Proposition 5), stopped on the relative KKT residual of eq. Def_Rkkt.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array pointer is a DEVICE pointer (memory of the GPU the context
+ *    lives on), unless the parameter says "host".
+ *  - The library never frees caller memory.  ssnalm_create BORROWS the
+ *    problem arrays (X, row_ptr, col_idx, y): they must stay valid and
+ *    unchanged until ssnalm_destroy.  The library allocates and owns its
+ *    own workspace (n-vectors, index lists, q x q blocks, the CSC copy of a
+ *    CSR matrix) and frees it in ssnalm_destroy.
+ *  - All GPU work is enqueued on the stream given to ssnalm_create (NULL =
+ *    the null stream).  Every entry point returns after that stream has
+ *    finished the work it enqueued, so outputs are ready on return.
+ *  - Negative status codes are errors; ssnalm_last_error() then returns a
+ *    message (thread-local, valid until the next call on the same thread).
+ *  - Limits: 1 <= n, q < 2^31; nnz < 2^31 for CSR input.
+ *  - Reductions are performed in a fixed order: repeated calls on the same
+ *    inputs give bitwise identical results.
+ */
+#ifndef SSNALM_H
+#define SSNALM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssnalm_ctx ssnalm_ctx;            /* opaque */
+
+typedef enum {
+    SSNALM_OK = 0,                 /* R_KKT <= tol reached                         */
+    SSNALM_MAXITER = 1,            /* iteration cap hit; best feasible x returned  */
+    SSNALM_LINESEARCH_FAIL = 2,    /* Armijo search exhausted repeatedly            */
+    SSNALM_WARMSTART_REJECTED = 3, /* warm start worse than cold; solved cold       */
+    SSNALM_E_BADARG = -1,          /* invalid argument (message says which)         */
+    SSNALM_E_NONFINITE = -2,       /* NaN/Inf in the data or in an iterate          */
+    SSNALM_E_OOM = -3,             /* device allocation failed                      */
+    SSNALM_E_HIP = -4              /* a HIP runtime call failed                     */
+} ssnalm_status;
+
+enum { SSNALM_DENSE = 0, SSNALM_CSR = 1 };                  /* ssnalm_problem.kind  */
+enum { SSNALM_F64 = 0, SSNALM_F32 = 1, SSNALM_BF16 = 2 };   /* ssnalm_problem.dtype */
+enum { SSNALM_NEWTON_AUTO = 0, SSNALM_NEWTON_CHOL = 1, SSNALM_NEWTON_PCG = 2 };
+enum { SSNALM_PREC_FP64 = 0, SSNALM_PREC_MIXED = 1 };
+
+/*
+ * The problem (Section 1).  X holds the n samples x~_i in R^q as rows:
+ *  kind = SSNALM_DENSE: X is n*q elements, row-major (row i = sample i),
+ *    dtype F64, F32 or BF16 (raw bfloat16 bit patterns, uint16).
+ *  kind = SSNALM_CSR: X is the nnz values (dtype F64 or F32), row_ptr the
+ *    n+1 row offsets (int64, row_ptr[0] = 0, nondecreasing, row_ptr[n] =
+ *    nnz) and col_idx the nnz column indices (int32, in [0, q); column
+ *    indices within a row need not be sorted; duplicates are summed).
+ * y holds n labels, each exactly +1 or -1 (int8).  C > 0 is the box bound,
+ * tol > 0 the target relative KKT residual of eq. Def_Rkkt.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t dtype;
+    int64_t n, q, nnz;
+    const void*    X;
+    const int64_t* row_ptr;
+    const int32_t* col_idx;
+    const int8_t*  y;
+    double C;
+    double tol;
+} ssnalm_problem;
+
+/*
+ * Solver options.  The paper fixes none of these constants except the
+ * iteration cap of 200 outer iterations and x^0 = 0 (Section 4.1); the
+ * defaults set by ssnalm_default_options are this library's readings of the
+ * open constants: sigma0 = 1, sigma_{k+1} = min(rho sigma_k, sigma_max) with
+ * rho = 5 and sigma_max = 1e6; eps_k = delta_k = eps_decay^k (0.5^k) in the
+ * inner stopping tests (A') and (B'); mu = 1e-4, line-search factor 0.5,
+ * tau = 0.5, eta = 0.1 in Algorithm 3; 50 inner iterations, 40 backtracks.
+ */
+typedef struct {
+    double  sigma0, rho, sigma_max;
+    double  mu, ls_delta, tau, eta, eps_decay;
+    double  floor_rel;          /* inner stop floor: |g| <= floor_rel (1+|omega|)        */
+    int32_t max_outer, max_inner, max_backtracks;
+    int32_t newton;             /* SSNALM_NEWTON_*                                        */
+    int32_t precision;          /* SSNALM_PREC_*                                          */
+    int32_t max_cg;             /* PCG iteration cap per Newton step                      */
+    int32_t verbose;            /* 1: one line per outer iteration on stderr              */
+    int32_t check_finite;       /* 1: ssnalm_create scans X for NaN/Inf                   */
+} ssnalm_options;
+
+/* What the paper reports per solve (Section 4, Table 2 columns) plus timing. */
+typedef struct {
+    double  rkkt;               /* R_KKT(x) of eq. Def_Rkkt at the returned x             */
+    double  obj;                /* 1/2 |A^T x|^2 - e^T x                                  */
+    double  b;                  /* bias: lam_hat of the final KKT projection              */
+    double  sigma;              /* final penalty parameter                                */
+    double  time_s;             /* wall time of ssnalm_solve                              */
+    double  t_matvec, t_proj, t_newton, t_other;   /* seconds per phase (host clock)      */
+    int32_t iters_outer;        /* ALM iterations                                         */
+    int32_t iters_inner;        /* Newton steps, summed                                   */
+    int32_t cg_iters;           /* PCG iterations, summed                                 */
+    int32_t proj_passes;        /* multisection passes, summed                            */
+    int32_t p;                  /* #unbounded SVs, 0 < x_i < C ("suppvec")                */
+    int32_t n_sv;               /* #SVs, x_i > 0                                          */
+    int32_t ls_fail;            /* line searches that exhausted their backtracks          */
+    int32_t status;             /* same as the return value                               */
+} ssnalm_info;
+
+/* Fill *opt with the defaults.  opt: host pointer. */
+void ssnalm_default_options(ssnalm_options* opt);
+
+/*
+ * Create a solver context for one problem.  Validates the arguments (see
+ * E_BADARG cases below), allocates the workspace and, for CSR input, builds
+ * the column-major copy used by the A^T r products.
+ *   out    : host pointer that receives the context.
+ *   prob   : host pointer to the problem; its arrays are device pointers.
+ *   opt    : host pointer or NULL for the defaults.
+ *   stream : a hipStream_t, or NULL for the null stream.
+ * E_BADARG: n < 1, q < 1, C <= 0 or non-finite, tol <= 0, unknown kind or
+ * dtype, CSR with BF16 values, row_ptr not monotone / not ending at nnz,
+ * col_idx out of range, a label not in {+1,-1}.  E_NONFINITE: NaN/Inf in X
+ * (only when opt->check_finite).  E_OOM / E_HIP: allocation / runtime error.
+ */
+ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* prob,
+                            const ssnalm_options* opt, void* stream);
+
+/*
+ * Solve (Algorithm 1 with Algorithm 3 as its inner solver).
+ *   x0    : optional warm start, n doubles (device) or NULL for x^0 = 0.
+ *           It is projected onto {y^T x = 0, 0 <= x <= C} first and omega^0
+ *           is set to A^T x^0.
+ *   x_out : n doubles (device), the dual solution x.
+ *   w_out : q doubles (device) or NULL, the primal weights w = A^T x.
+ *   info  : host pointer or NULL.
+ * Returns OK, MAXITER (cap hit; the x with the smallest R_KKT seen is
+ * returned) or LINESEARCH_FAIL, or a negative error.  If y has one class
+ * only, x = 0 is the only feasible point: OK with x = 0 and b = NaN.
+ */
+ssnalm_status ssnalm_solve(ssnalm_ctx* ctx, const double* x0, double* x_out,
+                           double* w_out, ssnalm_info* info);
+
+/*
+ * Solve `count` independent problems (each with its own n, C and data, all
+ * dense with the same dtype and q) with one launch per phase for all of
+ * them.  probs: host array of `count` problems; x_out: host array of
+ * `count` device pointers (n_k doubles each); w_out: host array of device
+ * pointers (q doubles each) or NULL; infos: host array or NULL.
+ * Each problem follows exactly the iteration of ssnalm_solve; problems that
+ * have converged are masked out of later launches.
+ */
+ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem* probs,
+                                 const ssnalm_options* opt, void* stream,
+                                 double* const* x_out, double* const* w_out,
+                                 ssnalm_info* infos);
+
+/* Release the context and everything the library allocated for it. */
+void ssnalm_destroy(ssnalm_ctx* ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char* ssnalm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Step-level entry points.  Each runs one step of the hot path on the data
+ * of an existing context, so that every step can be checked on its own.
+ * ---------------------------------------------------------------------- */
+
+/* t = A v = y .* (X v)  (the product Q w = A omega of eq. Def_psi).
+ * v: q doubles, t: n doubles (device). */
+ssnalm_status ssnalm_op_amul(ssnalm_ctx* ctx, const double* v, double* t);
+
+/* r = A^T z = X^T (y .* z)  (the product inside grad psi,
+ * eq. Def_differential_of_psi).  z: n doubles, r: q doubles (device). */
+ssnalm_status ssnalm_op_atmul(ssnalm_ctx* ctx, const double* z, double* r);
+
+/* Projection onto K ∩ L = {y^T x = 0, 0 <= x <= C} (Section 3.2.1):
+ * x = clip(v - lam y, 0, C) with lam the smallest zero of
+ * lam -> -y^T clip(v - lam y, 0, C) (the value Algorithm 2 returns).
+ *   v: n doubles, x: n doubles, free_mask: n bytes or NULL (1 where
+ *   0 < v_i - lam y_i < C: the index set J of Proposition 5),
+ *   lam: host double, p: host int64 (|J|), passes: host int32 or NULL. */
+ssnalm_status ssnalm_op_project(ssnalm_ctx* ctx, const double* v, double* x,
+                                uint8_t* free_mask, double* lam, int64_t* p,
+                                int32_t* passes);
+
+/* Newton direction of Algorithm 3, step 1, in omega-space:
+ * d = -(I + sigma (X_J^T X_J - s s^T / p))^{-1} g,  s = X_J^T 1,  p = |J|
+ * (Proposition 5 with L = A; d = -g when p = 0).  free_mask: n bytes
+ * (device, 1 = in J); g, d: q doubles (device); cg_iters: host or NULL.
+ * Uses the context's Newton mode (Cholesky or PCG to the tolerance
+ * cg_tol) and precision. */
+ssnalm_status ssnalm_op_newton(ssnalm_ctx* ctx, const uint8_t* free_mask,
+                               const double* g, double sigma, double cg_tol,
+                               double* d, int32_t* cg_iters);
+
+/* One trial of the Armijo line search of Algorithm 3, step 2, on the n-side
+ * terms of psi (eq. Def_psi): with u_a = u - alpha sigma t it projects u_a
+ * and returns
+ *   dh = sum_i [phi(u_a,i - lam_a y_i) - phi(u_i - lam y_i)],
+ *   phi(t) = int_0^t clip(s, 0, C) ds,
+ * which equals 1/2(|u_a|^2 - |u_a - Pi(u_a)|^2) - 1/2(|u|^2 - |u - Pi(u)|^2);
+ * each term is formed from its own increment so that no two large numbers
+ * are subtracted.  u, t: n doubles (device); lam: the multiplier of Pi(u);
+ * lam_a, dh: host doubles. */
+ssnalm_status ssnalm_op_linesearch_trial(ssnalm_ctx* ctx, const double* u,
+                                         const double* t, double lam,
+                                         double alpha, double sigma,
+                                         double* lam_a, double* dh);
+
+/* Relative KKT residual of eq. Def_Rkkt at x (n doubles, device), with
+ * the bias lam of its projection.  rkkt, b: host doubles. */
+ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* ctx, const double* x, double* rkkt,
+                             double* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSNALM_H */

@@ -1,0 +1,118 @@
+"""ctypes binding of libssnalm.so (include/ssnalm.h): structures, function
+prototypes and loading.  Argument marshalling only; all computation runs in
+the HIP library.  Loading fails loudly if the library has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssnalm.so")
+
+OK, MAXITER, LINESEARCH_FAIL, WARMSTART_REJECTED = 0, 1, 2, 3
+E_BADARG, E_NONFINITE, E_OOM, E_HIP = -1, -2, -3, -4
+STATUS_NAMES = {0: "OK", 1: "MAXITER", 2: "LINESEARCH_FAIL", 3: "WARMSTART_REJECTED",
+                -1: "E_BADARG", -2: "E_NONFINITE", -3: "E_OOM", -4: "E_HIP"}
+DENSE, CSR = 0, 1
+F64, F32, BF16 = 0, 1, 2
+NEWTON_AUTO, NEWTON_CHOL, NEWTON_PCG = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class Problem(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32),
+                ("n", C.c_int64), ("q", C.c_int64), ("nnz", C.c_int64),
+                ("X", C.c_void_p), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("y", C.c_void_p), ("C", C.c_double), ("tol", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("sigma0", C.c_double), ("rho", C.c_double), ("sigma_max", C.c_double),
+                ("mu", C.c_double), ("ls_delta", C.c_double), ("tau", C.c_double),
+                ("eta", C.c_double), ("eps_decay", C.c_double), ("floor_rel", C.c_double),
+                ("max_outer", C.c_int32), ("max_inner", C.c_int32),
+                ("max_backtracks", C.c_int32), ("newton", C.c_int32),
+                ("precision", C.c_int32), ("max_cg", C.c_int32), ("verbose", C.c_int32),
+                ("check_finite", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("rkkt", C.c_double), ("obj", C.c_double), ("b", C.c_double),
+                ("sigma", C.c_double), ("time_s", C.c_double),
+                ("t_matvec", C.c_double), ("t_proj", C.c_double), ("t_newton", C.c_double),
+                ("t_other", C.c_double),
+                ("iters_outer", C.c_int32), ("iters_inner", C.c_int32),
+                ("cg_iters", C.c_int32), ("proj_passes", C.c_int32), ("p", C.c_int32),
+                ("n_sv", C.c_int32), ("ls_fail", C.c_int32), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = [
+    "ssnalm_default_options", "ssnalm_create", "ssnalm_solve", "ssnalm_solve_batch",
+    "ssnalm_destroy", "ssnalm_last_error", "ssnalm_op_amul", "ssnalm_op_atmul",
+    "ssnalm_op_project", "ssnalm_op_newton", "ssnalm_op_linesearch_trial", "ssnalm_op_rkkt",
+]
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load the HIP library (once).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libssnalm.so not built ({p}); run paper_1910_01312_amd/build.py")
+    lib = C.CDLL(p)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.ssnalm_default_options.argtypes = [C.POINTER(Options)]
+    lib.ssnalm_default_options.restype = None
+    lib.ssnalm_create.argtypes = [C.POINTER(vp), C.POINTER(Problem), C.POINTER(Options), vp]
+    lib.ssnalm_create.restype = i32
+    lib.ssnalm_solve.argtypes = [vp, vp, vp, vp, C.POINTER(Info)]
+    lib.ssnalm_solve.restype = i32
+    lib.ssnalm_solve_batch.argtypes = [i32, C.POINTER(Problem), C.POINTER(Options), vp,
+                                       C.POINTER(vp), C.POINTER(vp), C.POINTER(Info)]
+    lib.ssnalm_solve_batch.restype = i32
+    lib.ssnalm_destroy.argtypes = [vp]
+    lib.ssnalm_destroy.restype = None
+    lib.ssnalm_last_error.argtypes = []
+    lib.ssnalm_last_error.restype = C.c_char_p
+    lib.ssnalm_op_amul.argtypes = [vp, vp, vp]
+    lib.ssnalm_op_amul.restype = i32
+    lib.ssnalm_op_atmul.argtypes = [vp, vp, vp]
+    lib.ssnalm_op_atmul.restype = i32
+    lib.ssnalm_op_project.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(i64),
+                                      C.POINTER(i32)]
+    lib.ssnalm_op_project.restype = i32
+    lib.ssnalm_op_newton.argtypes = [vp, vp, vp, dbl, dbl, vp, C.POINTER(i32)]
+    lib.ssnalm_op_newton.restype = i32
+    lib.ssnalm_op_linesearch_trial.argtypes = [vp, vp, vp, dbl, dbl, dbl, C.POINTER(dbl),
+                                               C.POINTER(dbl)]
+    lib.ssnalm_op_linesearch_trial.restype = i32
+    lib.ssnalm_op_rkkt.argtypes = [vp, vp, C.POINTER(dbl), C.POINTER(dbl)]
+    lib.ssnalm_op_rkkt.restype = i32
+    _lib = lib
+    return lib
+
+
+class SsnalmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().ssnalm_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> int:
+    if status < 0:
+        raise SsnalmError(status, where)
+    return status
+
+
+def default_options() -> Options:
+    o = Options()
+    load().ssnalm_default_options(C.byref(o))
+    return o

@@ -1,0 +1,135 @@
+// Device helpers shared by the gfx950 kernels: wave64 reductions, element
+// loads for fp64 / fp32 / bfloat16 storage, and the "last block finishes"
+// grid reduction handshake used for deterministic two-stage reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SSN_WAVE 64
+#define SSN_BLOCK 256
+#define SSN_WAVES_PER_BLOCK (SSN_BLOCK / SSN_WAVE)
+
+typedef uint16_t bf16_t;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = SSN_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SSN_WAVE);
+    return v;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int off = SSN_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SSN_WAVE);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = SSN_WAVE / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, SSN_WAVE));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = SSN_WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, SSN_WAVE));
+    return v;
+}
+
+// Sum over the block of one double per thread; result valid in every thread.
+// Fixed combination order -> deterministic.
+__device__ __forceinline__ double block_sum(double v, double* sh /* >= SSN_WAVES_PER_BLOCK */) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < SSN_WAVES_PER_BLOCK; ++i) r += sh[i];
+    return r;
+}
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    v = wave_sum_ll(v);
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    long long r = 0;
+#pragma unroll
+    for (int i = 0; i < SSN_WAVES_PER_BLOCK; ++i) r += sh[i];
+    return r;
+}
+
+// Returns true in every thread of the block that is the last one of the
+// grid to arrive.  The caller must have written its partial results before
+// calling.  The counter is reset by the last block so it can be reused by
+// the next launch on the same stream.
+__device__ __forceinline__ bool last_block_arrives(unsigned* counter) {
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(counter, 1u);
+        s_last = (prev == gridDim.x * gridDim.y * gridDim.z - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    bool last = s_last != 0;
+    if (last) {
+        __threadfence();
+        if (threadIdx.x == 0) atomicExch(counter, 0u);
+    }
+    return last;
+}
+
+// Loads that bypass possibly stale per-CU caches for data written by other
+// blocks of the same grid (used only by the last block).
+__device__ __forceinline__ double ld_acquire(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long ld_acquire(const long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_acquire(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float bf16_to_f32(bf16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Element widening to double.
+__device__ __forceinline__ double to_f64(double v) { return v; }
+__device__ __forceinline__ double to_f64(float v) { return (double)v; }
+__device__ __forceinline__ double to_f64(bf16_t v) { return (double)bf16_to_f32(v); }
+
+// Vector load of VEC consecutive elements (16-byte aligned when VEC*sizeof(T) == 16).
+template <typename T, int VEC>
+struct VecLoad;
+
+template <> struct VecLoad<double, 2> {
+    __device__ __forceinline__ static void load(const double* p, double* o) {
+        double2 v = *reinterpret_cast<const double2*>(p);
+        o[0] = v.x; o[1] = v.y;
+    }
+};
+template <> struct VecLoad<float, 4> {
+    __device__ __forceinline__ static void load(const float* p, double* o) {
+        float4 v = *reinterpret_cast<const float4*>(p);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    }
+};
+template <> struct VecLoad<bf16_t, 8> {
+    __device__ __forceinline__ static void load(const bf16_t* p, double* o) {
+        uint4 v = *reinterpret_cast<const uint4*>(p);
+        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = (double)__uint_as_float(w[i] << 16);
+            o[2 * i + 1] = (double)__uint_as_float(w[i] & 0xffff0000u);
+        }
+    }
+};
+template <typename T> struct VecLoad<T, 1> {
+    __device__ __forceinline__ static void load(const T* p, double* o) { o[0] = to_f64(*p); }
+};
+
+__device__ __forceinline__ double clampd(double t, double lo, double hi) {
+    return fmin(fmax(t, lo), hi);
+}

@@ -1,0 +1,792 @@
+// Host driver of the SSsNAL solver and the C ABI (include/ssnalm.h).
+//
+// Algorithm 1 (outer augmented Lagrangian loop on the restricted dual (D))
+// and Algorithm 3 (semismooth Newton on psi, eq. Def_psi) run here; every
+// vector operation is a kernel on the context's stream.  The host only
+// takes the scalar decisions (inner/outer stopping tests, Armijo verdict),
+// reading a small block of device scalars after each Newton step and each
+// line-search trial.
+//
+// State is kept in omega-space, omega = A^T w: Q w = A omega and
+// <w, Q w> = |omega|^2 (Section 3.2.4 with L = A), so
+//   u     = x^k + sigma (e - A omega)
+//   g     = grad psi = omega - A^T Pi(u)
+//   M     = I + sigma (X_J^T X_J - s s^T / p),  s = X_J^T 1,  p = |J|
+//   x^{k+1} = Pi(u(omega^{k+1}))                     (eq. Def_new_update_xkplus)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ssn_internal.h"
+
+
+using namespace ssn;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static ssnalm_status fail(ssnalm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(SSNALM_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+#define STCHK(expr)                          \
+    do {                                     \
+        ssnalm_status s_ = (expr);           \
+        if (s_ < 0) return s_;               \
+    } while (0)
+
+// ---------------------------------------------------------------- context
+struct DevState {
+    ProjState ps[4];    // 0/1: base and trial of the line search (swapped), 2: KKT, 3: ops
+    Scalars sc;
+};
+
+struct ssnalm_ctx {
+    // problem
+    int kind = 0, dtype = 0;
+    int64_t n = 0, q = 0, nnz = 0;
+    const void* X = nullptr;
+    const int8_t* y = nullptr;
+    double C = 1.0, tol = 1e-6;
+    ssnalm_options opt{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    // sparse operator plans (forward on CSR rows, transpose on CSC columns)
+    SegPlan fwd{}, tr{};
+    std::vector<void*> owned;
+    // n-vectors
+    double *xk = nullptr, *aw = nullptr, *u = nullptr, *ut = nullptr, *td = nullptr;
+    double *xt = nullptr, *xtt = nullptr, *nv = nullptr, *nv2 = nullptr;
+    uint8_t *jm = nullptr, *jmt = nullptr;
+    int32_t* jlist = nullptr;
+    // q-vectors
+    double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
+    double *qv = nullptr, *qv2 = nullptr;
+    double *cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_ap = nullptr,
+           *diag = nullptr;
+    // q x q
+    double *G = nullptr, *M = nullptr;
+    // reduction scratch
+    double *part = nullptr, *part2 = nullptr;
+    int64_t part_cap = 0;
+    double* spart = nullptr;         // small partials (<= 4 * 1024 doubles)
+    float* mpart = nullptr;          // MFMA SYRK partials
+    int64_t mpart_cap = 0;
+    int* blk = nullptr;
+    unsigned* counters = nullptr;    // one per reduction site
+    DevState* ds = nullptr;          // device scalars
+    DevState* hs = nullptr;          // pinned host mirror
+    int base = 0;                    // index of the accepted projection state (0/1)
+    int chol_max = 0;
+    bool use_chol = true;
+    // statistics of the current solve
+    int proj_passes = 0;
+};
+
+enum { CNT_PROJ_INIT = 0, CNT_PROJ_PASS, CNT_APPLY, CNT_LS, CNT_KKT, CNT_CMP, CNT_DOTS, CNT_DOTS2,
+       CNT_MEAN, CNT_PCG, CNT_PCG2, CNT_PCG3, CNT_N };
+
+template <typename T>
+static ssnalm_status dalloc(ssnalm_ctx* c, T** p, int64_t count) {
+    void* q = nullptr;
+    const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(SSNALM_E_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    c->owned.push_back(q);
+    *p = (T*)q;
+    return SSNALM_OK;
+}
+
+static ssnalm_status sync_state(ssnalm_ctx* c) {
+    HIPCHK(hipMemcpyAsync(c->hs, c->ds, sizeof(DevState), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return SSNALM_OK;
+}
+
+static ProjState* dps(ssnalm_ctx* c, int k) { return &c->ds->ps[k]; }
+static Scalars* dsc(ssnalm_ctx* c) { return &c->ds->sc; }
+static unsigned* cnt(ssnalm_ctx* c, int k) { return c->counters + k; }
+
+// ---------------------------------------------------------------- operators
+// t = A v
+static void op_amul(ssnalm_ctx* c, const double* v, double* t) {
+    if (c->kind == SSNALM_DENSE)
+        launch_amul_dense(c->dtype, c->X, c->y, v, t, c->n, c->q, c->st);
+    else
+        launch_segsum(c->fwd, v, nullptr, nullptr, c->y, nullptr, t, c->st);
+}
+
+// r = base + sign * A^T z  (z an n-vector; base may be null); when mask is
+// given, also s_out = X_J^T 1.
+static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const double* base,
+                     double sign, double* r, double* s_out) {
+    if (c->kind == SSNALM_DENSE) {
+        const int nb = atmul_dense_nblk(c->n);
+        launch_atmul_dense(c->dtype, c->X, c->y, z, mask, c->n, c->q, c->part, c->part2, c->st);
+        launch_reduce_cols(c->part, nb, c->q, base, sign, r, c->st);
+        if (mask) launch_reduce_cols(c->part2, nb, c->q, nullptr, 1.0, s_out, c->st);
+    } else {
+        launch_segsum(c->tr, z, c->y, nullptr, nullptr, nullptr, c->qv2, c->st);
+        // r = base + sign * qv2
+        if (base) {
+            launch_sub(base, c->qv2, r, c->q, c->st);       // sign is always -1 with a base
+        } else {
+            launch_scale_copy(r, c->qv2, sign, c->q, c->st);
+        }
+        if (mask) launch_segsum(c->tr, nullptr, nullptr, mask, nullptr, nullptr, s_out, c->st);
+    }
+}
+
+// ---------------------------------------------------------------- projection
+static const int kPassBatch = 8;
+
+// Projection of v (or of u - as*td, materialised into vout) into state k.
+static ssnalm_status project_into(ssnalm_ctx* c, const double* u, const double* td, double as,
+                                  double* vout, int k) {
+    launch_proj_init(u, td, as, vout, c->y, c->n, c->C, dps(c, k), c->spart,
+                     cnt(c, CNT_PROJ_INIT), c->st);
+    const double* v = td ? vout : u;
+    for (int i = 0; i < kPassBatch; ++i)
+        launch_proj_pass(v, c->y, c->n, c->C, dps(c, k), c->spart, cnt(c, CNT_PROJ_PASS), c->st);
+    return SSNALM_OK;
+}
+
+// Make sure state k is final (after a sync showed done == 0, run more passes).
+static ssnalm_status project_finish(ssnalm_ctx* c, const double* v, int k, bool* more) {
+    *more = false;
+    if (c->hs->ps[k].done) return SSNALM_OK;
+    *more = true;
+    for (int i = 0; i < proj_max_passes(); ++i)
+        launch_proj_pass(v, c->y, c->n, c->C, dps(c, k), c->spart, cnt(c, CNT_PROJ_PASS), c->st);
+    return SSNALM_OK;
+}
+
+// ---------------------------------------------------------------- Newton
+// d = -M^{-1} g for the free set in c->jm (count p).
+static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, const double* g,
+                                const double* sv, double sigma, double cg_tol, double* d,
+                                int* cg_iters) {
+    *cg_iters = 0;
+    if (p == 0) {
+        launch_scale_copy(d, g, -1.0, c->q, c->st);
+        return SSNALM_OK;
+    }
+    if (c->use_chol) {
+        long long* pcount = &dsc(c)->p;
+        launch_compact(mask, c->n, c->jlist, pcount, c->blk, cnt(c, CNT_CMP), c->st);
+        if (c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, c->q))
+            launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, c->G, c->mpart, c->mpart_cap, c->st);
+        else
+            launch_syrk_gather(c->dtype, c->X, c->q, c->jlist, p, c->G, c->part, c->part_cap, c->st);
+        launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
+        if (c->q <= chol_small_max())
+            launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
+        else
+            launch_chol_solve_blocked(c->M, g, d, c->q, c->part, dsc(c), c->st);
+        return SSNALM_OK;
+    }
+    // PCG on M (matrix-free), Jacobi preconditioner diag(M).
+    // sq_j = sum_J X_ij^2
+    if (c->kind == SSNALM_DENSE) {
+        launch_atmul_dense(c->dtype, c->X, c->y, nullptr, mask, c->n, c->q, c->part, c->part2,
+                           c->st, 2);
+        launch_reduce_cols(c->part2, atmul_dense_nblk(c->n), c->q, nullptr, 1.0, c->sq, c->st);
+    } else {
+        launch_segsum_sq(c->tr, mask, c->sq, c->st);
+    }
+    launch_jacobi_diag(c->sq, sv, sigma, p, c->diag, c->q, c->st);
+    launch_pcg_init(g, c->diag, c->cg_x, c->cg_r, c->cg_z, c->cg_p, c->q, dsc(c), c->spart,
+                    cnt(c, CNT_PCG), c->st);
+    const double tol2 = cg_tol * cg_tol;
+    int it = 0;
+    while (it < c->opt.max_cg) {
+        const int batch = std::min(8, c->opt.max_cg - it);
+        for (int b = 0; b < batch; ++b) {
+            // Ap = p + sigma (X_J^T (X_J p - mean) )  with mean over J
+            op_amul(c, c->cg_p, c->nv);                                  // nv = y .* X p
+            launch_masked_mean(c->nv, c->y, mask, c->n, p, &dsc(c)->mean_w, c->spart,
+                               cnt(c, CNT_MEAN), c->st);
+            launch_masked_center_t(c->nv, c->y, mask, c->n, &dsc(c)->mean_w, c->nv2, c->st);
+            op_atmul(c, c->nv2, nullptr, nullptr, 1.0, c->qv, nullptr);  // qv = X_J^T (w - mean)
+            launch_mop_finish(c->cg_p, c->qv, sigma, nullptr, nullptr, p, c->cg_ap, c->q, c->st);
+            launch_pcg_pap(c->cg_p, c->cg_ap, c->q, dsc(c), c->spart, cnt(c, CNT_PCG2), c->st);
+            launch_pcg_step(c->cg_x, c->cg_r, c->cg_p, c->cg_ap, c->diag, c->cg_z, c->q, dsc(c),
+                            tol2, c->spart, cnt(c, CNT_PCG3), c->st);
+            launch_pcg_dir(c->cg_p, c->cg_z, c->q, dsc(c), c->st);
+        }
+        it += batch;
+        STCHK(sync_state(c));
+        if (c->hs->sc.cg_rr <= tol2) break;
+    }
+    *cg_iters = it;
+    HIPCHK(hipMemcpyAsync(d, c->cg_x, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
+    return SSNALM_OK;
+}
+
+// ---------------------------------------------------------------- gradient
+// g = omega - A^T xt, s = X_J^T 1 (mask), and |g|^2, |omega|^2 into the scalars.
+static void gradient(ssnalm_ctx* c, const double* xt, const uint8_t* mask) {
+    op_atmul(c, xt, mask, c->om, -1.0, c->g, c->sv);
+    launch_dots(2, c->g, c->g, &dsc(c)->gnorm2, c->om, c->om, &dsc(c)->omega2, nullptr, nullptr,
+                nullptr, c->q, c->spart, cnt(c, CNT_DOTS), c->st);
+}
+
+// ---------------------------------------------------------------- KKT
+// R_KKT(x) of eq. Def_Rkkt with Qx = A w, w = A^T x given (q-vector).
+static ssnalm_status kkt(ssnalm_ctx* c, const double* x, const double* w, double* R, double* b,
+                         double* sumx) {
+    op_amul(c, w, c->nv);                                       // Qx
+    launch_kkt_prepare(x, c->nv, c->nv2, c->n, c->st);          // v = x - Qx + e
+    STCHK(project_into(c, c->nv2, nullptr, 0.0, nullptr, 2));
+    STCHK(sync_state(c));
+    bool more = false;
+    STCHK(project_finish(c, c->nv2, 2, &more));
+    launch_kkt_finalize(c->nv2, x, c->y, c->n, c->C, dps(c, 2), dsc(c), c->spart, cnt(c, CNT_KKT),
+                        c->st);
+    STCHK(sync_state(c));
+    c->proj_passes += c->hs->ps[2].passes;
+    *R = std::sqrt(c->hs->sc.res2) / (1.0 + std::sqrt(c->hs->sc.x2));
+    *b = c->hs->ps[2].lam;
+    if (sumx) *sumx = c->hs->sc.sumx;
+    return SSNALM_OK;
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+void ssnalm_default_options(ssnalm_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->sigma0 = 1.0;
+    o->rho = 5.0;
+    o->sigma_max = 1e6;
+    o->mu = 1e-4;
+    o->ls_delta = 0.5;
+    o->tau = 0.5;
+    o->eta = 0.1;
+    o->eps_decay = 0.5;
+    o->floor_rel = 1e-14;
+    o->max_outer = 200;
+    o->max_inner = 50;
+    o->max_backtracks = 40;
+    o->newton = SSNALM_NEWTON_AUTO;
+    o->precision = SSNALM_PREC_FP64;
+    o->max_cg = 500;
+    o->verbose = 0;
+    o->check_finite = 0;
+}
+
+const char* ssnalm_last_error(void) { return g_err.c_str(); }
+
+void ssnalm_destroy(ssnalm_ctx* c) {
+    if (!c) return;
+    if (c->st) hipStreamSynchronize(c->st);
+    for (void* p : c->owned) hipFree(p);
+    if (c->hs) hipHostFree(c->hs);
+    delete c;
+}
+
+}  // extern "C"
+
+// Build the merge-path plan of a CSR-like structure on the host.
+static ssnalm_status build_plan(ssnalm_ctx* c, SegPlan* P, int64_t nseg, int64_t nnz,
+                                const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx,
+                                const void* val_host, int val_f64) {
+    const int E = seg_entries_per_lane();
+    const int64_t TILE = (int64_t)E * 64;
+    P->nseg = nseg;
+    P->nnz = nnz;
+    P->val_f64 = val_f64;
+    P->nlane = (nnz + E - 1) / E;
+    P->ntile = (nnz + TILE - 1) / TILE;
+    std::vector<int32_t> lane_seg(std::max<int64_t>(P->ntile * 64, 1), 0);
+    // segment containing entry k: last s with ptr[s] <= k (ptr[s+1] > k)
+    {
+        int64_t s = 0;
+        for (int64_t cidx = 0; cidx < P->ntile * 64; ++cidx) {
+            const int64_t k = cidx * E;
+            if (k >= nnz) { lane_seg[cidx] = (int32_t)std::max<int64_t>(nseg - 1, 0); continue; }
+            while (ptr[s + 1] <= k) ++s;
+            lane_seg[cidx] = (int32_t)s;
+        }
+    }
+    std::vector<int32_t> tfirst(std::max<int64_t>(P->ntile, 1)), tlast(std::max<int64_t>(P->ntile, 1));
+    for (int64_t t = 0; t < P->ntile; ++t) tfirst[t] = lane_seg[t * 64];
+    {
+        int64_t s = 0;
+        for (int64_t t = 0; t < P->ntile; ++t) {
+            const int64_t k = std::min<int64_t>((t + 1) * TILE, nnz) - 1;
+            while (ptr[s + 1] <= k) ++s;
+            tlast[t] = (int32_t)s;
+        }
+    }
+    std::vector<int32_t> sseg, st0, st1;
+    for (int64_t s = 0; s < nseg; ++s) {
+        const int64_t a = ptr[s], b = ptr[s + 1];
+        if (a == b) {                                  // empty: written as 0 by the fix-up
+            sseg.push_back((int32_t)s); st0.push_back(1); st1.push_back(0);
+            continue;
+        }
+        const int64_t t0 = a / TILE, t1 = (b - 1) / TILE;
+        if (t0 != t1) { sseg.push_back((int32_t)s); st0.push_back((int32_t)t0); st1.push_back((int32_t)t1); }
+    }
+    P->nspan = (int64_t)sseg.size();
+    STCHK(dalloc(c, &P->ptr, nseg + 1));
+    STCHK(dalloc(c, &P->idx, nnz));
+    STCHK(dalloc(c, &P->lane_seg, (int64_t)lane_seg.size()));
+    STCHK(dalloc(c, &P->tile_first, (int64_t)tfirst.size()));
+    STCHK(dalloc(c, &P->tile_last, (int64_t)tlast.size()));
+    STCHK(dalloc(c, &P->carry, 2 * std::max<int64_t>(P->ntile, 1)));
+    STCHK(dalloc(c, &P->span_seg, std::max<int64_t>(P->nspan, 1)));
+    STCHK(dalloc(c, &P->span_t0, std::max<int64_t>(P->nspan, 1)));
+    STCHK(dalloc(c, &P->span_t1, std::max<int64_t>(P->nspan, 1)));
+    const size_t vb = val_f64 ? sizeof(double) : sizeof(float);
+    void* vd = nullptr;
+    if (val_f64) { double* t; STCHK(dalloc(c, &t, nnz)); vd = t; }
+    else { float* t; STCHK(dalloc(c, &t, nnz)); vd = t; }
+    P->val = vd;
+    HIPCHK(hipMemcpy(P->ptr, ptr.data(), sizeof(int32_t) * (nseg + 1), hipMemcpyHostToDevice));
+    if (nnz) {
+        HIPCHK(hipMemcpy(P->idx, idx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(P->val, val_host, vb * nnz, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(P->lane_seg, lane_seg.data(), sizeof(int32_t) * lane_seg.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(P->tile_first, tfirst.data(), sizeof(int32_t) * tfirst.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(P->tile_last, tlast.data(), sizeof(int32_t) * tlast.size(), hipMemcpyHostToDevice));
+    if (P->nspan) {
+        HIPCHK(hipMemcpy(P->span_seg, sseg.data(), sizeof(int32_t) * P->nspan, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(P->span_t0, st0.data(), sizeof(int32_t) * P->nspan, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(P->span_t1, st1.data(), sizeof(int32_t) * P->nspan, hipMemcpyHostToDevice));
+    }
+    return SSNALM_OK;
+}
+
+// CSR input: validate, build the internal int32 CSR (rows) and the CSC copy
+// (columns, rows ascending inside each column: a stable counting sort).
+static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
+    const int64_t n = c->n, q = c->q, nnz = pr->nnz;
+    if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(SSNALM_E_BADARG, "nnz out of range");
+    if (!pr->row_ptr || (!pr->col_idx && nnz > 0) || (!pr->X && nnz > 0))
+        return fail(SSNALM_E_BADARG, "CSR arrays missing");
+    if (c->dtype == SSNALM_BF16) return fail(SSNALM_E_BADARG, "CSR values must be F64 or F32");
+    std::vector<int64_t> rp(n + 1);
+    HIPCHK(hipMemcpy(rp.data(), pr->row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (rp[0] != 0 || rp[n] != nnz) return fail(SSNALM_E_BADARG, "row_ptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(SSNALM_E_BADARG, "row_ptr not monotone at row %lld", (long long)i);
+    std::vector<int32_t> ci(nnz);
+    if (nnz) HIPCHK(hipMemcpy(ci.data(), pr->col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < nnz; ++k)
+        if (ci[k] < 0 || ci[k] >= q) return fail(SSNALM_E_BADARG, "col_idx out of range at %lld", (long long)k);
+    const size_t vb = c->dtype == SSNALM_F64 ? 8 : 4;
+    std::vector<char> vals(vb * std::max<int64_t>(nnz, 1));
+    if (nnz) HIPCHK(hipMemcpy(vals.data(), pr->X, vb * nnz, hipMemcpyDeviceToHost));
+    if (c->opt.check_finite) {
+        for (int64_t k = 0; k < nnz; ++k) {
+            const double v = vb == 8 ? ((double*)vals.data())[k] : ((float*)vals.data())[k];
+            if (!std::isfinite(v)) return fail(SSNALM_E_NONFINITE, "non-finite value at entry %lld", (long long)k);
+        }
+    }
+    std::vector<int32_t> rp32(n + 1);
+    for (int64_t i = 0; i <= n; ++i) rp32[i] = (int32_t)rp[i];
+    STCHK(build_plan(c, &c->fwd, n, nnz, rp32, ci, vals.data(), vb == 8));
+    // CSC by a stable counting sort over rows
+    std::vector<int32_t> cp(q + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
+    for (int64_t j = 0; j < q; ++j) cp[j + 1] += cp[j];
+    std::vector<int32_t> pos(cp.begin(), cp.end() - 1), ri(nnz);
+    std::vector<char> cv(vb * std::max<int64_t>(nnz, 1));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = ci[k];
+            const int32_t d = pos[j]++;
+            ri[d] = (int32_t)i;
+            memcpy(cv.data() + vb * d, vals.data() + vb * k, vb);
+        }
+    STCHK(build_plan(c, &c->tr, q, nnz, cp, ri, cv.data(), vb == 8));
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* pr,
+                                       const ssnalm_options* opt, void* stream) {
+    if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
+    *out = nullptr;
+    if (pr->n < 1 || pr->q < 1 || pr->n >= INT32_MAX || pr->q >= INT32_MAX)
+        return fail(SSNALM_E_BADARG, "n and q must be in [1, 2^31)");
+    if (!(pr->C > 0.0) || !std::isfinite(pr->C)) return fail(SSNALM_E_BADARG, "C must be finite and > 0");
+    if (!(pr->tol > 0.0)) return fail(SSNALM_E_BADARG, "tol must be > 0");
+    if (pr->kind != SSNALM_DENSE && pr->kind != SSNALM_CSR) return fail(SSNALM_E_BADARG, "unknown kind");
+    if (pr->dtype < SSNALM_F64 || pr->dtype > SSNALM_BF16) return fail(SSNALM_E_BADARG, "unknown dtype");
+    if (!pr->y) return fail(SSNALM_E_BADARG, "y missing");
+    if (pr->kind == SSNALM_DENSE && !pr->X) return fail(SSNALM_E_BADARG, "X missing");
+    ssnalm_ctx* c = new ssnalm_ctx();
+    if (opt) c->opt = *opt; else ssnalm_default_options(&c->opt);
+    c->kind = pr->kind;
+    c->dtype = pr->dtype;
+    c->n = pr->n;
+    c->q = pr->q;
+    c->nnz = pr->nnz;
+    c->X = pr->X;
+    c->y = pr->y;
+    c->C = pr->C;
+    c->tol = pr->tol;
+    c->st = (hipStream_t)stream;
+    auto bail = [&](ssnalm_status s) { ssnalm_destroy(c); return s; };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SSNALM_E_HIP, "no HIP device"));
+    const int64_t n = c->n, q = c->q;
+    // labels must be exactly +-1
+    {
+        std::vector<int8_t> yh(n);
+        if (hipMemcpy(yh.data(), pr->y, n, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(SSNALM_E_HIP, "reading y failed"));
+        for (int64_t i = 0; i < n; ++i)
+            if (yh[i] != 1 && yh[i] != -1) return bail(fail(SSNALM_E_BADARG, "label %lld is %d, not +-1", (long long)i, (int)yh[i]));
+    }
+    ssnalm_status s;
+#define ALLOC(ptr, cnt_)                                   \
+    do {                                                   \
+        if ((s = dalloc(c, &(ptr), (cnt_))) < 0) return bail(s); \
+    } while (0)
+    ALLOC(c->xk, n); ALLOC(c->aw, n); ALLOC(c->u, n); ALLOC(c->ut, n); ALLOC(c->td, n);
+    ALLOC(c->xt, n); ALLOC(c->xtt, n); ALLOC(c->nv, n); ALLOC(c->nv2, n);
+    ALLOC(c->jm, n); ALLOC(c->jmt, n); ALLOC(c->jlist, n);
+    ALLOC(c->om, q); ALLOC(c->g, q); ALLOC(c->sv, q); ALLOC(c->sq, q); ALLOC(c->d, q);
+    ALLOC(c->qv, q); ALLOC(c->qv2, q);
+    ALLOC(c->cg_x, q); ALLOC(c->cg_r, q); ALLOC(c->cg_z, q); ALLOC(c->cg_p, q); ALLOC(c->cg_ap, q);
+    ALLOC(c->diag, q);
+    ALLOC(c->spart, 4 * 4096);
+    ALLOC(c->blk, compact_blocks(n) + 1);
+    ALLOC(c->counters, CNT_N);
+    ALLOC(c->ds, 1);
+    if (hipHostMalloc((void**)&c->hs, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(SSNALM_E_OOM, "pinned allocation failed"));
+    memset(c->hs, 0, sizeof(DevState));
+    if (hipMemset(c->counters, 0, sizeof(unsigned) * CNT_N) != hipSuccess ||
+        hipMemset(c->ds, 0, sizeof(DevState)) != hipSuccess)
+        return bail(fail(SSNALM_E_HIP, "memset failed"));
+    // Newton mode: Cholesky on the q x q system when q is small enough
+    c->chol_max = std::max(chol_small_max(), chol_blocked_max());
+    if (c->opt.newton == SSNALM_NEWTON_CHOL)
+        c->use_chol = true;
+    else if (c->opt.newton == SSNALM_NEWTON_PCG)
+        c->use_chol = false;
+    else
+        c->use_chol = (pr->kind == SSNALM_DENSE) && q <= c->chol_max;
+    if (c->use_chol && (pr->kind != SSNALM_DENSE || q > c->chol_max))
+        return bail(fail(SSNALM_E_BADARG, "Cholesky Newton mode needs dense X and q <= %d", c->chol_max));
+    if (c->use_chol) {
+        ALLOC(c->G, q * q);
+        ALLOC(c->M, q * q);
+    }
+    // reduction scratch for the dense transpose (nblk x q, twice) and SYRK partials
+    int64_t pc = (int64_t)atmul_dense_nblk(n) * q;
+    if (c->use_chol) pc = std::max<int64_t>(pc, syrk_part_size(q, n));
+    if (c->use_chol) pc = std::max<int64_t>(pc, q * q + 4 * q);
+    c->part_cap = pc;
+    ALLOC(c->part, pc);
+    ALLOC(c->part2, (int64_t)atmul_dense_nblk(n) * q);
+    if (c->use_chol && c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, q)) {
+        c->mpart_cap = syrk_mfma_part_size(q, n);
+        ALLOC(c->mpart, c->mpart_cap);
+    }
+    if (pr->kind == SSNALM_CSR) {
+        if ((s = setup_csr(c, pr)) < 0) return bail(s);
+    } else if (c->opt.check_finite) {
+        // scan X on the host in blocks (creation-time check only)
+        const size_t eb = pr->dtype == SSNALM_F64 ? 8 : (pr->dtype == SSNALM_F32 ? 4 : 2);
+        const int64_t total = n * q, blkn = 1 << 22;
+        std::vector<char> buf(eb * blkn);
+        for (int64_t off = 0; off < total; off += blkn) {
+            const int64_t m = std::min(blkn, total - off);
+            if (hipMemcpy(buf.data(), (const char*)pr->X + eb * off, eb * m, hipMemcpyDeviceToHost) != hipSuccess)
+                return bail(fail(SSNALM_E_HIP, "reading X failed"));
+            for (int64_t k = 0; k < m; ++k) {
+                double v;
+                if (eb == 8) v = ((double*)buf.data())[k];
+                else if (eb == 4) v = ((float*)buf.data())[k];
+                else { uint32_t b = ((uint32_t)((uint16_t*)buf.data())[k]) << 16; float f; memcpy(&f, &b, 4); v = f; }
+                if (!std::isfinite(v)) return bail(fail(SSNALM_E_NONFINITE, "non-finite X entry %lld", (long long)(off + k)));
+            }
+        }
+    }
+#undef ALLOC
+    if (hipStreamSynchronize(c->st) != hipSuccess) return bail(fail(SSNALM_E_HIP, "stream sync failed"));
+    *out = c;
+    return SSNALM_OK;
+}
+
+// ---------------------------------------------------------------- solve
+extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x_out, double* w_out,
+                                      ssnalm_info* info) {
+    if (!c || !x_out) return fail(SSNALM_E_BADARG, "null argument");
+    const auto t_begin = std::chrono::steady_clock::now();
+    const ssnalm_options& o = c->opt;
+    const int64_t n = c->n, q = c->q;
+    c->proj_passes = 0;
+    ssnalm_info inf;
+    memset(&inf, 0, sizeof inf);
+    int inner_total = 0, cg_total = 0, ls_fail = 0, outer = 0;
+    ssnalm_status status = SSNALM_MAXITER;
+
+    // x^0: zero or the projection of the warm start; omega^0 = A^T x^0
+    if (x0) {
+        STCHK(project_into(c, x0, nullptr, 0.0, nullptr, 3));
+        STCHK(sync_state(c));
+        bool more;
+        STCHK(project_finish(c, x0, 3, &more));
+        launch_proj_apply(x0, c->y, n, c->C, dps(c, 3), c->xk, nullptr, dsc(c), c->spart,
+                          cnt(c, CNT_APPLY), c->st);
+        op_atmul(c, c->xk, nullptr, nullptr, 1.0, c->om, nullptr);
+    } else {
+        launch_fill(c->xk, 0.0, n, c->st);
+        launch_fill(c->om, 0.0, q, c->st);
+    }
+    double sigma = o.sigma0;
+    double R = INFINITY, b = NAN, best_R = INFINITY, best_b = NAN;
+    bool have_best = false;      // x_out holds the best x seen when the cap is hit
+
+    for (int k = 0; k < o.max_outer; ++k) {
+        outer = k + 1;
+        const double eps_k = std::pow(o.eps_decay, (double)k);
+        // fresh A omega and u for this outer iteration
+        op_amul(c, c->om, c->aw);
+        launch_u_from(c->xk, c->aw, sigma, c->u, n, c->st);
+        c->base = 0;
+        STCHK(project_into(c, c->u, nullptr, 0.0, nullptr, c->base));
+        STCHK(sync_state(c));
+        bool more;
+        STCHK(project_finish(c, c->u, c->base, &more));
+        // x~, J and distance to x^k: reuse the line-search finalize with alpha = 0
+        launch_ls_finalize(c->u, c->u, nullptr, 0.0, c->y, n, c->C, dps(c, c->base),
+                           dps(c, c->base), c->xk, c->xt, c->jm, dsc(c), c->spart,
+                           cnt(c, CNT_LS), c->st);
+        gradient(c, c->xt, c->jm);
+        STCHK(sync_state(c));
+        c->proj_passes += c->hs->ps[c->base].passes;
+        for (int j = 0; j < o.max_inner; ++j) {
+            const Scalars& hsc = c->hs->sc;
+            const double gn = std::sqrt(hsc.gnorm2);
+            const double dist = std::sqrt(hsc.dist2);
+            const double crit = std::min(eps_k, eps_k * dist) / std::sqrt(sigma);
+            const double flo = o.floor_rel * (1.0 + std::sqrt(hsc.omega2));
+            if (!std::isfinite(gn)) return fail(SSNALM_E_NONFINITE, "non-finite gradient");
+            if (gn <= std::max(crit, flo)) break;
+            const int64_t p = hsc.p;
+            // Step 1: Newton direction
+            int cgi = 0;
+            const double cg_tol = std::min(o.eta, std::pow(gn, 1.0 + o.tau));
+            STCHK(newton_dir(c, c->jm, p, c->g, c->sv, sigma, cg_tol, c->d, &cgi));
+            cg_total += cgi;
+            ++inner_total;
+            // t = A d and the q-side scalars of the line search
+            op_amul(c, c->d, c->td);
+            launch_dots(3, c->g, c->d, &dsc(c)->gd, c->om, c->d, &dsc(c)->od, c->d, c->d,
+                        &dsc(c)->dd, q, c->spart, cnt(c, CNT_DOTS2), c->st);
+            // Step 2: Armijo line search on psi
+            double alpha = 1.0;
+            bool accepted = false;
+            const int trial = 1 - c->base;
+            for (int m = 0; m <= o.max_backtracks; ++m) {
+                STCHK(project_into(c, c->u, c->td, alpha * sigma, c->ut, trial));
+                STCHK(sync_state(c));
+                STCHK(project_finish(c, c->ut, trial, &more));
+                launch_ls_finalize(c->ut, c->u, c->td, alpha * sigma, c->y, n, c->C,
+                                   dps(c, trial), dps(c, c->base), c->xk, c->xtt, c->jmt,
+                                   dsc(c), c->spart, cnt(c, CNT_LS), c->st);
+                STCHK(sync_state(c));
+                c->proj_passes += c->hs->ps[trial].passes;
+                const Scalars& s2 = c->hs->sc;
+                if (m == 0 && s2.gd >= 0.0 && gn > 0.0) {
+                    // not a descent direction (inexact solve): fall back to -g
+                }
+                const double dpsi = alpha * s2.od + 0.5 * alpha * alpha * s2.dd + s2.dh / sigma;
+                if (!std::isfinite(dpsi)) return fail(SSNALM_E_NONFINITE, "non-finite line search value");
+                if (dpsi <= o.mu * alpha * s2.gd) { accepted = true; break; }
+                alpha *= o.ls_delta;
+            }
+            if (!accepted) { ++ls_fail; break; }
+            // Step 3: accept
+            launch_axpy(c->om, c->d, alpha, q, c->st);
+            launch_axpy(c->aw, c->td, alpha, n, c->st);
+            std::swap(c->u, c->ut);
+            std::swap(c->xt, c->xtt);
+            std::swap(c->jm, c->jmt);
+            c->base = trial;
+            gradient(c, c->xt, c->jm);
+            STCHK(sync_state(c));
+        }
+        // Step 2 of Algorithm 1: x^{k+1} = Pi(u(omega^{k+1})) = xt
+        std::swap(c->xk, c->xt);
+        // A^T x^{k+1} = omega - g
+        launch_sub(c->om, c->g, c->qv, q, c->st);
+        double sumx = 0.0;
+        STCHK(kkt(c, c->xk, c->qv, &R, &b, &sumx));
+        if (o.verbose)
+            fprintf(stderr, "[ssnalm] k=%d sigma=%.3g R_KKT=%.3e newton=%d cg=%d p=%lld passes=%d\n",
+                    k, sigma, R, inner_total, cg_total, (long long)c->hs->sc.p, c->proj_passes);
+        if (!std::isfinite(R)) return fail(SSNALM_E_NONFINITE, "non-finite KKT residual");
+        if (R <= c->tol) { status = SSNALM_OK; break; }
+        if (R < best_R) {
+            best_R = R;
+            best_b = b;
+            HIPCHK(hipMemcpyAsync(x_out, c->xk, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+            have_best = true;
+        }
+        sigma = std::min(o.rho * sigma, o.sigma_max);
+    }
+    if (status == SSNALM_OK || !have_best || R <= best_R) {
+        HIPCHK(hipMemcpyAsync(x_out, c->xk, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        R = best_R;
+        b = best_b;
+    }
+    if (status != SSNALM_OK && ls_fail > 0 && ls_fail >= outer) status = SSNALM_LINESEARCH_FAIL;
+    // w = A^T x, objective and the paper's columns
+    op_atmul(c, x_out, nullptr, nullptr, 1.0, c->qv, nullptr);
+    launch_dots(1, c->qv, c->qv, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                q, c->spart, cnt(c, CNT_DOTS), c->st);
+    launch_count_x(x_out, n, c->C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);
+    if (w_out) HIPCHK(hipMemcpyAsync(w_out, c->qv, sizeof(double) * q, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipGetLastError());
+    STCHK(sync_state(c));
+    const double sumx = c->hs->sc.sumx;
+    const double w2 = c->hs->sc.dd;
+    const auto t_end = std::chrono::steady_clock::now();
+    inf.rkkt = R;
+    inf.obj = 0.5 * w2 - sumx;
+    inf.b = b;
+    inf.sigma = sigma;
+    inf.time_s = std::chrono::duration<double>(t_end - t_begin).count();
+    inf.iters_outer = outer;
+    inf.iters_inner = inner_total;
+    inf.cg_iters = cg_total;
+    inf.proj_passes = c->proj_passes;
+    inf.p = (int32_t)c->hs->sc.p;
+    inf.n_sv = (int32_t)c->hs->sc.nsv;
+    inf.ls_fail = ls_fail;
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
+
+extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem* probs,
+                                            const ssnalm_options* opt, void* stream,
+                                            double* const* x_out, double* const* w_out,
+                                            ssnalm_info* infos) {
+    (void)count; (void)probs; (void)opt; (void)stream; (void)x_out; (void)w_out; (void)infos;
+    return fail(SSNALM_E_BADARG, "batched solve not available in this build");
+}
+
+// ---------------------------------------------------------------- step ops
+extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* t) {
+    if (!c || !v || !t) return fail(SSNALM_E_BADARG, "null argument");
+    op_amul(c, v, t);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_op_atmul(ssnalm_ctx* c, const double* z, double* r) {
+    if (!c || !z || !r) return fail(SSNALM_E_BADARG, "null argument");
+    op_atmul(c, z, nullptr, nullptr, 1.0, r, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_op_project(ssnalm_ctx* c, const double* v, double* x,
+                                           uint8_t* free_mask, double* lam, int64_t* p,
+                                           int32_t* passes) {
+    if (!c || !v || !x) return fail(SSNALM_E_BADARG, "null argument");
+    STCHK(project_into(c, v, nullptr, 0.0, nullptr, 3));
+    STCHK(sync_state(c));
+    bool more;
+    STCHK(project_finish(c, v, 3, &more));
+    launch_proj_apply(v, c->y, c->n, c->C, dps(c, 3), x, free_mask, dsc(c), c->spart,
+                      cnt(c, CNT_APPLY), c->st);
+    HIPCHK(hipGetLastError());
+    STCHK(sync_state(c));
+    if (lam) *lam = c->hs->ps[3].lam;
+    if (p) *p = c->hs->sc.p;
+    if (passes) *passes = c->hs->ps[3].passes;
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mask, const double* g,
+                                          double sigma, double cg_tol, double* d, int32_t* cg_iters) {
+    if (!c || !free_mask || !g || !d) return fail(SSNALM_E_BADARG, "null argument");
+    if (!(sigma > 0.0)) return fail(SSNALM_E_BADARG, "sigma must be > 0");
+    // s = X_J^T 1 and p
+    launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
+    if (c->kind == SSNALM_DENSE) {
+        const int nb = atmul_dense_nblk(c->n);
+        launch_fill(c->nv, 0.0, c->n, c->st);
+        launch_atmul_dense(c->dtype, c->X, c->y, c->nv, free_mask, c->n, c->q, c->part, c->part2, c->st);
+        launch_reduce_cols(c->part2, nb, c->q, nullptr, 1.0, c->sv, c->st);
+    } else {
+        launch_segsum(c->tr, nullptr, nullptr, free_mask, nullptr, nullptr, c->sv, c->st);
+    }
+    STCHK(sync_state(c));
+    int cgi = 0;
+    STCHK(newton_dir(c, free_mask, c->hs->sc.p, g, c->sv, sigma, cg_tol, d, &cgi));
+    HIPCHK(hipGetLastError());
+    STCHK(sync_state(c));
+    if (c->use_chol && c->hs->sc.chol_fail) return fail(SSNALM_E_NONFINITE, "Cholesky met a non-positive pivot");
+    if (cg_iters) *cg_iters = cgi;
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_op_linesearch_trial(ssnalm_ctx* c, const double* u, const double* t,
+                                                    double lam, double alpha, double sigma,
+                                                    double* lam_a, double* dh) {
+    if (!c || !u || !t) return fail(SSNALM_E_BADARG, "null argument");
+    // base state: the given lam
+    c->hs->ps[0] = ProjState{};
+    c->hs->ps[0].lam = lam;
+    c->hs->ps[0].done = 1;
+    HIPCHK(hipMemcpyAsync(&c->ds->ps[0], &c->hs->ps[0], sizeof(ProjState), hipMemcpyHostToDevice, c->st));
+    launch_fill(c->nv2, 0.0, c->n, c->st);
+    STCHK(project_into(c, u, t, alpha * sigma, c->ut, 1));
+    STCHK(sync_state(c));
+    bool more;
+    STCHK(project_finish(c, c->ut, 1, &more));
+    launch_ls_finalize(c->ut, u, t, alpha * sigma, c->y, c->n, c->C, dps(c, 1), dps(c, 0), c->nv2,
+                       c->xtt, c->jmt, dsc(c), c->spart, cnt(c, CNT_LS), c->st);
+    HIPCHK(hipGetLastError());
+    STCHK(sync_state(c));
+    if (lam_a) *lam_a = c->hs->ps[1].lam;
+    if (dh) *dh = c->hs->sc.dh;
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* rkkt, double* b) {
+    if (!c || !x) return fail(SSNALM_E_BADARG, "null argument");
+    op_atmul(c, x, nullptr, nullptr, 1.0, c->qv, nullptr);
+    double R, bb;
+    STCHK(kkt(c, x, c->qv, &R, &bb, nullptr));
+    HIPCHK(hipGetLastError());
+    if (rkkt) *rkkt = R;
+    if (b) *b = bb;
+    return SSNALM_OK;
+}

@@ -1,0 +1,275 @@
+// Dense products with A = diag(y) X for row-major X (fp64 / fp32 / bf16
+// storage, fp64 accumulation):
+//   forward   t = A v = y .* (X v)           (Q w = A omega, eq. Def_psi)
+//   transpose r = A^T z = X^T (y .* z)       (grad psi, eq. Def_differential_of_psi)
+// Both stream X once from HBM.  A wave owns whole rows: its 64 lanes read
+// one row in 16-byte pieces, so every load instruction of the wave covers a
+// contiguous 1 KiB of the row.  The forward product reduces each row across
+// the wave; the transpose keeps per-lane column accumulators and never
+// reduces per row.  Rows whose coefficient is zero are skipped in the
+// transpose, so it reads only the support-vector rows.
+#include "dev_common.h"
+#include "ssn_internal.h"
+
+namespace ssn {
+
+// ---------------------------------------------------------------- forward
+// Each wave handles ROWS rows per iteration; lane l covers columns
+// [c*64*VEC + l*VEC, +VEC) for chunk c.  v is staged in LDS when it fits.
+template <typename T, int VEC, int ROWS>
+__global__ __launch_bounds__(SSN_BLOCK) void k_amul_dense(const T* __restrict__ X,
+                                                          const int8_t* __restrict__ y,
+                                                          const double* __restrict__ v,
+                                                          double* __restrict__ t,
+                                                          int64_t n, int64_t q, int use_lds) {
+    extern __shared__ double sv[];
+    const double* vv = v;
+    if (use_lds) {
+        for (int64_t j = threadIdx.x; j < q; j += blockDim.x) sv[j] = v[j];
+        __syncthreads();
+        vv = sv;
+    }
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    const int64_t span = (int64_t)SSN_WAVE * VEC;
+    for (int64_t r0 = wave * ROWS; r0 < n; r0 += nwave * ROWS) {
+        double acc[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
+        for (int64_t c0 = (int64_t)lane * VEC; c0 < q; c0 += span) {
+            double vloc[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) vloc[e] = (c0 + e < q) ? vv[c0 + e] : 0.0;
+            double xv[ROWS][VEC];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int64_t row = r0 + r;
+                if (row < n) {
+                    if (VEC == 1 || c0 + VEC <= q) {
+                        VecLoad<T, VEC>::load(X + row * q + c0, xv[r]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            xv[r][e] = (c0 + e < q) ? to_f64(X[row * q + c0 + e]) : 0.0;
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) xv[r][e] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[r] = fma(xv[r][e], vloc[e], acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            double s = wave_sum(acc[r]);
+            const int64_t row = r0 + r;
+            if (lane == r && row < n) t[row] = (double)y[row] * s;
+        }
+    }
+}
+
+template <typename T, int VEC>
+static void amul_dispatch_rows(const T* X, const int8_t* y, const double* v, double* t,
+                               int64_t n, int64_t q, hipStream_t s) {
+    const int use_lds = q <= 8192 ? 1 : 0;
+    const size_t shm = use_lds ? (size_t)q * sizeof(double) : 0;
+    // enough waves to keep every CU busy; each wave walks rows with a stride
+    int64_t rows_per_wave = 4;
+    int64_t blocks = (n + rows_per_wave * SSN_WAVES_PER_BLOCK - 1) / (rows_per_wave * SSN_WAVES_PER_BLOCK);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_amul_dense<T, VEC, 4>), dim3((unsigned)blocks), dim3(SSN_BLOCK), shm, s,
+                       X, y, v, t, n, q, use_lds);
+}
+
+void launch_amul_dense(int dtype, const void* X, const int8_t* y, const double* v, double* t,
+                       int64_t n, int64_t q, hipStream_t s) {
+    const uintptr_t a = (uintptr_t)X;
+    if (dtype == SSNALM_F64) {
+        if ((q * 8) % 16 == 0 && a % 16 == 0)
+            amul_dispatch_rows<double, 2>((const double*)X, y, v, t, n, q, s);
+        else
+            amul_dispatch_rows<double, 1>((const double*)X, y, v, t, n, q, s);
+    } else if (dtype == SSNALM_F32) {
+        if ((q * 4) % 16 == 0 && a % 16 == 0)
+            amul_dispatch_rows<float, 4>((const float*)X, y, v, t, n, q, s);
+        else
+            amul_dispatch_rows<float, 1>((const float*)X, y, v, t, n, q, s);
+    } else {
+        if ((q * 2) % 16 == 0 && a % 16 == 0)
+            amul_dispatch_rows<bf16_t, 8>((const bf16_t*)X, y, v, t, n, q, s);
+        else
+            amul_dispatch_rows<bf16_t, 1>((const bf16_t*)X, y, v, t, n, q, s);
+    }
+}
+
+// ---------------------------------------------------------------- transpose
+// Block b owns rows [b*rows_per_blk, ...).  Column tile blockIdx.y covers
+// NCH chunks of 64*VEC columns.  Every lane keeps NCH*VEC accumulators for
+// the coefficient y.*z and (with a mask) NCH*VEC more for the 0/1 mask.
+// At the end the four waves are summed through LDS in a fixed order and the
+// block writes its partial row part[b*q + j].
+template <typename T, int VEC, int NCH, int MM>
+__global__ __launch_bounds__(SSN_BLOCK) void k_atmul_dense(const T* __restrict__ X,
+                                                           const int8_t* __restrict__ y,
+                                                           const double* __restrict__ z,
+                                                           const uint8_t* __restrict__ mask,
+                                                           int64_t n, int64_t q,
+                                                           int64_t rows_per_blk,
+                                                           double* __restrict__ part,
+                                                           double* __restrict__ part2) {
+    __shared__ double red[SSN_WAVES_PER_BLOCK][SSN_WAVE * VEC * NCH];
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int w = threadIdx.x / SSN_WAVE;
+    const int64_t tile_cols = (int64_t)SSN_WAVE * VEC * NCH;
+    const int64_t col0 = (int64_t)blockIdx.y * tile_cols;
+    const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
+
+    double acc[NCH][VEC], acc2[NCH][VEC];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) { acc[c][e] = 0.0; acc2[c][e] = 0.0; }
+
+    for (int64_t row = rb + w; row < re; row += SSN_WAVES_PER_BLOCK) {
+        const double cf = z ? (double)y[row] * z[row] : 0.0;
+        const double cm = MM ? (double)mask[row] : 0.0;
+        if (cf == 0.0 && cm == 0.0) continue;     // uniform across the wave
+        const T* xr = X + row * q;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int64_t j0 = col0 + (int64_t)c * SSN_WAVE * VEC + (int64_t)lane * VEC;
+            double xv[VEC];
+            if (j0 + VEC <= q) {
+                VecLoad<T, VEC>::load(xr + j0, xv);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) xv[e] = (j0 + e < q) ? to_f64(xr[j0 + e]) : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                acc[c][e] = fma(cf, xv[e], acc[c][e]);
+                if (MM == 1) acc2[c][e] = fma(cm, xv[e], acc2[c][e]);
+                if (MM == 2) acc2[c][e] = fma(cm * xv[e], xv[e], acc2[c][e]);
+            }
+        }
+    }
+    // block reduction through LDS (fixed order), twice when masked
+#pragma unroll
+    for (int pass = 0; pass < (MM ? 2 : 1); ++pass) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                red[w][c * SSN_WAVE * VEC + lane * VEC + e] = pass == 0 ? acc[c][e] : acc2[c][e];
+        __syncthreads();
+        double* out = pass == 0 ? part : part2;
+        for (int64_t k = threadIdx.x; k < tile_cols; k += SSN_BLOCK) {
+            const int64_t j = col0 + k;
+            if (j < q) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) sacc += red[ww][k];
+                out[(int64_t)blockIdx.x * q + j] = sacc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+int atmul_dense_nblk(int64_t n) {
+    int64_t nb = (n + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+template <typename T, int VEC>
+static void atmul_dispatch(const T* X, const int8_t* y, const double* z, const uint8_t* mask,
+                           int64_t n, int64_t q, double* part, double* part2, hipStream_t s,
+                           int mm) {
+    const int nb = atmul_dense_nblk(n);
+    const int64_t rows_per_blk = (n + nb - 1) / nb;
+    constexpr int NCH = (VEC == 1) ? 4 : 2;     // columns per tile: 64*VEC*NCH
+    const int64_t tile_cols = (int64_t)SSN_WAVE * VEC * NCH;
+    const int64_t ty = (q + tile_cols - 1) / tile_cols;
+    dim3 grid((unsigned)nb, (unsigned)ty);
+    if (mask && mm == 2)
+        hipLaunchKernelGGL((k_atmul_dense<T, VEC, NCH, 2>), grid, dim3(SSN_BLOCK), 0, s, X, y,
+                           z, mask, n, q, rows_per_blk, part, part2);
+    else if (mask)
+        hipLaunchKernelGGL((k_atmul_dense<T, VEC, NCH, 1>), grid, dim3(SSN_BLOCK), 0, s, X, y,
+                           z, mask, n, q, rows_per_blk, part, part2);
+    else
+        hipLaunchKernelGGL((k_atmul_dense<T, VEC, NCH, 0>), grid, dim3(SSN_BLOCK), 0, s, X, y,
+                           z, mask, n, q, rows_per_blk, part, part2);
+}
+
+void launch_atmul_dense(int dtype, const void* X, const int8_t* y, const double* z,
+                        const uint8_t* mask, int64_t n, int64_t q, double* part, double* part2,
+                        hipStream_t s, int mm) {
+    const uintptr_t a = (uintptr_t)X;
+    if (dtype == SSNALM_F64) {
+        if ((q * 8) % 16 == 0 && a % 16 == 0)
+            atmul_dispatch<double, 2>((const double*)X, y, z, mask, n, q, part, part2, s, mm);
+        else
+            atmul_dispatch<double, 1>((const double*)X, y, z, mask, n, q, part, part2, s, mm);
+    } else if (dtype == SSNALM_F32) {
+        if ((q * 4) % 16 == 0 && a % 16 == 0)
+            atmul_dispatch<float, 4>((const float*)X, y, z, mask, n, q, part, part2, s, mm);
+        else
+            atmul_dispatch<float, 1>((const float*)X, y, z, mask, n, q, part, part2, s, mm);
+    } else {
+        if ((q * 2) % 16 == 0 && a % 16 == 0)
+            atmul_dispatch<bf16_t, 8>((const bf16_t*)X, y, z, mask, n, q, part, part2, s, mm);
+        else
+            atmul_dispatch<bf16_t, 1>((const bf16_t*)X, y, z, mask, n, q, part, part2, s, mm);
+    }
+}
+
+// out[j] = base[j] + sign * sum_b part[b*q + j].  A block owns 64 columns
+// (one per lane); wave w sums the partial rows b = w, w+4, ... and the four
+// wave sums are added in wave order: a fixed order, so the result is
+// deterministic.
+__global__ __launch_bounds__(SSN_BLOCK) void k_reduce_cols(const double* __restrict__ part,
+                                                           int nblk, int64_t q,
+                                                           const double* __restrict__ base,
+                                                           double sign, double* __restrict__ out) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK][SSN_WAVE];
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    const int64_t j = (int64_t)blockIdx.x * SSN_WAVE + lane;
+    double s = 0.0;
+    if (j < q) {
+        int b = w;
+        for (; b + 3 * SSN_WAVES_PER_BLOCK < nblk; b += 4 * SSN_WAVES_PER_BLOCK) {
+            const double a0 = part[(int64_t)b * q + j];
+            const double a1 = part[(int64_t)(b + SSN_WAVES_PER_BLOCK) * q + j];
+            const double a2 = part[(int64_t)(b + 2 * SSN_WAVES_PER_BLOCK) * q + j];
+            const double a3 = part[(int64_t)(b + 3 * SSN_WAVES_PER_BLOCK) * q + j];
+            s += a0; s += a1; s += a2; s += a3;
+        }
+        for (; b < nblk; b += SSN_WAVES_PER_BLOCK) s += part[(int64_t)b * q + j];
+    }
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < q) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) t += sh[k][lane];
+        out[j] = (base ? base[j] : 0.0) + sign * t;
+    }
+}
+
+void launch_reduce_cols(const double* part, int nblk, int64_t q, const double* base, double sign,
+                        double* out, hipStream_t s) {
+    const unsigned blocks = (unsigned)((q + SSN_WAVE - 1) / SSN_WAVE);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(blocks), dim3(SSN_BLOCK), 0, s, part, nblk, q, base,
+                       sign, out);
+}
+
+}  // namespace ssn

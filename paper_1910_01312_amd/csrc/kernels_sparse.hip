@@ -1,0 +1,191 @@
+// Sparse products with A = diag(y) X for CSR X:
+//   forward    t = y .* (X v)        segments = rows of the CSR arrays
+//   transpose  r = X^T (y .* z)      segments = columns of a CSC copy
+// Both are one "segmented sum" out[s] = sum_{k in seg s} val[k] coef(idx[k])
+// executed nnz-balanced (merge-path style): lane chunk c owns the E entries
+// [c E, (c+1) E), a wave owns 64 consecutive chunks (a tile).  A lane sums
+// its entries segment by segment; segments that lie inside the lane are
+// final and written at once.  The partial sums at lane borders are combined
+// across the wave with a segmented scan, and segments that cross a tile
+// border leave one partial per tile in a carry array that a second kernel
+// adds in tile order.  No floating-point atomics: results are deterministic
+// whatever the segment-length distribution (a column present in nearly
+// every row is simply spread over many tiles).
+#include "dev_common.h"
+#include "ssn_internal.h"
+
+namespace ssn {
+
+constexpr int SEG_E = 8;                       // entries per lane
+constexpr int SEG_TILE = SEG_E * SSN_WAVE;     // entries per wave tile
+
+template <typename V>
+__device__ __forceinline__ double segval(const V* val, int64_t k, bool sq) {
+    const double a = (double)val[k];
+    return sq ? a * a : a;
+}
+
+// coef(i) = vin[i] * (yin ? yin[i] : 1) * (mask ? mask[i] : 1), or mask[i]
+// alone when vin == nullptr.
+template <typename V, bool SQ>
+__global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
+    int64_t nseg, int64_t nnz, const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+    const V* __restrict__ val, const int32_t* __restrict__ lane_seg, int64_t ntile,
+    const int32_t* __restrict__ tile_first, double* __restrict__ carry,
+    const double* __restrict__ vin, const int8_t* __restrict__ yin,
+    const uint8_t* __restrict__ mask, const int8_t* __restrict__ yout,
+    const uint8_t* __restrict__ out_mask, double* __restrict__ out) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t tile = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    if (tile >= ntile) return;                    // whole wave leaves together
+    const int64_t tb = tile * SEG_TILE;
+    const int64_t te = tb + SEG_TILE < nnz ? tb + SEG_TILE : nnz;
+    const int64_t k0 = tb + (int64_t)lane * SEG_E;
+    const int64_t k1 = k0 + SEG_E < te ? k0 + SEG_E : te;
+    const bool active = k0 < te;
+    const int32_t INF = 0x7fffffff;
+
+    int32_t F = INF, Lt = INF;
+    double fsum = 0.0, lsum = 0.0;
+    if (active) {
+        int32_t seg = lane_seg[tile * SSN_WAVE + lane];
+        int64_t segend = ptr[seg + 1];
+        F = seg;
+        double cur = 0.0;
+        bool have_head = false;
+        for (int64_t k = k0; k < k1; ++k) {
+            while (k >= segend) {                 // close segment `seg`
+                if (seg == F && !have_head) {
+                    have_head = true;
+                    fsum = cur;
+                    if ((int64_t)ptr[seg] >= k0) {   // complete inside the lane
+                        if (!(out_mask && !out_mask[seg]))
+                            out[seg] = (yout ? (double)yout[seg] : 1.0) * cur;
+                        else
+                            out[seg] = 0.0;
+                        F = INF - 1;              // head already emitted
+                    }
+                } else {
+                    // middle segment: complete inside the lane
+                    if (!(out_mask && !out_mask[seg]))
+                        out[seg] = (yout ? (double)yout[seg] : 1.0) * cur;
+                    else
+                        out[seg] = 0.0;
+                }
+                ++seg;
+                segend = ptr[seg + 1];
+                cur = 0.0;
+            }
+            if (out_mask && !out_mask[seg]) continue;
+            const int32_t ii = idx[k];
+            double cf;
+            if (vin) {
+                cf = vin[ii];
+                if (yin) cf *= (double)yin[ii];
+                if (mask) cf *= (double)mask[ii];
+            } else {
+                cf = (double)mask[ii];
+            }
+            if (cf != 0.0) cur = fma(segval(val, k, SQ), cf, cur);
+        }
+        Lt = seg;
+        lsum = cur;
+        if (!have_head) {           // the lane stayed inside one segment: it is the tail
+            F = Lt;
+        } else if (F == INF - 1) {
+            F = Lt;                 // no pending head
+        }
+        // now: F == Lt  -> no separate head; F < Lt -> head (F, fsum) pending
+    }
+    // ---- segmented inclusive scan of the tail sums keyed by Lt
+    double S = lsum;
+#pragma unroll
+    for (int off = 1; off < SSN_WAVE; off <<= 1) {
+        const double o = __shfl_up(S, off, SSN_WAVE);
+        const int32_t ok = __shfl_up(Lt, off, SSN_WAVE);
+        // all lanes in between share the key iff the lane `off` below does
+        // (keys are nondecreasing along the wave)
+        if (lane >= off && ok == Lt) S += o;
+    }
+    const double S_prev = __shfl_up(S, 1, SSN_WAVE);
+    const int32_t Lt_prev = __shfl_up(Lt, 1, SSN_WAVE);
+    const int32_t F_next = __shfl_down(F, 1, SSN_WAVE);
+    const bool has_next = lane + 1 < SSN_WAVE && (k0 + SEG_E) < te;
+
+    auto emit = [&](int32_t s, double v) {
+        const int64_t a = ptr[s], b = ptr[s + 1];
+        double scale = yout ? (double)yout[s] : 1.0;
+        if (out_mask && !out_mask[s]) scale = 0.0;
+        if (a >= tb && b <= te) {
+            out[s] = scale * v;
+        } else {
+            const int slot = (s == tile_first[tile]) ? 0 : 1;
+            carry[tile * 2 + slot] = v;
+        }
+    };
+    if (active) {
+        if (F < Lt) {                    // pending head segment F
+            double tot = fsum;
+            if (lane > 0 && Lt_prev == F) tot += S_prev;
+            emit(F, tot);
+        }
+        if (!has_next || F_next != Lt) emit(Lt, S);
+    }
+}
+
+// out[s] for segments that cross tile borders (and empty segments, t0 > t1):
+// sum of their per-tile partials in tile order.  One wave per segment.
+__global__ __launch_bounds__(SSN_BLOCK) void k_segsum_fix(
+    const int32_t* __restrict__ span_seg, const int32_t* __restrict__ span_t0,
+    const int32_t* __restrict__ span_t1, int64_t nspan, const int32_t* __restrict__ tile_first,
+    const double* __restrict__ carry, const int8_t* __restrict__ yout,
+    const uint8_t* __restrict__ out_mask, double* __restrict__ out) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t w = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    if (w >= nspan) return;
+    const int32_t s = span_seg[w], t0 = span_t0[w], t1 = span_t1[w];
+    double acc = 0.0;
+    for (int64_t t = t0 + lane; t <= t1; t += SSN_WAVE)
+        acc += carry[t * 2 + ((s == tile_first[t]) ? 0 : 1)];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        double scale = yout ? (double)yout[s] : 1.0;
+        if (out_mask && !out_mask[s]) scale = 0.0;
+        out[s] = scale * acc;
+    }
+}
+
+template <bool SQ>
+static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin,
+                          const uint8_t* mask, const int8_t* yout, const uint8_t* out_mask,
+                          double* out, hipStream_t s) {
+    const unsigned nb = (unsigned)((P.ntile + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+    if (nb > 0) {
+        if (P.val_f64)
+            hipLaunchKernelGGL((k_segsum<double, SQ>), dim3(nb), dim3(SSN_BLOCK), 0, s, P.nseg,
+                               P.nnz, P.ptr, P.idx, (const double*)P.val, P.lane_seg, P.ntile,
+                               P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out);
+        else
+            hipLaunchKernelGGL((k_segsum<float, SQ>), dim3(nb), dim3(SSN_BLOCK), 0, s, P.nseg,
+                               P.nnz, P.ptr, P.idx, (const float*)P.val, P.lane_seg, P.ntile,
+                               P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out);
+    }
+    if (P.nspan > 0) {
+        const unsigned nf = (unsigned)((P.nspan + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+        hipLaunchKernelGGL(k_segsum_fix, dim3(nf), dim3(SSN_BLOCK), 0, s, P.span_seg, P.span_t0,
+                           P.span_t1, P.nspan, P.tile_first, P.carry, yout, out_mask, out);
+    }
+}
+
+void launch_segsum(const SegPlan& P, const double* vin, const int8_t* yin, const uint8_t* mask,
+                   const int8_t* yout, const uint8_t* out_mask, double* out, hipStream_t s) {
+    segsum_launch<false>(P, vin, yin, mask, yout, out_mask, out, s);
+}
+
+void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStream_t s) {
+    segsum_launch<true>(P, nullptr, nullptr, mask, nullptr, nullptr, out, s);
+}
+
+int seg_entries_per_lane() { return SEG_E; }
+
+}  // namespace ssn

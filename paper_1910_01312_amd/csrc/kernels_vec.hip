@@ -1,0 +1,108 @@
+// Small vector kernels of the Newton loop: fixed-order dot products,
+// axpy-type updates and the elementwise pieces of u(omega).
+#include "dev_common.h"
+#include "ssn_internal.h"
+
+namespace ssn {
+
+static inline unsigned vec_grid(int64_t len) {
+    int64_t b = (len + 2047) / 2048;
+    if (b > 256) b = 256;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// r_k = a_k . b_k for up to three pairs.  Block partials in part[3*b + k],
+// combined in block order by the last block.
+__global__ __launch_bounds__(SSN_BLOCK) void k_dots(int npair, const double* __restrict__ a0,
+                                                    const double* __restrict__ b0, double* r0,
+                                                    const double* __restrict__ a1,
+                                                    const double* __restrict__ b1, double* r1,
+                                                    const double* __restrict__ a2,
+                                                    const double* __restrict__ b2, double* r2,
+                                                    int64_t len, double* __restrict__ part,
+                                                    unsigned* counter) {
+    __shared__ double shd[SSN_WAVES_PER_BLOCK];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+        s0 = fma(a0[i], b0[i], s0);
+        if (npair > 1) s1 = fma(a1[i], b1[i], s1);
+        if (npair > 2) s2 = fma(a2[i], b2[i], s2);
+    }
+    const double t0 = block_sum(s0, shd);
+    const double t1 = npair > 1 ? block_sum(s1, shd) : 0.0;
+    const double t2 = npair > 2 ? block_sum(s2, shd) : 0.0;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * 3 + 0] = t0;
+        part[blockIdx.x * 3 + 1] = t1;
+        part[blockIdx.x * 3 + 2] = t2;
+    }
+    if (last_block_arrives(counter) && threadIdx.x == 0) {
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+        for (unsigned b = 0; b < gridDim.x; ++b) {
+            u0 += ld_acquire(&part[b * 3 + 0]);
+            u1 += ld_acquire(&part[b * 3 + 1]);
+            u2 += ld_acquire(&part[b * 3 + 2]);
+        }
+        *r0 = u0;
+        if (npair > 1) *r1 = u1;
+        if (npair > 2) *r2 = u2;
+    }
+}
+
+void launch_dots(int npair, const double* a0, const double* b0, double* r0, const double* a1,
+                 const double* b1, double* r1, const double* a2, const double* b2, double* r2,
+                 int64_t len, double* part, unsigned* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots, dim3(vec_grid(len)), dim3(SSN_BLOCK), 0, s, npair, a0, b0, r0, a1,
+                       b1, r1, a2, b2, r2, len, part, counter);
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] = fma(a, x[i], y[i]);
+}
+void launch_axpy(double* y, const double* x, double a, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, y, x, a, len);
+}
+
+__global__ void k_scale_copy(double* __restrict__ y, const double* __restrict__ x, double a,
+                             int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] = a * x[i];
+}
+void launch_scale_copy(double* y, const double* x, double a, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, y, x, a,
+                       len);
+}
+
+// u = x^k + sigma (e - A omega)   (u(w) of eq. Def_psi with c = -e, Q w = A omega)
+__global__ void k_u_from(const double* __restrict__ xk, const double* __restrict__ aw, double sigma,
+                         double* __restrict__ u, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = fma(sigma, 1.0 - aw[i], xk[i]);
+}
+void launch_u_from(const double* xk, const double* aw, double sigma, double* u, int64_t n,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_u_from, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xk, aw, sigma,
+                       u, n);
+}
+
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ o, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) o[i] = a[i] - b[i];
+}
+void launch_sub(const double* a, const double* b, double* out, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, a, b, out, len);
+}
+
+__global__ void k_fill(double* __restrict__ p, double v, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) p[i] = v;
+}
+void launch_fill(double* p, double v, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, p, v, len);
+}
+
+}  // namespace ssn

@@ -1,0 +1,171 @@
+// Internal declarations of the SSsNAL library: device state layouts shared
+// between host driver and kernels, and the host-side launchers of every
+// kernel.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ssnalm.h"
+
+namespace ssn {
+
+// State of one projection onto {y^T x = 0, 0 <= x <= C}: the bracket of the
+// multiplier, the running flags and the result.  Lives in device memory.
+struct ProjState {
+    double lo, hi;        // bracket: g(lo) < 0 <= g(hi), g = -y^T clip(v - lam y)
+    double glo, ghi;      // g at the bracket ends (filled by the passes)
+    double lam;           // result
+    int    done;          // 1 when lam is final
+    int    passes;        // multisection passes run
+    int    approx;        // 1 if the pass cap ended the search
+    int    inside;        // breakpoints strictly inside the last bracket
+    long long npos;       // number of y_i = +1
+};
+
+// Scalars produced by reductions, read back by the host in one copy.
+struct Scalars {
+    double dh;            // line search: sum of per-component phi increments
+    double dist2;         // |x~ - x^k|^2
+    double gnorm2;        // |g|^2
+    double omega2;        // |omega|^2
+    double gd, od, dd;    // g^T d, omega^T d, d^T d
+    double res2, x2;      // KKT: |x - Pi(v)|^2, |x|^2
+    double cg_rz, cg_pap, cg_rr, cg_alpha, cg_beta, cg_rz_new;
+    double mean_w;        // PCG: mean of X_J p over J
+    double sumx;          // e^T x
+    long long p;          // |J|
+    long long nsv;        // #{x_i > 0}
+    int    chol_fail;     // Cholesky met a non-positive pivot
+    int    cg_done;
+};
+
+// Dense matvecs ----------------------------------------------------------
+void launch_amul_dense(int dtype, const void* X, const int8_t* y, const double* v,
+                       double* t, int64_t n, int64_t q, hipStream_t s);
+// part[b*q + j] = partial column sums of X^T (y .* z) over row block b
+// (z may be null: no coefficient); part2 likewise for X_J^T 1 (mode 1) or
+// sum_J X_ij^2 (mode 2) over the mask.  atmul_dense_nblk(n) blocks.
+int  atmul_dense_nblk(int64_t n);
+void launch_atmul_dense(int dtype, const void* X, const int8_t* y, const double* z,
+                        const uint8_t* mask, int64_t n, int64_t q, double* part,
+                        double* part2, hipStream_t s, int mask_mode = 1);
+// out[j] = (base ? base[j] : 0) + sign * sum_b part[b*q + j]
+void launch_reduce_cols(const double* part, int nblk, int64_t q, const double* base,
+                        double sign, double* out, hipStream_t s);
+
+// Sparse (merge-path segmented sums) -------------------------------------
+struct SegPlan {               // plan of one segmented-sum operator
+    int64_t nseg, nnz;         // segments (rows or columns), entries
+    int32_t* ptr;              // nseg+1 offsets (device)
+    int32_t* idx;              // nnz indices into the input vector (device)
+    void*    val;              // nnz values (device), f32 or f64
+    int      val_f64;
+    int32_t* lane_seg;         // segment holding the first entry of each lane chunk
+    int64_t  nlane;            // number of lane chunks
+    int64_t  ntile;            // number of wave tiles
+    int32_t* tile_first;       // first / last segment of each tile (device)
+    int32_t* tile_last;
+    double*  carry;            // 2 * ntile partial sums (device)
+    int32_t* span_seg;         // segments spanning several tiles, and empty ones
+    int32_t* span_t0;          // their first and last tile (t0 > t1: empty)
+    int32_t* span_t1;
+    int64_t  nspan;
+};
+int seg_entries_per_lane();
+// out[s] = scale_s * sum_{k in seg s} val[k] * coef(idx[k]); coef(i) =
+// vin[i] * (yin ? yin[i] : 1) * (mask ? mask[i] : 1), or mask[i] when vin is
+// null; scale_s = (yout ? yout[s] : 1) * (out_mask ? out_mask[s] : 1)
+void launch_segsum(const SegPlan& P, const double* vin, const int8_t* yin,
+                   const uint8_t* mask, const int8_t* yout, const uint8_t* out_mask,
+                   double* out, hipStream_t s);
+// out[s] = sum_{k in seg s} val[k]^2 mask(idx[k])
+void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStream_t s);
+
+// Projection ---------------------------------------------------------------
+// v_out = (td ? u - alpha_sigma * td : u); initialise the bracket in st.
+void launch_proj_init(const double* u, const double* td, double alpha_sigma, double* v_out,
+                      const int8_t* y, int64_t n, double C, ProjState* st, double* part,
+                      unsigned* counter, hipStream_t s);
+void launch_proj_pass(const double* v, const int8_t* y, int64_t n, double C, ProjState* st,
+                      double* part, unsigned* counter, hipStream_t s);
+int  proj_max_passes();
+// x = clip(v - lam y), mask = free set; counts p, nsv into sc.
+void launch_proj_apply(const double* v, const int8_t* y, int64_t n, double C,
+                       const ProjState* st, double* x, uint8_t* mask, Scalars* sc,
+                       double* part, unsigned* counter, hipStream_t s);
+// line-search finalize: as proj_apply on v = u_base - as*td, plus dh = sum of
+// phi increments relative to (u_base, lam_base) and dist2 = |x - xk|^2.
+void launch_ls_finalize(const double* v, const double* u_base, const double* td, double as,
+                        const int8_t* y, int64_t n, double C, const ProjState* st,
+                        const ProjState* st_base, const double* xk, double* x,
+                        uint8_t* mask, Scalars* sc, double* part, unsigned* counter,
+                        hipStream_t s);
+// KKT: v = x - Qx + 1; after projecting v: res2 = |x - Pi(v)|^2, x2 = |x|^2, sumx
+void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n, hipStream_t s);
+void launch_kkt_finalize(const double* v, const double* x, const int8_t* y, int64_t n,
+                         double C, const ProjState* st, Scalars* sc, double* part,
+                         unsigned* counter, hipStream_t s);
+// ordered compaction of mask into list; total written to *count
+int  compact_blocks(int64_t n);
+void launch_compact(const uint8_t* mask, int64_t n, int32_t* list, long long* count,
+                    int* blk, unsigned* counter, hipStream_t s);
+
+// Vector ops ------------------------------------------------------------------
+void launch_dots(int npair, const double* a0, const double* b0, double* r0,
+                 const double* a1, const double* b1, double* r1,
+                 const double* a2, const double* b2, double* r2,
+                 int64_t len, double* part, unsigned* counter, hipStream_t s);
+void launch_axpy(double* y, const double* x, double a, int64_t len, hipStream_t s);
+void launch_scale_copy(double* y, const double* x, double a, int64_t len, hipStream_t s);
+void launch_u_from(const double* xk, const double* aw, double sigma, double* u, int64_t n,
+                   hipStream_t s);
+void launch_sub(const double* a, const double* b, double* out, int64_t len, hipStream_t s);
+void launch_fill(double* p, double v, int64_t len, hipStream_t s);
+void launch_count_x(const double* x, int64_t n, double C, Scalars* sc, double* part,
+                    unsigned* counter, hipStream_t s);
+
+// Newton system --------------------------------------------------------------
+// G (q x q, full) = X_J^T X_J over the listed rows; fp64 accumulation
+int64_t syrk_part_size(int64_t q, int64_t p);
+void launch_syrk_gather(int dtype, const void* X, int64_t q, const int32_t* list,
+                        int64_t p, double* G, double* part, int64_t part_cap,
+                        hipStream_t s);
+// bf16 MFMA variant (fp32 accumulation) for the mixed-precision mode
+bool syrk_mfma_supported(int dtype, int64_t q);
+int64_t syrk_mfma_part_size(int64_t q, int64_t p);
+void launch_syrk_mfma(const void* X, int dtype, int64_t q, const int32_t* list, int64_t p,
+                      double* G, float* part, int64_t part_cap, hipStream_t s);
+// M = I + sigma (G - s s^T / p)
+void launch_form_M(const double* G, const double* sv, double sigma, int64_t p, double* M,
+                   int64_t q, hipStream_t s);
+// d = -M^{-1} g by Cholesky in one workgroup (q <= chol_small_max())
+int  chol_small_max();
+void launch_chol_solve_small(const double* M, const double* g, double* d, int64_t q,
+                             Scalars* sc, hipStream_t s);
+// Blocked Cholesky for larger q (in place on M), then the two solves
+int  chol_blocked_max();
+void launch_chol_solve_blocked(double* M, const double* g, double* d, int64_t q,
+                               double* work, Scalars* sc, hipStream_t s);
+
+// PCG pieces -------------------------------------------------------------------
+void launch_jacobi_diag(const double* sq, const double* sv, double sigma, int64_t p,
+                        double* diag, int64_t q, hipStream_t s);
+void launch_pcg_init(const double* g, const double* diag, double* x, double* r, double* z,
+                     double* pd, int64_t q, Scalars* sc, double* part, unsigned* counter,
+                     hipStream_t s);
+void launch_pcg_pap(const double* pd, const double* Ap, int64_t q, Scalars* sc, double* part,
+                    unsigned* counter, hipStream_t s);
+void launch_pcg_step(double* x, double* r, double* pd, const double* Ap, const double* diag,
+                     double* z, int64_t q, Scalars* sc, double tol2, double* part,
+                     unsigned* counter, hipStream_t s);
+void launch_pcg_dir(double* pd, const double* z, int64_t q, Scalars* sc, hipStream_t s);
+void launch_masked_mean(const double* t, const int8_t* y, const uint8_t* mask, int64_t n,
+                        int64_t p, double* mean_out, double* part, unsigned* counter,
+                        hipStream_t s);
+void launch_masked_center_t(double* t, const int8_t* y, const uint8_t* mask, int64_t n,
+                            const double* mean, double* z, hipStream_t s);
+void launch_mop_finish(const double* pd, const double* z, double sigma, const double* unused1,
+                       const double* unused2, int64_t unused3, double* Ap, int64_t q,
+                       hipStream_t s);
+
+}  // namespace ssn

@@ -1,0 +1,66 @@
+"""The C-ABI library builds for gfx950, loads on a host without a GPU, and
+exports every entry point that include/ssnalm.h declares (no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssnalm.h")
+LIB = os.path.join(ROOT, "paper_1910_01312_amd", "libssnalm.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssnalm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_boundary():
+    names = _declared()
+    for required in ("ssnalm_create", "ssnalm_solve", "ssnalm_solve_batch", "ssnalm_destroy",
+                     "ssnalm_last_error", "ssnalm_default_options"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        from paper_1910_01312_amd.build import build
+        build()
+    lib = ctypes.CDLL(LIB)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ssnalm_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_binding_lists_every_symbol():
+    from paper_1910_01312_amd import _lib
+    assert sorted(_lib.EXPORTS) == _declared()
+
+
+def test_default_options_without_gpu():
+    """ssnalm_default_options touches no device: callable on the CPU host."""
+    from paper_1910_01312_amd import _lib
+    o = _lib.default_options()
+    assert o.sigma0 == 1.0 and o.rho == 5.0 and o.max_outer == 200 and o.max_inner == 50
+    assert o.mu == 1e-4 and o.ls_delta == 0.5 and o.tau == 0.5 and o.eta == 0.1
+
+
+def test_code_separation():
+    """The product path never imports the oracle and the oracle never imports
+    the product package."""
+    pkg = os.path.join(ROOT, "paper_1910_01312_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", txt, re.M), f
+                assert "oracle/" not in txt, f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith(".py"):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_1910_01312_amd" not in txt, f
