@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X SSsNAL solver.
+
+One step = one full solve of the linear C-SVC dual QP to R_KKT <= 1e-6
+(Algorithm 1 with Algorithm 3 inside, every §-step of the hot path on the
+GPU) with the data already resident in HBM.  The default workload is the
+sparse text-like problem: CSR X with n = 500,000 rows, q = 100,000 columns,
+~60 nonzeros per row with Zipf(1.1) column frequencies, lognormal values,
+L2-normalised rows, noisy linear labels, C = 1.
+
+Prints ONE JSON line with the metric, the per-solve time, the roofline of
+the dominant kernel (HIP-event timing inside the library over the timed
+solves, algorithmic bytes per launch) and a CPU baseline of the FP64 oracle
+measured on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+METRIC = "time-to-KKT≤1e-6 per SVM QP (s); matvec HBM GB/s; warm-start vs plain speedup"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import numpy as np
+    import synth
+    if name == "sparse-text":
+        vals, ci, rp, y = synth.sparse_text()
+        n, q = rp.size - 1, 100_000
+        cfg = {"workload": "sparse-text CSR n=500000 q=100000 ~60 nnz/row Zipf(1.1) fp32 values",
+               "n": int(n), "q": q, "nnz": int(vals.size), "C": 1.0, "tol": 1e-6}
+        return {"csr": (vals, ci, rp, n, q), "y": y, "C": 1.0, "cfg": cfg}
+    if name == "dense-small":
+        X, y = synth.dense_two_gaussians()
+        cfg = {"workload": "dense two-Gaussian n=2000 q=50 fp64", "n": 2000, "q": 50,
+               "C": 1.0, "tol": 1e-6}
+        return {"X": X, "y": y, "C": 1.0, "cfg": cfg}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def oracle_sample(wl, budget_s, gpu_newton_steps):
+    """Time the FP64 oracle on the same workload for about budget_s seconds
+    and scale its seconds per Newton step to the GPU solve's step count."""
+    import numpy as np
+    import psutil
+    import scipy.sparse as sp
+    from oracle import ssnal
+    if "csr" in wl:
+        vals, ci, rp, n, q = wl["csr"]
+        X = sp.csr_matrix((vals.astype(np.float64), ci, rp), shape=(n, q))
+        mode = "pcg"
+    else:
+        X = wl["X"]
+        mode = "qspace"
+    proc = psutil.Process()
+    c0 = proc.cpu_times()
+    t0 = time.perf_counter()
+    r = ssnal.solve(X, wl["y"], wl["C"], tol=1e-6, newton=mode, time_budget_s=budget_s,
+                    max_cg=2000)
+    wall = time.perf_counter() - t0
+    c1 = proc.cpu_times()
+    cores = max(1, round(((c1.user - c0.user) + (c1.system - c0.system)) / max(wall, 1e-9)))
+    steps = max(r.inner, 1)
+    if r.status == "OK":
+        est = wall
+        sample = (f"full oracle solve of the same workload ({r.inner} Newton steps, "
+                  f"{r.cg_iters} CG iterations, {wall:.1f} s)")
+    else:
+        est = wall / steps * gpu_newton_steps
+        sample = (f"first {wall:.1f} s of the oracle solve of the same workload: {steps} Newton "
+                  f"steps ({r.cg_iters} CG iterations, {r.outer} ALM iterations); seconds per "
+                  f"Newton step x the {gpu_newton_steps} Newton steps of the GPU solve")
+    return {"value": est, "unit": "s", "cores": int(cores), "kind": "oracle", "sample": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sparse-text")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the solver runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1910_01312_amd import _lib
+    from paper_1910_01312_amd.solver import Solver
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs the GPU")
+    _lib.load()
+    log(f"[bench] generating workload {args.workload}")
+    t = time.perf_counter()
+    wl = make_workload(args.workload)
+    log(f"[bench] generated in {time.perf_counter() - t:.1f} s")
+
+    kw = {}
+    if "csr" in wl:
+        kw["csr"] = wl["csr"]
+    else:
+        kw["X"] = wl["X"]
+    t = time.perf_counter()
+    s = Solver(y=wl["y"], C_=wl["C"], tol=1e-6, profile=1, **kw)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t
+    log(f"[bench] create {create_s:.2f} s")
+
+    for i in range(args.warmup):
+        x, w, info = s.solve()
+        log(f"[bench] warmup {i}: {info['time_s']:.3f} s status={info['status_name']} "
+            f"R_KKT={info['rkkt']:.2e} outer={info['iters_outer']} newton={info['iters_inner']} "
+            f"cg={info['cg_iters']} p={info['p']}")
+    s.kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        x, w, info = s.solve()
+        infos.append(info)
+        log(f"[bench] step {i}: {info['time_s']:.3f} s R_KKT={info['rkkt']:.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = (t1 - t0) / args.steps
+    ks = s.kernel_stats()
+
+    # dominant kernel: largest summed device time among classes with a roofline figure
+    best = None
+    for name, k in ks.items():
+        if k["launches"] == 0 or (k["bytes"] <= 0 and k["flops"] <= 0):
+            continue
+        if best is None or k["seconds"] > ks[best]["seconds"]:
+            best = name
+    roofline = None
+    if best is not None:
+        k = ks[best]
+        avg = k["seconds"] / k["launches"]
+        if best in ("syrk", "chol"):
+            achieved = k["flops"] / k["launches"] / avg / 1e12
+            roofline = {"bound": "mfma" if best == "syrk" else "alu", "kernel": best,
+                        "achieved": achieved, "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s",
+                        "frac": achieved / PEAKS_TFLOPS["f64"], "traffic": None}
+        else:
+            achieved = k["bytes"] / k["launches"] / avg / 1e9
+            roofline = {"bound": "hbm", "kernel": best, "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": None, "bytes_per_launch": k["bytes"] / k["launches"],
+                        "avg_launch_us": avg * 1e6, "launches": k["launches"]}
+
+    # correctness of the timed result, checked by the oracle's own KKT code
+    rk_oracle = None
+    try:
+        import scipy.sparse as sp
+        from oracle import ssnal
+        xh = x.cpu().numpy()
+        if "csr" in wl:
+            vals, ci, rp, n, q = wl["csr"]
+            Xo = sp.csr_matrix((vals.astype(np.float64), ci, rp), shape=(n, q))
+        else:
+            Xo = wl["X"]
+        rk_oracle, _ = ssnal.rkkt(Xo, wl["y"], wl["C"], xh)
+    except Exception as e:  # pragma: no cover - reporting only
+        log(f"[bench] oracle KKT check failed: {e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle for ~{args.cpu_budget:.0f} s")
+        cpu = oracle_sample(wl, args.cpu_budget, infos[-1]["iters_inner"])
+
+    last = infos[-1]
+    out = {
+        "metric": METRIC,
+        "value": per,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": wl["cfg"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "solve": {"status": last["status_name"], "rkkt": last["rkkt"], "rkkt_oracle": rk_oracle,
+                  "outer": last["iters_outer"], "newton": last["iters_inner"],
+                  "cg": last["cg_iters"], "proj_passes": last["proj_passes"], "p": last["p"],
+                  "n_sv": last["n_sv"], "obj": last["obj"], "create_s": create_s},
+        "kernels": {k: {"launches": v["launches"], "ms": v["seconds"] * 1e3,
+                        "GBps": (v["bytes"] / v["seconds"] / 1e9) if v["seconds"] > 0 and v["bytes"] > 0 else None}
+                    for k, v in ks.items() if v["launches"]},
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,7 @@ typedef struct {
     int32_t max_cg;             /* PCG iteration cap per Newton step                      */
     int32_t verbose;            /* 1: one line per outer iteration on stderr              */
     int32_t check_finite;       /* 1: ssnalm_create scans X for NaN/Inf                   */
+    int32_t profile;            /* 1: time the hot kernels with HIP events on the stream  */
 } ssnalm_options;
 
 /* What the paper reports per solve (Section 4, Table 2 columns) plus timing. */
@@ -217,6 +218,31 @@ ssnalm_status ssnalm_op_linesearch_trial(ssnalm_ctx* ctx, const double* u,
                                          const double* t, double lam,
                                          double alpha, double sigma,
                                          double* lam_a, double* dh);
+
+/* Kernel classes timed when ssnalm_options.profile = 1. */
+enum {
+    SSNALM_K_AMUL = 0,        /* A v over all rows (line-search direction, KKT)      */
+    SSNALM_K_ATMUL = 1,       /* A^T z over the support rows (gradient of psi)       */
+    SSNALM_K_AMUL_J = 2,      /* X_J v inside the matrix-free Newton operator        */
+    SSNALM_K_ATMUL_J = 3,     /* X_J^T w inside the matrix-free Newton operator      */
+    SSNALM_K_PROJ = 4,        /* one multisection pass of the projection             */
+    SSNALM_K_SYRK = 5,        /* X_J^T X_J                                           */
+    SSNALM_K_CHOL = 6,        /* Cholesky factor + solves                            */
+    SSNALM_K_COUNT = 7
+};
+typedef struct {
+    int64_t launches;         /* timed launches since the last reset                 */
+    double  seconds;          /* summed device time between the event pairs          */
+    double  bytes;            /* summed algorithmic HBM bytes (what the step must    */
+                              /* read and write at least once)                       */
+    double  flops;            /* summed algorithmic flops                            */
+} ssnalm_kstat;
+
+/* Per-class kernel statistics accumulated by ssnalm_solve while
+ * opt.profile = 1.  which: SSNALM_K_*; out: host pointer.  reset != 0
+ * clears all classes after reading. */
+ssnalm_status ssnalm_kernel_stats(ssnalm_ctx* ctx, int32_t which, ssnalm_kstat* out,
+                                  int32_t reset);
 
 /* Relative KKT residual of eq. Def_Rkkt at x (n doubles, device), with
  * the bias lam of its projection.  rkkt, b: host doubles. */

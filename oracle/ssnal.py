@@ -285,6 +285,7 @@ class Options:
     newton: str = "qspace"       # qspace | pspace | pcg
     max_cg: int = 500
     record: bool = False
+    time_budget_s: float = 0.0    # > 0: stop (status "BUDGET") once exceeded
 
 
 @dataclass
@@ -342,7 +343,13 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
         eps_k = opt.eps_decay ** k
         Aomega = amul(X, y, omega)
         xk = x
+        if opt.time_budget_s > 0 and time.perf_counter() - t_start > opt.time_budget_s:
+            status = "BUDGET"
+            break
         for j in range(opt.max_inner):
+            if opt.time_budget_s > 0 and time.perf_counter() - t_start > opt.time_budget_s:
+                status = "BUDGET"
+                break
             u = xk + sigma * (1.0 - Aomega)
             xt, lam, free = project_svm(u, y, C)
             g = omega - atmul(X, y, xt)
@@ -379,6 +386,9 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
             # Step 3
             omega = omega + alpha * d
             Aomega = amul(X, y, omega)
+        if status == "BUDGET":
+            x = xk
+            break
         # Step 2 of Algorithm 1
         u = xk + sigma * (1.0 - Aomega)
         x, _, free = project_svm(u, y, C)
@@ -392,7 +402,7 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
         if best is None or R < best[0]:
             best = (R, x.copy(), b)
         sigma = min(opt.rho * sigma, opt.sigma_max)
-    if status != "OK" and best is not None and best[0] < R:
+    if status == "MAXITER" and best is not None and best[0] < R:
         R, x, b = best
 
     w = atmul(X, y, x)

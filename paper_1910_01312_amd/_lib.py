@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("max_outer", C.c_int32), ("max_inner", C.c_int32),
                 ("max_backtracks", C.c_int32), ("newton", C.c_int32),
                 ("precision", C.c_int32), ("max_cg", C.c_int32), ("verbose", C.c_int32),
-                ("check_finite", C.c_int32)]
+                ("check_finite", C.c_int32), ("profile", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -49,10 +49,19 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class KStat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
+K_AMUL, K_ATMUL, K_AMUL_J, K_ATMUL_J, K_PROJ, K_SYRK, K_CHOL, K_COUNT = range(8)
+K_NAMES = ["amul", "atmul", "amul_J", "atmul_J", "proj_pass", "syrk", "chol"]
+
 EXPORTS = [
     "ssnalm_default_options", "ssnalm_create", "ssnalm_solve", "ssnalm_solve_batch",
     "ssnalm_destroy", "ssnalm_last_error", "ssnalm_op_amul", "ssnalm_op_atmul",
     "ssnalm_op_project", "ssnalm_op_newton", "ssnalm_op_linesearch_trial", "ssnalm_op_rkkt",
+    "ssnalm_kernel_stats",
 ]
 
 _lib = None
@@ -95,6 +104,8 @@ def load(path: str | None = None):
     lib.ssnalm_op_linesearch_trial.restype = i32
     lib.ssnalm_op_rkkt.argtypes = [vp, vp, C.POINTER(dbl), C.POINTER(dbl)]
     lib.ssnalm_op_rkkt.restype = i32
+    lib.ssnalm_kernel_stats.argtypes = [vp, i32, C.POINTER(KStat), i32]
+    lib.ssnalm_kernel_stats.restype = i32
     _lib = lib
     return lib
 

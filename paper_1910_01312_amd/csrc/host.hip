@@ -102,6 +102,13 @@ struct ssnalm_ctx {
     bool use_chol = true;
     // statistics of the current solve
     int proj_passes = 0;
+    long long last_nsv = -1;         // support rows of the current x~ (for byte counts)
+    // kernel profiling (opt.profile): HIP event pairs around the hot launches
+    struct Pending { int cls; hipEvent_t a, b; double bytes, flops; };
+    std::vector<hipEvent_t> ev_free;
+    std::vector<Pending> pend;
+    hipEvent_t ev_cur = nullptr;
+    ssnalm_kstat kst[SSNALM_K_COUNT] = {};
 };
 
 enum { CNT_PROJ_INIT = 0, CNT_PROJ_PASS, CNT_APPLY, CNT_LS, CNT_KKT, CNT_CMP, CNT_DOTS, CNT_DOTS2,
@@ -121,7 +128,63 @@ static ssnalm_status dalloc(ssnalm_ctx* c, T** p, int64_t count) {
 static ssnalm_status sync_state(ssnalm_ctx* c) {
     HIPCHK(hipMemcpyAsync(c->hs, c->ds, sizeof(DevState), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
+    c->last_nsv = c->hs->sc.nsv;
     return SSNALM_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+static hipEvent_t ev_get(ssnalm_ctx* c) {
+    if (c->ev_free.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+}
+static void prof_harvest(ssnalm_ctx* c) {
+    for (auto& p : c->pend) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ssnalm_kstat& k = c->kst[p.cls];
+            k.launches += 1;
+            k.seconds += 1e-3 * (double)ms;
+            k.bytes += p.bytes;
+            k.flops += p.flops;
+        }
+        c->ev_free.push_back(p.a);
+        c->ev_free.push_back(p.b);
+    }
+    c->pend.clear();
+}
+static void prof_begin(ssnalm_ctx* c) {
+    if (!c->opt.profile) return;
+    c->ev_cur = ev_get(c);
+    if (c->ev_cur) hipEventRecord(c->ev_cur, c->st);
+}
+static void prof_end(ssnalm_ctx* c, int cls, double bytes, double flops) {
+    if (!c->opt.profile || !c->ev_cur) return;
+    hipEvent_t b = ev_get(c);
+    if (!b) return;
+    hipEventRecord(b, c->st);
+    c->pend.push_back({cls, c->ev_cur, b, bytes, flops});
+    c->ev_cur = nullptr;
+    if (c->pend.size() >= 8192) prof_harvest(c);
+}
+static double elem_bytes(int dtype) { return dtype == SSNALM_F64 ? 8.0 : (dtype == SSNALM_F32 ? 4.0 : 2.0); }
+// algorithmic bytes of A v over all rows and of A^T z over `rows` rows
+static double bytes_amul(const ssnalm_ctx* c) {
+    if (c->kind == SSNALM_DENSE)
+        return (double)c->n * c->q * elem_bytes(c->dtype) + 9.0 * c->n + 8.0 * c->q;
+    return (double)c->nnz * (elem_bytes(c->dtype) + 4.0) + 4.0 * (c->n + 1) + 9.0 * c->n + 8.0 * c->q;
+}
+static double bytes_atmul(const ssnalm_ctx* c, long long rows) {
+    if (c->kind == SSNALM_DENSE) {
+        const double r = rows >= 0 ? (double)rows : (double)c->n;
+        return r * c->q * elem_bytes(c->dtype) + 9.0 * c->n + 8.0 * c->q;
+    }
+    return (double)c->nnz * (elem_bytes(c->dtype) + 4.0) + 4.0 * (c->q + 1) + 9.0 * c->n + 8.0 * c->q;
 }
 
 static ProjState* dps(ssnalm_ctx* c, int k) { return &c->ds->ps[k]; }
@@ -129,18 +192,22 @@ static Scalars* dsc(ssnalm_ctx* c) { return &c->ds->sc; }
 static unsigned* cnt(ssnalm_ctx* c, int k) { return c->counters + k; }
 
 // ---------------------------------------------------------------- operators
-// t = A v
-static void op_amul(ssnalm_ctx* c, const double* v, double* t) {
+// t = A v (rows restricted to out_mask when given: X_J v inside the Newton operator)
+static void op_amul(ssnalm_ctx* c, const double* v, double* t, const uint8_t* out_mask = nullptr) {
+    prof_begin(c);
     if (c->kind == SSNALM_DENSE)
         launch_amul_dense(c->dtype, c->X, c->y, v, t, c->n, c->q, c->st);
     else
-        launch_segsum(c->fwd, v, nullptr, nullptr, c->y, nullptr, t, c->st);
+        launch_segsum(c->fwd, v, nullptr, nullptr, c->y, out_mask, t, c->st);
+    if (out_mask) prof_end(c, SSNALM_K_AMUL_J, 0.0, 0.0);
+    else prof_end(c, SSNALM_K_AMUL, bytes_amul(c), 2.0 * (c->kind == SSNALM_DENSE ? (double)c->n * c->q : (double)c->nnz));
 }
 
 // r = base + sign * A^T z  (z an n-vector; base may be null); when mask is
 // given, also s_out = X_J^T 1.
 static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const double* base,
-                     double sign, double* r, double* s_out) {
+                     double sign, double* r, double* s_out, int cls = SSNALM_K_ATMUL) {
+    prof_begin(c);
     if (c->kind == SSNALM_DENSE) {
         const int nb = atmul_dense_nblk(c->n);
         launch_atmul_dense(c->dtype, c->X, c->y, z, mask, c->n, c->q, c->part, c->part2, c->st);
@@ -156,6 +223,11 @@ static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const 
         }
         if (mask) launch_segsum(c->tr, nullptr, nullptr, mask, nullptr, nullptr, s_out, c->st);
     }
+    if (cls == SSNALM_K_ATMUL)
+        prof_end(c, cls, bytes_atmul(c, c->last_nsv) * (mask && c->kind == SSNALM_CSR ? 2.0 : 1.0),
+                 2.0 * (c->kind == SSNALM_DENSE ? (double)c->n * c->q : (double)c->nnz));
+    else
+        prof_end(c, cls, 0.0, 0.0);
 }
 
 // ---------------------------------------------------------------- projection
@@ -167,8 +239,11 @@ static ssnalm_status project_into(ssnalm_ctx* c, const double* u, const double* 
     launch_proj_init(u, td, as, vout, c->y, c->n, c->C, dps(c, k), c->spart,
                      cnt(c, CNT_PROJ_INIT), c->st);
     const double* v = td ? vout : u;
-    for (int i = 0; i < kPassBatch; ++i)
+    for (int i = 0; i < kPassBatch; ++i) {
+        prof_begin(c);
         launch_proj_pass(v, c->y, c->n, c->C, dps(c, k), c->spart, cnt(c, CNT_PROJ_PASS), c->st);
+        prof_end(c, SSNALM_K_PROJ, 9.0 * c->n, 0.0);
+    }
     return SSNALM_OK;
 }
 
@@ -195,15 +270,20 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
     if (c->use_chol) {
         long long* pcount = &dsc(c)->p;
         launch_compact(mask, c->n, c->jlist, pcount, c->blk, cnt(c, CNT_CMP), c->st);
+        prof_begin(c);
         if (c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, c->q))
             launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, c->G, c->mpart, c->mpart_cap, c->st);
         else
             launch_syrk_gather(c->dtype, c->X, c->q, c->jlist, p, c->G, c->part, c->part_cap, c->st);
+        prof_end(c, SSNALM_K_SYRK, (double)p * c->q * elem_bytes(c->dtype) + 4.0 * p + 8.0 * c->q * c->q,
+                 (double)p * c->q * (c->q + 1));
         launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
+        prof_begin(c);
         if (c->q <= chol_small_max())
             launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
         else
             launch_chol_solve_blocked(c->M, g, d, c->q, c->part, dsc(c), c->st);
+        prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q, (double)c->q * c->q * c->q / 3.0 + 2.0 * c->q * c->q);
         return SSNALM_OK;
     }
     // PCG on M (matrix-free), Jacobi preconditioner diag(M).
@@ -224,11 +304,11 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         const int batch = std::min(8, c->opt.max_cg - it);
         for (int b = 0; b < batch; ++b) {
             // Ap = p + sigma (X_J^T (X_J p - mean) )  with mean over J
-            op_amul(c, c->cg_p, c->nv);                                  // nv = y .* X p
+            op_amul(c, c->cg_p, c->nv, c->kind == SSNALM_CSR ? mask : nullptr);   // nv = y .* X_J p
             launch_masked_mean(c->nv, c->y, mask, c->n, p, &dsc(c)->mean_w, c->spart,
                                cnt(c, CNT_MEAN), c->st);
             launch_masked_center_t(c->nv, c->y, mask, c->n, &dsc(c)->mean_w, c->nv2, c->st);
-            op_atmul(c, c->nv2, nullptr, nullptr, 1.0, c->qv, nullptr);  // qv = X_J^T (w - mean)
+            op_atmul(c, c->nv2, nullptr, nullptr, 1.0, c->qv, nullptr, SSNALM_K_ATMUL_J);  // qv = X_J^T (w - mean)
             launch_mop_finish(c->cg_p, c->qv, sigma, nullptr, nullptr, p, c->cg_ap, c->q, c->st);
             launch_pcg_pap(c->cg_p, c->cg_ap, c->q, dsc(c), c->spart, cnt(c, CNT_PCG2), c->st);
             launch_pcg_step(c->cg_x, c->cg_r, c->cg_p, c->cg_ap, c->diag, c->cg_z, c->q, dsc(c),
@@ -302,6 +382,8 @@ const char* ssnalm_last_error(void) { return g_err.c_str(); }
 void ssnalm_destroy(ssnalm_ctx* c) {
     if (!c) return;
     if (c->st) hipStreamSynchronize(c->st);
+    for (auto& p : c->pend) { c->ev_free.push_back(p.a); c->ev_free.push_back(p.b); }
+    for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
     for (void* p : c->owned) hipFree(p);
     if (c->hs) hipHostFree(c->hs);
     delete c;
@@ -671,6 +753,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     HIPCHK(hipGetLastError());
     STCHK(sync_state(c));
     const double sumx = c->hs->sc.sumx;
+    prof_harvest(c);
     const double w2 = c->hs->sc.dd;
     const auto t_end = std::chrono::steady_clock::now();
     inf.rkkt = R;
@@ -777,6 +860,15 @@ extern "C" ssnalm_status ssnalm_op_linesearch_trial(ssnalm_ctx* c, const double*
     STCHK(sync_state(c));
     if (lam_a) *lam_a = c->hs->ps[1].lam;
     if (dh) *dh = c->hs->sc.dh;
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_kernel_stats(ssnalm_ctx* c, int32_t which, ssnalm_kstat* out,
+                                             int32_t reset) {
+    if (!c || which < 0 || which >= SSNALM_K_COUNT) return fail(SSNALM_E_BADARG, "bad kernel class");
+    prof_harvest(c);
+    if (out) *out = c->kst[which];
+    if (reset) memset(c->kst, 0, sizeof c->kst);
     return SSNALM_OK;
 }
 

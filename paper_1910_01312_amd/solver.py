@@ -40,7 +40,7 @@ def _stream_handle():
 
 _OPT_KEYS = {"sigma0", "rho", "sigma_max", "mu", "ls_delta", "tau", "eta", "eps_decay",
              "floor_rel", "max_outer", "max_inner", "max_backtracks", "newton", "precision",
-             "max_cg", "verbose", "check_finite"}
+             "max_cg", "verbose", "check_finite", "profile"}
 
 
 def make_options(**kw) -> L.Options:
@@ -177,6 +177,22 @@ class Solver:
         L.check(self._lib.ssnalm_op_rkkt(self._ctx, _ptr(x), C.byref(r), C.byref(b)),
                 "ssnalm_op_rkkt")
         return r.value, b.value
+
+    def kernel_stats(self, reset=False):
+        """Per-class kernel statistics (needs profile=1): {name: {launches,
+        seconds, bytes, flops}}."""
+        out = {}
+        for k, name in enumerate(L.K_NAMES):
+            ks = L.KStat()
+            L.check(self._lib.ssnalm_kernel_stats(self._ctx, k, C.byref(ks), 0),
+                    "ssnalm_kernel_stats")
+            out[name] = {"launches": ks.launches, "seconds": ks.seconds, "bytes": ks.bytes,
+                         "flops": ks.flops}
+        if reset:
+            ks = L.KStat()
+            L.check(self._lib.ssnalm_kernel_stats(self._ctx, 0, C.byref(ks), 1),
+                    "ssnalm_kernel_stats")
+        return out
 
     def close(self):
         if getattr(self, "_ctx", None):

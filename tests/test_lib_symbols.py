@@ -64,3 +64,32 @@ def test_code_separation():
         if f.endswith(".py"):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_1910_01312_amd" not in txt, f
+
+
+def test_struct_layouts_match_header():
+    """The ctypes mirrors of ssnalm_problem / ssnalm_options / ssnalm_info /
+    ssnalm_kstat have exactly the header's fields, in order."""
+    import ctypes
+    from paper_1910_01312_amd import _lib
+
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+
+    def fields(struct_name):
+        m = re.search(r"typedef struct \{([^{}]*)\}\s*" + struct_name + r"\s*;", src, re.S)
+        body = m.group(1)
+        out = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            m2 = re.match(r"^(?:const\s+)?\w+\s*\**\s*(.*)$", decl, re.S)
+            names = m2.group(1).replace("*", " ")
+            for nm in names.split(","):
+                nm = nm.strip()
+                if nm:
+                    out.append(nm)
+        return out
+
+    for cls, name in [(_lib.Problem, "ssnalm_problem"), (_lib.Options, "ssnalm_options"),
+                      (_lib.Info, "ssnalm_info"), (_lib.KStat, "ssnalm_kstat")]:
+        assert [f for f, _ in cls._fields_] == fields(name), name
