@@ -127,7 +127,7 @@ def main():
     for i in range(args.warmup):
         x, w, info = s.solve()
         log(f"[bench] warmup {i}: {info['time_s']:.3f} s status={info['status_name']} "
-            f"R_KKT={info['rkkt']:.2e} outer={info['iters_outer']} newton={info['iters_inner']} "
+            f"R_KKT={info['rkkt']:.2e} trials={info['ls_trials']} passes={info['proj_passes']} outer={info['iters_outer']} newton={info['iters_inner']} "
             f"cg={info['cg_iters']} p={info['p']}")
     s.kernel_stats(reset=True)
     torch.cuda.synchronize()

@@ -115,6 +115,7 @@ typedef struct {
     int32_t p;                  /* #unbounded SVs, 0 < x_i < C ("suppvec")                */
     int32_t n_sv;               /* #SVs, x_i > 0                                          */
     int32_t ls_fail;            /* line searches that exhausted their backtracks          */
+    int32_t ls_trials;          /* line-search trials (projections of u - alpha sigma t)  */
     int32_t status;             /* same as the return value                               */
 } ssnalm_info;
 

@@ -43,7 +43,8 @@ class Info(C.Structure):
                 ("t_other", C.c_double),
                 ("iters_outer", C.c_int32), ("iters_inner", C.c_int32),
                 ("cg_iters", C.c_int32), ("proj_passes", C.c_int32), ("p", C.c_int32),
-                ("n_sv", C.c_int32), ("ls_fail", C.c_int32), ("status", C.c_int32)]
+                ("n_sv", C.c_int32), ("ls_fail", C.c_int32), ("ls_trials", C.c_int32),
+                ("status", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -90,6 +90,26 @@ __device__ __forceinline__ int ld_acquire(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Sum of column c of a partials array (part[b*stride + c], b < nb) by the
+// whole block: thread t sums b = t, t+blockDim, ... with four independent
+// accumulators (loads in flight), then a fixed-order block reduction.  The
+// mapping from b to thread and the combination order are fixed, so the
+// result is deterministic.  Every thread of the block must call it.
+__device__ __forceinline__ double grid_colsum(const double* part, int nb, int stride, int c,
+                                              double* sh) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int T = blockDim.x;
+    int b = threadIdx.x;
+    for (; b + 3 * T < nb; b += 4 * T) {
+        a0 += ld_acquire(&part[(int64_t)b * stride + c]);
+        a1 += ld_acquire(&part[(int64_t)(b + T) * stride + c]);
+        a2 += ld_acquire(&part[(int64_t)(b + 2 * T) * stride + c]);
+        a3 += ld_acquire(&part[(int64_t)(b + 3 * T) * stride + c]);
+    }
+    for (; b < nb; b += T) a0 += ld_acquire(&part[(int64_t)b * stride + c]);
+    return block_sum((a0 + a1) + (a2 + a3), sh);
+}
+
 __device__ __forceinline__ float bf16_to_f32(bf16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);
 }

@@ -80,6 +80,11 @@ struct ssnalm_ctx {
     double *xt = nullptr, *xtt = nullptr, *nv = nullptr, *nv2 = nullptr;
     uint8_t *jm = nullptr, *jmt = nullptr;
     int32_t* jlist = nullptr;
+    // compact column-major copy of X_J (sparse PCG), rebuilt per Newton step
+    int32_t *jrank = nullptr, *jr = nullptr, *jc = nullptr;
+    void* jv = nullptr;
+    int *tcount = nullptr, *toff = nullptr;
+    double *wJ = nullptr, *kcarry = nullptr, *cgpart = nullptr;
     // q-vectors
     double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
     double *qv = nullptr, *qv2 = nullptr;
@@ -231,13 +236,13 @@ static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const 
 }
 
 // ---------------------------------------------------------------- projection
-static const int kPassBatch = 8;
+static const int kPassBatch = 5;
 
 // Projection of v (or of u - as*td, materialised into vout) into state k.
 static ssnalm_status project_into(ssnalm_ctx* c, const double* u, const double* td, double as,
-                                  double* vout, int k) {
+                                  double* vout, int k, const ProjState* hint = nullptr) {
     launch_proj_init(u, td, as, vout, c->y, c->n, c->C, dps(c, k), c->spart,
-                     cnt(c, CNT_PROJ_INIT), c->st);
+                     cnt(c, CNT_PROJ_INIT), c->st, hint);
     const double* v = td ? vout : u;
     for (int i = 0; i < kPassBatch; ++i) {
         prof_begin(c);
@@ -286,6 +291,55 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q, (double)c->q * c->q * c->q / 3.0 + 2.0 * c->q * c->q);
         return SSNALM_OK;
     }
+    if (c->kind == SSNALM_CSR) {
+        // compact X_J for this Newton step, then fence-free PCG on it
+        launch_compact(mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
+        launch_rank_from_list(c->jlist, &dsc(c)->p, c->n, c->jrank, c->st);
+        launch_jcsc_build(c->tr, mask, c->jrank, c->tcount, c->toff, &dsc(c)->nnzj, c->jr, c->jc,
+                          c->jv, c->st);
+        STCHK(sync_state(c));
+        const int64_t nnzj = c->hs->sc.nnzj;
+        const int vf64 = c->dtype == SSNALM_F64;
+        launch_keyed_tr(1, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sv, c->q, c->st);
+        launch_keyed_tr(2, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sq, c->q, c->st);
+        launch_jacobi_diag(c->sq, c->sv, sigma, p, c->diag, c->q, c->st);
+        const double tol2 = cg_tol * cg_tol;
+        double* Pw = c->cgpart;
+        double* Pdir = c->cgpart + 1024;
+        double* Pst[2] = {c->cgpart + 1024 + 512, c->cgpart + 1024 + 1024};
+        launch_cg_init(g, c->diag, c->sv, c->q, c->cg_x, c->cg_r, c->cg_z, c->cg_p, Pst[0], Pdir,
+                       c->st);
+        launch_cg_publish(Pst[0], c->q, tol2, dsc(c), c->st);
+        launch_fill(c->qv, 0.0, c->q, c->st);      // later zeroed by the direction kernel
+        STCHK(sync_state(c));
+        const int nbw = (int)cg_rows_grid(p);
+        const double vb = elem_bytes(c->dtype);
+        int it = 0, par = 0;
+        while (it < c->opt.max_cg && !c->hs->sc.cg_done) {
+            const int batch = std::min(8, c->opt.max_cg - it);
+            for (int b = 0; b < batch; ++b) {
+                prof_begin(c);
+                launch_cg_rows(c->fwd, c->jlist, p, c->cg_p, c->wJ, Pw, c->st);
+                prof_end(c, SSNALM_K_AMUL_J, (double)nnzj * (vb + 4.0) + 20.0 * p + 8.0 * c->q,
+                         2.0 * (double)nnzj);
+                prof_begin(c);
+                launch_keyed_tr(0, c->jr, c->jc, c->jv, vf64, nnzj, c->wJ, c->kcarry, c->qv, c->q,
+                                c->st, false);
+                prof_end(c, SSNALM_K_ATMUL_J, (double)nnzj * (8.0 + vb) + 8.0 * p + 8.0 * c->q,
+                         2.0 * (double)nnzj);
+                launch_cg_step(c->cg_x, c->cg_r, c->cg_p, c->qv, c->sv, c->diag, c->cg_z, c->q,
+                               sigma, p, Pw, nbw, Pdir, Pst[par], Pst[1 - par], tol2, c->st);
+                launch_cg_dir(c->cg_p, c->cg_z, c->sv, c->q, Pst[par], Pst[1 - par], Pdir, tol2,
+                              dsc(c), c->qv, c->st);
+                par = 1 - par;
+            }
+            it += batch;
+            STCHK(sync_state(c));
+        }
+        *cg_iters = it;
+        HIPCHK(hipMemcpyAsync(d, c->cg_x, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
+        return SSNALM_OK;
+    }
     // PCG on M (matrix-free), Jacobi preconditioner diag(M).
     // sq_j = sum_J X_ij^2
     if (c->kind == SSNALM_DENSE) {
@@ -327,7 +381,9 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
 // ---------------------------------------------------------------- gradient
 // g = omega - A^T xt, s = X_J^T 1 (mask), and |g|^2, |omega|^2 into the scalars.
 static void gradient(ssnalm_ctx* c, const double* xt, const uint8_t* mask) {
-    op_atmul(c, xt, mask, c->om, -1.0, c->g, c->sv);
+    // s = X_J^T 1 rides along the dense transposed product; the sparse path
+    // computes it from the compact copy of X_J in the Newton step
+    op_atmul(c, xt, c->kind == SSNALM_DENSE ? mask : nullptr, c->om, -1.0, c->g, c->sv);
     launch_dots(2, c->g, c->g, &dsc(c)->gnorm2, c->om, c->om, &dsc(c)->omega2, nullptr, nullptr,
                 nullptr, c->q, c->spart, cnt(c, CNT_DOTS), c->st);
 }
@@ -557,7 +613,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
     ALLOC(c->qv, q); ALLOC(c->qv2, q);
     ALLOC(c->cg_x, q); ALLOC(c->cg_r, q); ALLOC(c->cg_z, q); ALLOC(c->cg_p, q); ALLOC(c->cg_ap, q);
     ALLOC(c->diag, q);
-    ALLOC(c->spart, 4 * 4096);
+    ALLOC(c->spart, 8 * 4096);
     ALLOC(c->blk, compact_blocks(n) + 1);
     ALLOC(c->counters, CNT_N);
     ALLOC(c->ds, 1);
@@ -594,6 +650,14 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
     }
     if (pr->kind == SSNALM_CSR) {
         if ((s = setup_csr(c, pr)) < 0) return bail(s);
+        if (!c->use_chol) {
+            const int64_t nz = std::max<int64_t>(pr->nnz, 1);
+            ALLOC(c->jrank, n); ALLOC(c->jr, nz); ALLOC(c->jc, nz); ALLOC(c->wJ, n);
+            ALLOC(c->tcount, c->tr.ntile + 1); ALLOC(c->toff, c->tr.ntile + 2);
+            ALLOC(c->kcarry, 2 * (nz / 128 + 2)); ALLOC(c->cgpart, 1024 + 512 + 1024);
+            if (c->dtype == SSNALM_F64) { double* t; ALLOC(t, nz); c->jv = t; }
+            else { float* t; ALLOC(t, nz); c->jv = t; }
+        }
     } else if (c->opt.check_finite) {
         // scan X on the host in blocks (creation-time check only)
         const size_t eb = pr->dtype == SSNALM_F64 ? 8 : (pr->dtype == SSNALM_F32 ? 4 : 2);
@@ -628,7 +692,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     c->proj_passes = 0;
     ssnalm_info inf;
     memset(&inf, 0, sizeof inf);
-    int inner_total = 0, cg_total = 0, ls_fail = 0, outer = 0;
+    int inner_total = 0, cg_total = 0, ls_fail = 0, outer = 0, ls_trials = 0;
     ssnalm_status status = SSNALM_MAXITER;
 
     // x^0: zero or the projection of the warm start; omega^0 = A^T x^0
@@ -690,7 +754,8 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
             bool accepted = false;
             const int trial = 1 - c->base;
             for (int m = 0; m <= o.max_backtracks; ++m) {
-                STCHK(project_into(c, c->u, c->td, alpha * sigma, c->ut, trial));
+                ++ls_trials;
+                STCHK(project_into(c, c->u, c->td, alpha * sigma, c->ut, trial, dps(c, c->base)));
                 STCHK(sync_state(c));
                 STCHK(project_finish(c, c->ut, trial, &more));
                 launch_ls_finalize(c->ut, c->u, c->td, alpha * sigma, c->y, n, c->C,
@@ -768,6 +833,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     inf.p = (int32_t)c->hs->sc.p;
     inf.n_sv = (int32_t)c->hs->sc.nsv;
     inf.ls_fail = ls_fail;
+    inf.ls_trials = ls_trials;
     inf.status = status;
     if (info) *info = inf;
     return status;

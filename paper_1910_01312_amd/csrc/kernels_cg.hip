@@ -1,0 +1,431 @@
+// Conjugate gradients for step 1 of Algorithm 3 on sparse input, solved to
+// the paper's residual tolerance min(eta, |grad psi|^{1+tau}):
+//     M d = -g,   M = I + sigma X_J^T (I - 1 1^T/p) X_J,
+// with the Jacobi preconditioner diag(M).  Writing w = X_J v and s = X_J^T 1,
+//     M v = v + sigma (X_J^T w - (s.v / p) s),
+//     v.M v = |v|^2 + sigma (|w|^2 - (s.v)^2 / p),
+// so one CG iteration needs X_J v, X_J^T w and a handful of q-vector sums.
+//
+// Cross-block sums never use atomics or fences: every kernel writes one
+// partial per block, and the NEXT kernel (whose blocks all start after the
+// writer finished) re-reduces those partials itself, in the same fixed order
+// in every block.  All blocks therefore see bit-identical scalars.
+//
+// X_J^T w runs over the compact column-major copy of X_J (entries sorted by
+// column) in fixed chunks of 512 entries (8 per lane, one wave per chunk).
+// Runs of equal column inside a chunk are summed by a segmented scan; a run
+// that reaches a chunk border is left as a carry and the chunk where the
+// run starts adds the carries of the chunks it runs through, in chunk order.
+#include "dev_common.h"
+#include "ssn_internal.h"
+
+namespace ssn {
+
+constexpr int KE = 4;
+constexpr int KCH = KE * SSN_WAVE;     // entries per chunk
+
+// --------------------------------------------------------------- partials
+// Fixed-order sum of part[b*stride + c], b < nb, by the whole block (every
+// block computes the same value).
+__device__ __forceinline__ double red_col(const double* __restrict__ part, int nb, int stride,
+                                          int c, double* sh) {
+    double a0 = 0.0, a1 = 0.0;
+    int b = threadIdx.x;
+    const int T = blockDim.x;
+    for (; b + T < nb; b += 2 * T) {
+        a0 += part[(int64_t)b * stride + c];
+        a1 += part[(int64_t)(b + T) * stride + c];
+    }
+    for (; b < nb; b += T) a0 += part[(int64_t)b * stride + c];
+    return block_sum(a0 + a1, sh);
+}
+
+static inline unsigned qgrid(int64_t q) {
+    int64_t b = (q + 2047) / 2048;
+    if (b > 256) b = 256;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+unsigned cg_qgrid(int64_t q) { return qgrid(q); }
+
+// --------------------------------------------------------------- init
+// x = 0, r = -g, z = r/diag, p = z; partials: Pst = (r.z, r.r), Pdir = (p.p, s.p)
+__global__ __launch_bounds__(SSN_BLOCK) void k_cg_init(const double* __restrict__ g,
+                                                       const double* __restrict__ diag,
+                                                       const double* __restrict__ sv, int64_t q,
+                                                       double* __restrict__ x,
+                                                       double* __restrict__ r,
+                                                       double* __restrict__ z,
+                                                       double* __restrict__ pd,
+                                                       double* __restrict__ Pst,
+                                                       double* __restrict__ Pdir) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    double rz = 0.0, rr = 0.0, pp = 0.0, sp = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
+        const double rj = -g[j];
+        const double zj = rj / diag[j];
+        x[j] = 0.0;
+        r[j] = rj;
+        z[j] = zj;
+        pd[j] = zj;
+        rz = fma(rj, zj, rz);
+        rr = fma(rj, rj, rr);
+        pp = fma(zj, zj, pp);
+        sp = fma(sv[j], zj, sp);
+    }
+    const double a = block_sum(rz, sh), b = block_sum(rr, sh);
+    const double c = block_sum(pp, sh), d = block_sum(sp, sh);
+    if (threadIdx.x == 0) {
+        Pst[blockIdx.x * 2] = a;
+        Pst[blockIdx.x * 2 + 1] = b;
+        Pdir[blockIdx.x * 2] = c;
+        Pdir[blockIdx.x * 2 + 1] = d;
+    }
+}
+
+// --------------------------------------------------------------- X_J v
+// w[k] = (X_J v)_k for the k-th row of the ordered J list; Pw[b] = sum w^2.
+// 16 lanes per row; each lane issues its loads four entries at a time.
+template <typename V>
+__global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       const V* __restrict__ val,
+                                                       const int32_t* __restrict__ list, int64_t p,
+                                                       const double* __restrict__ v,
+                                                       double* __restrict__ w,
+                                                       double* __restrict__ Pw) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int grp = lane >> 4, sub = lane & 15;
+    const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    double ww = 0.0;
+    for (int64_t base = wave * 4; base < p; base += nwave * 4) {
+        const int64_t k = base + grp;
+        double acc = 0.0;
+        if (k < p) {
+            const int32_t r = list[k];
+            const int32_t e0 = rp[r], e1 = rp[r + 1];
+            int32_t e = e0 + sub;
+            for (; e + 48 < e1; e += 64) {
+                const int32_t c0 = ci[e], c1 = ci[e + 16], c2 = ci[e + 32], c3 = ci[e + 48];
+                const double a0 = (double)val[e], a1 = (double)val[e + 16];
+                const double a2 = (double)val[e + 32], a3 = (double)val[e + 48];
+                const double v0 = v[c0], v1 = v[c1], v2 = v[c2], v3 = v[c3];
+                acc = fma(a0, v0, acc);
+                acc = fma(a1, v1, acc);
+                acc = fma(a2, v2, acc);
+                acc = fma(a3, v3, acc);
+            }
+            for (; e < e1; e += 16) acc = fma((double)val[e], v[ci[e]], acc);
+        }
+        acc += __shfl_xor(acc, 8, SSN_WAVE);
+        acc += __shfl_xor(acc, 4, SSN_WAVE);
+        acc += __shfl_xor(acc, 2, SSN_WAVE);
+        acc += __shfl_xor(acc, 1, SSN_WAVE);
+        if (k < p && sub == 0) {
+            w[k] = acc;
+            ww = fma(acc, acc, ww);
+        }
+    }
+    const double bs = block_sum(ww, sh);
+    if (threadIdx.x == 0) Pw[blockIdx.x] = bs;
+}
+
+unsigned cg_rows_grid(int64_t p) {
+    int64_t b = (p + 15) / 16;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+void launch_cg_rows(const SegPlan& F, const int32_t* list, int64_t p, const double* v, double* w,
+                    double* Pw, hipStream_t s) {
+    const unsigned g = cg_rows_grid(p);
+    if (F.val_f64)
+        hipLaunchKernelGGL((k_cg_rows<double>), dim3(g), dim3(SSN_BLOCK), 0, s, F.ptr, F.idx,
+                           (const double*)F.val, list, p, v, w, Pw);
+    else
+        hipLaunchKernelGGL((k_cg_rows<float>), dim3(g), dim3(SSN_BLOCK), 0, s, F.ptr, F.idx,
+                           (const float*)F.val, list, p, v, w, Pw);
+}
+
+// --------------------------------------------------------------- X_J^T w
+// out[c] = sum over compact entries of column c of coef, coef =
+//   MODE 0: val * w[rank];  MODE 1: val;  MODE 2: val^2.
+// Carry slots per chunk: [0] the run that ends here coming from the left,
+// [1] the run that leaves to the right (possibly having come from the left).
+template <typename V, int MODE>
+__global__ __launch_bounds__(SSN_BLOCK) void k_keyed_tr(const int32_t* __restrict__ jr,
+                                                        const int32_t* __restrict__ jc,
+                                                        const V* __restrict__ jv, int64_t nnzj,
+                                                        const double* __restrict__ w,
+                                                        double* __restrict__ carry,
+                                                        double* __restrict__ out) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t ch = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t cb = ch * KCH;
+    if (cb >= nnzj) return;
+    const int64_t ce = cb + KCH < nnzj ? cb + KCH : nnzj;
+    const int64_t k0 = cb + (int64_t)lane * KE;
+    const int64_t k1 = k0 + KE < ce ? k0 + KE : ce;
+    const bool active = k0 < ce;
+    const int32_t kfirst = jc[cb], klast = jc[ce - 1];
+    const bool left_in = cb > 0 && jc[cb - 1] == kfirst;       // first run continues from the left
+    const bool right_out = ce < nnzj && jc[ce] == klast;        // last run continues to the right
+    const int32_t INF = 0x7fffffff;
+    int32_t F = INF, Lt = INF;
+    double fsum = 0.0, lsum = 0.0;
+    if (active) {
+        int32_t keys[KE];
+        double cf[KE];
+#pragma unroll
+        for (int e = 0; e < KE; ++e) {
+            const int64_t k = k0 + e;
+            if (k < k1) {
+                keys[e] = jc[k];
+                const double a = (double)jv[k];
+                if (MODE == 0) cf[e] = a * w[jr[k]];
+                else if (MODE == 1) cf[e] = a;
+                else cf[e] = a * a;
+            } else {
+                keys[e] = -1;
+                cf[e] = 0.0;
+            }
+        }
+        int32_t key = keys[0];
+        F = key;
+        double cur = 0.0;
+        bool first_closed = false;
+#pragma unroll
+        for (int e = 0; e < KE; ++e) {
+            if (keys[e] < 0) break;
+            if (keys[e] != key) {
+                if (!first_closed) {
+                    first_closed = true;
+                    fsum = cur;
+                } else {
+                    out[key] = cur;                 // run strictly inside the lane: complete
+                }
+                key = keys[e];
+                cur = 0.0;
+            }
+            cur += cf[e];
+        }
+        Lt = key;
+        lsum = cur;
+        if (!first_closed) F = Lt;
+    }
+    double S = lsum;
+#pragma unroll
+    for (int off = 1; off < SSN_WAVE; off <<= 1) {
+        const double o = __shfl_up(S, off, SSN_WAVE);
+        const int32_t ok = __shfl_up(Lt, off, SSN_WAVE);
+        if (lane >= off && ok == Lt) S += o;
+    }
+    const double S_prev = __shfl_up(S, 1, SSN_WAVE);
+    const int32_t Lt_prev = __shfl_up(Lt, 1, SSN_WAVE);
+    const int32_t F_next = __shfl_down(F, 1, SSN_WAVE);
+    const bool has_next = lane + 1 < SSN_WAVE && (k0 + KE) < ce;
+    auto emit = [&](int32_t c, double v) {
+        const bool l = (c == kfirst) && left_in;
+        const bool r = (c == klast) && right_out;
+        if (r) carry[ch * 2 + 1] = v;
+        else if (l) carry[ch * 2 + 0] = v;
+        else out[c] = v;
+    };
+    if (active) {
+        if (F < Lt) {
+            double tot = fsum;
+            if (lane > 0 && Lt_prev == F) tot += S_prev;
+            emit(F, tot);
+        }
+        if (!has_next || F_next != Lt) emit(Lt, S);
+    }
+}
+
+// Chunks where a border-crossing run starts (its last run leaves to the
+// right without having come from the left) add the carries of the chunks
+// the run passes through and of the chunk where it ends.  One wave each.
+__global__ __launch_bounds__(SSN_BLOCK) void k_keyed_fix(const int32_t* __restrict__ jc,
+                                                         int64_t nnzj, int64_t nch,
+                                                         const double* __restrict__ carry,
+                                                         double* __restrict__ out) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t ch = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    if (ch >= nch) return;
+    const int64_t cb = ch * KCH;
+    const int64_t ce = cb + KCH < nnzj ? cb + KCH : nnzj;
+    const int32_t K = jc[ce - 1];
+    const bool right_out = ce < nnzj && jc[ce] == K;
+    if (!right_out) return;
+    const bool single = jc[cb] == K;
+    const bool left_in = single && cb > 0 && jc[cb - 1] == K;
+    if (left_in) return;                       // not where the run starts
+    double tot = 0.0;
+    if (lane == 0) tot = carry[ch * 2 + 1];
+    int64_t base = ch + 1;
+    for (;;) {
+        const int64_t c2 = base + lane;
+        bool pass = false, valid = c2 < nch;
+        if (valid) {
+            const int64_t b2 = c2 * KCH;
+            const int64_t e2 = b2 + KCH < nnzj ? b2 + KCH : nnzj;
+            pass = jc[b2] == K && jc[e2 - 1] == K && e2 < nnzj && jc[e2] == K;
+        }
+        const unsigned long long stop = __ballot(valid && !pass);
+        const int term = stop ? __ffsll((long long)stop) - 1 : SSN_WAVE;
+        double v = 0.0;
+        if (lane < term && valid) v = carry[c2 * 2 + 1];
+        if (lane == term) v = carry[c2 * 2 + 0];
+        tot += wave_sum(v);
+        if (term < SSN_WAVE) break;
+        base += SSN_WAVE;
+        if (base >= nch) break;
+    }
+    if (lane == 0) out[K] = tot;
+}
+
+void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
+                     int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
+                     hipStream_t s, bool zero_out) {
+    if (zero_out) launch_fill(out, 0.0, q, s);
+    if (nnzj <= 0) return;
+    const int64_t nch = (nnzj + KCH - 1) / KCH;
+    const unsigned nb = (unsigned)((nch + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+#define KT(V, M) hipLaunchKernelGGL((k_keyed_tr<V, M>), dim3(nb), dim3(SSN_BLOCK), 0, s, jr, jc, \
+                                    (const V*)jv, nnzj, w, carry, out)
+    if (val_f64) {
+        if (mode == 0) KT(double, 0); else if (mode == 1) KT(double, 1); else KT(double, 2);
+    } else {
+        if (mode == 0) KT(float, 0); else if (mode == 1) KT(float, 1); else KT(float, 2);
+    }
+#undef KT
+    hipLaunchKernelGGL(k_keyed_fix, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, nch, carry, out);
+}
+
+// --------------------------------------------------------------- step
+// Scalars from the partials: rz = r.z, rr = r.r (previous step), pp = p.p,
+// sp = s.p (direction kernel), ww = |X_J p|^2 (row kernel).  Then
+// pAp = pp + sigma (ww - sp^2/p), alpha = rz / pAp, and with
+// Ap = p + sigma (t - (sp/p) s):  x += alpha p, r -= alpha Ap, z = r / diag.
+// Once rr <= tol2 (or pAp <= 0) the step leaves x unchanged and passes the
+// partials through, so later iterations stay put.
+__global__ __launch_bounds__(SSN_BLOCK) void k_cg_step(
+    double* __restrict__ x, double* __restrict__ r, const double* __restrict__ pd,
+    const double* __restrict__ t, const double* __restrict__ sv, const double* __restrict__ diag,
+    double* __restrict__ z, int64_t q, double sigma, double inv_p, const double* __restrict__ Pw,
+    int nbw, const double* __restrict__ Pdir, const double* __restrict__ Pold,
+    double* __restrict__ Pnew, double tol2) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    const int nbq = gridDim.x;
+    const double rz = red_col(Pold, nbq, 2, 0, sh);
+    const double rr = red_col(Pold, nbq, 2, 1, sh);
+    const double pp = red_col(Pdir, nbq, 2, 0, sh);
+    const double sp = red_col(Pdir, nbq, 2, 1, sh);
+    const double ww = red_col(Pw, nbw, 1, 0, sh);
+    const double pap = pp + sigma * (ww - sp * sp * inv_p);
+    const bool done = !(rr > tol2) || !(pap > 0.0) || !(rz > 0.0);
+    if (done) {
+        if (threadIdx.x == 0) {
+            Pnew[blockIdx.x * 2] = Pold[blockIdx.x * 2];
+            Pnew[blockIdx.x * 2 + 1] = 0.0;            // sticky: rr = 0 from now on
+        }
+        return;
+    }
+    const double alpha = rz / pap, m = sp * inv_p;
+    double a = 0.0, b = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
+        const double pj = pd[j];
+        const double apj = fma(sigma, t[j] - m * sv[j], pj);
+        x[j] = fma(alpha, pj, x[j]);
+        const double rj = fma(-alpha, apj, r[j]);
+        r[j] = rj;
+        const double zj = rj / diag[j];
+        z[j] = zj;
+        a = fma(rj, zj, a);
+        b = fma(rj, rj, b);
+    }
+    const double sa = block_sum(a, sh), sb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        Pnew[blockIdx.x * 2] = sa;
+        Pnew[blockIdx.x * 2 + 1] = sb;
+    }
+}
+
+// beta = rz_new / rz_old; p = z + beta p; partials (p.p, s.p).  Block 0 also
+// publishes rr and the done flag for the host.
+__global__ __launch_bounds__(SSN_BLOCK) void k_cg_dir(double* __restrict__ pd,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ sv, int64_t q,
+                                                      const double* __restrict__ Pold,
+                                                      const double* __restrict__ Pnew,
+                                                      double* __restrict__ Pdir, double tol2,
+                                                      Scalars* sc, double* __restrict__ tz) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    const int nbq = gridDim.x;
+    const double rz_old = red_col(Pold, nbq, 2, 0, sh);
+    const double rz_new = red_col(Pnew, nbq, 2, 0, sh);
+    const double rr_new = red_col(Pnew, nbq, 2, 1, sh);
+    const bool done = !(rr_new > tol2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->cg_rr = rr_new;
+        sc->cg_done = done ? 1 : 0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (done) {                       // p unchanged; the next step passes through
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride)
+            tz[j] = 0.0;
+        return;
+    }
+    const double beta = rz_old > 0.0 ? rz_new / rz_old : 0.0;
+    double pp = 0.0, sp = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
+        const double pj = fma(beta, pd[j], z[j]);
+        pd[j] = pj;
+        tz[j] = 0.0;                  // output of the next X_J^T w starts at zero
+        pp = fma(pj, pj, pp);
+        sp = fma(sv[j], pj, sp);
+    }
+    const double a = block_sum(pp, sh), b = block_sum(sp, sh);
+    if (threadIdx.x == 0) {
+        Pdir[blockIdx.x * 2] = a;
+        Pdir[blockIdx.x * 2 + 1] = b;
+    }
+}
+
+void launch_cg_init(const double* g, const double* diag, const double* sv, int64_t q, double* x,
+                    double* r, double* z, double* pd, double* Pst, double* Pdir, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, g, diag, sv, q, x, r, z, pd,
+                       Pst, Pdir);
+}
+void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
+                    const double* diag, double* z, int64_t q, double sigma, int64_t p,
+                    const double* Pw, int nbw, const double* Pdir, const double* Pold, double* Pnew,
+                    double tol2, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_step, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, x, r, pd, t, sv, diag, z, q,
+                       sigma, p > 0 ? 1.0 / (double)p : 0.0, Pw, nbw, Pdir, Pold, Pnew, tol2);
+}
+void launch_cg_dir(double* pd, const double* z, const double* sv, int64_t q, const double* Pold,
+                   const double* Pnew, double* Pdir, double tol2, Scalars* sc, double* tz,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_dir, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, pd, z, sv, q, Pold, Pnew,
+                       Pdir, tol2, sc, tz);
+}
+
+// rr and done flag straight after init (one block)
+__global__ void k_cg_publish(const double* __restrict__ Pst, int nbq, double tol2, Scalars* sc) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    const double rr = red_col(Pst, nbq, 2, 1, sh);
+    if (threadIdx.x == 0) {
+        sc->cg_rr = rr;
+        sc->cg_done = rr > tol2 ? 0 : 1;
+    }
+}
+void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_publish, dim3(1), dim3(SSN_BLOCK), 0, s, Pst, (int)qgrid(q), tol2, sc);
+}
+
+}  // namespace ssn

@@ -52,15 +52,14 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_init(const double* __restrict
     }
     const double a = block_sum(rz, shd), b = block_sum(rr, shd);
     if (threadIdx.x == 0) { part[blockIdx.x * 2] = a; part[blockIdx.x * 2 + 1] = b; }
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) {
-            s0 += ld_acquire(&part[k * 2]);
-            s1 += ld_acquire(&part[k * 2 + 1]);
+    if (last_block_arrives(counter)) {
+        const double s0 = grid_colsum(part, gridDim.x, 2, 0, shd);
+        const double s1 = grid_colsum(part, gridDim.x, 2, 1, shd);
+        if (threadIdx.x == 0) {
+            sc->cg_rz = s0;
+            sc->cg_rr = s1;
+            sc->cg_done = 0;
         }
-        sc->cg_rz = s0;
-        sc->cg_rr = s1;
-        sc->cg_done = 0;
     }
 }
 void launch_pcg_init(const double* g, const double* diag, double* x, double* r, double* z, double* pd,
@@ -82,10 +81,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_pap(const double* __restrict_
         s = fma(pd[j], Ap[j], s);
     const double a = block_sum(s, shd);
     if (threadIdx.x == 0) part[blockIdx.x] = a;
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double t = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) t += ld_acquire(&part[k]);
-        sc->cg_pap = t;
+    if (last_block_arrives(counter)) {
+        const double t = grid_colsum(part, gridDim.x, 1, 0, shd);
+        if (threadIdx.x == 0) sc->cg_pap = t;
     }
 }
 void launch_pcg_pap(const double* pd, const double* Ap, int64_t q, Scalars* sc, double* part,
@@ -122,16 +120,15 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_step(double* __restrict__ x,
     }
     const double sa = block_sum(a, shd), sb = block_sum(b, shd);
     if (threadIdx.x == 0) { part[blockIdx.x * 2] = sa; part[blockIdx.x * 2 + 1] = sb; }
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) {
-            s0 += ld_acquire(&part[k * 2]);
-            s1 += ld_acquire(&part[k * 2 + 1]);
+    if (last_block_arrives(counter)) {
+        const double s0 = grid_colsum(part, gridDim.x, 2, 0, shd);
+        const double s1 = grid_colsum(part, gridDim.x, 2, 1, shd);
+        if (threadIdx.x == 0) {
+            sc->cg_beta = rz > 0.0 ? s0 / rz : 0.0;
+            sc->cg_rz = s0;
+            sc->cg_rr = s1;
+            if (s1 <= tol2 || !(alpha > 0.0)) sc->cg_done = 1;
         }
-        sc->cg_beta = rz > 0.0 ? s0 / rz : 0.0;
-        sc->cg_rz = s0;
-        sc->cg_rr = s1;
-        if (s1 <= tol2 || !(alpha > 0.0)) sc->cg_done = 1;
     }
 }
 void launch_pcg_step(double* x, double* r, double* pd, const double* Ap, const double* diag,
@@ -167,10 +164,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_masked_mean(const double* __restr
         if (mask[i]) s += (double)y[i] * t[i];
     const double a = block_sum(s, shd);
     if (threadIdx.x == 0) part[blockIdx.x] = a;
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double tot = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) tot += ld_acquire(&part[k]);
-        *mean_out = tot * inv_p;
+    if (last_block_arrives(counter)) {
+        const double tot = grid_colsum(part, gridDim.x, 1, 0, shd);
+        if (threadIdx.x == 0) *mean_out = tot * inv_p;
     }
 }
 void launch_masked_mean(const double* t, const int8_t* y, const uint8_t* mask, int64_t n, int64_t p,
@@ -230,16 +226,15 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_count_x(const double* __restrict_
         part[blockIdx.x * 3 + 1] = (double)bn;
         part[blockIdx.x * 3 + 2] = bs;
     }
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double a = 0.0, b = 0.0, c = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) {
-            a += ld_acquire(&part[k * 3]);
-            b += ld_acquire(&part[k * 3 + 1]);
-            c += ld_acquire(&part[k * 3 + 2]);
+    if (last_block_arrives(counter)) {
+        const double a = grid_colsum(part, gridDim.x, 3, 0, shd);
+        const double b = grid_colsum(part, gridDim.x, 3, 1, shd);
+        const double c = grid_colsum(part, gridDim.x, 3, 2, shd);
+        if (threadIdx.x == 0) {
+            sc->p = (long long)a;
+            sc->nsv = (long long)b;
+            sc->sumx = c;
         }
-        sc->p = (long long)a;
-        sc->nsv = (long long)b;
-        sc->sumx = c;
     }
 }
 void launch_count_x(const double* x, int64_t n, double C, Scalars* sc, double* part,

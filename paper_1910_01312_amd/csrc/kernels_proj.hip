@@ -9,20 +9,23 @@
 //     -y_i clip(v_i - lam y_i, 0, C) = clip(lam - b_i, 0, C) - C [y_i > 0],
 // so g has the 2n breakpoints b_i and b_i + C.  Instead of sorting them
 // (Algorithm 2) the GPU brackets the root by multisection: each pass
-// evaluates g at PK+1 equally spaced points of the current bracket
-// [lo, hi] (g(lo) < 0 <= g(hi)) in one sweep over the data, keeps the
-// sub-interval where g changes sign, and counts the breakpoints strictly
-// inside the current bracket.  When none is inside, g is affine on the
-// bracket and the zero is found by the same linear interpolation that
+// evaluates g at PK+1 points of the current bracket [lo, hi]
+// (g(lo) < 0 <= g(hi)) in one sweep over the data, keeps the sub-interval
+// where g changes sign, and counts (integer histogram) the breakpoints
+// strictly inside every sub-interval.  When the kept one holds none, g is
+// affine on it and the zero is found by the same linear interpolation that
 // Algorithm 2 performs between its two final breakpoints; the result is the
-// smallest zero of g, the value Algorithm 2 returns.
+// smallest zero of g, the value Algorithm 2 returns.  The points are equally
+// spaced, except in the first pass of a projection that has a nearby
+// multiplier (a line-search trial next to the accepted point): there they
+// lie at hint -/+ C 4^e, e = -15..15, plus the two ends.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
 namespace ssn {
 
-constexpr int PK = 32;            // sub-intervals per pass
-constexpr int PNV = PK + 2;       // partial values per block: PK+1 g-values, 1 count
+constexpr int PK = 64;            // sub-intervals per pass
+constexpr int PNV = PK + 1;       // partial values per block: PK+1 g-values
 constexpr int PROJ_MAXPASS = 48;
 constexpr int PROJ_GRID_MAX = 256;
 
@@ -45,7 +48,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
                                                          const int8_t* __restrict__ y, int64_t n,
                                                          double C, ProjState* st,
                                                          double* __restrict__ part,
-                                                         unsigned* counter) {
+                                                         unsigned* counter,
+                                                         const ProjState* hint) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     __shared__ long long shl[SSN_WAVES_PER_BLOCK];
     double bmin = 1.0 / 0.0, bmax = -1.0 / 0.0;
@@ -83,19 +87,32 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
         part[blockIdx.x * 3 + 2] = (double)c;
     }
     if (last_block_arrives(counter)) {
+        // min / max are order-independent; the count is an exact integer
+        double mn = 1.0 / 0.0, mx = -1.0 / 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+            mn = fmin(mn, ld_acquire(&part[b * 3 + 0]));
+            mx = fmax(mx, ld_acquire(&part[b * 3 + 1]));
+        }
+        mn = wave_min(mn);
+        mx = wave_max(mx);
+        __syncthreads();
+        if (lane == 0) { shd[w] = mn; }
+        __syncthreads();
+        for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) mn = fmin(mn, shd[k]);
+        __syncthreads();
+        if (lane == 0) { shd[w] = mx; }
+        __syncthreads();
+        for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) mx = fmax(mx, shd[k]);
+        const double cnt = grid_colsum(part, gridDim.x, 3, 2, shd);
         if (threadIdx.x == 0) {
-            double mn = 1.0 / 0.0, mx = -1.0 / 0.0, cnt = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) {
-                mn = fmin(mn, ld_acquire(&part[b * 3 + 0]));
-                mx = fmax(mx, ld_acquire(&part[b * 3 + 1]));
-                cnt += ld_acquire(&part[b * 3 + 2]);
-            }
             st->lo = mn;
             st->hi = mx + 2.0 * C;
             st->npos = (long long)cnt;
             st->passes = 0;
             st->approx = 0;
             st->inside = -1;
+            st->mode = hint ? 1 : 0;
+            st->hint = hint ? hint->lam : 0.0;
             st->glo = -C * cnt;
             st->ghi = C * ((double)n - cnt);
             if (cnt == 0.0) {          // g <= 0 everywhere: the search's left end
@@ -111,37 +128,55 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
 
 void launch_proj_init(const double* u, const double* td, double alpha_sigma, double* v_out,
                       const int8_t* y, int64_t n, double C, ProjState* st, double* part,
-                      unsigned* counter, hipStream_t s) {
+                      unsigned* counter, hipStream_t s, const ProjState* hint) {
     const unsigned g = proj_grid(n);
     if (td)
         hipLaunchKernelGGL((k_proj_init<true>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, alpha_sigma,
-                           v_out, y, n, C, st, part, counter);
+                           v_out, y, n, C, st, part, counter, hint);
     else
         hipLaunchKernelGGL((k_proj_init<false>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, 0.0,
-                           v_out, y, n, C, st, part, counter);
+                           v_out, y, n, C, st, part, counter, hint);
 }
 
 // ------------------------------------------------------------------ pass
-__device__ __forceinline__ double cand(double lo, double hi, int k) {
+__device__ __forceinline__ double cand_uniform(double lo, double hi, int k) {
     return k == PK ? hi : lo + (hi - lo) * ((double)k / (double)PK);
+}
+// geometric points around the hint: k = 1..31 -> hint - C 4^(16-k),
+// k = 32 -> hint, k = 33..63 -> hint + C 4^(k-48); clamped to [lo, hi]
+__device__ __forceinline__ double cand_geometric(double lo, double hi, double hint, double C, int k) {
+    if (k == 0) return lo;
+    if (k == PK) return hi;
+    double v;
+    if (k < 32) v = hint - C * ldexp(1.0, 2 * (16 - k));
+    else if (k == 32) v = hint;
+    else v = hint + C * ldexp(1.0, 2 * (k - 48));
+    return fmin(fmax(v, lo), hi);
 }
 
 __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restrict__ v,
                                                          const int8_t* __restrict__ y, int64_t n,
                                                          double C, ProjState* st,
                                                          double* __restrict__ part,
+                                                         int* __restrict__ hpart,
                                                          unsigned* counter) {
     __shared__ double lam_s[PK + 1];
     __shared__ double red[SSN_WAVES_PER_BLOCK][PNV];
-    __shared__ double fin[8][PNV];
+    __shared__ double fin[PNV];
+    __shared__ int hist[PK];
+    __shared__ int hfin[PK];
     if (ld_acquire(&st->done)) return;         // uniform over the grid
     const double lo = st->lo, hi = st->hi;
-    if (threadIdx.x <= PK) lam_s[threadIdx.x] = cand(lo, hi, threadIdx.x);
+    const bool geo = st->mode == 1;
+    const double hint = st->hint;
+    if (threadIdx.x <= PK)
+        lam_s[threadIdx.x] = geo ? cand_geometric(lo, hi, hint, C, threadIdx.x)
+                                 : cand_uniform(lo, hi, threadIdx.x);
+    if (threadIdx.x < PK) hist[threadIdx.x] = 0;
     __syncthreads();
     double acc[PK + 1];
 #pragma unroll
     for (int k = 0; k <= PK; ++k) acc[k] = 0.0;
-    double inside = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double vi = v[i];
@@ -151,8 +186,19 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
         const double cp = pos ? C : 0.0;
 #pragma unroll
         for (int k = 0; k <= PK; ++k) acc[k] += clampd(lam_s[k] - b, 0.0, C) - cp;
-        inside += (b > lo && b < hi) ? 1.0 : 0.0;
-        inside += (bh > lo && bh < hi) ? 1.0 : 0.0;
+        // histogram of breakpoints strictly inside each sub-interval
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double t = h ? bh : b;
+            if (t > lam_s[0] && t < lam_s[PK]) {
+                int lo_k = 0, hi_k = PK;           // lam_s[lo_k] < t < lam_s[hi_k]
+                while (hi_k - lo_k > 1) {
+                    const int mid = (lo_k + hi_k) >> 1;
+                    if (lam_s[mid] < t) lo_k = mid; else hi_k = mid;
+                }
+                if (t < lam_s[lo_k + 1]) atomicAdd(&hist[lo_k], 1);
+            }
+        }
     }
     const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
 #pragma unroll
@@ -160,63 +206,76 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
         const double s = wave_sum(acc[k]);
         if (lane == 0) red[w][k] = s;
     }
-    {
-        const double s = wave_sum(inside);
-        if (lane == 0) red[w][PK + 1] = s;
-    }
     __syncthreads();
+    const int nb = gridDim.x;                   // <= PROJ_GRID_MAX
     if (threadIdx.x < PNV) {
         double s = 0.0;
 #pragma unroll
         for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) s += red[ww][threadIdx.x];
-        part[(int64_t)blockIdx.x * PNV + threadIdx.x] = s;
+        part[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = s;   // [column][block]
     }
+    if (threadIdx.x < PK) hpart[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = hist[threadIdx.x];
     if (!last_block_arrives(counter)) return;
-    // ---- last block: fixed-order reduction over blocks, then the decision
-    const int nb = gridDim.x;
-    for (int e = threadIdx.x; e < 8 * PNV; e += blockDim.x) {
-        const int c = e % PNV, gi = e / PNV;
-        double s = 0.0;
-        for (int b = gi; b < nb; b += 8) s += ld_acquire(&part[(int64_t)b * PNV + c]);
-        fin[gi][c] = s;
+    // ---- last block: fixed-order reduction over blocks, then the decision.
+    // Column c is summed by wave c mod 4: lane l owns blocks l, l+64, l+128,
+    // l+192; all loads of the wave's columns are issued before any sum.
+    {
+        constexpr int CPW = (PNV + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
+        constexpr int BPL = PROJ_GRID_MAX / SSN_WAVE;
+        double vals[CPW][BPL];
+#pragma unroll
+        for (int i = 0; i < CPW; ++i) {
+            const int c = w + i * SSN_WAVES_PER_BLOCK;
+#pragma unroll
+            for (int j = 0; j < BPL; ++j) {
+                const int bb = lane + j * SSN_WAVE;
+                vals[i][j] = (c < PNV && bb < nb) ? ld_acquire(&part[(int64_t)c * PROJ_GRID_MAX + bb]) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CPW; ++i) {
+            const int c = w + i * SSN_WAVES_PER_BLOCK;
+            double sum = 0.0;
+#pragma unroll
+            for (int j = 0; j < BPL; ++j) sum += vals[i][j];
+            sum = wave_sum(sum);
+            if (lane == 0 && c < PNV) fin[c] = sum;
+        }
+        // histogram: integer sums (exact in any order)
+        for (int c = w; c < PK; c += SSN_WAVES_PER_BLOCK) {
+            long long hsum = 0;
+            for (int bb = lane; bb < nb; bb += SSN_WAVE) hsum += ld_acquire(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]);
+            hsum = wave_sum_ll(hsum);
+            if (lane == 0) hfin[c] = (int)hsum;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double G[PK + 1];
-        for (int c = 0; c <= PK; ++c) {
-            double s = 0.0;
-            for (int gi = 0; gi < 8; ++gi) s += fin[gi][c];
-            G[c] = s;
-        }
-        double ins = 0.0;
-        for (int gi = 0; gi < 8; ++gi) ins += fin[gi][PK + 1];
         const int passes = st->passes + 1;
         st->passes = passes;
-        st->inside = (int)ins;
-        st->glo = G[0];
-        st->ghi = G[PK];
-        bool finish = (ins == 0.0) || passes >= PROJ_MAXPASS;
+        st->mode = 0;
         int j = 0;
-        if (!finish) {
-            for (int k = 0; k < PK; ++k)
-                if (G[k] < 0.0) j = k;
-            const double nlo = cand(lo, hi, j), nhi = cand(lo, hi, j + 1);
-            if (!(nlo > lo || nhi < hi)) {
-                finish = true;         // bracket cannot be split further
-            } else {
-                st->lo = nlo;
-                st->hi = nhi;
-            }
-        }
-        if (finish) {
+        for (int k = 0; k < PK; ++k)
+            if (fin[k] < 0.0) j = k;
+        const double nlo = lam_s[j], nhi = lam_s[j + 1];
+        const double g0 = fin[j], g1 = fin[j + 1];
+        const int ins = hfin[j];
+        st->inside = ins;
+        st->lo = nlo;
+        st->hi = nhi;
+        st->glo = g0;
+        st->ghi = g1;
+        // done: no breakpoint inside the kept sub-interval, the interval can
+        // no longer be split, or the pass cap
+        const bool tiny = !(nlo < nhi) || !(nlo + (nhi - nlo) / (double)PK > nlo);
+        if (ins == 0 || tiny || passes >= PROJ_MAXPASS) {
             double lam;
-            const double g0 = G[0], g1 = G[PK];
-            if (g1 == 0.0) lam = hi;
-            else if (g1 > g0) lam = lo + (-g0) / (g1 - g0) * (hi - lo);
-            else lam = lo;
-            lam = fmin(fmax(lam, lo), hi);
+            if (g1 == 0.0) lam = nhi;
+            else if (g1 > g0) lam = nlo + (-g0) / (g1 - g0) * (nhi - nlo);
+            else lam = nlo;
+            lam = fmin(fmax(lam, nlo), nhi);
             st->lam = lam;
-            st->approx = (ins == 0.0) ? 0 : 1;
+            st->approx = (ins == 0) ? 0 : 1;
             __threadfence();
             atomicExch(&st->done, 1);
         }
@@ -225,8 +284,10 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
 
 void launch_proj_pass(const double* v, const int8_t* y, int64_t n, double C, ProjState* st,
                       double* part, unsigned* counter, hipStream_t s) {
+    // doubles for the g-values, then ints for the histogram, in one scratch
+    int* hpart = reinterpret_cast<int*>(part + (int64_t)PNV * PROJ_GRID_MAX);
     hipLaunchKernelGGL(k_proj_pass, dim3(proj_grid(n)), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, part,
-                       counter);
+                       hpart, counter);
 }
 
 // ------------------------------------------------------------------ apply
@@ -241,6 +302,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_apply(const double* __restri
                                                           Scalars* sc, double* __restrict__ part,
                                                           unsigned* counter) {
     __shared__ long long shl[SSN_WAVES_PER_BLOCK];
+    __shared__ double shd[SSN_WAVES_PER_BLOCK];
     const double lam = st->lam;
     long long p = 0, nsv = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -259,14 +321,13 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_apply(const double* __restri
         part[blockIdx.x * 2 + 0] = (double)bp;
         part[blockIdx.x * 2 + 1] = (double)bs;
     }
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) {
-            a += ld_acquire(&part[k * 2 + 0]);
-            b += ld_acquire(&part[k * 2 + 1]);
+    if (last_block_arrives(counter)) {
+        const double a = grid_colsum(part, gridDim.x, 2, 0, shd);
+        const double b = grid_colsum(part, gridDim.x, 2, 1, shd);
+        if (threadIdx.x == 0) {
+            sc->p = (long long)a;
+            sc->nsv = (long long)b;
         }
-        sc->p = (long long)a;
-        sc->nsv = (long long)b;
     }
 }
 
@@ -331,18 +392,17 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_ls_finalize(
         part[blockIdx.x * 4 + 2] = (double)bp;
         part[blockIdx.x * 4 + 3] = (double)bs;
     }
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) {
-            a += ld_acquire(&part[k * 4 + 0]);
-            b += ld_acquire(&part[k * 4 + 1]);
-            c += ld_acquire(&part[k * 4 + 2]);
-            d += ld_acquire(&part[k * 4 + 3]);
+    if (last_block_arrives(counter)) {
+        const double a = grid_colsum(part, gridDim.x, 4, 0, shd);
+        const double b = grid_colsum(part, gridDim.x, 4, 1, shd);
+        const double c = grid_colsum(part, gridDim.x, 4, 2, shd);
+        const double d = grid_colsum(part, gridDim.x, 4, 3, shd);
+        if (threadIdx.x == 0) {
+            sc->dh = a;
+            sc->dist2 = b;
+            sc->p = (long long)c;
+            sc->nsv = (long long)d;
         }
-        sc->dh = a;
-        sc->dist2 = b;
-        sc->p = (long long)c;
-        sc->nsv = (long long)d;
     }
 }
 
@@ -392,16 +452,15 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_kkt_finalize(const double* __rest
         part[blockIdx.x * 3 + 1] = b;
         part[blockIdx.x * 3 + 2] = c;
     }
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) {
-            s0 += ld_acquire(&part[k * 3 + 0]);
-            s1 += ld_acquire(&part[k * 3 + 1]);
-            s2 += ld_acquire(&part[k * 3 + 2]);
+    if (last_block_arrives(counter)) {
+        const double s0 = grid_colsum(part, gridDim.x, 3, 0, shd);
+        const double s1 = grid_colsum(part, gridDim.x, 3, 1, shd);
+        const double s2 = grid_colsum(part, gridDim.x, 3, 2, shd);
+        if (threadIdx.x == 0) {
+            sc->res2 = s0;
+            sc->x2 = s1;
+            sc->sumx = s2;
         }
-        sc->res2 = s0;
-        sc->x2 = s1;
-        sc->sumx = s2;
     }
 }
 
@@ -432,14 +491,29 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_compact_count(const uint8_t* __re
         if (base + e < n) c += mask[base + e] ? 1 : 0;
     const long long bc = block_sum_ll(c, shl);
     if (threadIdx.x == 0) blk[blockIdx.x] = (int)bc;
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        long long run = 0;
-        for (unsigned b = 0; b < gridDim.x; ++b) {
+    if (last_block_arrives(counter)) {
+        // exclusive scan of the block counts: thread t owns a contiguous run
+        __shared__ long long run_sh[SSN_BLOCK];
+        const int nb = gridDim.x;
+        const int per = (nb + SSN_BLOCK - 1) / SSN_BLOCK;
+        const int b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+        long long loc = 0;
+        for (int b = b0; b < b1; ++b) loc += ld_acquire(&blk[b]);
+        run_sh[threadIdx.x] = loc;
+        __syncthreads();
+        for (int off = 1; off < SSN_BLOCK; off <<= 1) {
+            const long long t = threadIdx.x >= off ? run_sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            run_sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        long long run = run_sh[threadIdx.x] - loc;
+        for (int b = b0; b < b1; ++b) {
             const int cb = ld_acquire(&blk[b]);
             blk[b] = (int)run;
             run += cb;
         }
-        *total = run;
+        if (threadIdx.x == SSN_BLOCK - 1) *total = run_sh[SSN_BLOCK - 1];
     }
 }
 

@@ -48,48 +48,76 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
     int32_t F = INF, Lt = INF;
     double fsum = 0.0, lsum = 0.0;
     if (active) {
-        int32_t seg = lane_seg[tile * SSN_WAVE + lane];
-        int64_t segend = ptr[seg + 1];
-        F = seg;
+        const int32_t seg0 = lane_seg[tile * SSN_WAVE + lane];
+        const int ne = (int)(k1 - k0);
+        // all loads of the lane first: entry indices and values (vector
+        // loads for a full, aligned chunk), the next segment ends, then the
+        // gathered coefficients
+        int32_t ii[SEG_E];
+        double av[SEG_E];
+        if (ne == SEG_E) {
+            const int4* ip = reinterpret_cast<const int4*>(idx + k0);
+            const int4 i0 = ip[0], i1 = ip[1];
+            ii[0] = i0.x; ii[1] = i0.y; ii[2] = i0.z; ii[3] = i0.w;
+            ii[4] = i1.x; ii[5] = i1.y; ii[6] = i1.z; ii[7] = i1.w;
+#pragma unroll
+            for (int e = 0; e < SEG_E; ++e) av[e] = (double)val[k0 + e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < SEG_E; ++e) {
+                ii[e] = e < ne ? idx[k0 + e] : 0;
+                av[e] = e < ne ? (double)val[k0 + e] : 0.0;
+            }
+        }
+        int32_t ends[SEG_E];
+#pragma unroll
+        for (int j = 0; j < SEG_E; ++j)
+            ends[j] = (seg0 + 1 + j <= nseg) ? ptr[seg0 + 1 + j] : 0x7fffffff;
+        double cfv[SEG_E];
+#pragma unroll
+        for (int e = 0; e < SEG_E; ++e) {
+            double cf = 0.0;
+            if (e < ne) {
+                const int32_t i = ii[e];
+                if (vin) {
+                    cf = vin[i];
+                    if (yin) cf *= (double)yin[i];
+                    if (mask) cf *= (double)mask[i];
+                } else {
+                    cf = (double)mask[i];
+                }
+            }
+            cfv[e] = SQ ? cf * av[e] * av[e] : cf * av[e];
+        }
+        // walk the lane's entries segment by segment
+        int j = 0;                             // current segment = seg0 + j
+        int64_t segend = ends[0];
+        F = seg0;
         double cur = 0.0;
         bool have_head = false;
-        for (int64_t k = k0; k < k1; ++k) {
-            while (k >= segend) {                 // close segment `seg`
-                if (seg == F && !have_head) {
+        for (int e = 0; e < ne; ++e) {
+            const int64_t k = k0 + e;
+            while (k >= segend) {                 // close segment seg0 + j
+                const int32_t sg = seg0 + j;
+                const bool omask = out_mask && !out_mask[sg];
+                if (sg == F && !have_head) {
                     have_head = true;
                     fsum = cur;
-                    if ((int64_t)ptr[seg] >= k0) {   // complete inside the lane
-                        if (!(out_mask && !out_mask[seg]))
-                            out[seg] = (yout ? (double)yout[seg] : 1.0) * cur;
-                        else
-                            out[seg] = 0.0;
-                        F = INF - 1;              // head already emitted
+                    if ((int64_t)ptr[sg] >= k0) {  // complete inside the lane
+                        out[sg] = omask ? 0.0 : (yout ? (double)yout[sg] : 1.0) * cur;
+                        F = INF - 1;               // head already emitted
                     }
                 } else {
-                    // middle segment: complete inside the lane
-                    if (!(out_mask && !out_mask[seg]))
-                        out[seg] = (yout ? (double)yout[seg] : 1.0) * cur;
-                    else
-                        out[seg] = 0.0;
+                    out[sg] = omask ? 0.0 : (yout ? (double)yout[sg] : 1.0) * cur;
                 }
-                ++seg;
-                segend = ptr[seg + 1];
+                ++j;
+                segend = j < SEG_E ? ends[j] : ptr[seg0 + 1 + j];
                 cur = 0.0;
             }
-            if (out_mask && !out_mask[seg]) continue;
-            const int32_t ii = idx[k];
-            double cf;
-            if (vin) {
-                cf = vin[ii];
-                if (yin) cf *= (double)yin[ii];
-                if (mask) cf *= (double)mask[ii];
-            } else {
-                cf = (double)mask[ii];
-            }
-            if (cf != 0.0) cur = fma(segval(val, k, SQ), cf, cur);
+            cur += cfv[e];
         }
-        Lt = seg;
-        lsum = cur;
+        Lt = seg0 + j;
+        lsum = (out_mask && !out_mask[Lt]) ? 0.0 : cur;
         if (!have_head) {           // the lane stayed inside one segment: it is the tail
             F = Lt;
         } else if (F == INF - 1) {
@@ -187,5 +215,13 @@ void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStr
 }
 
 int seg_entries_per_lane() { return SEG_E; }
+
+void launch_segsum_fix_only(const SegPlan& P, double* out, hipStream_t s) {
+    if (P.nspan > 0) {
+        const unsigned nf = (unsigned)((P.nspan + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+        hipLaunchKernelGGL(k_segsum_fix, dim3(nf), dim3(SSN_BLOCK), 0, s, P.span_seg, P.span_t0,
+                           P.span_t1, P.nspan, P.tile_first, P.carry, nullptr, nullptr, out);
+    }
+}
 
 }  // namespace ssn

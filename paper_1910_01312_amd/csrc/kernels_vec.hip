@@ -38,16 +38,15 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_dots(int npair, const double* __r
         part[blockIdx.x * 3 + 1] = t1;
         part[blockIdx.x * 3 + 2] = t2;
     }
-    if (last_block_arrives(counter) && threadIdx.x == 0) {
-        double u0 = 0.0, u1 = 0.0, u2 = 0.0;
-        for (unsigned b = 0; b < gridDim.x; ++b) {
-            u0 += ld_acquire(&part[b * 3 + 0]);
-            u1 += ld_acquire(&part[b * 3 + 1]);
-            u2 += ld_acquire(&part[b * 3 + 2]);
+    if (last_block_arrives(counter)) {
+        const double u0 = grid_colsum(part, gridDim.x, 3, 0, shd);
+        const double u1 = npair > 1 ? grid_colsum(part, gridDim.x, 3, 1, shd) : 0.0;
+        const double u2 = npair > 2 ? grid_colsum(part, gridDim.x, 3, 2, shd) : 0.0;
+        if (threadIdx.x == 0) {
+            *r0 = u0;
+            if (npair > 1) *r1 = u1;
+            if (npair > 2) *r2 = u2;
         }
-        *r0 = u0;
-        if (npair > 1) *r1 = u1;
-        if (npair > 2) *r2 = u2;
     }
 }
 

@@ -19,6 +19,9 @@ struct ProjState {
     int    passes;        // multisection passes run
     int    approx;        // 1 if the pass cap ended the search
     int    inside;        // breakpoints strictly inside the last bracket
+    int    mode;          // 1: next pass places its points geometrically around hint
+    int    pad_;
+    double hint;          // multiplier of a nearby projection (warm start)
     long long npos;       // number of y_i = +1
 };
 
@@ -34,6 +37,7 @@ struct Scalars {
     double mean_w;        // PCG: mean of X_J p over J
     double sumx;          // e^T x
     long long p;          // |J|
+    long long nnzj;       // nonzeros of the rows in J (sparse input)
     long long nsv;        // #{x_i > 0}
     int    chol_fail;     // Cholesky met a non-positive pivot
     int    cg_done;
@@ -85,7 +89,7 @@ void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStr
 // v_out = (td ? u - alpha_sigma * td : u); initialise the bracket in st.
 void launch_proj_init(const double* u, const double* td, double alpha_sigma, double* v_out,
                       const int8_t* y, int64_t n, double C, ProjState* st, double* part,
-                      unsigned* counter, hipStream_t s);
+                      unsigned* counter, hipStream_t s, const ProjState* hint = nullptr);
 void launch_proj_pass(const double* v, const int8_t* y, int64_t n, double C, ProjState* st,
                       double* part, unsigned* counter, hipStream_t s);
 int  proj_max_passes();
@@ -146,6 +150,43 @@ void launch_chol_solve_small(const double* M, const double* g, double* d, int64_
 int  chol_blocked_max();
 void launch_chol_solve_blocked(double* M, const double* g, double* d, int64_t q,
                                double* work, Scalars* sc, hipStream_t s);
+
+// Sparse products restricted to J (kernels_jcsr.hip) --------------------------
+void launch_rank_from_list(const int32_t* list, const long long* pdev, int64_t n, int32_t* rank,
+                           hipStream_t s);
+// w[k] = (X_J v)_k for the k-th listed row; *mean_out = mean of w
+void launch_rows_fwd(const SegPlan& F, const int32_t* list, int64_t p, const double* v, double* w,
+                     double* mean_out, double* part, unsigned* counter, hipStream_t s);
+// column-major copy of X_J filtered from the full one (entries: rank, column, value)
+void launch_jcsc_build(const SegPlan& T, const uint8_t* mask, const int32_t* rank, int* tcount,
+                       int* toff, long long* total, int32_t* jr, int32_t* jc, void* jv,
+                       hipStream_t s);
+// out = X_J^T (w - mean) (mode 0), X_J^T 1 (mode 1) or sum_J X_ij^2 (mode 2)
+void launch_jcsc_tr(int mode, const SegPlan& T, const int* toff, const int32_t* jr,
+                    const int32_t* jc, const void* jv, const double* w, const double* mean,
+                    double* out, int64_t q, hipStream_t s);
+// Ap = p + sigma z, pap = p . Ap
+void launch_mop_pap(const double* pd, const double* z, double sigma, double* Ap, int64_t q,
+                    Scalars* sc, double* part, unsigned* counter, hipStream_t s);
+
+// Fence-free CG on the compact X_J (kernels_cg.hip) ----------------------------
+unsigned cg_qgrid(int64_t q);
+unsigned cg_rows_grid(int64_t p);
+void launch_cg_init(const double* g, const double* diag, const double* sv, int64_t q, double* x,
+                    double* r, double* z, double* pd, double* Pst, double* Pdir, hipStream_t s);
+void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, hipStream_t s);
+void launch_cg_rows(const SegPlan& F, const int32_t* list, int64_t p, const double* v, double* w,
+                    double* Pw, hipStream_t s);
+void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
+                     int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
+                     hipStream_t s, bool zero_out = true);
+void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
+                    const double* diag, double* z, int64_t q, double sigma, int64_t p,
+                    const double* Pw, int nbw, const double* Pdir, const double* Pold, double* Pnew,
+                    double tol2, hipStream_t s);
+void launch_cg_dir(double* pd, const double* z, const double* sv, int64_t q, const double* Pold,
+                   const double* Pnew, double* Pdir, double tol2, Scalars* sc, double* tz,
+                   hipStream_t s);
 
 // PCG pieces -------------------------------------------------------------------
 void launch_jacobi_diag(const double* sq, const double* sv, double sigma, int64_t p,
