@@ -206,6 +206,14 @@ ssnalm_status ssnalm_op_newton(ssnalm_ctx* ctx, const uint8_t* free_mask,
                                const double* g, double sigma, double cg_tol,
                                double* d, int32_t* cg_iters);
 
+/* Gram matrix of the free rows, G = X_J^T X_J (q x q, row-major, full),
+ * the product inside A^T P A of Proposition 5 (labels cancel).  Uses the
+ * context's SYRK: bf16 operands on the matrix cores with fp32 accumulation
+ * when the context is mixed precision with bf16 X, fp64 otherwise.
+ * free_mask: n bytes (device, 1 = in J); G: q*q doubles (device).  Dense
+ * contexts only. */
+ssnalm_status ssnalm_op_gram(ssnalm_ctx* ctx, const uint8_t* free_mask, double* G);
+
 /* One trial of the Armijo line search of Algorithm 3, step 2, on the n-side
  * terms of psi (eq. Def_psi): with u_a = u - alpha sigma t it projects u_a
  * and returns

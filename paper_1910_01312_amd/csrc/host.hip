@@ -85,6 +85,9 @@ struct ssnalm_ctx {
     void* jv = nullptr;
     int *tcount = nullptr, *toff = nullptr;
     double *wJ = nullptr, *kcarry = nullptr, *cgpart = nullptr;
+    double* zJ = nullptr;            // n-vector, nonzero on J only (mixed refinement)
+    bool mixed = false;              // bf16 SYRK + refinement
+    int refine_total = 0;
     // q-vectors
     double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
     double *qv = nullptr, *qv2 = nullptr;
@@ -276,7 +279,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         long long* pcount = &dsc(c)->p;
         launch_compact(mask, c->n, c->jlist, pcount, c->blk, cnt(c, CNT_CMP), c->st);
         prof_begin(c);
-        if (c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, c->q))
+        if (c->mixed)
             launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, c->G, c->mpart, c->mpart_cap, c->st);
         else
             launch_syrk_gather(c->dtype, c->X, c->q, c->jlist, p, c->G, c->part, c->part_cap, c->st);
@@ -284,11 +287,34 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                  (double)p * c->q * (c->q + 1));
         launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
         prof_begin(c);
-        if (c->q <= chol_small_max())
+        if (!c->mixed && c->q <= chol_small_max()) {
             launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
-        else
-            launch_chol_solve_blocked(c->M, g, d, c->q, c->part, dsc(c), c->st);
+        } else {
+            launch_chol_factor_blocked(c->M, c->q, dsc(c), c->st);
+            launch_chol_solve_factored(c->M, g, d, c->q, c->part, c->st);
+        }
         prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q, (double)c->q * c->q * c->q / 3.0 + 2.0 * c->q * c->q);
+        if (c->mixed) {
+            // iterative refinement with the exact operator
+            //   M v = v + sigma X_J^T (X_J v - mean(X_J v) 1)
+            // in fp64, preconditioned by the factor of the bf16 Gram matrix
+            const double tol2 = cg_tol * cg_tol;
+            const int nbw = (int)dense_rows_grid(p);
+            launch_fill(c->zJ, 0.0, c->n, c->st);
+            for (int it = 0; it < 10; ++it) {
+                launch_dense_rows(c->dtype, c->X, c->q, c->jlist, p, d, c->wJ, c->cgpart, c->st);
+                launch_scatter_centered(c->jlist, p, c->wJ, c->cgpart, nbw, c->y, c->zJ, c->st);
+                op_atmul(c, c->zJ, nullptr, nullptr, 1.0, c->qv, nullptr, SSNALM_K_ATMUL_J);
+                launch_refine_res(g, d, c->qv, sigma, c->qv2, c->q, c->st);
+                launch_dots(1, c->qv2, c->qv2, &dsc(c)->cg_rr, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, nullptr, c->q, c->spart, cnt(c, CNT_DOTS), c->st);
+                STCHK(sync_state(c));
+                ++*cg_iters;
+                if (!(c->hs->sc.cg_rr > tol2)) break;
+                launch_chol_solve_factored(c->M, c->qv2, c->qv, c->q, c->part, c->st);
+                launch_axpy(d, c->qv, 1.0, c->q, c->st);
+            }
+        }
         return SSNALM_OK;
     }
     if (c->kind == SSNALM_CSR) {
@@ -636,6 +662,10 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
     if (c->use_chol) {
         ALLOC(c->G, q * q);
         ALLOC(c->M, q * q);
+        c->mixed = c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, q);
+        if (c->mixed) {
+            ALLOC(c->zJ, n); ALLOC(c->wJ, n); ALLOC(c->cgpart, 1024 + 512 + 1024);
+        }
     }
     // reduction scratch for the dense transpose (nblk x q, twice) and SYRK partials
     int64_t pc = (int64_t)atmul_dense_nblk(n) * q;
@@ -644,7 +674,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
     c->part_cap = pc;
     ALLOC(c->part, pc);
     ALLOC(c->part2, (int64_t)atmul_dense_nblk(n) * q);
-    if (c->use_chol && c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, q)) {
+    if (c->mixed) {
         c->mpart_cap = syrk_mfma_part_size(q, n);
         ALLOC(c->mpart, c->mpart_cap);
     }
@@ -903,6 +933,24 @@ extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mas
     STCHK(sync_state(c));
     if (c->use_chol && c->hs->sc.chol_fail) return fail(SSNALM_E_NONFINITE, "Cholesky met a non-positive pivot");
     if (cg_iters) *cg_iters = cgi;
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_op_gram(ssnalm_ctx* c, const uint8_t* free_mask, double* G) {
+    if (!c || !free_mask || !G) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->kind != SSNALM_DENSE || !c->use_chol) return fail(SSNALM_E_BADARG, "Gram matrix needs a dense Cholesky context");
+    launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
+    STCHK(sync_state(c));
+    const int64_t p = c->hs->sc.p;
+    if (p == 0) {
+        launch_fill(G, 0.0, c->q * c->q, c->st);
+    } else if (c->mixed) {
+        launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, G, c->mpart, c->mpart_cap, c->st);
+    } else {
+        launch_syrk_gather(c->dtype, c->X, c->q, c->jlist, p, G, c->part, c->part_cap, c->st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
     return SSNALM_OK;
 }
 

@@ -1,10 +1,206 @@
-// Blocked fp64 Cholesky for q larger than the LDS-resident kernel handles
-// (placeholder: no blocked path yet, so q above the LDS limit uses PCG).
+// Blocked fp64 Cholesky of the reduced Newton matrix
+//     M = I + sigma (X_J^T X_J - s s^T / p)   (q x q, symmetric positive definite)
+// for q above the LDS-resident kernel's limit, and the two triangular solves
+// giving d = -M^{-1} g.  Right-looking with 64 x 64 blocks: for each block
+// column kb, factor the diagonal block in LDS, solve the panel below it, and
+// update the trailing lower tiles.  The factor is kept in the lower triangle
+// of M and mirrored into the upper triangle (row j of the upper part holds
+// column j of L), so both solves read contiguous rows.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
 namespace ssn {
-int chol_blocked_max() { return 0; }
-void launch_chol_solve_blocked(double*, const double*, double*, int64_t, double*, Scalars*,
-                               hipStream_t) {}
+
+constexpr int NB = 64;
+constexpr int CHOL_BLOCKED_MAX = 2048;
+
+int chol_blocked_max() { return CHOL_BLOCKED_MAX; }
+
+// Factor the diagonal block kb in LDS.  A non-positive pivot is replaced by 1
+// and reported through sc->chol_fail.
+__global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M, int q, int kb,
+                                                         Scalars* sc) {
+    __shared__ double A[NB][NB + 1];
+    if (kb == 0 && threadIdx.x == 0) sc->chol_fail = 0;
+    const int o = kb * NB;
+    const int m = min(NB, q - o);
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        A[i][j] = (i < m && j < m) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        double akk = A[k][k];
+        if (!(akk > 0.0)) {
+            if (threadIdx.x == 0) sc->chol_fail = 1;
+            akk = 1.0;
+        }
+        const double lkk = sqrt(akk);
+        __syncthreads();
+        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) A[i][k] /= lkk;
+        if (threadIdx.x == 0) A[k][k] = lkk;
+        __syncthreads();
+        const int r = m - k - 1;
+        for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+            const int a = e / r, b = e % r;
+            if (b <= a) A[k + 1 + a][k + 1 + b] -= A[k + 1 + a][k] * A[k + 1 + b][k];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int i = e / m, j = e % m;
+        if (j <= i) {
+            const double v = A[i][j];
+            M[(int64_t)(o + i) * q + o + j] = v;
+            M[(int64_t)(o + j) * q + o + i] = v;
+        }
+    }
+}
+
+// Panel solve: rows below the diagonal block, L_ib,kb = A_ib,kb L_kb,kb^{-T}.
+// One block per row block, one thread per row.
+__global__ __launch_bounds__(NB) void k_chol_trsm(double* __restrict__ M, int q, int kb) {
+    __shared__ double L[NB][NB + 1];
+    const int o = kb * NB;
+    const int m = min(NB, q - o);
+    const int ib = kb + 1 + blockIdx.x;
+    const int ro = ib * NB;
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        L[i][j] = (i < m && j < m && j <= i) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
+    }
+    __syncthreads();
+    const int r = ro + threadIdx.x;
+    if (r >= q) return;
+    double x[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) x[j] = j < m ? M[(int64_t)r * q + o + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < m) {
+            double a = x[j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) a -= x[k] * L[j][k];
+            x[j] = a / L[j][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < m) {
+            M[(int64_t)r * q + o + j] = x[j];
+            M[(int64_t)(o + j) * q + r] = x[j];
+        }
+    }
+}
+
+// Trailing update of the lower tiles (ib >= jb > kb):
+// A_ib,jb -= L_ib,kb L_jb,kb^T.  One 64 x 64 tile per block, 4 x 4 per thread.
+__global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ M, int q, int kb) {
+    __shared__ double Li[NB][NB + 1];
+    __shared__ double Lj[NB][NB + 1];
+    const int nt = (q + NB - 1) / NB - kb - 1;      // trailing block count
+    // blockIdx.x -> (a, b), a >= b, over the nt x nt lower triangle
+    int t = blockIdx.x, a = 0;
+    while (t > a) { t -= a + 1; ++a; }
+    const int b = t;
+    const int ib = kb + 1 + a, jb = kb + 1 + b;
+    (void)nt;
+    const int o = kb * NB, io = ib * NB, jo = jb * NB;
+    const int m = min(NB, q - o);
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, k = e % NB;
+        Li[i][k] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
+        Lj[i][k] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int k = 0; k < m; ++k) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = Li[ty * 4 + u][k];
+            y[u] = Lj[tx * 4 + u][k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = io + ty * 4 + u, j = jo + tx * 4 + v;
+            if (i < q && j < q && j <= i) M[(int64_t)i * q + j] -= acc[u][v];
+        }
+}
+
+// d = -M^{-1} g with the factor in M: forward L w = -g using row j of the
+// upper triangle (= column j of L), backward L^T d = w using row j of L.
+__global__ __launch_bounds__(1024) void k_chol_solve2(const double* __restrict__ M,
+                                                      const double* __restrict__ g,
+                                                      double* __restrict__ d, int q) {
+    extern __shared__ double z[];                  // q doubles
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < q; i += nt) z[i] = -g[i];
+    __syncthreads();
+    __shared__ double zj_s;
+    for (int j = 0; j < q; ++j) {
+        if (tid == 0) {
+            const double v = z[j] / M[(int64_t)j * q + j];
+            z[j] = v;
+            zj_s = v;
+        }
+        __syncthreads();
+        const double zj = zj_s;
+        const double* row = M + (int64_t)j * q;      // upper part: L[i][j] for i > j
+        for (int i = j + 1 + tid; i < q; i += nt) z[i] -= row[i] * zj;
+        __syncthreads();
+    }
+    for (int j = q - 1; j >= 0; --j) {
+        if (tid == 0) {
+            const double v = z[j] / M[(int64_t)j * q + j];
+            z[j] = v;
+            zj_s = v;
+        }
+        __syncthreads();
+        const double zj = zj_s;
+        const double* row = M + (int64_t)j * q;      // lower part: L[j][i] for i < j
+        for (int i = tid; i < j; i += nt) z[i] -= row[i] * zj;
+        __syncthreads();
+    }
+    for (int i = tid; i < q; i += nt) d[i] = z[i];
+}
+
+void launch_chol_factor_blocked(double* M, int64_t q, Scalars* sc, hipStream_t s) {
+    const int nblk = (int)((q + NB - 1) / NB);
+    for (int kb = 0; kb < nblk; ++kb) {
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, sc);
+        const int nt = nblk - kb - 1;
+        if (nt > 0) {
+            hipLaunchKernelGGL(k_chol_trsm, dim3(nt), dim3(NB), 0, s, M, (int)q, kb);
+            hipLaunchKernelGGL(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(SSN_BLOCK), 0, s, M,
+                               (int)q, kb);
+        }
+    }
+}
+
+void launch_chol_solve_factored(const double* M, const double* g, double* d, int64_t q,
+                                double* work, hipStream_t s) {
+    (void)work;
+    hipLaunchKernelGGL(k_chol_solve2, dim3(1), dim3(1024), (size_t)q * sizeof(double), s, M, g, d,
+                       (int)q);
+}
+
+void launch_chol_solve_blocked(double* M, const double* g, double* d, int64_t q, double* work,
+                               Scalars* sc, hipStream_t s) {
+    launch_chol_factor_blocked(M, q, sc, s);
+    launch_chol_solve_factored(M, g, d, q, work, s);
+}
+
 }  // namespace ssn

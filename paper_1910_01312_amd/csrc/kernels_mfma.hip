@@ -1,12 +1,274 @@
-// bf16 MFMA gather-SYRK for the mixed-precision Newton system (placeholder
-// until the MFMA tile kernel is enabled: reports "unsupported" so the fp64
-// gather-SYRK is used).
+// Mixed-precision pieces of the dense Newton step.
+//
+// Gather-SYRK  G = X_J^T X_J  on the matrix cores: bf16 operands, fp32
+// accumulation (v_mfma_f32_32x32x16_bf16), 128 x 128 output tiles of the
+// lower triangle, split over the row list J.  A block stages 32 gathered
+// rows x 128 columns of each column block in LDS, stored transposed (column
+// major, 8 consecutive rows contiguous) so that each lane's MFMA operand is
+// one 16-byte LDS read.  Four waves each own a 64 x 64 sub-tile (2 x 2 MFMA
+// tiles).  The per-split fp32 partial tiles are summed in split order in fp64.
+//
+// Dense X_J v over a row list (one wave per row, fp64 accumulation), used by
+// the exact Newton operator of the iterative refinement.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
 namespace ssn {
-bool syrk_mfma_supported(int, int64_t) { return false; }
-int64_t syrk_mfma_part_size(int64_t, int64_t) { return 1; }
-void launch_syrk_mfma(const void*, int, int64_t, const int32_t*, int64_t, double*, float*, int64_t,
-                      hipStream_t) {}
+
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+constexpr int MT = 128;          // output tile
+constexpr int KC = 32;           // rows staged per step
+constexpr int KP = KC + 8;       // padded row count in the transposed LDS tile
+
+bool syrk_mfma_supported(int dtype, int64_t q) { return dtype == SSNALM_BF16 && q >= 1; }
+
+static inline int mfma_ntile(int64_t q) {
+    const int nt = (int)((q + MT - 1) / MT);
+    return nt * (nt + 1) / 2;
+}
+static inline int64_t mfma_nsplit(int64_t q, int64_t p) {
+    const int ntile = mfma_ntile(q);
+    int64_t ns = (512 + ntile - 1) / ntile;
+    const int64_t maxs = (p + 2 * KC - 1) / (2 * KC);
+    if (ns > maxs) ns = maxs;
+    if (ns > 32) ns = 32;
+    if (ns < 1) ns = 1;
+    return ns;
+}
+int64_t syrk_mfma_part_size(int64_t q, int64_t p) {
+    return mfma_nsplit(q, p) * (int64_t)mfma_ntile(q) * MT * MT;
+}
+
+// stage rows [rb, rb+KC) of the list, columns [c0, c0+MT) into s (transposed)
+__device__ __forceinline__ void stage_tile(const bf16_t* __restrict__ X, int64_t q,
+                                           const int32_t* __restrict__ list, int64_t rb,
+                                           int64_t r1, int64_t c0, bf16_t (*s)[KP]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = (t >> 4) + 16 * h;            // 0..31
+        const int cg = t & 15;                      // 16 groups of 8 columns
+        const int64_t row = rb + r;
+        const int64_t col = c0 + cg * 8;
+        bf16_t v[8];
+        if (row < r1) {
+            const bf16_t* src = X + (int64_t)list[row] * q + col;
+            if (col + 8 <= q && ((q & 7) == 0)) {
+                const uint4 u = *reinterpret_cast<const uint4*>(src);
+                v[0] = (bf16_t)(u.x & 0xffff); v[1] = (bf16_t)(u.x >> 16);
+                v[2] = (bf16_t)(u.y & 0xffff); v[3] = (bf16_t)(u.y >> 16);
+                v[4] = (bf16_t)(u.z & 0xffff); v[5] = (bf16_t)(u.z >> 16);
+                v[6] = (bf16_t)(u.w & 0xffff); v[7] = (bf16_t)(u.w >> 16);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (col + e < q) ? src[e] : (bf16_t)0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = 0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[cg * 8 + e][r] = v[e];
+    }
+}
+
+__global__ __launch_bounds__(SSN_BLOCK) void k_syrk_mfma(const bf16_t* __restrict__ X, int64_t q,
+                                                         const int32_t* __restrict__ list,
+                                                         int64_t p, int64_t rows_per_split,
+                                                         float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) bf16_t sA[MT][KP];
+    __shared__ __attribute__((aligned(16))) bf16_t sB[MT][KP];
+    // lower-triangle tile (ti >= tj) from blockIdx.x
+    int t = blockIdx.x, ti = 0;
+    while (t > ti) { t -= ti + 1; ++ti; }
+    const int tj = t;
+    const bool diag = ti == tj;
+    const int64_t i0 = (int64_t)ti * MT, j0 = (int64_t)tj * MT;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+    const int64_t r1 = r0 + rows_per_split < p ? r0 + rows_per_split : p;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m = lane & 31, kg = lane >> 5;
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
+    bf16_t (*sBp)[KP] = diag ? sA : sB;
+    for (int64_t rb = r0; rb < r1; rb += KC) {
+        stage_tile(X, q, list, rb, r1, i0, sA);
+        if (!diag) stage_tile(X, q, list, rb, r1, j0, sB);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8_t fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                fa[a] = *reinterpret_cast<const bf16x8_t*>(&sA[wm * 64 + a * 32 + m][ks * 16 + kg * 8]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                fb[b] = *reinterpret_cast<const bf16x8_t*>(&sBp[wn * 64 + b * 32 + m][ks * 16 + kg * 8]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float* out = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * MT * MT;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = wm * 64 + a * 32 + 8 * (e >> 2) + 4 * kg + (e & 3);
+                const int col = wn * 64 + b * 32 + m;
+                out[row * MT + col] = acc[a][b][e];
+            }
+}
+
+// G[i][j] (lower tiles, mirrored) = sum over splits, in split order, in fp64
+__global__ void k_syrk_mfma_reduce(const float* __restrict__ part, int ntile, int nsplit,
+                                   double* __restrict__ G, int64_t q) {
+    int t = blockIdx.x, ti = 0;
+    while (t > ti) { t -= ti + 1; ++ti; }
+    const int tj = t;
+    for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
+        const int a = e / MT, b = e % MT;
+        const int64_t i = (int64_t)ti * MT + a, j = (int64_t)tj * MT + b;
+        if (i >= q || j >= q || j > i) continue;
+        double s = 0.0;
+        for (int k = 0; k < nsplit; ++k) s += (double)part[((int64_t)k * ntile + blockIdx.x) * MT * MT + e];
+        G[i * q + j] = s;
+        G[j * q + i] = s;
+    }
+}
+
+void launch_syrk_mfma(const void* X, int dtype, int64_t q, const int32_t* list, int64_t p,
+                      double* G, float* part, int64_t part_cap, hipStream_t s) {
+    (void)dtype;
+    const int ntile = mfma_ntile(q);
+    int64_t ns = mfma_nsplit(q, p);
+    while (ns > 1 && ns * ntile * MT * MT > part_cap) --ns;
+    int64_t rps = (p + ns - 1) / ns;
+    rps = (rps + KC - 1) / KC * KC;
+    hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
+                       (const bf16_t*)X, q, list, p, rps, part);
+    hipLaunchKernelGGL(k_syrk_mfma_reduce, dim3((unsigned)ntile), dim3(SSN_BLOCK), 0, s, part, ntile,
+                       (int)ns, G, q);
+}
+
+// ------------------------------------------------------------------ X_J v (dense)
+// w[k] = X[list[k]] . v (fp64 accumulation); Pw[b] = block sum of w (for the mean)
+template <typename T, int VEC>
+__global__ __launch_bounds__(SSN_BLOCK) void k_dense_rows(const T* __restrict__ X, int64_t q,
+                                                          const int32_t* __restrict__ list,
+                                                          int64_t p, const double* __restrict__ v,
+                                                          double* __restrict__ w,
+                                                          double* __restrict__ Pw) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    double loc = 0.0;
+    for (int64_t k = wave; k < p; k += nwave) {
+        const T* xr = X + (int64_t)list[k] * q;
+        double acc = 0.0;
+        for (int64_t c0 = (int64_t)lane * VEC; c0 < q; c0 += (int64_t)SSN_WAVE * VEC) {
+            double xv[VEC];
+            if (c0 + VEC <= q) {
+                VecLoad<T, VEC>::load(xr + c0, xv);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) xv[e] = (c0 + e < q) ? to_f64(xr[c0 + e]) : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (c0 + e < q) acc = fma(xv[e], v[c0 + e], acc);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            w[k] = acc;
+            loc += acc;
+        }
+    }
+    const double bs = block_sum(loc, sh);
+    if (threadIdx.x == 0) Pw[blockIdx.x] = bs;
+}
+
+unsigned dense_rows_grid(int64_t p) {
+    int64_t b = (p + 3) / 4;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+void launch_dense_rows(int dtype, const void* X, int64_t q, const int32_t* list, int64_t p,
+                       const double* v, double* w, double* Pw, hipStream_t s) {
+    const unsigned g = dense_rows_grid(p);
+    const uintptr_t a = (uintptr_t)X;
+    if (dtype == SSNALM_F64) {
+        if ((q * 8) % 16 == 0 && a % 16 == 0)
+            hipLaunchKernelGGL((k_dense_rows<double, 2>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
+        else
+            hipLaunchKernelGGL((k_dense_rows<double, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
+    } else if (dtype == SSNALM_F32) {
+        if ((q * 4) % 16 == 0 && a % 16 == 0)
+            hipLaunchKernelGGL((k_dense_rows<float, 4>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
+        else
+            hipLaunchKernelGGL((k_dense_rows<float, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
+    } else {
+        if ((q * 2) % 16 == 0 && a % 16 == 0)
+            hipLaunchKernelGGL((k_dense_rows<bf16_t, 8>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
+        else
+            hipLaunchKernelGGL((k_dense_rows<bf16_t, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
+    }
+}
+
+// z[list[k]] = y_i (w_k - mean), mean = sum(Pw) / p (every block reduces the
+// partials itself, fixed order); the transposed product of A then gives
+// X_J^T (w - mean 1).
+__global__ __launch_bounds__(SSN_BLOCK) void k_scatter_centered(const int32_t* __restrict__ list,
+                                                                int64_t p, const double* __restrict__ w,
+                                                                const double* __restrict__ Pw, int nbw,
+                                                                const int8_t* __restrict__ y,
+                                                                double* __restrict__ z) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nbw; b += blockDim.x) a += Pw[b];
+    const double mean = p > 0 ? block_sum(a, sh) / (double)p : 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < p;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = list[k];
+        z[i] = (double)y[i] * (w[k] - mean);
+    }
+}
+void launch_scatter_centered(const int32_t* list, int64_t p, const double* w, const double* Pw,
+                             int nbw, const int8_t* y, double* z, hipStream_t s) {
+    int64_t b = (p + 255) / 256;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL(k_scatter_centered, dim3((unsigned)b), dim3(SSN_BLOCK), 0, s, list, p, w, Pw,
+                       nbw, y, z);
+}
+
+// rn = g + d + sigma t  (= -(residual of M d = -g)), out for the next solve
+__global__ void k_refine_res(const double* __restrict__ g, const double* __restrict__ d,
+                             const double* __restrict__ t, double sigma, double* __restrict__ rn,
+                             int64_t q) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < q) rn[j] = g[j] + d[j] + sigma * t[j];
+}
+void launch_refine_res(const double* g, const double* d, const double* t, double sigma, double* rn,
+                       int64_t q, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_res, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, g, d, t,
+                       sigma, rn, q);
+}
+
 }  // namespace ssn

@@ -139,6 +139,17 @@ bool syrk_mfma_supported(int dtype, int64_t q);
 int64_t syrk_mfma_part_size(int64_t q, int64_t p);
 void launch_syrk_mfma(const void* X, int dtype, int64_t q, const int32_t* list, int64_t p,
                       double* G, float* part, int64_t part_cap, hipStream_t s);
+// mixed-precision refinement pieces (kernels_mfma.hip)
+unsigned dense_rows_grid(int64_t p);
+void launch_dense_rows(int dtype, const void* X, int64_t q, const int32_t* list, int64_t p,
+                       const double* v, double* w, double* Pw, hipStream_t s);
+void launch_scatter_centered(const int32_t* list, int64_t p, const double* w, const double* Pw,
+                             int nbw, const int8_t* y, double* z, hipStream_t s);
+void launch_refine_res(const double* g, const double* d, const double* t, double sigma, double* rn,
+                       int64_t q, hipStream_t s);
+void launch_chol_factor_blocked(double* M, int64_t q, Scalars* sc, hipStream_t s);
+void launch_chol_solve_factored(const double* M, const double* g, double* d, int64_t q,
+                                double* work, hipStream_t s);
 // M = I + sigma (G - s s^T / p)
 void launch_form_M(const double* G, const double* sv, double sigma, int64_t p, double* M,
                    int64_t q, hipStream_t s);

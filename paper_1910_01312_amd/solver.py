@@ -162,6 +162,12 @@ class Solver:
                 "ssnalm_op_newton")
         return d, it.value
 
+    def gram(self, free_mask):
+        fm = _to_dev(free_mask, torch.uint8)
+        G = torch.empty(self.q * self.q, dtype=torch.float64, device=fm.device)
+        L.check(self._lib.ssnalm_op_gram(self._ctx, _ptr(fm), _ptr(G)), "ssnalm_op_gram")
+        return G.view(self.q, self.q)
+
     def linesearch_trial(self, u, t, lam, alpha, sigma):
         u = _to_dev(u, torch.float64)
         t = _to_dev(t, torch.float64)

@@ -285,3 +285,58 @@ def test_rkkt_parity():
         R, b = s.rkkt(r.x)
     assert abs(R - R_ref) <= 1e-10 * R_ref + 1e-14
     assert abs(b - b_ref) <= 1e-9
+
+
+# ------------------------------------------------------------------ mixed precision
+
+@pytest.mark.parametrize("q,p_frac", [(128, 0.3), (256, 0.05), (512, 0.2), (200, 0.5)])
+def test_gram_mfma_bf16(q, p_frac):
+    """bf16 MFMA SYRK with fp32 accumulation: exact on small-integer bf16
+    data (every partial sum is an integer below 2^24), and within the fp32
+    accumulation bound on Gaussian data."""
+    n = 3000
+    rng = np.random.default_rng(q)
+    free = rng.random(n) < p_frac
+    y = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    Xi = rng.integers(-4, 5, size=(n, q)).astype(np.float32)
+    bits = synth.to_bf16_bits(Xi)
+    Xr = synth.bf16_bits_to_f32(bits).astype(np.float64)
+    with _solver(bits, y, 1.0, bf16=True, newton="chol", precision="mixed") as s:
+        G = _np(s.gram(free.astype(np.uint8)))
+    np.testing.assert_array_equal(G, Xr[free].T @ Xr[free])
+    Xg = rng.standard_normal((n, q)).astype(np.float32)
+    bits = synth.to_bf16_bits(Xg)
+    Xr = synth.bf16_bits_to_f32(bits).astype(np.float64)
+    with _solver(bits, y, 1.0, bf16=True, newton="chol", precision="mixed") as s:
+        G = _np(s.gram(free.astype(np.uint8)))
+    XJ = Xr[free]
+    ref = XJ.T @ XJ
+    bound = 4 * 2.0 ** -24 * free.sum() * (np.abs(XJ).T @ np.abs(XJ))
+    assert np.all(np.abs(G - ref) <= bound + 1e-30)
+
+
+@pytest.mark.parametrize("q", [160, 512])
+def test_newton_blocked_cholesky_fp64(q):
+    X, y = synth.dense_two_gaussians(n=4000, q=q, seed=6)
+    sigma = 3.0
+    u, lam, free, g, _, _ = _newton_state(X, y, 1.0, sigma, 4)
+    d_ref = ssnal.newton_qspace(X, free, g, sigma)
+    with _solver(X, y, 1.0, newton="chol") as s:
+        d, _ = s.newton(free.astype(np.uint8), g, sigma)
+    d = _np(d)
+    assert np.linalg.norm(d - d_ref) <= 1e-9 * (1 + np.linalg.norm(d_ref))
+
+
+def test_newton_mixed_refined():
+    """bf16 Gram + fp64 Cholesky + refinement reaches the fp64 direction."""
+    bits, y = synth.dense_bf16_directions(n=6000, q=256, seed=31)
+    Xr = synth.bf16_bits_to_f32(bits).astype(np.float64)
+    sigma = 40.0
+    u, lam, free, g, _, _ = _newton_state(Xr, y, 1.0, sigma, 5)
+    d_ref = ssnal.newton_qspace(Xr, free, g, sigma)
+    tol = 1e-10 * np.linalg.norm(g)
+    with _solver(bits, y, 1.0, bf16=True, newton="chol", precision="mixed") as s:
+        d, its = s.newton(free.astype(np.uint8), g, sigma, cg_tol=tol)
+    d = _np(d)
+    assert its <= 6
+    assert np.linalg.norm(d - d_ref) <= 1e-8 * (1 + np.linalg.norm(d_ref))

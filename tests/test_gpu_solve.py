@@ -4,7 +4,7 @@ x* is generally not unique (rank Q <= q < n), so the comparison uses what is
 unique: the optimal value f*, the primal weights w* = A^T x*, R_KKT
 recomputed by the oracle on the GPU's x, feasibility, and b when p > 0.
 Bars: R_KKT <= 1e-6 and |f - f*| / max(1, |f*|) <= 1e-8 against an oracle
-reference solved to R_KKT <= 1e-10; when the 1e-6 stop leaves the objective
+reference solved to R_KKT <= 1e-8; when the 1e-6 stop leaves the objective
 outside 1e-8 the GPU is re-run at tol 1e-8 for the objective check.
 """
 import numpy as np
@@ -34,6 +34,15 @@ def _solve(*a, **k):
         return x.cpu().numpy(), w.cpu().numpy(), info
 
 
+def _ref(X, y, C, **kw):
+    """Oracle reference: R_KKT <= 1e-8, at most 25 ALM iterations (the best x
+    is kept).  In fp64 the method's attainable R_KKT floor at large sigma is
+    a few 1e-9 on some of these problems (1e-10 is not reachable there); at
+    1e-8 the objective already agrees with the best attainable one to ~1e-11
+    relative, three orders inside the 1e-8 objective bar."""
+    return ssnal.solve(X, y, C, tol=1e-8, max_outer=25, **kw)
+
+
 def _check_solution(X, y, C, x, w, info, ref, tol=1e-6, rerun=None):
     yf = y.astype(np.float64)
     assert info["status_name"] == "OK", info
@@ -55,7 +64,7 @@ def _check_solution(X, y, C, x, w, info, ref, tol=1e-6, rerun=None):
 
 def test_c1_dense_fp64():
     X, y = synth.dense_two_gaussians()
-    ref = ssnal.solve(X, y, 1.0, tol=1e-10)
+    ref = _ref(X, y, 1.0)
     x, w, info = _solve(X, y, 1.0, tol=1e-6)
     _check_solution(X, y, 1.0, x, w, info, ref,
                     rerun=lambda: _solve(X, y, 1.0, tol=1e-8))
@@ -68,7 +77,7 @@ def test_c1_dense_fp64():
 @pytest.mark.parametrize("C", [0.01, 1.0, 100.0])
 def test_dense_small_various_C(C):
     X, y = synth.dense_two_gaussians(n=600, q=12, shift=0.3, seed=77)
-    ref = ssnal.solve(X, y, C, tol=1e-10)
+    ref = _ref(X, y, C)
     x, w, info = _solve(X, y, C, tol=1e-6)
     _check_solution(X, y, C, x, w, info, ref, rerun=lambda: _solve(X, y, C, tol=1e-8))
 
@@ -108,7 +117,7 @@ def test_dense_low_precision_storage(dtype):
         kw = {"bf16": True}
     else:
         Xs, Xr, kw = X, X.astype(np.float64), {}
-    ref = ssnal.solve(Xr, y, 0.1, tol=1e-10)
+    ref = _ref(Xr, y, 0.1)
     x, w, info = _solve(Xs, y, 0.1, tol=1e-6, **kw)
     _check_solution(Xr, y, 0.1, x, w, info, ref,
                     rerun=lambda: _solve(Xs, y, 0.1, tol=1e-8, **kw))
@@ -118,7 +127,7 @@ def test_csr_pcg_solve():
     vals, ci, rp, y = synth.sparse_text(n=20000, q=4000, seed=21)
     n, q = rp.size - 1, 4000
     Xr = sp.csr_matrix((vals.astype(np.float64), ci, rp), shape=(n, q))
-    ref = ssnal.solve(Xr, y, 1.0, tol=1e-10, newton="pcg", max_cg=2000)
+    ref = _ref(Xr, y, 1.0, newton="pcg", max_cg=2000)
     x, w, info = _solve(csr=(vals, ci, rp, n, q), y=y, C_=1.0, tol=1e-6)
     _check_solution(Xr, y, 1.0, x, w, info, ref,
                     rerun=lambda: _solve(csr=(vals, ci, rp, n, q), y=y, C_=1.0, tol=1e-8))
@@ -126,7 +135,7 @@ def test_csr_pcg_solve():
 
 def test_warm_start_from_solution():
     X, y = synth.dense_two_gaussians(n=1000, q=20, seed=4)
-    ref = ssnal.solve(X, y, 1.0, tol=1e-10)
+    ref = _ref(X, y, 1.0)
     x, w, info = _solve(X, y, 1.0, tol=1e-6, x0=ref.x)
     assert info["status_name"] == "OK"
     assert info["iters_outer"] <= 2
@@ -151,3 +160,19 @@ def test_deterministic_solve():
     x2, w2, i2 = _solve(X, y, 1.0)
     np.testing.assert_array_equal(x1, x2)
     assert i1["iters_inner"] == i2["iters_inner"]
+
+
+@pytest.mark.parametrize("C", [0.1, 1.0])
+def test_mixed_precision_bf16_solve(C):
+    """Mixed precision (bf16 X, bf16 MFMA Gram, fp64 Cholesky + refinement,
+    fp64 iterates): same bars as the fp64 path against the fp64 oracle on the
+    same bf16 data."""
+    bits, y = synth.dense_bf16_directions(n=8000, q=256, seed=41)
+    Xr = synth.bf16_bits_to_f32(bits).astype(np.float64)
+    ref = _ref(Xr, y, C)
+    x, w, info = _solve(bits, y, C, tol=1e-6, bf16=True, precision="mixed")
+    _check_solution(Xr, y, C, x, w, info, ref,
+                    rerun=lambda: _solve(bits, y, C, tol=1e-8, bf16=True, precision="mixed"))
+    x2, w2, info2 = _solve(bits, y, C, tol=1e-6, bf16=True)       # fp64 Gram
+    _check_solution(Xr, y, C, x2, w2, info2, ref,
+                    rerun=lambda: _solve(bits, y, C, tol=1e-8, bf16=True))
