@@ -34,9 +34,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_workload(name):
+def make_workload(name, C=None):
     import numpy as np
     import synth
+    if name == "dense-bf16":
+        bits, y = synth.dense_bf16_directions()
+        Cv = 1.0 if C is None else C
+        cfg = {"workload": f"dense bf16 n=1000000 q=512, 4 informative directions, 5% flips, C={Cv}",
+               "n": 1_000_000, "q": 512, "C": Cv, "tol": 1e-6}
+        return {"X": bits, "bf16": True, "y": y, "C": Cv, "cfg": cfg}
     if name == "sparse-text":
         vals, ci, rp, y = synth.sparse_text()
         n, q = rp.size - 1, 100_000
@@ -62,6 +68,10 @@ def oracle_sample(wl, budget_s, gpu_newton_steps):
         vals, ci, rp, n, q = wl["csr"]
         X = sp.csr_matrix((vals.astype(np.float64), ci, rp), shape=(n, q))
         mode = "pcg"
+    elif wl.get("bf16"):
+        import synth
+        X = synth.bf16_bits_to_f32(wl["X"]).astype(np.float64)
+        mode = "qspace"
     else:
         X = wl["X"]
         mode = "qspace"
@@ -94,6 +104,8 @@ def main():
     ap.add_argument("--workload", default="sparse-text")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--C", type=float, default=None)
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -110,7 +122,7 @@ def main():
     _lib.load()
     log(f"[bench] generating workload {args.workload}")
     t = time.perf_counter()
-    wl = make_workload(args.workload)
+    wl = make_workload(args.workload, args.C)
     log(f"[bench] generated in {time.perf_counter() - t:.1f} s")
 
     kw = {}
@@ -118,6 +130,13 @@ def main():
         kw["csr"] = wl["csr"]
     else:
         kw["X"] = wl["X"]
+        if wl.get("bf16"):
+            kw["bf16"] = True
+            kw["precision"] = args.precision or "mixed"
+        elif args.precision:
+            kw["precision"] = args.precision
+    if "precision" in kw:
+        wl["cfg"]["precision"] = kw["precision"]
     t = time.perf_counter()
     s = Solver(y=wl["y"], C_=wl["C"], tol=1e-6, profile=1, **kw)
     torch.cuda.synchronize()
@@ -171,7 +190,10 @@ def main():
         import scipy.sparse as sp
         from oracle import ssnal
         xh = x.cpu().numpy()
-        if "csr" in wl:
+        if wl.get("bf16"):
+            import synth
+            Xo = synth.bf16_bits_to_f32(wl["X"])
+        elif "csr" in wl:
             vals, ci, rp, n, q = wl["csr"]
             Xo = sp.csr_matrix((vals.astype(np.float64), ci, rp), shape=(n, q))
         else:
@@ -197,7 +219,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if kw.get("precision") != "mixed" else "bf16+f64",
         "data": "synthetic",
         "config": wl["cfg"],
         "roofline": roofline,

@@ -83,7 +83,7 @@ typedef struct {
  * iteration cap of 200 outer iterations and x^0 = 0 (Section 4.1); the
  * defaults set by ssnalm_default_options are this library's readings of the
  * open constants: sigma0 = 1, sigma_{k+1} = min(rho sigma_k, sigma_max) with
- * rho = 5 and sigma_max = 1e6; eps_k = delta_k = eps_decay^k (0.5^k) in the
+ * rho = 2 and sigma_max = 1e6; eps_k = delta_k = eps_decay^k (0.5^k) in the
  * inner stopping tests (A') and (B'); mu = 1e-4, line-search factor 0.5,
  * tau = 0.5, eta = 0.1 in Algorithm 3; 50 inner iterations, 40 backtracks.
  */

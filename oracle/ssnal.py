@@ -25,7 +25,7 @@ because y_i^2 = 1 makes the labels cancel.  The x-update is
 x^{k+1} = Pi(u(omega^{k+1})) (eq. Def_new_update_xkplus).
 
 Readings of points the paper leaves open (all are keyword options):
-  sigma0 = 1, sigma_{k+1} = min(rho sigma_k, sigma_max), rho = 5, sigma_max = 1e6;
+  sigma0 = 1, sigma_{k+1} = min(rho sigma_k, sigma_max), rho = 2, sigma_max = 1e6;
   eps_k = delta_k = 0.5^k in (A') and (B'); the strong-convexity modulus of
   psi in omega-space is 1, so (A')+(B') read |g| <= min(eps_k, delta_k
   |x^{k+1}-x^k|)/sqrt(sigma), with an absolute floor 1e-14 (1 + |omega|);
@@ -271,7 +271,7 @@ def duality_gap(X, y, C, x):
 class Options:
     tol: float = 1e-6
     sigma0: float = 1.0
-    rho: float = 5.0
+    rho: float = 2.0
     sigma_max: float = 1e6
     max_outer: int = 200
     max_inner: int = 50
@@ -306,6 +306,7 @@ class Result:
     time_s: float = 0.0
     cg_iters: int = 0
     ls_fail: int = 0
+    ls_trials: int = 0
 
 
 def solve(X, y, C, tol=1e-6, x0=None, **kw):
@@ -333,6 +334,7 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
     inner_total = 0
     cg_total = 0
     ls_fail = 0
+    ls_trials = 0
     hist = []
     status = "MAXITER"
     R, b = math.inf, float("nan")
@@ -374,6 +376,7 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
             alpha = 1.0
             for m in range(opt.max_backtracks + 1):
                 alpha = opt.ls_delta ** m
+                ls_trials += 1
                 u_a = u - alpha * sigma * t
                 _, lam_a, _ = project_svm(u_a, y, C)
                 dpsi = psi_increment(omega, d, alpha, u, lam, u_a, lam_a, sigma, y, C)
@@ -412,4 +415,4 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
                   inner=inner_total, p=p, n_sv=int(np.sum(x > 0.0)), status=status,
                   sigma=sigma, omega=omega, history=hist,
                   time_s=time.perf_counter() - t_start, cg_iters=cg_total,
-                  ls_fail=ls_fail)
+                  ls_fail=ls_fail, ls_trials=ls_trials)

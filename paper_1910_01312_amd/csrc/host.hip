@@ -441,7 +441,7 @@ void ssnalm_default_options(ssnalm_options* o) {
     if (!o) return;
     memset(o, 0, sizeof *o);
     o->sigma0 = 1.0;
-    o->rho = 5.0;
+    o->rho = 2.0;
     o->sigma_max = 1e6;
     o->mu = 1e-4;
     o->ls_delta = 0.5;

@@ -140,41 +140,76 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ 
         }
 }
 
-// d = -M^{-1} g with the factor in M: forward L w = -g using row j of the
-// upper triangle (= column j of L), backward L^T d = w using row j of L.
-__global__ __launch_bounds__(1024) void k_chol_solve2(const double* __restrict__ M,
-                                                      const double* __restrict__ g,
-                                                      double* __restrict__ d, int q) {
+// d = -M^{-1} g with the factor in M, by 64-row blocks in one workgroup.
+// Forward L w = -g: for block B, subtract L[B, <B] w[<B] (rows of L, all
+// waves, one wave-reduction per row), then wave 0 solves the 64 x 64 lower
+// triangular block with lane i owning row i.  Backward L^T d = w: for block
+// B from the last, subtract L[>B, B]^T d[>B] (row j of the upper triangle
+// holds column j of L), then wave 0 solves the upper triangular L_BB^T.
+__global__ __launch_bounds__(SSN_BLOCK) void k_chol_solve2(const double* __restrict__ M,
+                                                           const double* __restrict__ g,
+                                                           double* __restrict__ d, int q) {
     extern __shared__ double z[];                  // q doubles
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = tid; i < q; i += nt) z[i] = -g[i];
+    __shared__ double Lb[NB][NB + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int i = tid; i < q; i += blockDim.x) z[i] = -g[i];
+    const int nblk = (q + NB - 1) / NB;
+    // ---- forward
+    for (int B = 0; B < nblk; ++B) {
+        const int o = B * NB, m = min(NB, q - o);
+        __syncthreads();
+        // z[o+r] -= sum_{c < o} L[o+r][c] z[c]
+        for (int r = wv; r < m; r += SSN_WAVES_PER_BLOCK) {
+            const double* row = M + (int64_t)(o + r) * q;
+            double acc = 0.0;
+            for (int c = lane; c < o; c += SSN_WAVE) acc = fma(row[c], z[c], acc);
+            acc = wave_sum(acc);
+            if (lane == 0) z[o + r] -= acc;
+        }
+        for (int e = tid; e < NB * NB; e += blockDim.x) {
+            const int i = e / NB, j = e % NB;
+            Lb[i][j] = (i < m && j < m && j <= i) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double ri = lane < m ? z[o + lane] : 0.0;
+            for (int j = 0; j < m; ++j) {
+                const double wj = __shfl(ri, j, SSN_WAVE) / Lb[j][j];
+                if (lane == j) ri = wj;
+                if (lane > j) ri -= Lb[lane][j] * wj;
+            }
+            if (lane < m) z[o + lane] = ri;
+        }
+    }
+    // ---- backward
+    for (int B = nblk - 1; B >= 0; --B) {
+        const int o = B * NB, m = min(NB, q - o), e0 = o + m;
+        __syncthreads();
+        // z[o+r] -= sum_{c >= e0} L[c][o+r] d[c] = sum upper[o+r][c] d[c]
+        for (int r = wv; r < m; r += SSN_WAVES_PER_BLOCK) {
+            const double* row = M + (int64_t)(o + r) * q;
+            double acc = 0.0;
+            for (int c = e0 + lane; c < q; c += SSN_WAVE) acc = fma(row[c], z[c], acc);
+            acc = wave_sum(acc);
+            if (lane == 0) z[o + r] -= acc;
+        }
+        for (int e = tid; e < NB * NB; e += blockDim.x) {
+            const int i = e / NB, j = e % NB;
+            Lb[i][j] = (i < m && j < m && j <= i) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double ri = lane < m ? z[o + lane] : 0.0;
+            for (int j = m - 1; j >= 0; --j) {
+                const double dj = __shfl(ri, j, SSN_WAVE) / Lb[j][j];
+                if (lane == j) ri = dj;
+                if (lane < j) ri -= Lb[j][lane] * dj;
+            }
+            if (lane < m) z[o + lane] = ri;
+        }
+    }
     __syncthreads();
-    __shared__ double zj_s;
-    for (int j = 0; j < q; ++j) {
-        if (tid == 0) {
-            const double v = z[j] / M[(int64_t)j * q + j];
-            z[j] = v;
-            zj_s = v;
-        }
-        __syncthreads();
-        const double zj = zj_s;
-        const double* row = M + (int64_t)j * q;      // upper part: L[i][j] for i > j
-        for (int i = j + 1 + tid; i < q; i += nt) z[i] -= row[i] * zj;
-        __syncthreads();
-    }
-    for (int j = q - 1; j >= 0; --j) {
-        if (tid == 0) {
-            const double v = z[j] / M[(int64_t)j * q + j];
-            z[j] = v;
-            zj_s = v;
-        }
-        __syncthreads();
-        const double zj = zj_s;
-        const double* row = M + (int64_t)j * q;      // lower part: L[j][i] for i < j
-        for (int i = tid; i < j; i += nt) z[i] -= row[i] * zj;
-        __syncthreads();
-    }
-    for (int i = tid; i < q; i += nt) d[i] = z[i];
+    for (int i = tid; i < q; i += blockDim.x) d[i] = z[i];
 }
 
 void launch_chol_factor_blocked(double* M, int64_t q, Scalars* sc, hipStream_t s) {
@@ -193,8 +228,8 @@ void launch_chol_factor_blocked(double* M, int64_t q, Scalars* sc, hipStream_t s
 void launch_chol_solve_factored(const double* M, const double* g, double* d, int64_t q,
                                 double* work, hipStream_t s) {
     (void)work;
-    hipLaunchKernelGGL(k_chol_solve2, dim3(1), dim3(1024), (size_t)q * sizeof(double), s, M, g, d,
-                       (int)q);
+    hipLaunchKernelGGL(k_chol_solve2, dim3(1), dim3(SSN_BLOCK), (size_t)q * sizeof(double), s, M, g,
+                       d, (int)q);
 }
 
 void launch_chol_solve_blocked(double* M, const double* g, double* d, int64_t q, double* work,

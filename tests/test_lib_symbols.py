@@ -46,7 +46,7 @@ def test_default_options_without_gpu():
     """ssnalm_default_options touches no device: callable on the CPU host."""
     from paper_1910_01312_amd import _lib
     o = _lib.default_options()
-    assert o.sigma0 == 1.0 and o.rho == 5.0 and o.max_outer == 200 and o.max_inner == 50
+    assert o.sigma0 == 1.0 and o.rho == 2.0 and o.max_outer == 200 and o.max_inner == 50
     assert o.mu == 1e-4 and o.ls_delta == 0.5 and o.tau == 0.5 and o.eta == 0.1
 
 
