@@ -98,6 +98,11 @@ typedef struct {
     int32_t verbose;            /* 1: one line per outer iteration on stderr              */
     int32_t check_finite;       /* 1: ssnalm_create scans X for NaN/Inf                   */
     int32_t profile;            /* 1: time the hot kernels with HIP events on the stream  */
+    int32_t batch_graphs;       /* batched solve: 1 replays captured HIP graphs of the    */
+                                /* Newton-direction and line-search-trial launches, 0     */
+                                /* issues the same launches one by one (same results)     */
+    int32_t autotune;           /* batched solve: 1 times candidate launch shapes once    */
+                                /* per shape class and keeps the fastest (same results)   */
 } ssnalm_options;
 
 /* What the paper reports per solve (Section 4, Table 2 columns) plus timing. */
@@ -154,13 +159,30 @@ ssnalm_status ssnalm_solve(ssnalm_ctx* ctx, const double* x0, double* x_out,
                            double* w_out, ssnalm_info* info);
 
 /*
- * Solve `count` independent problems (each with its own n, C and data, all
- * dense with the same dtype and q) with one launch per phase for all of
- * them.  probs: host array of `count` problems; x_out: host array of
- * `count` device pointers (n_k doubles each); w_out: host array of device
- * pointers (q doubles each) or NULL; infos: host array or NULL.
- * Each problem follows exactly the iteration of ssnalm_solve; problems that
- * have converged are masked out of later launches.
+ * Solve `count` independent problems with one launch per phase for all of
+ * them: the C-grid / one-vs-rest / cross-validation use of the method
+ * (Section 4 solves one QP per C value and per fold).  Each problem runs
+ * Algorithm 1 with Algorithm 3 as in ssnalm_solve (x^0 = 0, the Cholesky
+ * Newton step, the same options); the kernels sum in a different order than
+ * the single-problem ones, so iterates agree with ssnalm_solve to rounding.
+ * A problem that meets its own tol (or its caps) leaves the later launches.
+ *   count  : number of problems, >= 1.
+ *   probs  : host array of `count` problems; all SSNALM_DENSE with the same
+ *            dtype and the same q <= 128; n, C, tol, X and y per problem
+ *            (device pointers, X row-major as in ssnalm_create).
+ *   opt    : host pointer or NULL for the defaults (newton must be AUTO or
+ *            CHOL, precision FP64).
+ *   stream : hipStream_t or NULL; the call runs on a private stream ordered
+ *            after the work already on `stream` and returns when done.
+ *   x_out  : host array of `count` device pointers, n_k doubles each.
+ *   w_out  : host array of `count` device pointers (q doubles) or NULL;
+ *            a NULL entry skips that problem's w.
+ *   infos  : host array of `count` infos or NULL; time_s is the batch's
+ *            wall time, the per-phase times are 0.
+ * Returns OK when every problem reached its tol, otherwise the first
+ * non-OK status in problem order (infos[k].status has each one).
+ * E_BADARG: count < 1, a null pointer, a problem that is not dense, mixed
+ * dtypes or q, q > 128, or any ssnalm_create argument error; E_OOM / E_HIP.
  */
 ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem* probs,
                                  const ssnalm_options* opt, void* stream,

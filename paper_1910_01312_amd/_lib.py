@@ -33,7 +33,8 @@ class Options(C.Structure):
                 ("max_outer", C.c_int32), ("max_inner", C.c_int32),
                 ("max_backtracks", C.c_int32), ("newton", C.c_int32),
                 ("precision", C.c_int32), ("max_cg", C.c_int32), ("verbose", C.c_int32),
-                ("check_finite", C.c_int32), ("profile", C.c_int32)]
+                ("check_finite", C.c_int32), ("profile", C.c_int32),
+                ("batch_graphs", C.c_int32), ("autotune", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -42,6 +42,18 @@ static ssnalm_status fail(ssnalm_status st, const char* fmt, ...) {
     return st;
 }
 
+namespace ssn {
+ssnalm_status set_error(ssnalm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+}  // namespace ssn
+
 #define HIPCHK(expr)                                                                        \
     do {                                                                                    \
         hipError_t e_ = (expr);                                                             \
@@ -457,6 +469,9 @@ void ssnalm_default_options(ssnalm_options* o) {
     o->max_cg = 500;
     o->verbose = 0;
     o->check_finite = 0;
+    o->profile = 0;
+    o->batch_graphs = 1;
+    o->autotune = 1;
 }
 
 const char* ssnalm_last_error(void) { return g_err.c_str(); }
@@ -592,6 +607,29 @@ static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
     return SSNALM_OK;
 }
 
+namespace ssn {
+// Scan `count` elements of X (device, dtype) for NaN / Inf on the host, in
+// blocks of 4M elements.
+ssnalm_status scan_finite(const void* X, int dtype, int64_t total) {
+    const size_t eb = dtype == SSNALM_F64 ? 8 : (dtype == SSNALM_F32 ? 4 : 2);
+    const int64_t blkn = 1 << 22;
+    std::vector<char> buf(eb * blkn);
+    for (int64_t off = 0; off < total; off += blkn) {
+        const int64_t m = std::min(blkn, total - off);
+        if (hipMemcpy(buf.data(), (const char*)X + eb * off, eb * m, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(SSNALM_E_HIP, "reading X failed");
+        for (int64_t k = 0; k < m; ++k) {
+            double v;
+            if (eb == 8) v = ((double*)buf.data())[k];
+            else if (eb == 4) v = ((float*)buf.data())[k];
+            else { uint32_t b = ((uint32_t)((uint16_t*)buf.data())[k]) << 16; float f; memcpy(&f, &b, 4); v = f; }
+            if (!std::isfinite(v)) return fail(SSNALM_E_NONFINITE, "non-finite X entry %lld", (long long)(off + k));
+        }
+    }
+    return SSNALM_OK;
+}
+}  // namespace ssn
+
 extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* pr,
                                        const ssnalm_options* opt, void* stream) {
     if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
@@ -689,22 +727,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
             else { float* t; ALLOC(t, nz); c->jv = t; }
         }
     } else if (c->opt.check_finite) {
-        // scan X on the host in blocks (creation-time check only)
-        const size_t eb = pr->dtype == SSNALM_F64 ? 8 : (pr->dtype == SSNALM_F32 ? 4 : 2);
-        const int64_t total = n * q, blkn = 1 << 22;
-        std::vector<char> buf(eb * blkn);
-        for (int64_t off = 0; off < total; off += blkn) {
-            const int64_t m = std::min(blkn, total - off);
-            if (hipMemcpy(buf.data(), (const char*)pr->X + eb * off, eb * m, hipMemcpyDeviceToHost) != hipSuccess)
-                return bail(fail(SSNALM_E_HIP, "reading X failed"));
-            for (int64_t k = 0; k < m; ++k) {
-                double v;
-                if (eb == 8) v = ((double*)buf.data())[k];
-                else if (eb == 4) v = ((float*)buf.data())[k];
-                else { uint32_t b = ((uint32_t)((uint16_t*)buf.data())[k]) << 16; float f; memcpy(&f, &b, 4); v = f; }
-                if (!std::isfinite(v)) return bail(fail(SSNALM_E_NONFINITE, "non-finite X entry %lld", (long long)(off + k)));
-            }
-        }
+        if ((s = scan_finite(pr->X, pr->dtype, n * q)) < 0) return bail(s);
     }
 #undef ALLOC
     if (hipStreamSynchronize(c->st) != hipSuccess) return bail(fail(SSNALM_E_HIP, "stream sync failed"));
@@ -869,13 +892,6 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     return status;
 }
 
-extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem* probs,
-                                            const ssnalm_options* opt, void* stream,
-                                            double* const* x_out, double* const* w_out,
-                                            ssnalm_info* infos) {
-    (void)count; (void)probs; (void)opt; (void)stream; (void)x_out; (void)w_out; (void)infos;
-    return fail(SSNALM_E_BADARG, "batched solve not available in this build");
-}
 
 // ---------------------------------------------------------------- step ops
 extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* t) {

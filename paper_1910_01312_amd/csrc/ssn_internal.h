@@ -220,4 +220,87 @@ void launch_mop_finish(const double* pd, const double* z, double sigma, const do
                        const double* unused2, int64_t unused3, double* Ap, int64_t q,
                        hipStream_t s);
 
+// Batched solve (kernels_batch.hip) ------------------------------------------------
+constexpr int BRPI = 1024;     // rows per work item
+constexpr int BQMAX = 128;     // largest q of a batched solve
+int batch_rows_per_item();
+int batch_qmax();
+int batch_gram_items_max(int64_t n);   // Gram items of a problem with n rows (upper bound)
+int batch_proj_max_passes();
+
+struct BProb {                 // static description of problem k (device)
+    const void*   X;           // n x q row-major
+    const int8_t* y;           // n labels
+    int64_t n;
+    int64_t off;               // first row of problem k in the concatenated n-vectors
+    double  C;
+    int     item0, nitem;      // its items in the static item list
+};
+struct BPar {                  // per-phase parameters of problem k (uploaded by the host)
+    int    active;             // 1: problem k takes part in the launches
+    int    pad_;
+    double sigma, alpha;
+};
+enum {                         // per-problem scalar slots (BState::r)
+    BS_GN2 = 0, BS_OM2, BS_GD, BS_OD, BS_DD,
+    BS_DH, BS_DIST2, BS_PF, BS_NSV,
+    BS_RES2, BS_X2, BS_SUMX,
+    BS_FSUMX, BS_FNSV, BS_FP, BS_W2,
+    BS_NR
+};
+struct BState {                // per-problem device results, read back by the host
+    ProjState ps[3];           // 0: line-search base, 1: trial, 2: KKT
+    double    r[BS_NR];
+    long long p;               // |J| of the last compaction
+    int       chol_fail, pad_;
+};
+struct BArgs {                 // what every batched kernel receives
+    const BProb* prob;
+    const BPar*  par;
+    BState*      bs;
+    int4*        wl;           // active work list: (problem, first row, end row, 0)
+    int*         wl_n;
+    int*         ioff;         // per problem: first item in wl, item count
+    int*         icnt;
+    int          q, nprob;
+};
+struct BLaunch {
+    BArgs  A;
+    int    dtype, vec, unr, grid, ggrid;
+    double *part, *part2;      // item partials (max(q, 65) doubles per item)
+    int    *ipart, *ipart2;    // item partials (64 ints per item), item offsets
+    int4*  gwl;                // Gram work list and its per-problem offsets / counts
+    int*   gwl_n;
+    int    *goff, *gcnt;
+    double* gpart;             // q*q doubles per Gram item
+    hipStream_t s;
+};
+void lb_setup_attributes();
+void lb_build_wl(const BLaunch& L, const int4* items);
+void lb_amul(const BLaunch& L, const double* V, double* t);
+void lb_atmul(const BLaunch& L, const double* z, const uint8_t* mask, const double* base,
+              double sign, double* out, double* out2);
+void lb_elem(const BLaunch& L, int mode, const double* a, const double* b, double* o);
+void lb_accept(const BLaunch& L, double* om, const double* d, double* aw, const double* td,
+               double* u, const double* ut, double* xt, const double* xtt, uint8_t* jm,
+               const uint8_t* jmt);
+void lb_qvec(const BLaunch& L, int mode, const double* a, const double* b, double* o);
+void lb_qdots(const BLaunch& L, int npair, const double* a0, const double* b0, const double* a1,
+              const double* b1, const double* a2, const double* b2, int f0);
+void lb_proj_init(const BLaunch& L, const double* u, const double* td, double* vout, int w,
+                  int use_hint);
+void lb_proj_passes(const BLaunch& L, const double* v, int w, int npass);
+void lb_ls_fin(const BLaunch& L, const double* v, const double* ubase, const double* td, int w,
+               int wb, const double* xk, double* x, uint8_t* mask);
+void lb_kkt_fin(const BLaunch& L, const double* v, const double* x, int w);
+void lb_count(const BLaunch& L, const double* x);
+void lb_compact(const BLaunch& L, const uint8_t* mask, int32_t* list);
+void lb_newton(const BLaunch& L, const int32_t* list, const double* sv, const double* g, double* d,
+               double* M);
+
+// error reporting shared by the host files
+ssnalm_status set_error(ssnalm_status st, const char* fmt, ...);
+// NaN / Inf scan of `count` elements of X (device) on the host
+ssnalm_status scan_finite(const void* X, int dtype, int64_t count);
+
 }  // namespace ssn

@@ -40,7 +40,7 @@ def _stream_handle():
 
 _OPT_KEYS = {"sigma0", "rho", "sigma_max", "mu", "ls_delta", "tau", "eta", "eps_decay",
              "floor_rel", "max_outer", "max_inner", "max_backtracks", "newton", "precision",
-             "max_cg", "verbose", "check_finite", "profile"}
+             "max_cg", "verbose", "check_finite", "profile", "batch_graphs", "autotune"}
 
 
 def make_options(**kw) -> L.Options:
@@ -222,3 +222,53 @@ def solve(X, y, C_, tol=1e-6, x0=None, **opts):
     """One-shot solve: returns (x, w, info)."""
     with Solver(X, y, C_, tol, **opts) as s:
         return s.solve(x0)
+
+
+def _dense_dev(X, bf16=False):
+    """Device copy of a dense X and its library dtype code."""
+    if isinstance(X, torch.Tensor) and X.dtype == torch.bfloat16:
+        return _to_dev(X).view(torch.int16), L.BF16
+    if bf16:
+        return _to_dev(np.asarray(X).view(np.int16) if not isinstance(X, torch.Tensor) else X), L.BF16
+    Xd = _to_dev(X)
+    if Xd.dtype == torch.float64:
+        return Xd, L.F64
+    if Xd.dtype == torch.float32:
+        return Xd, L.F32
+    raise TypeError(f"unsupported X dtype {Xd.dtype}")
+
+
+def solve_batch(problems, tol=1e-6, *, bf16=False, want_w=True, **opts):
+    """Batched solve (ssnalm_solve_batch): `problems` is a sequence of
+    (X, y, C) with dense X of one dtype and one q <= 128.  tol is a number or
+    one value per problem.  Returns a list of (x, w, info) per problem."""
+    lib = L.load()
+    count = len(problems)
+    tols = [float(tol)] * count if np.isscalar(tol) else [float(t) for t in tol]
+    probs = (L.Problem * count)()
+    keep, xs, ws = [], [], []
+    dev = _dev()
+    for k, (X, y, C_) in enumerate(problems):
+        Xd, dt = _dense_dev(X, bf16)
+        yd = _to_dev(y, torch.int8)
+        keep += [Xd, yd]
+        n, q = Xd.shape
+        pr = probs[k]
+        pr.kind, pr.dtype = L.DENSE, dt
+        pr.n, pr.q, pr.nnz = int(n), int(q), 0
+        pr.X, pr.y = Xd.data_ptr(), yd.data_ptr()
+        pr.C, pr.tol = float(C_), tols[k]
+        xs.append(torch.empty(int(n), dtype=torch.float64, device=dev))
+        ws.append(torch.empty(int(q), dtype=torch.float64, device=dev) if want_w else None)
+    xp = (C.c_void_p * count)(*[x.data_ptr() for x in xs])
+    wp = (C.c_void_p * count)(*[w.data_ptr() for w in ws]) if want_w else None
+    infos = (L.Info * count)()
+    o = make_options(**opts)
+    st = lib.ssnalm_solve_batch(count, probs, C.byref(o), _stream_handle(), xp, wp, infos)
+    L.check(st, "ssnalm_solve_batch")
+    out = []
+    for k in range(count):
+        d = infos[k].as_dict()
+        d["status_name"] = L.STATUS_NAMES.get(infos[k].status, str(infos[k].status))
+        out.append((xs[k], ws[k], d))
+    return out
