@@ -96,6 +96,135 @@ def oracle_sample(wl, budget_s, gpu_newton_steps):
     return {"value": est, "unit": "s", "cores": int(cores), "kind": "oracle", "sample": sample}
 
 
+def run_batch(args):
+    """Batched workload: 256 dense FP32 QPs (two-class Gaussian mixtures,
+    q = 128, n_k uniform in [1000, 200000], C_k on the log grid 1e-3..1e2)
+    solved by one ssnalm_solve_batch call per step; value = seconds per QP.
+    Also times the same QPs one by one through ssnalm_solve (plain cold-start
+    GPU solves) and checks sampled solutions with the oracle's KKT code."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1910_01312_amd import _lib
+    from paper_1910_01312_amd.solver import Solver, batch_kernel_stats, solve_batch
+    from oracle import ssnal
+
+    _lib.load()
+    fam = synth.batch_family(count=args.count)
+    log(f"[bench] generating {len(fam)} problems (sum n = {sum(p['n'] for p in fam)})")
+    t = time.perf_counter()
+    probs = []
+    for i, p in enumerate(fam):
+        X, y = synth.mixture_problem(p["n"], q=p["q"], seed=p["seed"])
+        probs.append((torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), p["C"]))
+        if i % 32 == 31:
+            log(f"[bench]   {i + 1} problems on the GPU ({time.perf_counter() - t:.1f} s)")
+    torch.cuda.synchronize()
+    log(f"[bench] generated in {time.perf_counter() - t:.1f} s")
+    count = len(probs)
+    ntot = sum(p["n"] for p in fam)
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        out = solve_batch(probs, tol=1e-6, want_w=False, profile=1)
+        st = [o[2]["status_name"] for o in out]
+        log(f"[bench] warmup {i}: {time.perf_counter() - t:.3f} s, OK {st.count('OK')}/{count}, "
+            f"max newton {max(o[2]['iters_inner'] for o in out)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = solve_batch(probs, tol=1e-6, want_w=False, profile=1)
+        log(f"[bench] step {i} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per_batch = (t1 - t0) / args.steps
+    ks = batch_kernel_stats()["amul"]
+    roofline = None
+    if ks["launches"]:
+        avg = ks["seconds"] / ks["launches"]
+        achieved = ks["bytes"] / ks["launches"] / avg / 1e9
+        roofline = {"bound": "hbm", "kernel": "batched A v (all active problems)",
+                    "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "bytes_per_launch": ks["bytes"] / ks["launches"],
+                    "avg_launch_us": avg * 1e6, "launches": ks["launches"]}
+    infos = [o[2] for o in out]
+    # oracle KKT check on sampled problems: smallest and largest n, both C ends
+    idx = sorted({int(np.argmin([p["n"] for p in fam])), int(np.argmax([p["n"] for p in fam])),
+                  0, count - 1})
+    checks = []
+    for k in idx:
+        X, y = synth.mixture_problem(fam[k]["n"], q=fam[k]["q"], seed=fam[k]["seed"])
+        R, _ = ssnal.rkkt(X.astype(np.float64), y, fam[k]["C"], out[k][0].cpu().numpy())
+        checks.append({"problem": k, "n": fam[k]["n"], "C": fam[k]["C"], "rkkt_oracle": R})
+    seq = None
+    if not args.no_seq:
+        log("[bench] sequential single-problem GPU solves of the same QPs")
+        tsum, st_ok = 0.0, 0
+        for k, (Xd, yd, C_) in enumerate(probs):
+            with Solver(Xd, yd, C_, tol=1e-6) as s:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, _, inf = s.solve()
+                torch.cuda.synchronize()
+                tsum += time.perf_counter() - t
+                st_ok += inf["status_name"] == "OK"
+            if k % 32 == 31:
+                log(f"[bench]   {k + 1} sequential solves, {tsum:.1f} s")
+        seq = {"total_s": tsum, "per_qp_s": tsum / count, "ok": st_ok,
+               "batched_speedup": tsum / per_batch}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import psutil
+        log(f"[bench] cpu baseline: oracle solves for ~{args.cpu_budget:.0f} s")
+        proc = psutil.Process()
+        c0 = proc.cpu_times()
+        w0 = time.perf_counter()
+        tsolve, nrows, done = 0.0, 0, 0
+        for p in fam:
+            if time.perf_counter() - w0 > args.cpu_budget:
+                break
+            X, y = synth.mixture_problem(p["n"], q=p["q"], seed=p["seed"])
+            Xo = X.astype(np.float64)
+            t = time.perf_counter()
+            r = ssnal.solve(Xo, y, p["C"], tol=1e-6)
+            tsolve += time.perf_counter() - t
+            nrows += p["n"]
+            done += 1
+        wall = time.perf_counter() - w0
+        c1 = proc.cpu_times()
+        cores = max(1, round(((c1.user - c0.user) + (c1.system - c0.system)) / max(wall, 1e-9)))
+        est_total = tsolve / max(nrows, 1) * ntot
+        cpu = {"value": est_total / count, "unit": "s", "cores": int(cores), "kind": "oracle",
+               "sample": (f"oracle solves of the first {done} QPs of the family ({nrows} rows, "
+                          f"{tsolve:.1f} s), seconds per row x the family's {ntot} rows / {count} QPs")}
+    out_json = {
+        "metric": METRIC,
+        "value": per_batch / count,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per_batch * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {count} dense fp32 QPs, q=128, n in [1000, 200000] "
+                               f"(sum {ntot}), two-class Gaussian mixtures, C log grid 1e-3..1e2",
+                   "count": count, "sum_n": ntot, "q": 128, "tol": 1e-6},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "batch": {"seconds_per_batch": per_batch,
+                  "ok": sum(i["status_name"] == "OK" for i in infos),
+                  "newton_max": max(i["iters_inner"] for i in infos),
+                  "newton_sum": sum(i["iters_inner"] for i in infos),
+                  "outer_max": max(i["iters_outer"] for i in infos),
+                  "oracle_checks": checks, "sequential_gpu": seq},
+    }
+    print(json.dumps(out_json), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--C", type=float, default=None)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--count", type=int, default=256, help="batched workload: number of QPs")
+    ap.add_argument("--no-seq", action="store_true", help="batched workload: skip the one-by-one solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -119,6 +250,9 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs the GPU")
+    if args.workload == "batch":
+        run_batch(args)
+        return
     _lib.load()
     log(f"[bench] generating workload {args.workload}")
     t = time.perf_counter()

@@ -275,6 +275,12 @@ typedef struct {
 ssnalm_status ssnalm_kernel_stats(ssnalm_ctx* ctx, int32_t which, ssnalm_kstat* out,
                                   int32_t reset);
 
+/* The same statistics for the last ssnalm_solve_batch call made on this
+ * thread with opt.profile = 1 (launches timed outside the captured graphs:
+ * SSNALM_K_AMUL covers the A omega and Q x passes over all active
+ * problems; other classes read 0).  which: SSNALM_K_*; out: host pointer. */
+ssnalm_status ssnalm_batch_kernel_stats(int32_t which, ssnalm_kstat* out);
+
 /* Relative KKT residual of eq. Def_Rkkt at x (n doubles, device), with
  * the bias lam of its projection.  rkkt, b: host doubles. */
 ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* ctx, const double* x, double* rkkt,

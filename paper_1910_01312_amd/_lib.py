@@ -63,7 +63,7 @@ EXPORTS = [
     "ssnalm_default_options", "ssnalm_create", "ssnalm_solve", "ssnalm_solve_batch",
     "ssnalm_destroy", "ssnalm_last_error", "ssnalm_op_amul", "ssnalm_op_atmul",
     "ssnalm_op_project", "ssnalm_op_newton", "ssnalm_op_linesearch_trial", "ssnalm_op_rkkt",
-    "ssnalm_kernel_stats", "ssnalm_op_gram",
+    "ssnalm_kernel_stats", "ssnalm_op_gram", "ssnalm_batch_kernel_stats",
 ]
 
 _lib = None
@@ -110,6 +110,8 @@ def load(path: str | None = None):
     lib.ssnalm_op_gram.restype = i32
     lib.ssnalm_kernel_stats.argtypes = [vp, i32, C.POINTER(KStat), i32]
     lib.ssnalm_kernel_stats.restype = i32
+    lib.ssnalm_batch_kernel_stats.argtypes = [i32, C.POINTER(KStat)]
+    lib.ssnalm_batch_kernel_stats.restype = i32
     _lib = lib
     return lib
 

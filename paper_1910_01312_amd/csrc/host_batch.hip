@@ -59,6 +59,8 @@ struct Shape { int grid, unr; };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, Shape> g_tune;   // (dtype, q, vec, log2 items)
 
+thread_local ssnalm_kstat g_bks[SSNALM_K_COUNT];
+
 constexpr int kRing = 16;          // pinned parameter slots between two syncs
 constexpr int kPassBatch = 5;      // multisection passes issued before the first check
 
@@ -83,8 +85,15 @@ struct Batch {
     int32_t* list = nullptr;
     double *om = nullptr, *g = nullptr, *sv = nullptr, *d = nullptr, *qv = nullptr, *M = nullptr;
     hipGraphExec_t gx_newton = nullptr, gx_trial = nullptr;
+    // HIP-event timing of the full-pass A v launches (profile = 1)
+    bool prof = false;
+    struct Pend { hipEvent_t a, b; double bytes; };
+    std::vector<Pend> pend;
+    std::vector<hipEvent_t> evpool;
     ~Batch() {
         if (s) hipStreamSynchronize(s);
+        for (auto& p : pend) { evpool.push_back(p.a); evpool.push_back(p.b); }
+        for (hipEvent_t e : evpool) hipEventDestroy(e);
         if (gx_newton) hipGraphExecDestroy(gx_newton);
         if (gx_trial) hipGraphExecDestroy(gx_trial);
         for (void* p : owned) hipFree(p);
@@ -138,7 +147,47 @@ ssnalm_status readback(Batch& B) {
     BCHK(hipMemcpyAsync(B.bs_h, B.bs_d, sizeof(BState) * B.nprob, hipMemcpyDeviceToHost, B.s));
     BCHK(hipStreamSynchronize(B.s));
     B.ring = 0;
+    for (auto& p : B.pend) {              // every event pair has completed
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, p.a, p.b);
+        ssnalm_kstat& k = g_bks[SSNALM_K_AMUL];
+        k.launches += 1;
+        k.seconds += 1e-3 * ms;
+        k.bytes += p.bytes;
+        B.evpool.push_back(p.a);
+        B.evpool.push_back(p.b);
+    }
+    B.pend.clear();
     return SSNALM_OK;
+}
+
+hipEvent_t ev_get(Batch& B) {
+    if (!B.evpool.empty()) {
+        hipEvent_t e = B.evpool.back();
+        B.evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+// A v over the rows of the active problems, timed when profiling.  Bytes:
+// X rows, labels, the n-vector written, the q-vectors read.
+void timed_amul(Batch& B, const std::vector<char>& act, const double* V, double* t) {
+    if (!B.prof) {
+        lb_amul(B.L, V, t);
+        return;
+    }
+    const double esz = B.dtype == SSNALM_F64 ? 8.0 : (B.dtype == SSNALM_F32 ? 4.0 : 2.0);
+    double bytes = 0.0;
+    for (int k = 0; k < B.nprob; ++k)
+        if (act[k]) bytes += (double)B.hprob[k].n * (B.q * esz + 1.0 + 8.0) + 8.0 * B.q;
+    Batch::Pend p{ev_get(B), ev_get(B), bytes};
+    hipEventRecord(p.a, B.s);
+    lb_amul(B.L, V, t);
+    hipEventRecord(p.b, B.s);
+    B.pend.push_back(p);
 }
 
 // Newton direction for the active problems: J compaction, Gram, M,
@@ -377,6 +426,8 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
     BST(validate(count, probs, o, x_out));
     Batch B;
     BST(setup(B, count, probs, o));
+    B.prof = o.profile != 0;
+    if (B.prof) memset(g_bks, 0, sizeof g_bks);
     // order after the caller's stream
     BCHK(hipEventRecord(B.ev, (hipStream_t)stream));
     BCHK(hipStreamWaitEvent(B.s, B.ev, 0));
@@ -407,7 +458,7 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
         std::vector<int> S1 = set_of(PH_OUTER);
         if (!S1.empty()) {
             BST(activate(B, hp, flags(S1)));
-            lb_amul(B.L, B.om, B.aw);
+            timed_amul(B, act, B.om, B.aw);
             lb_elem(B.L, 0, B.xk, B.aw, B.u);
             lb_proj_init(B.L, B.u, nullptr, nullptr, 0, 0);
             lb_proj_passes(B.L, B.u, 0, kPassBatch);
@@ -501,7 +552,7 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
             BST(activate(B, hp, flags(S3)));
             lb_elem(B.L, 2, B.xt, nullptr, B.xk);
             lb_qvec(B.L, 1, B.om, B.g, B.qv);                 // A^T x^{k+1} = omega - g
-            lb_amul(B.L, B.qv, B.nv);                         // Q x
+            timed_amul(B, act, B.qv, B.nv);                   // Q x
             lb_elem(B.L, 1, B.xk, B.nv, B.nv2);               // x - Qx + e
             lb_proj_init(B.L, B.nv2, nullptr, nullptr, 2, 0);
             lb_proj_passes(B.L, B.nv2, 2, kPassBatch);
@@ -603,4 +654,10 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
     }
     (void)sweeps;
     return ret;
+}
+
+extern "C" ssnalm_status ssnalm_batch_kernel_stats(int32_t which, ssnalm_kstat* out) {
+    if (!out || which < 0 || which >= SSNALM_K_COUNT) return set_error(SSNALM_E_BADARG, "bad class or null pointer");
+    *out = g_bks[which];
+    return SSNALM_OK;
 }

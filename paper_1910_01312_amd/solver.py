@@ -272,3 +272,16 @@ def solve_batch(problems, tol=1e-6, *, bf16=False, want_w=True, **opts):
         d["status_name"] = L.STATUS_NAMES.get(infos[k].status, str(infos[k].status))
         out.append((xs[k], ws[k], d))
     return out
+
+
+def batch_kernel_stats():
+    """Kernel statistics of the last solve_batch call on this thread made
+    with profile=1: {name: {launches, seconds, bytes, flops}}."""
+    lib = L.load()
+    out = {}
+    for k, name in enumerate(L.K_NAMES):
+        ks = L.KStat()
+        L.check(lib.ssnalm_batch_kernel_stats(k, C.byref(ks)), "ssnalm_batch_kernel_stats")
+        out[name] = {"launches": ks.launches, "seconds": ks.seconds, "bytes": ks.bytes,
+                     "flops": ks.flops}
+    return out

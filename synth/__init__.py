@@ -182,23 +182,22 @@ def mixture_problem(n: int, q: int = 128, seed: int = 0, n_comp: int = 3,
                     mean_scale: float = 0.5):
     """One problem of the batched family: two classes, each a mixture of
     `n_comp` Gaussians with means ~ N(0, mean_scale^2 I) and identity
-    covariance; the positive-class share ~ U[0.3, 0.7].
+    covariance; the positive-class share ~ U[0.3, 0.7]; rows in random
+    order.  Draws in float32 (the workload's storage type).
     Returns (X float32 [n,q], y int8 [n])."""
     rng = np.random.default_rng(seed)
     frac = rng.uniform(0.3, 0.7)
     n_pos = int(round(frac * n))
     n_pos = min(max(n_pos, 1), n - 1)
-    means = rng.normal(0.0, mean_scale, size=(2, n_comp, q))
-    X = np.empty((n, q), dtype=np.float32)
-    y = np.empty(n, dtype=np.int8)
-    comp = rng.integers(0, n_comp, size=n)
-    cls = np.zeros(n, dtype=np.int64)
+    means = rng.normal(0.0, mean_scale, size=(2 * n_comp, q)).astype(np.float32)
+    cls = np.ones(n, dtype=np.int64)
     cls[:n_pos] = 0
-    cls[n_pos:] = 1
-    X[:] = (rng.standard_normal((n, q)) + means[cls, comp]).astype(np.float32)
-    y[:] = np.where(cls == 0, 1, -1)
-    perm = rng.permutation(n)
-    return np.ascontiguousarray(X[perm]), np.ascontiguousarray(y[perm])
+    rng.shuffle(cls)
+    comp = rng.integers(0, n_comp, size=n)
+    X = rng.standard_normal((n, q), dtype=np.float32)
+    X += means[cls * n_comp + comp]
+    y = np.where(cls == 0, 1, -1).astype(np.int8)
+    return X, y
 
 
 def batch_family(count: int = 256, q: int = 128, n_lo: int = 1000,
