@@ -235,3 +235,22 @@ def tiny_problem(n: int, q: int, seed: int, integer: bool = False,
             y[0] = -y[0]
     X = X + (1.0 if integer else 0.5) * y[:, None]
     return X, y
+
+
+def projection_matrix(q: int, k: int = 64, seed: int = 0) -> np.ndarray:
+    """Seeded Gaussian q x k matrix scaled by 1/sqrt(q) (float32): the
+    feature projection of the warm-start network."""
+    rng = np.random.default_rng(SEED_BASE + 5000 + q + 100000 * seed)
+    return (rng.standard_normal((q, k)) / np.sqrt(q)).astype(np.float32)
+
+
+def mlp_init(seed: int = 0, sizes=(66, 256, 256, 4)) -> np.ndarray:
+    """Seeded initial parameters of the warm-start network (float32, flat,
+    layout W1, b1, W2, b2, W3, b3): weights ~ N(0, 2 / (fan_in + fan_out)),
+    biases 0."""
+    rng = np.random.default_rng(SEED_BASE + 7000 + seed)
+    parts = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        parts.append((rng.standard_normal((a, b)) * np.sqrt(2.0 / (a + b))).ravel())
+        parts.append(np.zeros(b))
+    return np.concatenate(parts).astype(np.float32)
