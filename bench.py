@@ -225,6 +225,78 @@ def run_batch(args):
     print(json.dumps(out_json), flush=True)
 
 
+def run_warmstart(args):
+    """Learned warm start: 16 held-out dense fp32 QPs (n = 200,000, q = 256,
+    the batched family's generator, C on the log grid 1e-3..1e2), each
+    solved cold (ssnalm_solve from x = 0) and with the committed network
+    (features + inference + screened solves + full-problem KKT check);
+    value = mean warm time per QP, speedup = T_cold / (T_infer + T_warm)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1910_01312_amd import _lib
+    from paper_1910_01312_amd.solver import Solver
+    from paper_1910_01312_amd.warmstart import Net, warm_solve
+    from oracle import ssnal
+
+    _lib.load()
+    net = Net.load(os.path.join(ROOT, "paper_1910_01312_amd", "data", "warmstart_q256.npz"))
+    R = synth.projection_matrix(256)
+    count = args.count if args.count != 256 else 16
+    Cs = [10.0 ** (-3.0 + 5.0 * k / max(count - 1, 1)) for k in range(count)]
+    rows = []
+    tc_sum = tw_sum = ti_sum = 0.0
+    for k, C in enumerate(Cs):
+        X, y = synth.mixture_problem(200_000, q=256, seed=synth.seed_for(5, k + 1))
+        Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+        with Solver(Xd, yd, C, tol=1e-6) as s:
+            s.solve()
+            tcs, tws = [], []
+            for _ in range(args.steps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                xc, _, ic = s.solve()
+                torch.cuda.synchronize()
+                tcs.append(time.perf_counter() - t)
+                t = time.perf_counter()
+                xw, _, iw, sw = warm_solve(s, net, R, keep_frac=args.keep_frac)
+                torch.cuda.synchronize()
+                tws.append(time.perf_counter() - t)
+        tc, tw = float(np.median(tcs)), float(np.median(tws))
+        tc_sum += tc
+        tw_sum += tw
+        ti_sum += sw["t_infer"]
+        rec = {"C": C, "cold_s": tc, "warm_s": tw, "t_infer": sw["t_infer"], "kept": sw["kept"],
+               "rounds": sw["rounds"], "fallback": sw["fallback"], "newton_cold": ic["iters_inner"],
+               "newton_warm": iw["iters_inner"], "status": iw["status_name"]}
+        if k in (0, count // 2, count - 1):
+            rec["rkkt_oracle"] = ssnal.rkkt(X.astype(np.float64), y, C, xw.cpu().numpy())[0]
+        rows.append(rec)
+        log(f"[bench] C={C:.3g}: cold {tc:.3f} s, warm {tw:.3f} s, kept {sw['kept']}, rounds {sw['rounds']}")
+    out = {
+        "metric": METRIC,
+        "value": tw_sum / count,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": tw_sum / count * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"learned warm start: {count} held-out dense fp32 QPs n=200000 q=256, "
+                               "C log grid 1e-3..1e2", "count": count, "keep_frac": args.keep_frac},
+        "roofline": None,
+        "cpu_baseline": None,
+        "warmstart": {"speedup": tc_sum / tw_sum, "cold_s_per_qp": tc_sum / count,
+                      "warm_s_per_qp": tw_sum / count, "infer_s_per_qp": ti_sum / count,
+                      "per_qp": rows},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +309,7 @@ def main():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--count", type=int, default=256, help="batched workload: number of QPs")
     ap.add_argument("--no-seq", action="store_true", help="batched workload: skip the one-by-one solves")
+    ap.add_argument("--keep-frac", type=float, default=0.15, help="warm-start workload: rows kept")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -252,6 +325,9 @@ def main():
         raise SystemExit("bench.py needs the GPU")
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "warmstart":
+        run_warmstart(args)
         return
     _lib.load()
     log(f"[bench] generating workload {args.workload}")

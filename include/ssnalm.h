@@ -286,6 +286,104 @@ ssnalm_status ssnalm_batch_kernel_stats(int32_t which, ssnalm_kstat* out);
 ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* ctx, const double* x, double* rkkt,
                              double* b);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  The paper starts its exact-kernel solves from a
+ * cheaper approximate solution (Section 4, RBF experiments) and stresses
+ * the value of a good initial point (Remark 2); here a small network
+ * predicts x^0 for ssnalm_solve.  Nothing in the paper fixes the network, so
+ * its definition is this library's:
+ *   features  z_i = [x_i^T R (64), m_i, log10(n C)]  (66 floats, row-major),
+ *             R: q x 64 (caller's, float32, device);
+ *             p = Pi(C e) onto {y^T x = 0, 0 <= x <= C}; t* = clip(e^T p /
+ *             |A^T p|^2, 0, 1) (exact line search of the dual objective
+ *             along x = t p: one projected-gradient step from x = 0);
+ *             w1 = t* A^T p, s_i = x_i^T w1, b1 = -(mean of s over y = +1 +
+ *             mean of s over y = -1) / 2, m_i = y_i (s_i + b1).
+ *   network   A1 = Z W1 + b1, H1 = gelu(A1), A2 = H1 W2 + b2, H2 = gelu(A2),
+ *             O = H2 W3 + b3 (66 -> 256 -> 256 -> 4), gelu(a) = a Phi(a).
+ *   output    (P0, P1, P2, mult) = (softmax(O[0:3]), sigmoid(O[3])): the
+ *             probabilities of x_i* = 0, 0 < x_i* < C, x_i* = C, and x_i* / C.
+ *   loss      mean_i [-log P_{s_i}] + w_mse mean_i [s_i = 1] (mult_i - t_i)^2
+ *             with status s_i in {0, 1, 2} and target t_i = x_i* / C.
+ *   x0        by the most probable status (ties to the lower index):
+ *             x0_i = 0, C mult or C.
+ * Parameters live in one flat float32 vector: W1 (66 x 256, row-major), b1
+ * (256), W2 (256 x 256), b2 (256), W3 (256 x 4), b3 (4).  All pointers of
+ * the mlp_ calls are device pointers; every call is asynchronous on
+ * `stream` (hipStream_t or NULL).  Results are deterministic.
+ * ---------------------------------------------------------------------- */
+#define SSNALM_MLP_IN   66
+#define SSNALM_MLP_HID  256
+#define SSNALM_MLP_OUT  4
+#define SSNALM_MLP_NPROJ 64
+
+/* Number of parameters (floats) of the flat vector. */
+int64_t ssnalm_mlp_param_count(void);
+/* Floats of the forward workspace for n rows (activations kept for the
+ * backward pass) and of the backward scratch. */
+int64_t ssnalm_mlp_work_floats(int64_t n);
+int64_t ssnalm_mlp_scratch_floats(int64_t n);
+
+/* Forward pass: Z (n x 66) -> out (n x 4) = (P0, P1, P2, mult).  work:
+ * ssnalm_mlp_work_floats(n) floats.  E_BADARG: null pointer or n < 1 or
+ * n > 4194304. */
+ssnalm_status ssnalm_mlp_forward(const float* theta, const float* Z, int64_t n, float* out,
+                                 float* work, void* stream);
+
+/* Loss and gradient of the mean loss over the n rows of the last forward
+ * call on (theta, Z, work, out).  status: n int32 in {0, 1, 2}; target: n
+ * floats (read where status = 1); grad: param_count floats (overwritten);
+ * loss: 1 float; scratch: ssnalm_mlp_scratch_floats(n) floats. */
+ssnalm_status ssnalm_mlp_backward(const float* theta, const float* Z, int64_t n,
+                                  const float* work, const float* out, const int32_t* status,
+                                  const float* target, float w_mse, float* grad, float* loss,
+                                  float* scratch, void* stream);
+
+/* One Adam update (Kingma and Ba, bias-corrected) of count parameters at
+ * step >= 1; m and v are the moment vectors (zero before step 1). */
+ssnalm_status ssnalm_mlp_adam(float* theta, const float* grad, float* m, float* v, int64_t count,
+                              float lr, float beta1, float beta2, float eps, int32_t step,
+                              void* stream);
+
+/* Features z (n x 66 floats, device) of the context's problem (dense only)
+ * with projection R (q x 64 floats, device).  Runs on the context's stream
+ * and returns when done.  E_BADARG: null pointer, CSR problem. */
+ssnalm_status ssnalm_ws_features(ssnalm_ctx* ctx, const float* R, float* Z);
+
+/* What ssnalm_ws_solve did. */
+typedef struct {
+    int32_t rounds;           /* reduced solves run (0: went straight to the cold solve) */
+    int32_t kept;             /* rows of the last reduced problem                       */
+    int32_t fallback;         /* 1: the plain cold solve of the full problem was used   */
+    int32_t pad_;
+    double  rkkt_full;        /* R_KKT of the returned x on the full problem            */
+    double  t_reduced;        /* seconds spent in the reduced solves                   */
+} ssnalm_ws_stats;
+
+/*
+ * Solve the context's problem using the network's bound-status prediction
+ * (out: n x 4 floats, device, from ssnalm_mlp_forward on the features):
+ * the rows are ranked by P(x_i* = 0) and about keep_frac n of them, those
+ * least surely at 0, are kept (cut on a 4096-bin histogram of
+ * -log10(1 - P(x_i* = 0)) over [0, 8), ties in the cut bin kept); the kept
+ * rows are solved by ssnalm_solve at tol / 2, the result (zero on the left-out rows)
+ * is judged by R_KKT of the FULL problem (eq. Def_Rkkt); rows whose margin
+ * y_i (w^T x_i + b) is below 1 are added and the reduced solve repeated
+ * from the previous round's solution, at most max_rounds times; otherwise (or when more than half of the rows are
+ * kept) the plain cold solve of the full problem runs.  The returned x
+ * always satisfies R_KKT <= tol on the full problem when status is OK.
+ * x_out: n doubles (device); w_out: q doubles (device) or NULL; info,
+ * stats: host pointers or NULL.  Allocates the reduced copies per call.
+ * E_BADARG: null pointer, CSR problem, keep_frac outside (0, 1].
+ */
+ssnalm_status ssnalm_ws_solve(ssnalm_ctx* ctx, const float* out, double keep_frac,
+                              int32_t max_rounds, double* x_out, double* w_out,
+                              ssnalm_info* info, ssnalm_ws_stats* stats);
+
+/* x0 (n doubles, device) from the network output (n x 4 floats, device):
+ * 0, C mult or C by the most probable status, for ssnalm_solve(ctx, x0). */
+ssnalm_status ssnalm_ws_x0(ssnalm_ctx* ctx, const float* out, double* x0);
+
 #ifdef __cplusplus
 }
 #endif

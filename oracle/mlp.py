@@ -29,7 +29,8 @@ this project's, stated once and used by both implementations:
             mult = sigmoid(O[:, 3]).
   loss      L = mean_i[-log P_i,s_i] + w_mse * mean_i[ [s_i = inside] (mult_i - t_i)^2 ].
   labels    s_i = 0 if x_i <= 1e-8 C, 2 if x_i >= (1 - 1e-8) C, else 1; t_i = x_i / C.
-  x0        x0_i = C (P_i,2 + P_i,1 mult_i)  (then projected by the solver).
+  x0        the most probable status decides: x0_i = 0, C mult_i or C
+            (ties to the lower index); then projected by the solver.
   Adam      the update of Kingma & Ba (2015) with bias correction.
 
 Parameter vector layout (one flat array): W1 (66 x 256, row-major), b1 (256),
@@ -179,4 +180,5 @@ def labels(x, C, rel=1e-8):
 
 def x0_from_output(O, C):
     P, mult = head(np.asarray(O, np.float64))
-    return C * (P[:, 2] + P[:, 1] * mult)
+    k = np.argmax(P, axis=1)
+    return np.where(k == 0, 0.0, np.where(k == 1, C * mult, C))

@@ -37,6 +37,11 @@ class Options(C.Structure):
                 ("batch_graphs", C.c_int32), ("autotune", C.c_int32)]
 
 
+class WsStats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("kept", C.c_int32), ("fallback", C.c_int32),
+                ("pad_", C.c_int32), ("rkkt_full", C.c_double), ("t_reduced", C.c_double)]
+
+
 class Info(C.Structure):
     _fields_ = [("rkkt", C.c_double), ("obj", C.c_double), ("b", C.c_double),
                 ("sigma", C.c_double), ("time_s", C.c_double),
@@ -64,6 +69,9 @@ EXPORTS = [
     "ssnalm_destroy", "ssnalm_last_error", "ssnalm_op_amul", "ssnalm_op_atmul",
     "ssnalm_op_project", "ssnalm_op_newton", "ssnalm_op_linesearch_trial", "ssnalm_op_rkkt",
     "ssnalm_kernel_stats", "ssnalm_op_gram", "ssnalm_batch_kernel_stats",
+    "ssnalm_mlp_param_count", "ssnalm_mlp_work_floats", "ssnalm_mlp_scratch_floats",
+    "ssnalm_mlp_forward", "ssnalm_mlp_backward", "ssnalm_mlp_adam", "ssnalm_ws_features",
+    "ssnalm_ws_x0", "ssnalm_ws_solve",
 ]
 
 _lib = None
@@ -112,6 +120,24 @@ def load(path: str | None = None):
     lib.ssnalm_kernel_stats.restype = i32
     lib.ssnalm_batch_kernel_stats.argtypes = [i32, C.POINTER(KStat)]
     lib.ssnalm_batch_kernel_stats.restype = i32
+    for name in ("ssnalm_mlp_param_count", "ssnalm_mlp_work_floats", "ssnalm_mlp_scratch_floats"):
+        getattr(lib, name).restype = i64
+    lib.ssnalm_mlp_param_count.argtypes = []
+    lib.ssnalm_mlp_work_floats.argtypes = [i64]
+    lib.ssnalm_mlp_scratch_floats.argtypes = [i64]
+    lib.ssnalm_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.ssnalm_mlp_forward.restype = i32
+    lib.ssnalm_mlp_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, C.c_float, vp, vp, vp, vp]
+    lib.ssnalm_mlp_backward.restype = i32
+    lib.ssnalm_mlp_adam.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
+                                    C.c_float, i32, vp]
+    lib.ssnalm_mlp_adam.restype = i32
+    lib.ssnalm_ws_features.argtypes = [vp, vp, vp]
+    lib.ssnalm_ws_features.restype = i32
+    lib.ssnalm_ws_x0.argtypes = [vp, vp, vp]
+    lib.ssnalm_ws_x0.restype = i32
+    lib.ssnalm_ws_solve.argtypes = [vp, vp, dbl, i32, vp, vp, C.POINTER(Info), C.POINTER(WsStats)]
+    lib.ssnalm_ws_solve.restype = i32
     _lib = lib
     return lib
 

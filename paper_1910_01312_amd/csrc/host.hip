@@ -1012,3 +1012,199 @@ extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* 
     if (b) *b = bb;
     return SSNALM_OK;
 }
+
+// ---------------------------------------------------------------- warm start
+// Features of the learned warm start (definition in include/ssnalm.h):
+// p = Pi(C e), w1 = t* A^T p with the exact step t*, b1 from the class
+// means of x_i^T w1, margins m_i, and the projection X R.
+extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float* Z) {
+    if (!c || !R || !Z) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "warm-start features need dense X");
+    const int64_t n = c->n, q = c->q;
+    const double C = c->C;
+    launch_fill(c->nv, C, n, c->st);
+    STCHK(project_into(c, c->nv, nullptr, 0.0, nullptr, 3));
+    STCHK(sync_state(c));
+    bool more;
+    STCHK(project_finish(c, c->nv, 3, &more));
+    launch_proj_apply(c->nv, c->y, n, C, dps(c, 3), c->xt, nullptr, dsc(c), c->spart,
+                      cnt(c, CNT_APPLY), c->st);
+    op_atmul(c, c->xt, nullptr, nullptr, 1.0, c->qv, nullptr);              // A^T p
+    launch_dots(1, c->qv, c->qv, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                q, c->spart, cnt(c, CNT_DOTS), c->st);
+    launch_count_x(c->xt, n, C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);   // e^T p
+    STCHK(sync_state(c));
+    const double den = c->hs->sc.dd, sum = c->hs->sc.sumx;
+    const double t = den > 0.0 ? std::min(std::max(sum / den, 0.0), 1.0) : 0.0;
+    launch_scale_copy(c->qv2, c->qv, t, q, c->st);                            // w1
+    op_amul(c, c->qv2, c->aw);                                                // A w1
+    constexpr int nb = 256;
+    launch_class_sums(c->aw, c->y, n, c->spart, nb, c->st);
+    std::vector<double> cs(4 * nb);
+    HIPCHK(hipMemcpyAsync(cs.data(), c->spart, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    double sp = 0.0, cp = 0.0, sn = 0.0, cn = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        sp += cs[4 * b];
+        cp += cs[4 * b + 1];
+        sn += cs[4 * b + 2];
+        cn += cs[4 * b + 3];
+    }
+    const double b1 = (cp > 0.0 && cn > 0.0) ? -0.5 * (sp / cp + sn / cn) : -(sp + sn) / (cp + cn);
+    launch_ws_features(c->dtype, c->X, c->y, n, q, R, c->aw, b1, (float)std::log10((double)n * C), Z,
+                       c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_ws_x0(ssnalm_ctx* c, const float* out, double* x0) {
+    if (!c || !out || !x0) return fail(SSNALM_E_BADARG, "null argument");
+    launch_ws_x0(out, c->n, c->C, x0, c->st);
+    HIPCHK(hipGetLastError());
+    return SSNALM_OK;
+}
+
+// Screening solve from the network's status prediction (include/ssnalm.h).
+extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double keep_frac,
+                                         int32_t max_rounds, double* x_out, double* w_out,
+                                         ssnalm_info* info, ssnalm_ws_stats* stats) {
+    if (!c || !out || !x_out) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "screening needs dense X");
+    if (!(keep_frac > 0.0) || keep_frac > 1.0) return fail(SSNALM_E_BADARG, "keep_frac must be in (0, 1]");
+    const auto t_begin = std::chrono::steady_clock::now();
+    const int64_t n = c->n, q = c->q;
+    const size_t esz = c->dtype == SSNALM_F64 ? 8 : (c->dtype == SSNALM_F32 ? 4 : 2);
+    ssnalm_ws_stats st;
+    memset(&st, 0, sizeof st);
+    ssnalm_info agg;
+    memset(&agg, 0, sizeof agg);
+    // per-call buffers: keep mask, row list, reduced X / y / x / w
+    struct Bufs {
+        std::vector<void*> v;
+        ~Bufs() { for (void* p : v) hipFree(p); }
+    } bufs;
+    auto dal = [&](void** p, size_t bytes) -> ssnalm_status {
+        if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+            hipGetLastError();
+            return fail(SSNALM_E_OOM, "screening buffers: allocation of %zu bytes failed", bytes);
+        }
+        bufs.v.push_back(*p);
+        return SSNALM_OK;
+    };
+    uint8_t* keep = nullptr;
+    int32_t* list = nullptr;
+    void* Xk = nullptr;
+    int8_t* yk = nullptr;
+    double* xk = nullptr;
+    double* x0k = nullptr;
+    STCHK(dal((void**)&x0k, 8 * n));
+    STCHK(dal((void**)&keep, n));
+    STCHK(dal((void**)&list, 4 * n));
+    STCHK(dal(&Xk, esz * (size_t)n * q));
+    STCHK(dal((void**)&yk, n));
+    STCHK(dal((void**)&xk, 8 * n));
+    // rows ranked by P(x_i* = 0): keep the keep_frac n rows least surely at 0
+    // (cut at a histogram bin of -log10(1 - P0); ties in the cut bin are kept)
+    {
+        const int nb = p0_hist_bins();
+        unsigned* hist = nullptr;
+        STCHK(dal((void**)&hist, sizeof(unsigned) * nb));
+        launch_p0_hist(out, n, hist, c->st);
+        std::vector<unsigned> hh(nb);
+        HIPCHK(hipMemcpyAsync(hh.data(), hist, sizeof(unsigned) * nb, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        const double want = keep_frac * (double)n;
+        double acc = 0.0;
+        int cut = nb;
+        for (int b = 0; b < nb; ++b) {
+            acc += hh[b];
+            if (acc >= want) { cut = b + 1; break; }
+        }
+        launch_ws_keep_bin(out, n, cut, keep, c->st);
+    }
+    double t_red = 0.0;
+    bool done = false;
+    long long prev_m = -1;
+    for (int round = 0; round < max_rounds && !done; ++round) {
+        launch_compact(keep, n, list, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
+        STCHK(sync_state(c));
+        const long long m = c->hs->sc.p;
+        if (m == prev_m || m < 2 || 2 * m > n) break;        // nothing new, or not worth it
+        prev_m = m;
+        launch_gather_rows(c->dtype, c->X, c->y, list, m, q, Xk, yk, c->st);
+        HIPCHK(hipStreamSynchronize(c->st));
+        const auto t0 = std::chrono::steady_clock::now();
+        ssnalm_problem pk;
+        memset(&pk, 0, sizeof pk);
+        pk.kind = SSNALM_DENSE;
+        pk.dtype = c->dtype;
+        pk.n = m;
+        pk.q = q;
+        pk.X = Xk;
+        pk.y = yk;
+        pk.C = c->C;
+        pk.tol = 0.5 * c->tol;
+        ssnalm_options ok = c->opt;
+        ok.profile = 0;
+        ssnalm_ctx* sub = nullptr;
+        ssnalm_status s1 = ssnalm_create(&sub, &pk, &ok, c->st);
+        if (s1 < 0) return s1;
+        ssnalm_info ik;
+        // later rounds start from the previous round's solution (0 on the added rows)
+        if (round > 0) launch_gather_vec(x_out, list, m, x0k, c->st);
+        s1 = ssnalm_solve(sub, round > 0 ? x0k : nullptr, xk, c->qv2, &ik);
+        ssnalm_destroy(sub);
+        if (s1 < 0) return s1;
+        t_red += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        st.rounds = round + 1;
+        st.kept = (int32_t)m;
+        agg.iters_outer += ik.iters_outer;
+        agg.iters_inner += ik.iters_inner;
+        agg.proj_passes += ik.proj_passes;
+        agg.ls_trials += ik.ls_trials;
+        agg.ls_fail += ik.ls_fail;
+        // x on all rows, judged on the full problem; w = A_K^T x_K
+        launch_fill(x_out, 0.0, n, c->st);
+        launch_scatter(list, m, xk, x_out, c->st);
+        double R, b, sumx;
+        STCHK(kkt(c, x_out, c->qv2, &R, &b, &sumx));
+        if (s1 == SSNALM_OK && R <= c->tol) {
+            done = true;
+            st.rkkt_full = R;
+            agg.rkkt = R;
+            agg.b = b;
+            break;
+        }
+        // add the rows whose margin under (w, b) is below 1 (x_out keeps the
+        // reduced solution for the next round's start)
+        op_amul(c, c->qv2, c->aw);
+        launch_ws_violators(c->aw, c->y, n, b, keep, c->st);
+    }
+    st.t_reduced = t_red;
+    if (!done) {
+        st.fallback = 1;
+        const ssnalm_status s2 = ssnalm_solve(c, nullptr, x_out, w_out, info);
+        st.rkkt_full = info ? info->rkkt : NAN;
+        if (stats) *stats = st;
+        return s2;
+    }
+    // w, objective and counts of the returned x
+    op_atmul(c, x_out, nullptr, nullptr, 1.0, c->qv, nullptr);
+    launch_dots(1, c->qv, c->qv, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                q, c->spart, cnt(c, CNT_DOTS), c->st);
+    launch_count_x(x_out, n, c->C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);
+    if (w_out) HIPCHK(hipMemcpyAsync(w_out, c->qv, sizeof(double) * q, hipMemcpyDeviceToDevice, c->st));
+    STCHK(sync_state(c));
+    if (info) {
+        agg.obj = 0.5 * c->hs->sc.dd - c->hs->sc.sumx;
+        agg.sigma = NAN;
+        agg.p = (int32_t)c->hs->sc.p;
+        agg.n_sv = (int32_t)c->hs->sc.nsv;
+        agg.status = SSNALM_OK;
+        agg.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
+        *info = agg;
+    }
+    if (stats) *stats = st;
+    return SSNALM_OK;
+}

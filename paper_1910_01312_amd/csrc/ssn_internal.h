@@ -298,6 +298,33 @@ void lb_compact(const BLaunch& L, const uint8_t* mask, int32_t* list);
 void lb_newton(const BLaunch& L, const int32_t* list, const double* sv, const double* g, double* d,
                double* M);
 
+// Warm-start network (kernels_mlp.hip) -------------------------------------------
+constexpr int MLP_IN = 66, MLP_HID = 256, MLP_OUT = 4;
+int  mlp_splits(int64_t n);
+void launch_mlp_forward(const float* th, const float* Z, int64_t n, float* work, float* O,
+                        float* out, hipStream_t s);
+void launch_mlp_backward(const float* th, const float* Z, int64_t n, const float* work,
+                         const float* out, const int32_t* st, const float* tg, float w,
+                         float* grad, float* loss, float* scratch, hipStream_t s);
+void launch_adam(float* th, const float* g, float* m, float* v, int64_t count, float lr, float b1,
+                 float b2, float eps, int step, hipStream_t s);
+void launch_class_sums(const double* aw, const int8_t* y, int64_t n, double* part, int nb,
+                       hipStream_t s);
+void launch_ws_features(int dtype, const void* X, const int8_t* y, int64_t n, int64_t q,
+                        const float* R, const double* aw, double b1, float lognc, float* Z,
+                        hipStream_t s);
+void launch_ws_x0(const float* out, int64_t n, double C, double* x0, hipStream_t s);
+void launch_ws_keep(const float* out, int64_t n, float thr, uint8_t* keep, hipStream_t s);
+void launch_gather_rows(int dtype, const void* X, const int8_t* y, const int32_t* list, int64_t m,
+                        int64_t q, void* Xk, int8_t* yk, hipStream_t s);
+void launch_scatter(const int32_t* list, int64_t m, const double* xk, double* x, hipStream_t s);
+int  p0_hist_bins();
+void launch_p0_hist(const float* out, int64_t n, unsigned* hist, hipStream_t s);
+void launch_ws_keep_bin(const float* out, int64_t n, int cut, uint8_t* keep, hipStream_t s);
+void launch_gather_vec(const double* x, const int32_t* list, int64_t m, double* xk, hipStream_t s);
+void launch_ws_violators(const double* aw, const int8_t* y, int64_t n, double b, uint8_t* keep,
+                         hipStream_t s);
+
 // error reporting shared by the host files
 ssnalm_status set_error(ssnalm_status st, const char* fmt, ...);
 // NaN / Inf scan of `count` elements of X (device) on the host

@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_1910_01312_amd", "libssnalm.so")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ssnalm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ssnalm_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_boundary():
@@ -91,5 +91,6 @@ def test_struct_layouts_match_header():
         return out
 
     for cls, name in [(_lib.Problem, "ssnalm_problem"), (_lib.Options, "ssnalm_options"),
-                      (_lib.Info, "ssnalm_info"), (_lib.KStat, "ssnalm_kstat")]:
+                      (_lib.Info, "ssnalm_info"), (_lib.KStat, "ssnalm_kstat"),
+                      (_lib.WsStats, "ssnalm_ws_stats")]:
         assert [f for f, _ in cls._fields_] == fields(name), name

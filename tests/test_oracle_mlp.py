@@ -185,8 +185,9 @@ def test_features_layout():
 def test_labels_and_x0():
     s, t = mlp.labels(np.array([0.0, 1e-9, 0.5, 1.0 - 1e-9, 1.0]), 1.0)
     np.testing.assert_array_equal(s, [0, 0, 1, 2, 2])
-    # logits pinning the status: x0 = C * (P_C + P_inside * mult)
-    O = np.array([[50.0, 0.0, 0.0, 0.0],       # x = 0
-                  [0.0, 50.0, 0.0, 0.0],       # inside, mult = 1/2
-                  [0.0, 0.0, 50.0, 3.0]])      # x = C
-    np.testing.assert_allclose(mlp.x0_from_output(O, 2.0), [0.0, 1.0, 2.0], atol=1e-20)
+    # the most probable status decides: 0, C * mult or C
+    O = np.array([[0.3, 0.2, 0.1, 0.0],        # x = 0
+                  [0.0, 0.5, 0.4, 0.0],        # inside, mult = 1/2
+                  [0.0, 0.1, 0.2, 3.0],        # x = C
+                  [0.7, 0.7, 0.0, 1.0]])       # tie 0 / inside: the lower index
+    np.testing.assert_allclose(mlp.x0_from_output(O, 2.0), [0.0, 1.0, 2.0, 0.0], atol=1e-20)
