@@ -310,6 +310,9 @@ def main():
     ap.add_argument("--count", type=int, default=256, help="batched workload: number of QPs")
     ap.add_argument("--no-seq", action="store_true", help="batched workload: skip the one-by-one solves")
     ap.add_argument("--keep-frac", type=float, default=0.15, help="warm-start workload: rows kept")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device 3 times (a plain copy "
+                         "kernel of known size, to scale HBM counter readings)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -444,6 +447,15 @@ def main():
     }
     s.close()
     print(json.dumps(out), flush=True)
+    if args.calib_copy_mb:
+        nb = args.calib_copy_mb * (1 << 20)
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copies of {args.calib_copy_mb} MiB done")
 
 
 if __name__ == "__main__":
