@@ -97,7 +97,10 @@ typedef struct {
     int32_t max_cg;             /* PCG iteration cap per Newton step                      */
     int32_t verbose;            /* 1: one line per outer iteration on stderr              */
     int32_t check_finite;       /* 1: ssnalm_create scans X for NaN/Inf                   */
-    int32_t profile;            /* 1: time the hot kernels with HIP events on the stream  */
+    int32_t profile;            /* HIP-event timing of the hot kernel classes: 0 off, 1    */
+                                /* all classes, > 1 a mask with bit (k + 1) for class k    */
+                                /* (SSNALM_K_*).  Classes timed one by one are launched    */
+                                /* eagerly instead of from a captured graph                */
     int32_t batch_graphs;       /* batched solve: 1 replays captured HIP graphs of the    */
                                 /* Newton-direction and line-search-trial launches, 0     */
                                 /* issues the same launches one by one (same results)     */
@@ -134,7 +137,10 @@ void ssnalm_default_options(ssnalm_options* opt);
  *   out    : host pointer that receives the context.
  *   prob   : host pointer to the problem; its arrays are device pointers.
  *   opt    : host pointer or NULL for the defaults.
- *   stream : a hipStream_t, or NULL for the null stream.
+ *   stream : a hipStream_t, or NULL for the null stream.  The context works on
+ *            its own stream (default priority); every call is ordered after
+ *            the work already queued on `stream`, and work queued on `stream`
+ *            after a call returns is ordered after that call's work.
  * E_BADARG: n < 1, q < 1, C <= 0 or non-finite, tol <= 0, unknown kind or
  * dtype, CSR with BF16 values, row_ptr not monotone / not ending at nnz,
  * col_idx out of range, a label not in {+1,-1}.  E_NONFINITE: NaN/Inf in X
@@ -274,6 +280,9 @@ typedef struct {
  * clears all classes after reading. */
 ssnalm_status ssnalm_kernel_stats(ssnalm_ctx* ctx, int32_t which, ssnalm_kstat* out,
                                   int32_t reset);
+
+/* Change opt.profile of an existing context (same meaning). */
+ssnalm_status ssnalm_set_profile(ssnalm_ctx* ctx, int32_t profile);
 
 /* The same statistics for the last ssnalm_solve_batch call made on this
  * thread with opt.profile = 1 (launches timed outside the captured graphs:

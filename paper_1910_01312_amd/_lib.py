@@ -71,7 +71,7 @@ EXPORTS = [
     "ssnalm_kernel_stats", "ssnalm_op_gram", "ssnalm_batch_kernel_stats",
     "ssnalm_mlp_param_count", "ssnalm_mlp_work_floats", "ssnalm_mlp_scratch_floats",
     "ssnalm_mlp_forward", "ssnalm_mlp_backward", "ssnalm_mlp_adam", "ssnalm_ws_features",
-    "ssnalm_ws_x0", "ssnalm_ws_solve",
+    "ssnalm_ws_x0", "ssnalm_ws_solve", "ssnalm_set_profile",
 ]
 
 _lib = None
@@ -138,6 +138,8 @@ def load(path: str | None = None):
     lib.ssnalm_ws_x0.restype = i32
     lib.ssnalm_ws_solve.argtypes = [vp, vp, dbl, i32, vp, vp, C.POINTER(Info), C.POINTER(WsStats)]
     lib.ssnalm_ws_solve.restype = i32
+    lib.ssnalm_set_profile.argtypes = [vp, i32]
+    lib.ssnalm_set_profile.restype = i32
     _lib = lib
     return lib
 

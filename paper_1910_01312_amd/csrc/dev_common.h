@@ -153,3 +153,24 @@ template <typename T> struct VecLoad<T, 1> {
 __device__ __forceinline__ double clampd(double t, double lo, double hi) {
     return fmin(fmax(t, lo), hi);
 }
+
+// Appends `val` from every thread with `take` to list[base ...], in thread
+// order (deterministic), and returns how many the block appended.  Every
+// thread of the block must call it; wsum: SSN_WAVES_PER_BLOCK ints of LDS.
+__device__ __forceinline__ int block_append(bool take, double val, double* list, int base,
+                                            int* wsum) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    const unsigned long long m = __ballot(take);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) {
+        if (k < w) off += wsum[k];
+        tot += wsum[k];
+    }
+    if (take) list[base + off + before] = val;
+    return tot;
+}

@@ -82,7 +82,10 @@ struct ssnalm_ctx {
     const int8_t* y = nullptr;
     double C = 1.0, tol = 1e-6;
     ssnalm_options opt{};
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;        // the context's own stream (default priority)
+    hipStream_t ust = nullptr;       // the caller's stream: work is ordered after / before it
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t cg_graph = nullptr;   // CG batch of the current Newton step
     int device = 0;
     // sparse operator plans (forward on CSR rows, transpose on CSC columns)
     SegPlan fwd{}, tr{};
@@ -129,6 +132,24 @@ struct ssnalm_ctx {
     std::vector<Pending> pend;
     hipEvent_t ev_cur = nullptr;
     ssnalm_kstat kst[SSNALM_K_COUNT] = {};
+};
+
+// Orders the context's stream after the caller's stream on entry to an ABI
+// call and the caller's stream after the context's stream on exit.
+struct StreamScope {
+    ssnalm_ctx* c;
+    explicit StreamScope(ssnalm_ctx* c_) : c(c_) {
+        if (c->ev_in) {
+            (void)hipEventRecord(c->ev_in, c->ust);
+            (void)hipStreamWaitEvent(c->st, c->ev_in, 0);
+        }
+    }
+    ~StreamScope() {
+        if (c->ev_out) {
+            (void)hipEventRecord(c->ev_out, c->st);
+            (void)hipStreamWaitEvent(c->ust, c->ev_out, 0);
+        }
+    }
 };
 
 enum { CNT_PROJ_INIT = 0, CNT_PROJ_PASS, CNT_APPLY, CNT_LS, CNT_KKT, CNT_CMP, CNT_DOTS, CNT_DOTS2,
@@ -178,13 +199,18 @@ static void prof_harvest(ssnalm_ctx* c) {
     }
     c->pend.clear();
 }
-static void prof_begin(ssnalm_ctx* c) {
-    if (!c->opt.profile) return;
+// opt.profile: 1 times every class; a value > 1 is a mask, bit (k + 1) for class k.
+static bool prof_on(const ssnalm_ctx* c, int cls) {
+    const int p = c->opt.profile;
+    return p == 1 || (p > 1 && ((p >> (cls + 1)) & 1));
+}
+static void prof_begin(ssnalm_ctx* c, int cls) {
+    if (!prof_on(c, cls)) return;
     c->ev_cur = ev_get(c);
     if (c->ev_cur) hipEventRecord(c->ev_cur, c->st);
 }
 static void prof_end(ssnalm_ctx* c, int cls, double bytes, double flops) {
-    if (!c->opt.profile || !c->ev_cur) return;
+    if (!prof_on(c, cls) || !c->ev_cur) return;
     hipEvent_t b = ev_get(c);
     if (!b) return;
     hipEventRecord(b, c->st);
@@ -214,7 +240,7 @@ static unsigned* cnt(ssnalm_ctx* c, int k) { return c->counters + k; }
 // ---------------------------------------------------------------- operators
 // t = A v (rows restricted to out_mask when given: X_J v inside the Newton operator)
 static void op_amul(ssnalm_ctx* c, const double* v, double* t, const uint8_t* out_mask = nullptr) {
-    prof_begin(c);
+    prof_begin(c, out_mask ? SSNALM_K_AMUL_J : SSNALM_K_AMUL);
     if (c->kind == SSNALM_DENSE)
         launch_amul_dense(c->dtype, c->X, c->y, v, t, c->n, c->q, c->st);
     else
@@ -227,7 +253,7 @@ static void op_amul(ssnalm_ctx* c, const double* v, double* t, const uint8_t* ou
 // given, also s_out = X_J^T 1.
 static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const double* base,
                      double sign, double* r, double* s_out, int cls = SSNALM_K_ATMUL) {
-    prof_begin(c);
+    prof_begin(c, cls);
     if (c->kind == SSNALM_DENSE) {
         const int nb = atmul_dense_nblk(c->n);
         launch_atmul_dense(c->dtype, c->X, c->y, z, mask, c->n, c->q, c->part, c->part2, c->st);
@@ -260,7 +286,7 @@ static ssnalm_status project_into(ssnalm_ctx* c, const double* u, const double* 
                      cnt(c, CNT_PROJ_INIT), c->st, hint);
     const double* v = td ? vout : u;
     for (int i = 0; i < kPassBatch; ++i) {
-        prof_begin(c);
+        prof_begin(c, SSNALM_K_PROJ);
         launch_proj_pass(v, c->y, c->n, c->C, dps(c, k), c->spart, cnt(c, CNT_PROJ_PASS), c->st);
         prof_end(c, SSNALM_K_PROJ, 9.0 * c->n, 0.0);
     }
@@ -290,7 +316,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
     if (c->use_chol) {
         long long* pcount = &dsc(c)->p;
         launch_compact(mask, c->n, c->jlist, pcount, c->blk, cnt(c, CNT_CMP), c->st);
-        prof_begin(c);
+        prof_begin(c, SSNALM_K_SYRK);
         if (c->mixed)
             launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, c->G, c->mpart, c->mpart_cap, c->st);
         else
@@ -298,7 +324,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         prof_end(c, SSNALM_K_SYRK, (double)p * c->q * elem_bytes(c->dtype) + 4.0 * p + 8.0 * c->q * c->q,
                  (double)p * c->q * (c->q + 1));
         launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
-        prof_begin(c);
+        prof_begin(c, SSNALM_K_CHOL);
         if (!c->mixed && c->q <= chol_small_max()) {
             launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
         } else {
@@ -352,24 +378,57 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         STCHK(sync_state(c));
         const int nbw = (int)cg_rows_grid(p);
         const double vb = elem_bytes(c->dtype);
-        int it = 0, par = 0;
+        int it = 0;
+        // One CG iteration: X_J p, X_J^T w, the step and the direction (no host
+        // decision inside; the kernels stop changing x once the tolerance is met).
+        auto cg_iteration = [&](int par) {
+            prof_begin(c, SSNALM_K_AMUL_J);
+            launch_cg_rows(c->fwd, c->jlist, p, c->cg_p, c->wJ, Pw, c->st);
+            prof_end(c, SSNALM_K_AMUL_J, (double)nnzj * (vb + 4.0) + 20.0 * p + 8.0 * c->q,
+                     2.0 * (double)nnzj);
+            prof_begin(c, SSNALM_K_ATMUL_J);
+            launch_keyed_tr(0, c->jr, c->jc, c->jv, vf64, nnzj, c->wJ, c->kcarry, c->qv, c->q,
+                            c->st, false);
+            prof_end(c, SSNALM_K_ATMUL_J, (double)nnzj * (8.0 + vb) + 8.0 * p + 8.0 * c->q,
+                     2.0 * (double)nnzj);
+            launch_cg_step(c->cg_x, c->cg_r, c->cg_p, c->qv, c->sv, c->diag, c->cg_z, c->q,
+                           sigma, p, Pw, nbw, Pdir, Pst[par], Pst[1 - par], tol2, c->st);
+            launch_cg_dir(c->cg_p, c->cg_z, c->sv, c->q, Pst[par], Pst[1 - par], Pdir, tol2,
+                          dsc(c), c->qv, c->st);
+        };
+        // Batches of kCgBatch iterations between host checks; a full batch is
+        // captured once per Newton step into a HIP graph and replayed (unless its
+        // kernels are being timed one by one).
+        constexpr int kCgBatch = 8;
+        const bool use_graph = !prof_on(c, SSNALM_K_AMUL_J) && !prof_on(c, SSNALM_K_ATMUL_J);
+        bool captured = false;
         while (it < c->opt.max_cg && !c->hs->sc.cg_done) {
-            const int batch = std::min(8, c->opt.max_cg - it);
-            for (int b = 0; b < batch; ++b) {
-                prof_begin(c);
-                launch_cg_rows(c->fwd, c->jlist, p, c->cg_p, c->wJ, Pw, c->st);
-                prof_end(c, SSNALM_K_AMUL_J, (double)nnzj * (vb + 4.0) + 20.0 * p + 8.0 * c->q,
-                         2.0 * (double)nnzj);
-                prof_begin(c);
-                launch_keyed_tr(0, c->jr, c->jc, c->jv, vf64, nnzj, c->wJ, c->kcarry, c->qv, c->q,
-                                c->st, false);
-                prof_end(c, SSNALM_K_ATMUL_J, (double)nnzj * (8.0 + vb) + 8.0 * p + 8.0 * c->q,
-                         2.0 * (double)nnzj);
-                launch_cg_step(c->cg_x, c->cg_r, c->cg_p, c->qv, c->sv, c->diag, c->cg_z, c->q,
-                               sigma, p, Pw, nbw, Pdir, Pst[par], Pst[1 - par], tol2, c->st);
-                launch_cg_dir(c->cg_p, c->cg_z, c->sv, c->q, Pst[par], Pst[1 - par], Pdir, tol2,
-                              dsc(c), c->qv, c->st);
-                par = 1 - par;
+            const int batch = std::min(kCgBatch, c->opt.max_cg - it);
+            if (use_graph && batch == kCgBatch) {
+                if (!captured) {
+                    hipGraph_t gr = nullptr;
+                    HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed));
+                    for (int b = 0; b < kCgBatch; ++b) cg_iteration(b & 1);
+                    HIPCHK(hipStreamEndCapture(c->st, &gr));
+                    hipGraphExecUpdateResult ur;
+                    hipGraphNode_t en = nullptr;
+                    if (!c->cg_graph || hipGraphExecUpdate(c->cg_graph, gr, &en, &ur) != hipSuccess) {
+                        hipGetLastError();
+                        if (c->cg_graph) hipGraphExecDestroy(c->cg_graph);
+                        c->cg_graph = nullptr;
+                        const hipError_t e = hipGraphInstantiate(&c->cg_graph, gr, nullptr, nullptr, 0);
+                        if (e != hipSuccess) {
+                            hipGraphDestroy(gr);
+                            c->cg_graph = nullptr;
+                            return fail(SSNALM_E_HIP, "CG graph instantiation failed: %s", hipGetErrorString(e));
+                        }
+                    }
+                    hipGraphDestroy(gr);
+                    captured = true;
+                }
+                HIPCHK(hipGraphLaunch(c->cg_graph, c->st));
+            } else {
+                for (int b = 0; b < batch; ++b) cg_iteration(b & 1);
             }
             it += batch;
             STCHK(sync_state(c));
@@ -478,11 +537,15 @@ const char* ssnalm_last_error(void) { return g_err.c_str(); }
 
 void ssnalm_destroy(ssnalm_ctx* c) {
     if (!c) return;
-    if (c->st) hipStreamSynchronize(c->st);
+    if (c->st) (void)hipStreamSynchronize(c->st);
     for (auto& p : c->pend) { c->ev_free.push_back(p.a); c->ev_free.push_back(p.b); }
-    for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
-    for (void* p : c->owned) hipFree(p);
-    if (c->hs) hipHostFree(c->hs);
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    if (c->cg_graph) (void)hipGraphExecDestroy(c->cg_graph);
+    for (void* p : c->owned) (void)hipFree(p);
+    if (c->hs) (void)hipHostFree(c->hs);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->st) (void)hipStreamDestroy(c->st);
     delete c;
 }
 
@@ -653,8 +716,14 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
     c->y = pr->y;
     c->C = pr->C;
     c->tol = pr->tol;
-    c->st = (hipStream_t)stream;
+    c->ust = (hipStream_t)stream;
     auto bail = [&](ssnalm_status s) { ssnalm_destroy(c); return s; };
+    if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(SSNALM_E_HIP, "stream or event creation failed"));
+    (void)hipEventRecord(c->ev_in, c->ust);
+    (void)hipStreamWaitEvent(c->st, c->ev_in, 0);
     if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SSNALM_E_HIP, "no HIP device"));
     const int64_t n = c->n, q = c->q;
     // labels must be exactly +-1
@@ -739,6 +808,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
 extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x_out, double* w_out,
                                       ssnalm_info* info) {
     if (!c || !x_out) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     const auto t_begin = std::chrono::steady_clock::now();
     const ssnalm_options& o = c->opt;
     const int64_t n = c->n, q = c->q;
@@ -896,6 +966,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
 // ---------------------------------------------------------------- step ops
 extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* t) {
     if (!c || !v || !t) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     op_amul(c, v, t);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
@@ -904,6 +975,7 @@ extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* 
 
 extern "C" ssnalm_status ssnalm_op_atmul(ssnalm_ctx* c, const double* z, double* r) {
     if (!c || !z || !r) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     op_atmul(c, z, nullptr, nullptr, 1.0, r, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
@@ -914,6 +986,7 @@ extern "C" ssnalm_status ssnalm_op_project(ssnalm_ctx* c, const double* v, doubl
                                            uint8_t* free_mask, double* lam, int64_t* p,
                                            int32_t* passes) {
     if (!c || !v || !x) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     STCHK(project_into(c, v, nullptr, 0.0, nullptr, 3));
     STCHK(sync_state(c));
     bool more;
@@ -931,6 +1004,7 @@ extern "C" ssnalm_status ssnalm_op_project(ssnalm_ctx* c, const double* v, doubl
 extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mask, const double* g,
                                           double sigma, double cg_tol, double* d, int32_t* cg_iters) {
     if (!c || !free_mask || !g || !d) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     if (!(sigma > 0.0)) return fail(SSNALM_E_BADARG, "sigma must be > 0");
     // s = X_J^T 1 and p
     launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
@@ -954,6 +1028,7 @@ extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mas
 
 extern "C" ssnalm_status ssnalm_op_gram(ssnalm_ctx* c, const uint8_t* free_mask, double* G) {
     if (!c || !free_mask || !G) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE || !c->use_chol) return fail(SSNALM_E_BADARG, "Gram matrix needs a dense Cholesky context");
     launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
     STCHK(sync_state(c));
@@ -974,6 +1049,7 @@ extern "C" ssnalm_status ssnalm_op_linesearch_trial(ssnalm_ctx* c, const double*
                                                     double lam, double alpha, double sigma,
                                                     double* lam_a, double* dh) {
     if (!c || !u || !t) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     // base state: the given lam
     c->hs->ps[0] = ProjState{};
     c->hs->ps[0].lam = lam;
@@ -1002,8 +1078,15 @@ extern "C" ssnalm_status ssnalm_kernel_stats(ssnalm_ctx* c, int32_t which, ssnal
     return SSNALM_OK;
 }
 
+extern "C" ssnalm_status ssnalm_set_profile(ssnalm_ctx* c, int32_t profile) {
+    if (!c) return fail(SSNALM_E_BADARG, "null argument");
+    c->opt.profile = profile;
+    return SSNALM_OK;
+}
+
 extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* rkkt, double* b) {
     if (!c || !x) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     op_atmul(c, x, nullptr, nullptr, 1.0, c->qv, nullptr);
     double R, bb;
     STCHK(kkt(c, x, c->qv, &R, &bb, nullptr));
@@ -1019,6 +1102,7 @@ extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* 
 // means of x_i^T w1, margins m_i, and the projection X R.
 extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float* Z) {
     if (!c || !R || !Z) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "warm-start features need dense X");
     const int64_t n = c->n, q = c->q;
     const double C = c->C;
@@ -1060,6 +1144,7 @@ extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float
 
 extern "C" ssnalm_status ssnalm_ws_x0(ssnalm_ctx* c, const float* out, double* x0) {
     if (!c || !out || !x0) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     launch_ws_x0(out, c->n, c->C, x0, c->st);
     HIPCHK(hipGetLastError());
     return SSNALM_OK;
@@ -1070,6 +1155,7 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
                                          int32_t max_rounds, double* x_out, double* w_out,
                                          ssnalm_info* info, ssnalm_ws_stats* stats) {
     if (!c || !out || !x_out) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "screening needs dense X");
     if (!(keep_frac > 0.0) || keep_frac > 1.0) return fail(SSNALM_E_BADARG, "keep_frac must be in (0, 1]");
     const auto t_begin = std::chrono::steady_clock::now();

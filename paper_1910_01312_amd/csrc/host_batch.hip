@@ -85,6 +85,7 @@ struct Batch {
     int32_t* list = nullptr;
     double *om = nullptr, *g = nullptr, *sv = nullptr, *d = nullptr, *qv = nullptr, *M = nullptr;
     hipGraphExec_t gx_newton = nullptr, gx_trial = nullptr;
+    std::vector<char> built;       // active set of the current work list (empty: none)
     // HIP-event timing of the full-pass A v launches (profile = 1)
     bool prof = false;
     struct Pend { hipEvent_t a, b; double bytes; };
@@ -135,10 +136,13 @@ ssnalm_status upload(Batch& B, const std::vector<HP>& hp, const std::vector<char
     return SSNALM_OK;
 }
 
-// Upload, then rebuild the work list for that active set.
+// Upload, then rebuild the work list when the active set changed.
 ssnalm_status activate(Batch& B, const std::vector<HP>& hp, const std::vector<char>& act) {
     BST(upload(B, hp, act));
-    lb_build_wl(B.L, B.items);
+    if (B.built != act) {
+        lb_build_wl(B.L, B.items);
+        B.built = act;
+    }
     return SSNALM_OK;
 }
 
@@ -193,7 +197,6 @@ void timed_amul(Batch& B, const std::vector<char>& act, const double* V, double*
 // Newton direction for the active problems: J compaction, Gram, M,
 // Cholesky solve, t = A d and g^T d, omega^T d, d^T d.
 void seq_newton(Batch& B) {
-    lb_build_wl(B.L, B.items);
     lb_compact(B.L, B.jm, B.list);
     lb_newton(B.L, B.list, B.sv, B.g, B.d, B.M);
     lb_amul(B.L, B.d, B.td);
@@ -204,7 +207,6 @@ void seq_newton(Batch& B) {
 // u - alpha sigma t (first pass placed around the accepted multiplier), then
 // the increments of psi and |x - x^k|.
 void seq_trial(Batch& B) {
-    lb_build_wl(B.L, B.items);
     lb_proj_init(B.L, B.u, B.td, B.ut, 1, 1);
     lb_proj_passes(B.L, B.ut, 1, kPassBatch);
     lb_ls_fin(B.L, B.ut, B.u, B.td, 1, 0, B.xk, B.xtt, B.jmt);
@@ -370,7 +372,7 @@ ssnalm_status setup(Batch& B, int32_t count, const ssnalm_problem* probs, const 
     BLaunch& L = B.L;
     BA(L.A.wl, ni); BA(L.A.wl_n, 1); BA(L.A.ioff, np); BA(L.A.icnt, np);
     BA(L.part, ni * std::max<int64_t>(q, 65)); BA(L.part2, ni * q);
-    BA(L.ipart, ni * 64); BA(L.ipart2, ni);
+    BA(L.ipart, ni * 65); BA(L.ipart2, ni);
     BA(L.gwl, gcap); BA(L.gwl_n, 1); BA(L.goff, np); BA(L.gcnt, np);
     BA(L.gpart, (int64_t)gcap * q * q);
 #undef BA
@@ -504,12 +506,12 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
                 hp[k].inner += 1;
                 hp[k].inner_total += 1;
             }
-            BST(upload(B, hp, flags(S2)));
+            BST(activate(B, hp, flags(S2)));
             BST(run_seq(B, &B.gx_newton, seq_newton, graphs));
             // Armijo line search on psi, all problems in step
             std::vector<int> Lset = S2, accepted;
             for (int m = 0; !Lset.empty(); ++m) {
-                if (m > 0) BST(upload(B, hp, flags(Lset)));
+                if (m > 0) BST(activate(B, hp, flags(Lset)));
                 BST(run_seq(B, &B.gx_trial, seq_trial, graphs));
                 BST(readback(B));
                 BST(finish_open(B, hp, Lset, 1, B.ut, [&] {

@@ -78,6 +78,31 @@ __device__ __forceinline__ void bload(const T* __restrict__ xr, int q, int j, do
     }
 }
 
+// sum_{i < n} p[i * stride] with 8 independent accumulators (loads in
+// flight) combined in a fixed order: deterministic.
+__device__ __forceinline__ double sum_items(const double* __restrict__ p, int64_t stride, int n) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = 0;
+    for (; i + 8 <= n; i += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += p[(int64_t)(i + u) * stride];
+    }
+    for (int u = 0; i < n; ++i, ++u) a[u] += p[(int64_t)i * stride];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+__device__ __forceinline__ int isum_items(const int* __restrict__ p, int64_t stride, int n) {
+    int a = 0, b = 0, c = 0, d = 0;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+        a += p[(int64_t)i * stride];
+        b += p[(int64_t)(i + 1) * stride];
+        c += p[(int64_t)(i + 2) * stride];
+        d += p[(int64_t)(i + 3) * stride];
+    }
+    for (; i < n; ++i) a += p[(int64_t)i * stride];
+    return a + b + c + d;
+}
+
 // Sum over the 16 lanes of a row group (xor offsets stay inside the group).
 __device__ __forceinline__ double group_sum(double v) {
     v += __shfl_xor(v, 8);
@@ -88,9 +113,9 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 
 // ------------------------------------------------------------------ work list
-// One block.  wl = items of the active problems in problem order; ioff/icnt
-// per problem (icnt = 0 for inactive ones); *wl_n = length.
-__global__ __launch_bounds__(1024) void kb_build_wl(BArgs A, const int4* __restrict__ items) {
+// One block: ioff / icnt per problem (icnt = 0 for inactive ones) in problem
+// order and *wl_n = the length of the work list.
+__global__ __launch_bounds__(1024) void kb_wl_scan(BArgs A) {
     __shared__ int sc[1024];
     __shared__ int base;
     if (threadIdx.x == 0) base = 0;
@@ -106,25 +131,23 @@ __global__ __launch_bounds__(1024) void kb_build_wl(BArgs A, const int4* __restr
             sc[threadIdx.x] += t;
             __syncthreads();
         }
-        const int o = base + sc[threadIdx.x] - c;
         if (k < A.nprob) {
-            A.ioff[k] = o;
+            A.ioff[k] = base + sc[threadIdx.x] - c;
             A.icnt[k] = c;
-        }
-        __syncthreads();
-        // copy the items of this chunk's problems, one problem at a time
-        const int kend = min(A.nprob, k0 + 1024);
-        for (int kk = k0; kk < kend; ++kk) {
-            const int ck = A.icnt[kk];
-            if (ck == 0) continue;                      // uniform: same value in all threads
-            const int ok = A.ioff[kk], i0 = A.prob[kk].item0;
-            for (int i = threadIdx.x; i < ck; i += blockDim.x) A.wl[ok + i] = items[i0 + i];
         }
         __syncthreads();
         if (threadIdx.x == 0) base += sc[1023];
         __syncthreads();
     }
     if (threadIdx.x == 0) *A.wl_n = base;
+}
+// One block per problem: copy its items into the work list.
+__global__ __launch_bounds__(256) void kb_wl_copy(BArgs A, const int4* __restrict__ items) {
+    const int k = blockIdx.x;
+    const int ck = A.icnt[k];
+    if (ck == 0) return;
+    const int ok = A.ioff[k], i0 = A.prob[k].item0;
+    for (int i = threadIdx.x; i < ck; i += blockDim.x) A.wl[ok + i] = items[i0 + i];
 }
 
 // ------------------------------------------------------------------ A v
@@ -233,11 +256,8 @@ __global__ __launch_bounds__(128) void kb_atmul_fin(BArgs A, const double* __res
     if (!A.par[k].active) return;
     const int q = A.q, i0 = A.ioff[k], ni = A.icnt[k];
     for (int c = threadIdx.x; c < q; c += blockDim.x) {
-        double s = 0.0, sm = 0.0;
-        for (int i = 0; i < ni; ++i) {
-            s += part[(int64_t)(i0 + i) * q + c];
-            if (part2) sm += part2[(int64_t)(i0 + i) * q + c];
-        }
+        const double s = sum_items(part + (int64_t)i0 * q + c, q, ni);
+        const double sm = part2 ? sum_items(part2 + (int64_t)i0 * q + c, q, ni) : 0.0;
         const int64_t o = (int64_t)k * q + c;
         out[o] = (base ? base[o] : 0.0) + sign * s;
         if (out2) out2[o] = sm;
@@ -393,13 +413,13 @@ __global__ void kb_proj_init_fin(BArgs A, const double* __restrict__ part, int w
     if (k >= A.nprob || !A.par[k].active) return;
     const BProb Pr = A.prob[k];
     const int i0 = A.ioff[k], ni = A.icnt[k];
-    double mn = 1.0 / 0.0, mx = -1.0 / 0.0, cnt = 0.0;
-    for (int i = 0; i < ni; ++i) {
+    double mn = 1.0 / 0.0, mx = -1.0 / 0.0;
+    for (int i = 0; i < ni; ++i) {                     // min / max: order-free
         const int64_t o = (int64_t)(i0 + i) * 3;
         mn = fmin(mn, part[o]);
         mx = fmax(mx, part[o + 1]);
-        cnt += part[o + 2];
     }
+    const double cnt = sum_items(part + (int64_t)i0 * 3 + 2, 3, ni);
     ProjState P;
     P.lo = mn;
     P.hi = mx + 2.0 * Pr.C;
@@ -439,13 +459,19 @@ __device__ __forceinline__ double bcand(const ProjState& P, double C, int c) {
 }
 
 // one multisection pass: per item, g at the BPK+1 candidates and the
-// histogram of breakpoints strictly inside every sub-interval
+// histogram of breakpoints strictly inside every sub-interval.  Elements
+// whose breakpoints b, b + C both lie outside the bracket contribute a
+// constant (C or 0) or exactly (lam - lo) + (lo - b) over the whole bracket
+// and are summed in closed form; the others are gathered (thread order) into
+// an LDS list and evaluated at every candidate by the whole block.
 __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double* __restrict__ v,
                                                           int w, double* __restrict__ part,
                                                           int* __restrict__ hpart) {
     __shared__ double lam_s[BPK + 1];
     __shared__ double red[SSN_WAVES_PER_BLOCK][BPNV];
     __shared__ int hist[BPK];
+    __shared__ double list[BRPI];
+    __shared__ int wsum[SSN_WAVES_PER_BLOCK];
     const int nw = *A.wl_n;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < nw; it += gridDim.x) {
@@ -459,21 +485,40 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double*
         if (threadIdx.x <= BPK) lam_s[threadIdx.x] = bcand(P, C, threadIdx.x);
         if (threadIdx.x < BPK) hist[threadIdx.x] = 0;
         __syncthreads();
+        const double blo = lam_s[0], bhi = lam_s[BPK];
+        long long kc = 0;                  // C times this count: exact constant part
+        double lin_n = 0.0, lin_s = 0.0;
+        int cnt = 0;
+        for (int base = item.y; base < item.z; base += blockDim.x) {
+            const int r = base + threadIdx.x;
+            bool take = false;
+            double b = 0.0;
+            if (r < item.z) {
+                const double vi = v[Pr.off + r];
+                const bool pos = Pr.y[r] > 0;
+                b = pos ? vi - C : -vi;
+                const double bh = b + C;
+                kc -= pos ? 1 : 0;
+                if (bh <= blo) kc += 1;
+                else if (b >= bhi) {}
+                else if (b <= blo && bh >= bhi) { lin_n += 1.0; lin_s += blo - b; }
+                else take = true;
+            }
+            cnt += block_append(take, b, list, cnt, wsum);
+        }
+        __syncthreads();
         double acc[BPK + 1];
 #pragma unroll
         for (int c = 0; c <= BPK; ++c) acc[c] = 0.0;
-        for (int r = item.y + threadIdx.x; r < item.z; r += blockDim.x) {
-            const double vi = v[Pr.off + r];
-            const bool pos = Pr.y[r] > 0;
-            const double b = pos ? vi - C : -vi;
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const double b = list[e];
             const double bh = b + C;
-            const double cp = pos ? C : 0.0;
 #pragma unroll
-            for (int c = 0; c <= BPK; ++c) acc[c] += clampd(lam_s[c] - b, 0.0, C) - cp;
+            for (int c = 0; c <= BPK; ++c) acc[c] += clampd(lam_s[c] - b, 0.0, C);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const double t = h ? bh : b;
-                if (t > lam_s[0] && t < lam_s[BPK]) {
+                if (t > blo && t < bhi) {
                     int lo_k = 0, hi_k = BPK;
                     while (hi_k - lo_k > 1) {
                         const int mid = (lo_k + hi_k) >> 1;
@@ -483,9 +528,11 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double*
                 }
             }
         }
+        __shared__ long long shk[SSN_WAVES_PER_BLOCK];
+        const long long kblk = block_sum_ll(kc, shk);
 #pragma unroll
         for (int c = 0; c <= BPK; ++c) {
-            const double s = wave_sum(acc[c]);
+            const double s = wave_sum(acc[c] + lin_n * (lam_s[c] - blo) + lin_s);
             if (lane == 0) red[wv][c] = s;
         }
         __syncthreads();
@@ -495,7 +542,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double*
             for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) s += red[ww][threadIdx.x];
             part[(int64_t)it * BPNV + threadIdx.x] = s;
         }
-        if (threadIdx.x < BPK) hpart[(int64_t)it * BPK + threadIdx.x] = hist[threadIdx.x];
+        if (threadIdx.x < BPK) hpart[(int64_t)it * (BPK + 1) + threadIdx.x] = hist[threadIdx.x];
+        if (threadIdx.x == 0) hpart[(int64_t)it * (BPK + 1) + BPK] = (int)kblk;
     }
 }
 
@@ -512,16 +560,15 @@ __global__ __launch_bounds__(128) void kb_proj_sel(BArgs A, const double* __rest
     if (P.done) return;
     const double C = A.prob[k].C;
     const int i0 = A.ioff[k], ni = A.icnt[k];
-    for (int c = threadIdx.x; c < BPNV; c += blockDim.x) {
-        double s = 0.0;
-        for (int i = 0; i < ni; ++i) s += part[(int64_t)(i0 + i) * BPNV + c];
-        G[c] = s;
+    __shared__ int K;
+    for (int c = threadIdx.x; c <= BPK; c += blockDim.x) {
+        const int h = isum_items(hpart + (int64_t)i0 * (BPK + 1) + c, BPK + 1, ni);
+        if (c < BPK) H[c] = h;
+        else K = h;
     }
-    for (int c = threadIdx.x; c < BPK; c += blockDim.x) {
-        int h = 0;
-        for (int i = 0; i < ni; ++i) h += hpart[(int64_t)(i0 + i) * BPK + c];
-        H[c] = h;
-    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < BPNV; c += blockDim.x)
+        G[c] = sum_items(part + (int64_t)i0 * BPNV + c, BPNV, ni) + C * (double)K;
     __syncthreads();
     if (threadIdx.x != 0) return;
     const int passes = P.passes + 1;
@@ -673,11 +720,7 @@ __global__ void kb_sum4(BArgs A, const double* __restrict__ part, int f0, int nf
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.nprob || !A.par[k].active) return;
     const int i0 = A.ioff[k], ni = A.icnt[k];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = 0; i < ni; ++i)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) s[t] += part[(int64_t)(i0 + i) * 4 + t];
-    for (int t = 0; t < nf; ++t) A.bs[k].r[f0 + t] = s[t];
+    for (int t = 0; t < nf; ++t) A.bs[k].r[f0 + t] = sum_items(part + (int64_t)i0 * 4 + t, 4, ni);
 }
 
 // ------------------------------------------------------------------ compaction of J
@@ -846,8 +889,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_gram_fin(BArgs A, const double* 
     const long long p = A.bs[k].p;
     const double sigma = A.par[k].sigma, ip = p > 0 ? 1.0 / (double)p : 0.0;
     for (int e = threadIdx.x; e < q * q; e += blockDim.x) {
-        double g = 0.0;
-        for (int i = 0; i < ni; ++i) g += gpart[(int64_t)(i0 + i) * q * q + e];
+        const double g = sum_items(gpart + (int64_t)i0 * q * q + e, (int64_t)q * q, ni);
         const int r = e / q, c = e % q;
         const double sr = sv[(int64_t)k * q + r], scl = sv[(int64_t)k * q + c];
         M[(int64_t)k * q * q + e] = (r == c ? 1.0 : 0.0) + sigma * (g - sr * scl * ip);
@@ -947,7 +989,8 @@ static void atmul_t(const BLaunch& L, const double* z, const uint8_t* mask) {
 static inline unsigned pgrid(int n) { return (unsigned)((n + 63) / 64); }
 
 void lb_build_wl(const BLaunch& L, const int4* items) {
-    hipLaunchKernelGGL(kb_build_wl, dim3(1), dim3(1024), 0, L.s, L.A, items);
+    hipLaunchKernelGGL(kb_wl_scan, dim3(1), dim3(1024), 0, L.s, L.A);
+    hipLaunchKernelGGL(kb_wl_copy, dim3(L.A.nprob), dim3(256), 0, L.s, L.A, items);
 }
 void lb_amul(const BLaunch& L, const double* V, double* t) { BDISPATCH(amul_t, L, V, t); }
 void lb_atmul(const BLaunch& L, const double* z, const uint8_t* mask, const double* base,

@@ -28,6 +28,7 @@ constexpr int PK = 64;            // sub-intervals per pass
 constexpr int PNV = PK + 1;       // partial values per block: PK+1 g-values
 constexpr int PROJ_MAXPASS = 48;
 constexpr int PROJ_GRID_MAX = 256;
+constexpr int PASS_CAP = 2048;    // LDS list of elements evaluated at every candidate
 
 int proj_max_passes() { return PROJ_MAXPASS; }
 
@@ -165,6 +166,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
     __shared__ double fin[PNV];
     __shared__ int hist[PK];
     __shared__ int hfin[PK];
+    __shared__ long long kfin;
+    __shared__ double list[PASS_CAP];
+    __shared__ int wsum[SSN_WAVES_PER_BLOCK];
     if (ld_acquire(&st->done)) return;         // uniform over the grid
     const double lo = st->lo, hi = st->hi;
     const bool geo = st->mode == 1;
@@ -174,32 +178,74 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
                                  : cand_uniform(lo, hi, threadIdx.x);
     if (threadIdx.x < PK) hist[threadIdx.x] = 0;
     __syncthreads();
+    // Each element adds clip(lam - b, 0, C) - C [y > 0] to g(lam).  With both
+    // breakpoints b, b + C outside (lam_s[0], lam_s[PK]) that term is, over
+    // the whole bracket, the constant C (b + C <= lo), 0 (b >= hi) or
+    // exactly (lam - lo) + (lo - b) (b <= lo, b + C >= hi): summed in closed
+    // form.  Only elements with a breakpoint strictly inside the bracket are
+    // evaluated at every candidate; they are gathered (thread order) into an
+    // LDS list so that whole blocks work on them together.
+    const double blo = lam_s[0], bhi = lam_s[PK];
     double acc[PK + 1];
 #pragma unroll
     for (int k = 0; k <= PK; ++k) acc[k] = 0.0;
+    // the constant part is C times an integer count, kept exact so that g is
+    // exactly 0 on a flat stretch (no component strictly inside the box)
+    long long kc = 0;
+    double lin_n = 0.0, lin_s = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double vi = v[i];
-        const bool pos = y[i] > 0;
-        const double b = pos ? vi - C : -vi;
-        const double bh = b + C;
-        const double cp = pos ? C : 0.0;
-#pragma unroll
-        for (int k = 0; k <= PK; ++k) acc[k] += clampd(lam_s[k] - b, 0.0, C) - cp;
-        // histogram of breakpoints strictly inside each sub-interval
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const double t = h ? bh : b;
-            if (t > lam_s[0] && t < lam_s[PK]) {
-                int lo_k = 0, hi_k = PK;           // lam_s[lo_k] < t < lam_s[hi_k]
-                while (hi_k - lo_k > 1) {
-                    const int mid = (lo_k + hi_k) >> 1;
-                    if (lam_s[mid] < t) lo_k = mid; else hi_k = mid;
-                }
-                if (t < lam_s[lo_k + 1]) atomicAdd(&hist[lo_k], 1);
+    int64_t base = (int64_t)blockIdx.x * blockDim.x;
+    int cnt = 0;
+    for (;;) {
+        const bool more = base < n;                    // uniform over the block
+        if (more) {
+            const int64_t i = base + threadIdx.x;
+            bool take = false;
+            double b = 0.0;
+            if (i < n) {
+                const double vi = v[i];
+                const bool pos = y[i] > 0;
+                b = pos ? vi - C : -vi;
+                const double bh = b + C;
+                kc -= pos ? 1 : 0;
+                if (bh <= blo) kc += 1;
+                else if (b >= bhi) {}
+                else if (b <= blo && bh >= bhi) { lin_n += 1.0; lin_s += blo - b; }
+                else take = true;
             }
+            cnt += block_append(take, b, list, cnt, wsum);
+            base += stride;
+        }
+        if (!more || cnt > PASS_CAP - (int)blockDim.x) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+                const double b = list[e];
+                const double bh = b + C;
+#pragma unroll
+                for (int k = 0; k <= PK; ++k) acc[k] += clampd(lam_s[k] - b, 0.0, C);
+                // histogram of breakpoints strictly inside each sub-interval
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double t = h ? bh : b;
+                    if (t > blo && t < bhi) {
+                        int lo_k = 0, hi_k = PK;           // lam_s[lo_k] < t < lam_s[hi_k]
+                        while (hi_k - lo_k > 1) {
+                            const int mid = (lo_k + hi_k) >> 1;
+                            if (lam_s[mid] < t) lo_k = mid; else hi_k = mid;
+                        }
+                        if (t < lam_s[lo_k + 1]) atomicAdd(&hist[lo_k], 1);
+                    }
+                }
+            }
+            __syncthreads();
+            cnt = 0;
+            if (!more) break;
         }
     }
+#pragma unroll
+    for (int k = 0; k <= PK; ++k) acc[k] += lin_n * (lam_s[k] - blo) + lin_s;
+    __shared__ long long shk[SSN_WAVES_PER_BLOCK];
+    const long long kblk = block_sum_ll(kc, shk);
     const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
 #pragma unroll
     for (int k = 0; k <= PK; ++k) {
@@ -215,6 +261,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
         part[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = s;   // [column][block]
     }
     if (threadIdx.x < PK) hpart[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = hist[threadIdx.x];
+    if (threadIdx.x == 0) hpart[(int64_t)PK * PROJ_GRID_MAX + blockIdx.x] = (int)kblk;
     if (!last_block_arrives(counter)) return;
     // ---- last block: fixed-order reduction over blocks, then the decision.
     // Column c is summed by wave c mod 4: lane l owns blocks l, l+64, l+128,
@@ -241,14 +288,35 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
             sum = wave_sum(sum);
             if (lane == 0 && c < PNV) fin[c] = sum;
         }
-        // histogram: integer sums (exact in any order)
-        for (int c = w; c < PK; c += SSN_WAVES_PER_BLOCK) {
-            long long hsum = 0;
-            for (int bb = lane; bb < nb; bb += SSN_WAVE) hsum += ld_acquire(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]);
-            hsum = wave_sum_ll(hsum);
-            if (lane == 0) hfin[c] = (int)hsum;
+        // histogram and the constant count: integer sums (exact in any order),
+        // again with every load of the wave issued before any sum
+        {
+            int hv[CPW][BPL];
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+                const int c = w + i * SSN_WAVES_PER_BLOCK;
+#pragma unroll
+                for (int j = 0; j < BPL; ++j) {
+                    const int bb = lane + j * SSN_WAVE;
+                    hv[i][j] = (c <= PK && bb < nb) ? ld_acquire(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]) : 0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+                const int c = w + i * SSN_WAVES_PER_BLOCK;
+                long long hsum = 0;
+#pragma unroll
+                for (int j = 0; j < BPL; ++j) hsum += hv[i][j];
+                hsum = wave_sum_ll(hsum);
+                if (lane == 0 && c <= PK) {
+                    if (c < PK) hfin[c] = (int)hsum;
+                    else kfin = hsum;
+                }
+            }
         }
     }
+    __syncthreads();
+    if (threadIdx.x <= PK) fin[threadIdx.x] += C * (double)kfin;
     __syncthreads();
     if (threadIdx.x == 0) {
         const int passes = st->passes + 1;

@@ -19,6 +19,15 @@ namespace ssn {
 constexpr int SEG_E = 8;                       // entries per lane
 constexpr int SEG_TILE = SEG_E * SSN_WAVE;     // entries per wave tile
 
+// ends[j] for a run-time j < SEG_E without indexing a register array (which
+// would place it in scratch memory)
+__device__ __forceinline__ int32_t pick8(const int32_t (&a)[8], int j) {
+    int32_t r = a[0];
+#pragma unroll
+    for (int m = 1; m < 8; ++m) r = (j == m) ? a[m] : r;
+    return r;
+}
+
 template <typename V>
 __device__ __forceinline__ double segval(const V* val, int64_t k, bool sq) {
     const double a = (double)val[k];
@@ -95,7 +104,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
         F = seg0;
         double cur = 0.0;
         bool have_head = false;
-        for (int e = 0; e < ne; ++e) {
+#pragma unroll
+        for (int e = 0; e < SEG_E; ++e) {
+            if (e >= ne) break;
             const int64_t k = k0 + e;
             while (k >= segend) {                 // close segment seg0 + j
                 const int32_t sg = seg0 + j;
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
                     out[sg] = omask ? 0.0 : (yout ? (double)yout[sg] : 1.0) * cur;
                 }
                 ++j;
-                segend = j < SEG_E ? ends[j] : ptr[seg0 + 1 + j];
+                segend = j < SEG_E ? pick8(ends, j) : ptr[seg0 + 1 + j];
                 cur = 0.0;
             }
             cur += cfv[e];

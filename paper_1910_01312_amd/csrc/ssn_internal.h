@@ -221,7 +221,7 @@ void launch_mop_finish(const double* pd, const double* z, double sigma, const do
                        hipStream_t s);
 
 // Batched solve (kernels_batch.hip) ------------------------------------------------
-constexpr int BRPI = 1024;     // rows per work item
+constexpr int BRPI = 4096;     // rows per work item
 constexpr int BQMAX = 128;     // largest q of a batched solve
 int batch_rows_per_item();
 int batch_qmax();

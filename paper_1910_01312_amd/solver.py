@@ -184,6 +184,11 @@ class Solver:
                 "ssnalm_op_rkkt")
         return r.value, b.value
 
+    def set_profile(self, profile):
+        """HIP-event timing: 0 off, 1 all classes, or a mask with bit (k + 1)
+        for class k of K_NAMES."""
+        L.check(self._lib.ssnalm_set_profile(self._ctx, int(profile)), "ssnalm_set_profile")
+
     def kernel_stats(self, reset=False):
         """Per-class kernel statistics (needs profile=1): {name: {launches,
         seconds, bytes, flops}}."""
