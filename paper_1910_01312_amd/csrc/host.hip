@@ -110,6 +110,7 @@ struct ssnalm_ctx {
            *diag = nullptr;
     // q x q
     double *G = nullptr, *M = nullptr;
+    double* linv = nullptr;          // inverses of the diagonal factors (blocked Cholesky)
     // reduction scratch
     double *part = nullptr, *part2 = nullptr;
     int64_t part_cap = 0;
@@ -328,8 +329,8 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         if (!c->mixed && c->q <= chol_small_max()) {
             launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
         } else {
-            launch_chol_factor_blocked(c->M, c->q, dsc(c), c->st);
-            launch_chol_solve_factored(c->M, g, d, c->q, c->part, c->st);
+            launch_chol_factor_blocked(c->M, c->q, c->linv, dsc(c), c->st);
+            launch_chol_solve_factored(c->M, c->linv, g, d, c->q, c->st);
         }
         prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q, (double)c->q * c->q * c->q / 3.0 + 2.0 * c->q * c->q);
         if (c->mixed) {
@@ -349,7 +350,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                 STCHK(sync_state(c));
                 ++*cg_iters;
                 if (!(c->hs->sc.cg_rr > tol2)) break;
-                launch_chol_solve_factored(c->M, c->qv2, c->qv, c->q, c->part, c->st);
+                launch_chol_solve_factored(c->M, c->linv, c->qv2, c->qv, c->q, c->st);
                 launch_axpy(d, c->qv, 1.0, c->q, c->st);
             }
         }
@@ -770,6 +771,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
         ALLOC(c->G, q * q);
         ALLOC(c->M, q * q);
         c->mixed = c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, q);
+        if (c->mixed || q > chol_small_max()) ALLOC(c->linv, chol_inv_size(q));
         if (c->mixed) {
             ALLOC(c->zJ, n); ALLOC(c->wJ, n); ALLOC(c->cgpart, 1024 + 512 + 1024);
         }

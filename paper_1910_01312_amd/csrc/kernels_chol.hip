@@ -2,10 +2,12 @@
 //     M = I + sigma (X_J^T X_J - s s^T / p)   (q x q, symmetric positive definite)
 // for q above the LDS-resident kernel's limit, and the two triangular solves
 // giving d = -M^{-1} g.  Right-looking with 64 x 64 blocks: for each block
-// column kb, factor the diagonal block in LDS, solve the panel below it, and
-// update the trailing lower tiles.  The factor is kept in the lower triangle
-// of M and mirrored into the upper triangle (row j of the upper part holds
-// column j of L), so both solves read contiguous rows.
+// column kb, factor the diagonal block and form the inverse of its factor,
+// compute the panel below it as A_panel L_kk^{-T} (a small GEMM), and update
+// the trailing lower tiles.  The factor is kept in the lower triangle of M
+// and mirrored into the upper triangle (M[j][i] = L[i][j]), so that both
+// triangular solves read it with consecutive lanes on consecutive addresses;
+// the inverses of the diagonal factors turn the block solves into mat-vecs.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
@@ -13,82 +15,159 @@ namespace ssn {
 
 constexpr int NB = 64;
 constexpr int CHOL_BLOCKED_MAX = 2048;
+constexpr int SOLVE_THREADS = 512;                  // 8 waves: 64 rows x 8 column groups
+constexpr int SOLVE_PARTS = SOLVE_THREADS / NB;
+constexpr int TILE_PER_THREAD = NB * NB / SSN_BLOCK;
+constexpr int SOLVE_CHUNK = 16;                     // column loads in flight per thread
 
 int chol_blocked_max() { return CHOL_BLOCKED_MAX; }
+// per 64 x 64 diagonal block: its inverse factor X = L_kk^{-1} row-major and X^T
+int64_t chol_inv_size(int64_t q) { return (q + NB - 1) / NB * 2 * NB * NB; }
 
-// Factor the diagonal block kb in LDS.  A non-positive pivot is replaced by 1
-// and reported through sc->chol_fail.
+// Factor diagonal block kb and form X = L_kk^{-1}, both right-looking in
+// registers: thread t keeps row i = t % 64, columns 16 (t / 64) .. +15 of the
+// block (a) and of B (initially I).  Step k publishes column k of a and row k
+// of B through LDS (double buffered, one barrier per step); then
+//   l_kk = sqrt(a_kk),  l_ik = a_ik / l_kk,  X[k][.] = B[k][.] / l_kk,
+//   a_ij -= a_ik a_jk / a_kk  and  B[i][.] -= (a_ik / a_kk) B[k][.]  (i > k),
+// which is forward substitution of L X = I carried along with the
+// factorisation.  A non-positive pivot is replaced by 1 and reported in
+// sc->chol_fail.  Rows past q are padded with the identity.
 __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M, int q, int kb,
-                                                         Scalars* sc) {
-    __shared__ double A[NB][NB + 1];
-    if (kb == 0 && threadIdx.x == 0) sc->chol_fail = 0;
+                                                         double* __restrict__ inv, Scalars* sc) {
+    __shared__ double col[2][NB];
+    __shared__ double rowb[2][NB];
+    const int tid = threadIdx.x;
+    if (kb == 0 && tid == 0) sc->chol_fail = 0;
     const int o = kb * NB;
     const int m = min(NB, q - o);
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, j = e % NB;
-        A[i][j] = (i < m && j < m) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
+    const int i = tid & (NB - 1), cg = tid >> 6;
+    double a[16], b[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = cg * 16 + jj;
+        a[jj] = (i < m && j < m) ? M[(int64_t)(o + i) * q + o + j] : (i == j ? 1.0 : 0.0);
+        b[jj] = i == j ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (int k = 0; k < m; ++k) {
-        double akk = A[k][k];
+    // wave-uniform column group (scalar branches below)
+    const int cgu = __builtin_amdgcn_readfirstlane(cg);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        double* cr = col[k & 1];
+        double* rb = rowb[k & 1];
+        if (cgu == (k >> 4)) cr[i] = a[k & 15];
+        if (i == k) {
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) rb[cgu * 16 + jj] = b[jj];
+        }
+        __syncthreads();
+        // every LDS read of the step is issued here, ahead of the pivot math
+        double akk = cr[k];
+        const double cik = cr[i];
+        double cj[16], bj[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) cj[jj] = cr[cgu * 16 + jj];
+        if (cgu * 16 <= k) {
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) bj[jj] = rb[cgu * 16 + jj];
+        }
         if (!(akk > 0.0)) {
-            if (threadIdx.x == 0) sc->chol_fail = 1;
+            bad = true;
             akk = 1.0;
         }
         const double lkk = sqrt(akk);
-        __syncthreads();
-        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) A[i][k] /= lkk;
-        if (threadIdx.x == 0) A[k][k] = lkk;
-        __syncthreads();
-        const int r = m - k - 1;
-        for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
-            const int a = e / r, b = e % r;
-            if (b <= a) A[k + 1 + a][k + 1 + b] -= A[k + 1 + a][k] * A[k + 1 + b][k];
+        const double rk = 1.0 / akk;
+        const double rl = rk * lkk;                       // 1 / l_kk
+        const double t = i > k ? cik * rk : 0.0;
+        if (cgu == (k >> 4)) a[k & 15] = i > k ? cik * rl : (i == k ? lkk : 0.0);
+        if (cgu * 16 + 15 > k) {
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const double l = cgu * 16 + jj > k ? cj[jj] : 0.0;
+                a[jj] = fma(-t, l, a[jj]);
+            }
         }
-        __syncthreads();
+        if (cgu * 16 <= k) {                              // B[k][c] = 0 for c > k
+            const double f = i == k ? rl : 1.0;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) b[jj] = fma(-t, bj[jj], b[jj]) * f;
+        }
     }
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        const int i = e / m, j = e % m;
-        if (j <= i) {
-            const double v = A[i][j];
-            M[(int64_t)(o + i) * q + o + j] = v;
-            M[(int64_t)(o + j) * q + o + i] = v;
+    if (bad && tid == 0) sc->chol_fail = 1;
+    // factor back to M (lower entry and its upper mirror), X and X^T to inv
+    double* Xo = inv + (int64_t)kb * 2 * NB * NB;
+    double* XTo = Xo + NB * NB;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = cg * 16 + jj;
+        if (j <= i && i < m) {
+            M[(int64_t)(o + i) * q + o + j] = a[jj];
+            M[(int64_t)(o + j) * q + o + i] = a[jj];
         }
+        const double x = j <= i ? b[jj] : 0.0;
+        Xo[i * NB + j] = x;
+        XTo[j * NB + i] = x;
     }
 }
 
-// Panel solve: rows below the diagonal block, L_ib,kb = A_ib,kb L_kb,kb^{-T}.
-// One block per row block, one thread per row.
-__global__ __launch_bounds__(NB) void k_chol_trsm(double* __restrict__ M, int q, int kb) {
-    __shared__ double L[NB][NB + 1];
+// Panel below block kb: L_ib,kb = A_ib,kb X^T, X = L_kb,kb^{-1}, for the
+// 64-row block ib = kb + 1 + blockIdx.x; 4 x 4 outputs per thread, written to
+// the lower part and its upper mirror.
+__global__ __launch_bounds__(SSN_BLOCK) void k_chol_panel(double* __restrict__ M, int q, int kb,
+                                                          const double* __restrict__ inv) {
+    __shared__ double Ap[NB][NB + 1];
+    __shared__ double Xs[NB][NB + 1];
     const int o = kb * NB;
     const int m = min(NB, q - o);
-    const int ib = kb + 1 + blockIdx.x;
-    const int ro = ib * NB;
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, j = e % NB;
-        L[i][j] = (i < m && j < m && j <= i) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
-    }
-    __syncthreads();
-    const int r = ro + threadIdx.x;
-    if (r >= q) return;
-    double x[NB];
+    const int ro = (kb + 1 + blockIdx.x) * NB;
+    const int rm = min(NB, q - ro);
+    const double* Xo = inv + (int64_t)kb * 2 * NB * NB;
+    {
+        // all global loads of the tile first, then the LDS stores
+        double va[TILE_PER_THREAD], vx[TILE_PER_THREAD];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) x[j] = j < m ? M[(int64_t)r * q + o + j] : 0.0;
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, a = e / NB, b = e % NB;
+            va[h] = (a < rm && b < m) ? M[(int64_t)(ro + a) * q + o + b] : 0.0;
+            vx[h] = Xo[e];
+        }
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        if (j < m) {
-            double a = x[j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) a -= x[k] * L[j][k];
-            x[j] = a / L[j][j];
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, a = e / NB, b = e % NB;
+            Ap[a][b] = va[h];
+            Xs[a][b] = vx[h];
         }
     }
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        if (j < m) {
-            M[(int64_t)r * q + o + j] = x[j];
-            M[(int64_t)(o + j) * q + r] = x[j];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int mm = 0; mm < NB; ++mm) {
+        double x[4], w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = Ap[ty + 16 * u][mm];
+            w[u] = Xs[tx + 16 * u][mm];                 // X[j][mm], zero for mm > j
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], w[v], acc[u][v]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = ty + 16 * u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = tx + 16 * v;
+            if (r < rm && j < m) {
+                M[(int64_t)(ro + r) * q + o + j] = acc[u][v];
+                M[(int64_t)(o + j) * q + ro + r] = acc[u][v];
+            }
         }
     }
 }
@@ -98,19 +177,27 @@ __global__ __launch_bounds__(NB) void k_chol_trsm(double* __restrict__ M, int q,
 __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ M, int q, int kb) {
     __shared__ double Li[NB][NB + 1];
     __shared__ double Lj[NB][NB + 1];
-    const int nt = (q + NB - 1) / NB - kb - 1;      // trailing block count
-    // blockIdx.x -> (a, b), a >= b, over the nt x nt lower triangle
+    // blockIdx.x -> (a, b), a >= b, over the trailing lower triangle
     int t = blockIdx.x, a = 0;
     while (t > a) { t -= a + 1; ++a; }
     const int b = t;
     const int ib = kb + 1 + a, jb = kb + 1 + b;
-    (void)nt;
     const int o = kb * NB, io = ib * NB, jo = jb * NB;
     const int m = min(NB, q - o);
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, k = e % NB;
-        Li[i][k] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
-        Lj[i][k] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
+    {
+        double vi[TILE_PER_THREAD], vj[TILE_PER_THREAD];
+#pragma unroll
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+            vi[h] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
+            vj[h] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+            Li[i][k] = vi[h];
+            Lj[i][k] = vj[h];
+        }
     }
     __syncthreads();
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
@@ -123,8 +210,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ 
         double x[4], y[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            x[u] = Li[ty * 4 + u][k];
-            y[u] = Lj[tx * 4 + u][k];
+            x[u] = Li[ty + 16 * u][k];
+            y[u] = Lj[tx + 16 * u][k];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -135,107 +222,131 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ 
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = io + ty * 4 + u, j = jo + tx * 4 + v;
+            const int i = io + ty + 16 * u, j = jo + tx + 16 * v;
             if (i < q && j < q && j <= i) M[(int64_t)i * q + j] -= acc[u][v];
         }
 }
 
-// d = -M^{-1} g with the factor in M, by 64-row blocks in one workgroup.
-// Forward L w = -g: for block B, subtract L[B, <B] w[<B] (rows of L, all
-// waves, one wave-reduction per row), then wave 0 solves the 64 x 64 lower
-// triangular block with lane i owning row i.  Backward L^T d = w: for block
-// B from the last, subtract L[>B, B]^T d[>B] (row j of the upper triangle
-// holds column j of L), then wave 0 solves the upper triangular L_BB^T.
-__global__ __launch_bounds__(SSN_BLOCK) void k_chol_solve2(const double* __restrict__ M,
-                                                           const double* __restrict__ g,
-                                                           double* __restrict__ d, int q) {
-    extern __shared__ double z[];                  // q doubles
-    __shared__ double Lb[NB][NB + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// Sum of the column-group partials of every row (LDS), returned to the
+// threads of group 0.
+__device__ __forceinline__ double rows_reduce(double (*red)[NB], double s, int r, int part) {
+    red[part][r] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (part == 0) {
+#pragma unroll
+        for (int pp = 0; pp < SOLVE_PARTS; ++pp) t += red[pp][r];
+    }
+    return t;
+}
+
+// d = -M^{-1} g with the factor in M (lower + mirror) and the diagonal-block
+// inverses in inv, in one workgroup of SOLVE_THREADS threads: lane r of wave
+// part handles row r of the current 64-row block and every SOLVE_PARTS-th
+// column.
+// Forward L w = -g, block by block:  y = z_B - L[B, <B] w[<B], w_B = X_B y,
+// with L[o + r][c] read from the mirror M[c][o + r].
+// Backward L^T d = w from the last block: y = w_B - L[>B, B]^T d[>B], with
+// L[c][o + r] read from the lower part M[c][o + r]; then d_B = X_B^T y.
+// y_r = sum over c in [c0, c1) of M[c][o + r] z[c] for this thread's columns
+// c = c0 + part + SOLVE_PARTS h; the loads of a chunk are all issued before
+// any FMA.
+__device__ __forceinline__ double column_dot(const double* __restrict__ colp, const double* z,
+                                             int c0, int c1, int part, int64_t q, bool active) {
+    double s = 0.0;
+    if (!active) return s;
+    for (int base = c0 + part; base < c1; base += SOLVE_PARTS * SOLVE_CHUNK) {
+        double v[SOLVE_CHUNK];
+#pragma unroll
+        for (int h = 0; h < SOLVE_CHUNK; ++h) {
+            const int c = base + SOLVE_PARTS * h;
+            v[h] = c < c1 ? colp[(int64_t)c * q] : 0.0;
+        }
+        double s2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < SOLVE_CHUNK; ++h) {
+            const int c = base + SOLVE_PARTS * h;
+            s2[h & 3] = fma(v[h], c < c1 ? z[c] : 0.0, s2[h & 3]);
+        }
+        s += (s2[0] + s2[1]) + (s2[2] + s2[3]);
+    }
+    return s;
+}
+
+// d = -M^{-1} g with the factor in M (lower + mirror) and the diagonal-block
+// inverses in inv, in one workgroup of SOLVE_THREADS threads: lane r of wave
+// part handles row r of the current 64-row block and every SOLVE_PARTS-th
+// column.
+// Forward L w = -g, block by block:  y = z_B - L[B, <B] w[<B], w_B = X_B y,
+// with L[o + r][c] read from the mirror M[c][o + r].
+// Backward L^T d = w from the last block: y = w_B - L[>B, B]^T d[>B], with
+// L[c][o + r] read from the lower part M[c][o + r]; then d_B = X_B^T y.
+__global__ __launch_bounds__(SOLVE_THREADS) void k_chol_solve2(const double* __restrict__ M,
+                                                               const double* __restrict__ inv,
+                                                               const double* __restrict__ g,
+                                                               double* __restrict__ d, int q) {
+    extern __shared__ double z[];                    // q doubles
+    __shared__ double red[SOLVE_PARTS][NB];
+    __shared__ double yb[NB];
+    const int tid = threadIdx.x, r = tid & (NB - 1), part = tid >> 6;
     for (int i = tid; i < q; i += blockDim.x) z[i] = -g[i];
     const int nblk = (q + NB - 1) / NB;
-    // ---- forward
     for (int B = 0; B < nblk; ++B) {
         const int o = B * NB, m = min(NB, q - o);
+        // w_r = sum_{mm <= r} X[r][mm] y_mm = sum_mm X^T[mm][r] y_mm: this thread's
+        // four X^T entries, loaded ahead
+        const double* XT = inv + (int64_t)B * 2 * NB * NB + NB * NB;
+        double xv[NB / SOLVE_PARTS];
+#pragma unroll
+        for (int k = 0; k < NB / SOLVE_PARTS; ++k) xv[k] = XT[(part * (NB / SOLVE_PARTS) + k) * NB + r];
         __syncthreads();
-        // z[o+r] -= sum_{c < o} L[o+r][c] z[c]
-        for (int r = wv; r < m; r += SSN_WAVES_PER_BLOCK) {
-            const double* row = M + (int64_t)(o + r) * q;
-            double acc = 0.0;
-            for (int c = lane; c < o; c += SSN_WAVE) acc = fma(row[c], z[c], acc);
-            acc = wave_sum(acc);
-            if (lane == 0) z[o + r] -= acc;
-        }
-        for (int e = tid; e < NB * NB; e += blockDim.x) {
-            const int i = e / NB, j = e % NB;
-            Lb[i][j] = (i < m && j < m && j <= i) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
-        }
+        double t = rows_reduce(red, column_dot(M + o + r, z, 0, o, part, q, r < m), r, part);
+        if (part == 0) yb[r] = r < m ? z[o + r] - t : 0.0;
         __syncthreads();
-        if (wv == 0) {
-            double ri = lane < m ? z[o + lane] : 0.0;
-            for (int j = 0; j < m; ++j) {
-                const double wj = __shfl(ri, j, SSN_WAVE) / Lb[j][j];
-                if (lane == j) ri = wj;
-                if (lane > j) ri -= Lb[lane][j] * wj;
-            }
-            if (lane < m) z[o + lane] = ri;
-        }
+        double u = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB / SOLVE_PARTS; ++k) u = fma(xv[k], yb[part * (NB / SOLVE_PARTS) + k], u);
+        t = rows_reduce(red, u, r, part);
+        if (part == 0 && r < m) z[o + r] = t;
     }
-    // ---- backward
     for (int B = nblk - 1; B >= 0; --B) {
         const int o = B * NB, m = min(NB, q - o), e0 = o + m;
+        // d_r = sum_{mm >= r} X[mm][r] y_mm
+        const double* X = inv + (int64_t)B * 2 * NB * NB;
+        double xv[NB / SOLVE_PARTS];
+#pragma unroll
+        for (int k = 0; k < NB / SOLVE_PARTS; ++k) xv[k] = X[(part * (NB / SOLVE_PARTS) + k) * NB + r];
         __syncthreads();
-        // z[o+r] -= sum_{c >= e0} L[c][o+r] d[c] = sum upper[o+r][c] d[c]
-        for (int r = wv; r < m; r += SSN_WAVES_PER_BLOCK) {
-            const double* row = M + (int64_t)(o + r) * q;
-            double acc = 0.0;
-            for (int c = e0 + lane; c < q; c += SSN_WAVE) acc = fma(row[c], z[c], acc);
-            acc = wave_sum(acc);
-            if (lane == 0) z[o + r] -= acc;
-        }
-        for (int e = tid; e < NB * NB; e += blockDim.x) {
-            const int i = e / NB, j = e % NB;
-            Lb[i][j] = (i < m && j < m && j <= i) ? M[(int64_t)(o + i) * q + o + j] : 0.0;
-        }
+        double t = rows_reduce(red, column_dot(M + o + r, z, e0, q, part, q, r < m), r, part);
+        if (part == 0) yb[r] = r < m ? z[o + r] - t : 0.0;
         __syncthreads();
-        if (wv == 0) {
-            double ri = lane < m ? z[o + lane] : 0.0;
-            for (int j = m - 1; j >= 0; --j) {
-                const double dj = __shfl(ri, j, SSN_WAVE) / Lb[j][j];
-                if (lane == j) ri = dj;
-                if (lane < j) ri -= Lb[j][lane] * dj;
-            }
-            if (lane < m) z[o + lane] = ri;
-        }
+        double u = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB / SOLVE_PARTS; ++k) u = fma(xv[k], yb[part * (NB / SOLVE_PARTS) + k], u);
+        t = rows_reduce(red, u, r, part);
+        if (part == 0 && r < m) z[o + r] = t;
     }
     __syncthreads();
     for (int i = tid; i < q; i += blockDim.x) d[i] = z[i];
 }
 
-void launch_chol_factor_blocked(double* M, int64_t q, Scalars* sc, hipStream_t s) {
+void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s) {
     const int nblk = (int)((q + NB - 1) / NB);
     for (int kb = 0; kb < nblk; ++kb) {
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, sc);
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv, sc);
         const int nt = nblk - kb - 1;
         if (nt > 0) {
-            hipLaunchKernelGGL(k_chol_trsm, dim3(nt), dim3(NB), 0, s, M, (int)q, kb);
+            hipLaunchKernelGGL(k_chol_panel, dim3(nt), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv);
             hipLaunchKernelGGL(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(SSN_BLOCK), 0, s, M,
                                (int)q, kb);
         }
     }
 }
 
-void launch_chol_solve_factored(const double* M, const double* g, double* d, int64_t q,
-                                double* work, hipStream_t s) {
-    (void)work;
-    hipLaunchKernelGGL(k_chol_solve2, dim3(1), dim3(SSN_BLOCK), (size_t)q * sizeof(double), s, M, g,
-                       d, (int)q);
-}
-
-void launch_chol_solve_blocked(double* M, const double* g, double* d, int64_t q, double* work,
-                               Scalars* sc, hipStream_t s) {
-    launch_chol_factor_blocked(M, q, sc, s);
-    launch_chol_solve_factored(M, g, d, q, work, s);
+void launch_chol_solve_factored(const double* M, const double* inv, const double* g, double* d,
+                                int64_t q, hipStream_t s) {
+    hipLaunchKernelGGL(k_chol_solve2, dim3(1), dim3(SOLVE_THREADS), (size_t)q * sizeof(double), s, M,
+                       inv, g, d, (int)q);
 }
 
 }  // namespace ssn

@@ -133,21 +133,34 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_syrk_mfma(const bf16_t* __restric
             }
 }
 
-// G[i][j] (lower tiles, mirrored) = sum over splits, in split order, in fp64
-__global__ void k_syrk_mfma_reduce(const float* __restrict__ part, int ntile, int nsplit,
-                                   double* __restrict__ G, int64_t q) {
-    int t = blockIdx.x, ti = 0;
+// G[i][j] (lower tiles, mirrored) = sum over splits, in split order, in fp64;
+// one element per thread, RED_BLOCKS blocks per 128 x 128 tile
+constexpr int RED_BLOCKS = MT * MT / SSN_BLOCK;
+__global__ __launch_bounds__(SSN_BLOCK) void k_syrk_mfma_reduce(const float* __restrict__ part,
+                                                                int ntile, int nsplit,
+                                                                double* __restrict__ G, int64_t q) {
+    const int tile = blockIdx.x / RED_BLOCKS;
+    const int e = (blockIdx.x % RED_BLOCKS) * SSN_BLOCK + threadIdx.x;
+    int t = tile, ti = 0;
     while (t > ti) { t -= ti + 1; ++ti; }
     const int tj = t;
-    for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
-        const int a = e / MT, b = e % MT;
-        const int64_t i = (int64_t)ti * MT + a, j = (int64_t)tj * MT + b;
-        if (i >= q || j >= q || j > i) continue;
-        double s = 0.0;
-        for (int k = 0; k < nsplit; ++k) s += (double)part[((int64_t)k * ntile + blockIdx.x) * MT * MT + e];
-        G[i * q + j] = s;
-        G[j * q + i] = s;
+    const int a = e / MT, b = e % MT;
+    const int64_t i = (int64_t)ti * MT + a, j = (int64_t)tj * MT + b;
+    if (i >= q || j >= q || j > i) return;
+    const float* src = part + (int64_t)tile * MT * MT + e;
+    const int64_t stride = (int64_t)ntile * MT * MT;
+    double s = 0.0;
+    int k = 0;
+    for (; k + 8 <= nsplit; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) v[h] = src[(k + h) * stride];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) s += (double)v[h];
     }
+    for (; k < nsplit; ++k) s += (double)src[k * stride];
+    G[i * q + j] = s;
+    G[j * q + i] = s;
 }
 
 void launch_syrk_mfma(const void* X, int dtype, int64_t q, const int32_t* list, int64_t p,
@@ -160,8 +173,8 @@ void launch_syrk_mfma(const void* X, int dtype, int64_t q, const int32_t* list, 
     rps = (rps + KC - 1) / KC * KC;
     hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
                        (const bf16_t*)X, q, list, p, rps, part);
-    hipLaunchKernelGGL(k_syrk_mfma_reduce, dim3((unsigned)ntile), dim3(SSN_BLOCK), 0, s, part, ntile,
-                       (int)ns, G, q);
+    hipLaunchKernelGGL(k_syrk_mfma_reduce, dim3((unsigned)(ntile * RED_BLOCKS)), dim3(SSN_BLOCK), 0, s,
+                       part, ntile, (int)ns, G, q);
 }
 
 // ------------------------------------------------------------------ X_J v (dense)

@@ -147,9 +147,6 @@ void launch_scatter_centered(const int32_t* list, int64_t p, const double* w, co
                              int nbw, const int8_t* y, double* z, hipStream_t s);
 void launch_refine_res(const double* g, const double* d, const double* t, double sigma, double* rn,
                        int64_t q, hipStream_t s);
-void launch_chol_factor_blocked(double* M, int64_t q, Scalars* sc, hipStream_t s);
-void launch_chol_solve_factored(const double* M, const double* g, double* d, int64_t q,
-                                double* work, hipStream_t s);
 // M = I + sigma (G - s s^T / p)
 void launch_form_M(const double* G, const double* sv, double sigma, int64_t p, double* M,
                    int64_t q, hipStream_t s);
@@ -157,10 +154,14 @@ void launch_form_M(const double* G, const double* sv, double sigma, int64_t p, d
 int  chol_small_max();
 void launch_chol_solve_small(const double* M, const double* g, double* d, int64_t q,
                              Scalars* sc, hipStream_t s);
-// Blocked Cholesky for larger q (in place on M), then the two solves
-int  chol_blocked_max();
-void launch_chol_solve_blocked(double* M, const double* g, double* d, int64_t q,
-                               double* work, Scalars* sc, hipStream_t s);
+// Blocked Cholesky for larger q (kernels_chol.hip): the factor in place on M
+// (lower triangle and its upper mirror), the inverses of the 64 x 64 diagonal
+// factors in inv (chol_inv_size(q) doubles); then d = -M^{-1} g from both
+int     chol_blocked_max();
+int64_t chol_inv_size(int64_t q);
+void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s);
+void launch_chol_solve_factored(const double* M, const double* inv, const double* g, double* d,
+                                int64_t q, hipStream_t s);
 
 // Sparse products restricted to J (kernels_jcsr.hip) --------------------------
 void launch_rank_from_list(const int32_t* list, const long long* pdev, int64_t n, int32_t* rank,

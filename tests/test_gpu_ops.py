@@ -315,7 +315,7 @@ def test_gram_mfma_bf16(q, p_frac):
     assert np.all(np.abs(G - ref) <= bound + 1e-30)
 
 
-@pytest.mark.parametrize("q", [160, 512])
+@pytest.mark.parametrize("q", [160, 200, 512, 1000])
 def test_newton_blocked_cholesky_fp64(q):
     X, y = synth.dense_two_gaussians(n=4000, q=q, seed=6)
     sigma = 3.0
