@@ -155,6 +155,67 @@ __device__ __forceinline__ double cand_geometric(double lo, double hi, double hi
     return fmin(fmax(v, lo), hi);
 }
 
+// Reduce-scatter over the wave: on entry every lane holds a[0..63]; on exit
+// lane l returns the wave total of a[l].  At each step lanes paired by
+// xor h keep one half of their live values (the upper half if bit h is set)
+// and add the partner's copy of that half: 63 exchanges instead of 64 full
+// wave sums, in a fixed order.
+__device__ __forceinline__ double wave_reduce_scatter64(double (&a)[64]) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+#pragma unroll
+    for (int h = 32; h >= 1; h >>= 1) {
+        const bool up = (lane & h) != 0;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const double lo_v = a[j], hi_v = a[j + h];
+            const double send = up ? lo_v : hi_v;
+            const double keep = up ? hi_v : lo_v;
+            a[j] = keep + __shfl_xor(send, h, SSN_WAVE);
+        }
+    }
+    return a[0];
+}
+
+// block_append for U values per thread (value u of thread t is element
+// u * blockDim + t): one pair of barriers for all U, list order = element order
+template <int U>
+__device__ __forceinline__ int block_append_multi(const bool (&take)[U], const double (&val)[U],
+                                                  double* list, int base,
+                                                  int (*wsum)[SSN_WAVES_PER_BLOCK]) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    unsigned long long m[U];
+    int before[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        m[u] = __ballot(take[u]);
+        before[u] = __popcll(m[u] & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) wsum[u][w] = __popcll(m[u]);
+    }
+    __syncthreads();
+    int off = base;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int ou = 0, tu = 0;
+#pragma unroll
+        for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) {
+            const int c = wsum[u][k];
+            if (k < w) ou += c;
+            tu += c;
+        }
+        if (take[u]) list[off + ou + before[u]] = val[u];
+        off += tu;
+    }
+    return off - base;
+}
+
+constexpr int PU = 4;                     // elements per thread per sweep step
+constexpr int PCOL = PNV + 1;             // double columns per block: g partials, lin_s
+constexpr int PICOL = PK + 2;             // int columns: histogram, constant count, lin count
+
 __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restrict__ v,
                                                          const int8_t* __restrict__ y, int64_t n,
                                                          double C, ProjState* st,
@@ -162,13 +223,15 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
                                                          int* __restrict__ hpart,
                                                          unsigned* counter) {
     __shared__ double lam_s[PK + 1];
-    __shared__ double red[SSN_WAVES_PER_BLOCK][PNV];
+    __shared__ double red[SSN_WAVES_PER_BLOCK][PCOL];
+    __shared__ long long redl[SSN_WAVES_PER_BLOCK][2];
     __shared__ double fin[PNV];
     __shared__ int hist[PK];
     __shared__ int hfin[PK];
-    __shared__ long long kfin;
+    __shared__ long long kfin, linn_fin;
+    __shared__ double lins_fin;
     __shared__ double list[PASS_CAP];
-    __shared__ int wsum[SSN_WAVES_PER_BLOCK];
+    __shared__ int wsum[PU][SSN_WAVES_PER_BLOCK];
     if (ld_acquire(&st->done)) return;         // uniform over the grid
     const double lo = st->lo, hi = st->hi;
     const bool geo = st->mode == 1;
@@ -182,47 +245,63 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
     // breakpoints b, b + C outside (lam_s[0], lam_s[PK]) that term is, over
     // the whole bracket, the constant C (b + C <= lo), 0 (b >= hi) or
     // exactly (lam - lo) + (lo - b) (b <= lo, b + C >= hi): summed in closed
-    // form.  Only elements with a breakpoint strictly inside the bracket are
-    // evaluated at every candidate; they are gathered (thread order) into an
+    // form (counts and the sum of lo - b, combined once in the last block).
+    // Only elements with a breakpoint strictly inside the bracket are
+    // evaluated at every candidate; they are gathered (element order) into an
     // LDS list so that whole blocks work on them together.
     const double blo = lam_s[0], bhi = lam_s[PK];
-    double acc[PK + 1];
+    double acc[PK];
+    double acc_hi = 0.0;
 #pragma unroll
-    for (int k = 0; k <= PK; ++k) acc[k] = 0.0;
+    for (int k = 0; k < PK; ++k) acc[k] = 0.0;
     // the constant part is C times an integer count, kept exact so that g is
     // exactly 0 on a flat stretch (no component strictly inside the box)
-    long long kc = 0;
-    double lin_n = 0.0, lin_s = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t base = (int64_t)blockIdx.x * blockDim.x;
-    int cnt = 0;
+    long long kc = 0, lin_n = 0;
+    double lin_s = 0.0;
+    const int64_t step = (int64_t)gridDim.x * SSN_BLOCK * PU;
+    int64_t base = (int64_t)blockIdx.x * SSN_BLOCK * PU;
+    int cnt = 0, maxcnt = 0;
     for (;;) {
         const bool more = base < n;                    // uniform over the block
         if (more) {
-            const int64_t i = base + threadIdx.x;
-            bool take = false;
-            double b = 0.0;
-            if (i < n) {
-                const double vi = v[i];
-                const bool pos = y[i] > 0;
-                b = pos ? vi - C : -vi;
-                const double bh = b + C;
-                kc -= pos ? 1 : 0;
-                if (bh <= blo) kc += 1;
-                else if (b >= bhi) {}
-                else if (b <= blo && bh >= bhi) { lin_n += 1.0; lin_s += blo - b; }
-                else take = true;
+            double vv[PU];
+            int yy[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {             // every load of the step first
+                const int64_t i = base + u * SSN_BLOCK + threadIdx.x;
+                vv[u] = i < n ? v[i] : 0.0;
+                yy[u] = i < n ? (int)y[i] : 0;
             }
-            cnt += block_append(take, b, list, cnt, wsum);
-            base += stride;
+            bool take[PU];
+            double bb[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int64_t i = base + u * SSN_BLOCK + threadIdx.x;
+                take[u] = false;
+                bb[u] = 0.0;
+                if (i < n) {
+                    const bool pos = yy[u] > 0;
+                    const double b = pos ? vv[u] - C : -vv[u];
+                    const double bh = b + C;
+                    kc -= pos ? 1 : 0;
+                    if (bh <= blo) kc += 1;
+                    else if (b >= bhi) {}
+                    else if (b <= blo && bh >= bhi) { lin_n += 1; lin_s += blo - b; }
+                    else { take[u] = true; bb[u] = b; }
+                }
+            }
+            cnt += block_append_multi<PU>(take, bb, list, cnt, wsum);
+            base += step;
         }
-        if (!more || cnt > PASS_CAP - (int)blockDim.x) {
+        if (!more || cnt > PASS_CAP - PU * SSN_BLOCK) {
             __syncthreads();
+            maxcnt = max(maxcnt, cnt);
             for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
                 const double b = list[e];
                 const double bh = b + C;
 #pragma unroll
-                for (int k = 0; k <= PK; ++k) acc[k] += clampd(lam_s[k] - b, 0.0, C);
+                for (int k = 0; k < PK; ++k) acc[k] += clampd(lam_s[k] - b, 0.0, C);
+                acc_hi += clampd(bhi - b, 0.0, C);
                 // histogram of breakpoints strictly inside each sub-interval
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -242,55 +321,72 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
             if (!more) break;
         }
     }
-#pragma unroll
-    for (int k = 0; k <= PK; ++k) acc[k] += lin_n * (lam_s[k] - blo) + lin_s;
-    __shared__ long long shk[SSN_WAVES_PER_BLOCK];
-    const long long kblk = block_sum_ll(kc, shk);
     const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
-#pragma unroll
-    for (int k = 0; k <= PK; ++k) {
-        const double s = wave_sum(acc[k]);
-        if (lane == 0) red[w][k] = s;
+    // a wave whose threads evaluated no list entry holds zeros in acc
+    double gk = 0.0, ghi = 0.0;
+    if (maxcnt > w * SSN_WAVE) {
+        gk = wave_reduce_scatter64(acc);
+        ghi = wave_sum(acc_hi);
+    }
+    const double ls = wave_sum(lin_s);
+    const long long kw = wave_sum_ll(kc), lw = wave_sum_ll(lin_n);
+    red[w][lane] = gk;
+    if (lane == 0) {
+        red[w][PK] = ghi;
+        red[w][PK + 1] = ls;
+        redl[w][0] = kw;
+        redl[w][1] = lw;
     }
     __syncthreads();
     const int nb = gridDim.x;                   // <= PROJ_GRID_MAX
-    if (threadIdx.x < PNV) {
+    if (threadIdx.x < PCOL) {
         double s = 0.0;
 #pragma unroll
         for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) s += red[ww][threadIdx.x];
         part[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = s;   // [column][block]
     }
     if (threadIdx.x < PK) hpart[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = hist[threadIdx.x];
-    if (threadIdx.x == 0) hpart[(int64_t)PK * PROJ_GRID_MAX + blockIdx.x] = (int)kblk;
+    if (threadIdx.x == 0) {
+        long long k2 = 0, l2 = 0;
+#pragma unroll
+        for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) { k2 += redl[ww][0]; l2 += redl[ww][1]; }
+        hpart[(int64_t)PK * PROJ_GRID_MAX + blockIdx.x] = (int)k2;
+        hpart[(int64_t)(PK + 1) * PROJ_GRID_MAX + blockIdx.x] = (int)l2;
+    }
     if (!last_block_arrives(counter)) return;
     // ---- last block: fixed-order reduction over blocks, then the decision.
     // Column c is summed by wave c mod 4: lane l owns blocks l, l+64, l+128,
     // l+192; all loads of the wave's columns are issued before any sum.
     {
-        constexpr int CPW = (PNV + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
+        constexpr int CPW = (PCOL + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
         constexpr int BPL = PROJ_GRID_MAX / SSN_WAVE;
-        double vals[CPW][BPL];
+        static_assert(PICOL <= CPW * SSN_WAVES_PER_BLOCK, "int columns per wave");
+        {
+            double vals[CPW][BPL];
 #pragma unroll
-        for (int i = 0; i < CPW; ++i) {
-            const int c = w + i * SSN_WAVES_PER_BLOCK;
+            for (int i = 0; i < CPW; ++i) {
+                const int c = w + i * SSN_WAVES_PER_BLOCK;
 #pragma unroll
-            for (int j = 0; j < BPL; ++j) {
-                const int bb = lane + j * SSN_WAVE;
-                vals[i][j] = (c < PNV && bb < nb) ? ld_acquire(&part[(int64_t)c * PROJ_GRID_MAX + bb]) : 0.0;
+                for (int j = 0; j < BPL; ++j) {
+                    const int bb = lane + j * SSN_WAVE;
+                    vals[i][j] = (c < PCOL && bb < nb) ? ld_acquire(&part[(int64_t)c * PROJ_GRID_MAX + bb]) : 0.0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+                const int c = w + i * SSN_WAVES_PER_BLOCK;
+                double sum = 0.0;
+#pragma unroll
+                for (int j = 0; j < BPL; ++j) sum += vals[i][j];
+                sum = wave_sum(sum);
+                if (lane == 0) {
+                    if (c < PNV) fin[c] = sum;
+                    else if (c == PNV) lins_fin = sum;
+                }
             }
         }
-#pragma unroll
-        for (int i = 0; i < CPW; ++i) {
-            const int c = w + i * SSN_WAVES_PER_BLOCK;
-            double sum = 0.0;
-#pragma unroll
-            for (int j = 0; j < BPL; ++j) sum += vals[i][j];
-            sum = wave_sum(sum);
-            if (lane == 0 && c < PNV) fin[c] = sum;
-        }
-        // histogram and the constant count: integer sums (exact in any order),
-        // again with every load of the wave issued before any sum
         {
+            // integer sums: exact in any order
             int hv[CPW][BPL];
 #pragma unroll
             for (int i = 0; i < CPW; ++i) {
@@ -298,7 +394,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
 #pragma unroll
                 for (int j = 0; j < BPL; ++j) {
                     const int bb = lane + j * SSN_WAVE;
-                    hv[i][j] = (c <= PK && bb < nb) ? ld_acquire(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]) : 0;
+                    hv[i][j] = (c < PICOL && bb < nb) ? ld_acquire(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]) : 0;
                 }
             }
 #pragma unroll
@@ -308,15 +404,17 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
 #pragma unroll
                 for (int j = 0; j < BPL; ++j) hsum += hv[i][j];
                 hsum = wave_sum_ll(hsum);
-                if (lane == 0 && c <= PK) {
+                if (lane == 0) {
                     if (c < PK) hfin[c] = (int)hsum;
-                    else kfin = hsum;
+                    else if (c == PK) kfin = hsum;
+                    else if (c == PK + 1) linn_fin = hsum;
                 }
             }
         }
     }
     __syncthreads();
-    if (threadIdx.x <= PK) fin[threadIdx.x] += C * (double)kfin;
+    if (threadIdx.x <= PK)
+        fin[threadIdx.x] += C * (double)kfin + (double)linn_fin * (lam_s[threadIdx.x] - blo) + lins_fin;
     __syncthreads();
     if (threadIdx.x == 0) {
         const int passes = st->passes + 1;
@@ -353,7 +451,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
 void launch_proj_pass(const double* v, const int8_t* y, int64_t n, double C, ProjState* st,
                       double* part, unsigned* counter, hipStream_t s) {
     // doubles for the g-values, then ints for the histogram, in one scratch
-    int* hpart = reinterpret_cast<int*>(part + (int64_t)PNV * PROJ_GRID_MAX);
+    int* hpart = reinterpret_cast<int*>(part + (int64_t)PCOL * PROJ_GRID_MAX);
     hipLaunchKernelGGL(k_proj_pass, dim3(proj_grid(n)), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, part,
                        hpart, counter);
 }
