@@ -60,35 +60,35 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
 // Returns true in every thread of the block that is the last one of the
 // grid to arrive.  The caller must have written its partial results before
 // calling.  The counter is reset by the last block so it can be reused by
-// the next launch on the same stream.
+// the next launch on the same stream.  Every wave first waits for its own
+// stores to complete; then one thread per block makes them visible device
+// wide (one agent-scope fence per block: a fence in every wave costs several
+// times more on a multi-die device) and arrives.
 __device__ __forceinline__ bool last_block_arrives(unsigned* counter) {
     __shared__ int s_last;
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
-        s_last = (prev == gridDim.x * gridDim.y * gridDim.z - 1) ? 1 : 0;
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        const int last = (prev == gridDim.x * gridDim.y * gridDim.z - 1) ? 1 : 0;
+        if (last) {
+            __threadfence();
+            atomicExch(counter, 0u);
+        }
+        s_last = last;
     }
     __syncthreads();
-    bool last = s_last != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) atomicExch(counter, 0u);
-    }
-    return last;
+    return s_last != 0;
 }
 
-// Loads that bypass possibly stale per-CU caches for data written by other
-// blocks of the same grid (used only by the last block).
-__device__ __forceinline__ double ld_acquire(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ long long ld_acquire(const long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int ld_acquire(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Load of a value that another block of the grid wrote before
+// last_block_arrives (whose fences make it visible to the last block), or
+// that an earlier kernel wrote: a plain load, so that the compiler can keep
+// many of them in flight.
+__device__ __forceinline__ double ld_grid(const double* p) { return *p; }
+__device__ __forceinline__ long long ld_grid(const long long* p) { return *p; }
+__device__ __forceinline__ int ld_grid(const int* p) { return *p; }
 
 // Sum of column c of a partials array (part[b*stride + c], b < nb) by the
 // whole block: thread t sums b = t, t+blockDim, ... with four independent
@@ -101,12 +101,12 @@ __device__ __forceinline__ double grid_colsum(const double* part, int nb, int st
     const int T = blockDim.x;
     int b = threadIdx.x;
     for (; b + 3 * T < nb; b += 4 * T) {
-        a0 += ld_acquire(&part[(int64_t)b * stride + c]);
-        a1 += ld_acquire(&part[(int64_t)(b + T) * stride + c]);
-        a2 += ld_acquire(&part[(int64_t)(b + 2 * T) * stride + c]);
-        a3 += ld_acquire(&part[(int64_t)(b + 3 * T) * stride + c]);
+        a0 += ld_grid(&part[(int64_t)b * stride + c]);
+        a1 += ld_grid(&part[(int64_t)(b + T) * stride + c]);
+        a2 += ld_grid(&part[(int64_t)(b + 2 * T) * stride + c]);
+        a3 += ld_grid(&part[(int64_t)(b + 3 * T) * stride + c]);
     }
-    for (; b < nb; b += T) a0 += ld_acquire(&part[(int64_t)b * stride + c]);
+    for (; b < nb; b += T) a0 += ld_grid(&part[(int64_t)b * stride + c]);
     return block_sum((a0 + a1) + (a2 + a3), sh);
 }
 

@@ -101,6 +101,7 @@ struct ssnalm_ctx {
     int *tcount = nullptr, *toff = nullptr;
     double *wJ = nullptr, *kcarry = nullptr, *cgpart = nullptr;
     double* zJ = nullptr;            // n-vector, nonzero on J only (mixed refinement)
+    double* yz = nullptr;            // n-vector y .* z for the sparse A^T z
     bool mixed = false;              // bf16 SYRK + refinement
     int refine_total = 0;
     // q-vectors
@@ -261,7 +262,9 @@ static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const 
         launch_reduce_cols(c->part, nb, c->q, base, sign, r, c->st);
         if (mask) launch_reduce_cols(c->part2, nb, c->q, nullptr, 1.0, s_out, c->st);
     } else {
-        launch_segsum(c->tr, z, c->y, nullptr, nullptr, nullptr, c->qv2, c->st);
+        // one gathered coefficient per entry: y .* z, formed once
+        launch_mul_y(z, c->y, c->yz, c->n, c->st);
+        launch_segsum(c->tr, c->yz, nullptr, nullptr, nullptr, nullptr, c->qv2, c->st);
         // r = base + sign * qv2
         if (base) {
             launch_sub(base, c->qv2, r, c->q, c->st);       // sign is always -1 with a base
@@ -789,6 +792,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
     }
     if (pr->kind == SSNALM_CSR) {
         if ((s = setup_csr(c, pr)) < 0) return bail(s);
+        ALLOC(c->yz, n);
         if (!c->use_chol) {
             const int64_t nz = std::max<int64_t>(pr->nnz, 1);
             ALLOC(c->jrank, n); ALLOC(c->jr, nz); ALLOC(c->jc, nz); ALLOC(c->wJ, n);

@@ -376,7 +376,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_mop_pap(const double* __restrict_
                                                        Scalars* sc, double* __restrict__ part,
                                                        unsigned* counter) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
-    if (ld_acquire(&sc->cg_done)) return;
+    if (ld_grid(&sc->cg_done)) return;
     double s = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_pap(const double* __restrict_
                                                        Scalars* sc, double* __restrict__ part,
                                                        unsigned* counter) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
-    if (ld_acquire(&sc->cg_done)) return;
+    if (ld_grid(&sc->cg_done)) return;
     double s = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride)
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_step(double* __restrict__ x,
                                                         double* __restrict__ part,
                                                         unsigned* counter) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
-    if (ld_acquire(&sc->cg_done)) return;
+    if (ld_grid(&sc->cg_done)) return;
     const double pap = sc->cg_pap, rz = sc->cg_rz;
     const double alpha = (pap > 0.0 && rz > 0.0) ? rz / pap : 0.0;
     double a = 0.0, b = 0.0;
@@ -140,7 +140,7 @@ void launch_pcg_step(double* x, double* r, double* pd, const double* Ap, const d
 
 __global__ void k_pcg_dir(double* __restrict__ pd, const double* __restrict__ z, int64_t q,
                           const Scalars* sc) {
-    if (ld_acquire(&sc->cg_done)) return;
+    if (ld_grid(&sc->cg_done)) return;
     const double beta = sc->cg_beta;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < q) pd[j] = fma(beta, pd[j], z[j]);

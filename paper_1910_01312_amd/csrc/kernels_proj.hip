@@ -91,8 +91,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
         // min / max are order-independent; the count is an exact integer
         double mn = 1.0 / 0.0, mx = -1.0 / 0.0;
         for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-            mn = fmin(mn, ld_acquire(&part[b * 3 + 0]));
-            mx = fmax(mx, ld_acquire(&part[b * 3 + 1]));
+            mn = fmin(mn, ld_grid(&part[b * 3 + 0]));
+            mx = fmax(mx, ld_grid(&part[b * 3 + 1]));
         }
         mn = wave_min(mn);
         mx = wave_max(mx);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
     __shared__ double lins_fin;
     __shared__ double list[PASS_CAP];
     __shared__ int wsum[PU][SSN_WAVES_PER_BLOCK];
-    if (ld_acquire(&st->done)) return;         // uniform over the grid
+    if (ld_grid(&st->done)) return;         // uniform over the grid
     const double lo = st->lo, hi = st->hi;
     const bool geo = st->mode == 1;
     const double hint = st->hint;
@@ -361,54 +361,36 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
         constexpr int CPW = (PCOL + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
         constexpr int BPL = PROJ_GRID_MAX / SSN_WAVE;
         static_assert(PICOL <= CPW * SSN_WAVES_PER_BLOCK, "int columns per wave");
-        {
-            double vals[CPW][BPL];
+        double vals[CPW][BPL];
+        int hv[CPW][BPL];
 #pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int c = w + i * SSN_WAVES_PER_BLOCK;
+        for (int i = 0; i < CPW; ++i) {
+            const int c = w + i * SSN_WAVES_PER_BLOCK;
 #pragma unroll
-                for (int j = 0; j < BPL; ++j) {
-                    const int bb = lane + j * SSN_WAVE;
-                    vals[i][j] = (c < PCOL && bb < nb) ? ld_acquire(&part[(int64_t)c * PROJ_GRID_MAX + bb]) : 0.0;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int c = w + i * SSN_WAVES_PER_BLOCK;
-                double sum = 0.0;
-#pragma unroll
-                for (int j = 0; j < BPL; ++j) sum += vals[i][j];
-                sum = wave_sum(sum);
-                if (lane == 0) {
-                    if (c < PNV) fin[c] = sum;
-                    else if (c == PNV) lins_fin = sum;
-                }
+            for (int j = 0; j < BPL; ++j) {
+                const int bb = lane + j * SSN_WAVE;
+                vals[i][j] = (c < PCOL && bb < nb) ? ld_grid(&part[(int64_t)c * PROJ_GRID_MAX + bb]) : 0.0;
+                hv[i][j] = (c < PICOL && bb < nb) ? ld_grid(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]) : 0;
             }
         }
-        {
-            // integer sums: exact in any order
-            int hv[CPW][BPL];
 #pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int c = w + i * SSN_WAVES_PER_BLOCK;
+        for (int i = 0; i < CPW; ++i) {
+            const int c = w + i * SSN_WAVES_PER_BLOCK;
+            double sum = 0.0;
+            long long hsum = 0;
 #pragma unroll
-                for (int j = 0; j < BPL; ++j) {
-                    const int bb = lane + j * SSN_WAVE;
-                    hv[i][j] = (c < PICOL && bb < nb) ? ld_acquire(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]) : 0;
-                }
+            for (int j = 0; j < BPL; ++j) {
+                sum += vals[i][j];
+                hsum += hv[i][j];
             }
-#pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int c = w + i * SSN_WAVES_PER_BLOCK;
-                long long hsum = 0;
-#pragma unroll
-                for (int j = 0; j < BPL; ++j) hsum += hv[i][j];
-                hsum = wave_sum_ll(hsum);
-                if (lane == 0) {
-                    if (c < PK) hfin[c] = (int)hsum;
-                    else if (c == PK) kfin = hsum;
-                    else if (c == PK + 1) linn_fin = hsum;
-                }
+            sum = wave_sum(sum);
+            hsum = wave_sum_ll(hsum);        // integer sums: exact in any order
+            if (lane == 0) {
+                if (c < PNV) fin[c] = sum;
+                else if (c == PNV) lins_fin = sum;
+                if (c < PK) hfin[c] = (int)hsum;
+                else if (c == PK) kfin = hsum;
+                else if (c == PK + 1) linn_fin = hsum;
             }
         }
     }
@@ -664,7 +646,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_compact_count(const uint8_t* __re
         const int per = (nb + SSN_BLOCK - 1) / SSN_BLOCK;
         const int b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
         long long loc = 0;
-        for (int b = b0; b < b1; ++b) loc += ld_acquire(&blk[b]);
+        for (int b = b0; b < b1; ++b) loc += ld_grid(&blk[b]);
         run_sh[threadIdx.x] = loc;
         __syncthreads();
         for (int off = 1; off < SSN_BLOCK; off <<= 1) {
@@ -675,7 +657,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_compact_count(const uint8_t* __re
         }
         long long run = run_sh[threadIdx.x] - loc;
         for (int b = b0; b < b1; ++b) {
-            const int cb = ld_acquire(&blk[b]);
+            const int cb = ld_grid(&blk[b]);
             blk[b] = (int)run;
             run += cb;
         }

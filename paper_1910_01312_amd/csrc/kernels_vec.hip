@@ -96,6 +96,16 @@ void launch_sub(const double* a, const double* b, double* out, int64_t len, hipS
     hipLaunchKernelGGL(k_sub, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, a, b, out, len);
 }
 
+// o = y .* z (the coefficients of X^T (y .* z), gathered once per entry)
+__global__ void k_mul_y(const double* __restrict__ z, const int8_t* __restrict__ y,
+                        double* __restrict__ o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = (double)y[i] * z[i];
+}
+void launch_mul_y(const double* z, const int8_t* y, double* out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_mul_y, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, y, out, n);
+}
+
 __global__ void k_fill(double* __restrict__ p, double v, int64_t len) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) p[i] = v;

@@ -124,6 +124,7 @@ void launch_scale_copy(double* y, const double* x, double a, int64_t len, hipStr
 void launch_u_from(const double* xk, const double* aw, double sigma, double* u, int64_t n,
                    hipStream_t s);
 void launch_sub(const double* a, const double* b, double* out, int64_t len, hipStream_t s);
+void launch_mul_y(const double* z, const int8_t* y, double* out, int64_t n, hipStream_t s);
 void launch_fill(double* p, double v, int64_t len, hipStream_t s);
 void launch_count_x(const double* x, int64_t n, double C, Scalars* sc, double* part,
                     unsigned* counter, hipStream_t s);
