@@ -47,10 +47,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
                                                          const double* __restrict__ td,
                                                          double as, double* __restrict__ vout,
                                                          const int8_t* __restrict__ y, int64_t n,
-                                                         double C, ProjState* st,
-                                                         double* __restrict__ part,
-                                                         unsigned* counter,
-                                                         const ProjState* hint) {
+                                                         double C, double* __restrict__ part) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     __shared__ long long shl[SSN_WAVES_PER_BLOCK];
     double bmin = 1.0 / 0.0, bmax = -1.0 / 0.0;
@@ -87,10 +84,18 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
         part[blockIdx.x * 3 + 1] = r2;
         part[blockIdx.x * 3 + 2] = (double)c;
     }
-    if (last_block_arrives(counter)) {
+}
+
+// Part 2 of the init (one block): combine the nb block partials.
+__global__ __launch_bounds__(SSN_BLOCK) void k_proj_init_fin(int64_t n, double C, ProjState* st,
+                                                             const double* __restrict__ part, int nb,
+                                                             const ProjState* hint) {
+    __shared__ double shd[SSN_WAVES_PER_BLOCK];
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    {
         // min / max are order-independent; the count is an exact integer
         double mn = 1.0 / 0.0, mx = -1.0 / 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
             mn = fmin(mn, ld_grid(&part[b * 3 + 0]));
             mx = fmax(mx, ld_grid(&part[b * 3 + 1]));
         }
@@ -104,7 +109,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
         if (lane == 0) { shd[w] = mx; }
         __syncthreads();
         for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) mx = fmax(mx, shd[k]);
-        const double cnt = grid_colsum(part, gridDim.x, 3, 2, shd);
+        const double cnt = grid_colsum(part, nb, 3, 2, shd);
         if (threadIdx.x == 0) {
             st->lo = mn;
             st->hi = mx + 2.0 * C;
@@ -130,13 +135,15 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_init(const double* __restric
 void launch_proj_init(const double* u, const double* td, double alpha_sigma, double* v_out,
                       const int8_t* y, int64_t n, double C, ProjState* st, double* part,
                       unsigned* counter, hipStream_t s, const ProjState* hint) {
+    (void)counter;
     const unsigned g = proj_grid(n);
     if (td)
         hipLaunchKernelGGL((k_proj_init<true>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, alpha_sigma,
-                           v_out, y, n, C, st, part, counter, hint);
+                           v_out, y, n, C, part);
     else
         hipLaunchKernelGGL((k_proj_init<false>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, 0.0,
-                           v_out, y, n, C, st, part, counter, hint);
+                           v_out, y, n, C, part);
+    hipLaunchKernelGGL(k_proj_init_fin, dim3(1), dim3(SSN_BLOCK), 0, s, n, C, st, part, (int)g, hint);
 }
 
 // ------------------------------------------------------------------ pass
@@ -216,36 +223,38 @@ constexpr int PU = 4;                     // elements per thread per sweep step
 constexpr int PCOL = PNV + 1;             // double columns per block: g partials, lin_s
 constexpr int PICOL = PK + 2;             // int columns: histogram, constant count, lin count
 
-__global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restrict__ v,
-                                                         const int8_t* __restrict__ y, int64_t n,
-                                                         double C, ProjState* st,
-                                                         double* __restrict__ part,
-                                                         int* __restrict__ hpart,
-                                                         unsigned* counter) {
-    __shared__ double lam_s[PK + 1];
-    __shared__ double red[SSN_WAVES_PER_BLOCK][PCOL];
-    __shared__ long long redl[SSN_WAVES_PER_BLOCK][2];
-    __shared__ double fin[PNV];
-    __shared__ int hist[PK];
-    __shared__ int hfin[PK];
-    __shared__ long long kfin, linn_fin;
-    __shared__ double lins_fin;
-    __shared__ double list[PASS_CAP];
-    __shared__ int wsum[PU][SSN_WAVES_PER_BLOCK];
-    if (ld_grid(&st->done)) return;         // uniform over the grid
+// The candidates of the pass (both kernels of a pass compute the same ones).
+__device__ __forceinline__ void pass_candidates(const ProjState* st, double C, double* lam_s) {
     const double lo = st->lo, hi = st->hi;
     const bool geo = st->mode == 1;
     const double hint = st->hint;
     if (threadIdx.x <= PK)
         lam_s[threadIdx.x] = geo ? cand_geometric(lo, hi, hint, C, threadIdx.x)
                                  : cand_uniform(lo, hi, threadIdx.x);
+}
+
+// One multisection pass, part 1: every block sweeps its share of the data
+// and writes its partial g-values, histogram and closed-form counts.
+__global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restrict__ v,
+                                                         const int8_t* __restrict__ y, int64_t n,
+                                                         double C, const ProjState* st,
+                                                         double* __restrict__ part,
+                                                         int* __restrict__ hpart) {
+    __shared__ double lam_s[PK + 1];
+    __shared__ double red[SSN_WAVES_PER_BLOCK][PCOL];
+    __shared__ long long redl[SSN_WAVES_PER_BLOCK][2];
+    __shared__ int hist[PK];
+    __shared__ double list[PASS_CAP];
+    __shared__ int wsum[PU][SSN_WAVES_PER_BLOCK];
+    if (ld_grid(&st->done)) return;         // uniform over the grid
+    pass_candidates(st, C, lam_s);
     if (threadIdx.x < PK) hist[threadIdx.x] = 0;
     __syncthreads();
     // Each element adds clip(lam - b, 0, C) - C [y > 0] to g(lam).  With both
     // breakpoints b, b + C outside (lam_s[0], lam_s[PK]) that term is, over
     // the whole bracket, the constant C (b + C <= lo), 0 (b >= hi) or
     // exactly (lam - lo) + (lo - b) (b <= lo, b + C >= hi): summed in closed
-    // form (counts and the sum of lo - b, combined once in the last block).
+    // form (counts and the sum of lo - b, combined once by the decision).
     // Only elements with a breakpoint strictly inside the bracket are
     // evaluated at every candidate; they are gathered (element order) into an
     // LDS list so that whole blocks work on them together.
@@ -353,44 +362,74 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
         hpart[(int64_t)PK * PROJ_GRID_MAX + blockIdx.x] = (int)k2;
         hpart[(int64_t)(PK + 1) * PROJ_GRID_MAX + blockIdx.x] = (int)l2;
     }
-    if (!last_block_arrives(counter)) return;
-    // ---- last block: fixed-order reduction over blocks, then the decision.
-    // Column c is summed by wave c mod 4: lane l owns blocks l, l+64, l+128,
-    // l+192; all loads of the wave's columns are issued before any sum.
+}
+
+// One multisection pass, part 2 (one block): fixed-order reduction of the
+// partials of the nb blocks of part 1, then the decision.  Column c is summed
+// by wave c mod 4: lane l owns blocks l, l+64, l+128, l+192.  A separate
+// launch instead of a last-arriving block: the kernel boundary makes the
+// partials visible without a device-wide fence in every block.
+__global__ __launch_bounds__(SSN_BLOCK) void k_proj_decide(double C, ProjState* st,
+                                                           const double* __restrict__ part,
+                                                           const int* __restrict__ hpart, int nb) {
+    __shared__ double lam_s[PK + 1];
+    __shared__ double fin[PNV];
+    __shared__ int hfin[PK];
+    __shared__ long long kfin, linn_fin;
+    __shared__ double lins_fin;
+    if (ld_grid(&st->done)) return;
+    pass_candidates(st, C, lam_s);
+    const double blo = st->lo;
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
     {
         constexpr int CPW = (PCOL + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
         constexpr int BPL = PROJ_GRID_MAX / SSN_WAVE;
         static_assert(PICOL <= CPW * SSN_WAVES_PER_BLOCK, "int columns per wave");
-        double vals[CPW][BPL];
-        int hv[CPW][BPL];
+        // unconditional loads (column clamped into the arrays, entries of
+        // blocks past nb masked afterwards) so that none waits for another
+        {
+            double vals[CPW][BPL];
 #pragma unroll
-        for (int i = 0; i < CPW; ++i) {
-            const int c = w + i * SSN_WAVES_PER_BLOCK;
+            for (int i = 0; i < CPW; ++i) {
+                const int cc = min(w + i * SSN_WAVES_PER_BLOCK, PCOL - 1);
 #pragma unroll
-            for (int j = 0; j < BPL; ++j) {
-                const int bb = lane + j * SSN_WAVE;
-                vals[i][j] = (c < PCOL && bb < nb) ? ld_grid(&part[(int64_t)c * PROJ_GRID_MAX + bb]) : 0.0;
-                hv[i][j] = (c < PICOL && bb < nb) ? ld_grid(&hpart[(int64_t)c * PROJ_GRID_MAX + bb]) : 0;
+                for (int j = 0; j < BPL; ++j)
+                    vals[i][j] = ld_grid(&part[(int64_t)cc * PROJ_GRID_MAX + lane + j * SSN_WAVE]);
+            }
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+                const int c = w + i * SSN_WAVES_PER_BLOCK;
+                double sum = 0.0;
+#pragma unroll
+                for (int j = 0; j < BPL; ++j) sum += lane + j * SSN_WAVE < nb ? vals[i][j] : 0.0;
+                sum = wave_sum(sum);
+                if (lane == 0) {
+                    if (c < PNV) fin[c] = sum;
+                    else if (c == PNV) lins_fin = sum;
+                }
             }
         }
+        {
+            int hv[CPW][BPL];
 #pragma unroll
-        for (int i = 0; i < CPW; ++i) {
-            const int c = w + i * SSN_WAVES_PER_BLOCK;
-            double sum = 0.0;
-            long long hsum = 0;
+            for (int i = 0; i < CPW; ++i) {
+                const int cc = min(w + i * SSN_WAVES_PER_BLOCK, PICOL - 1);
 #pragma unroll
-            for (int j = 0; j < BPL; ++j) {
-                sum += vals[i][j];
-                hsum += hv[i][j];
+                for (int j = 0; j < BPL; ++j)
+                    hv[i][j] = ld_grid(&hpart[(int64_t)cc * PROJ_GRID_MAX + lane + j * SSN_WAVE]);
             }
-            sum = wave_sum(sum);
-            hsum = wave_sum_ll(hsum);        // integer sums: exact in any order
-            if (lane == 0) {
-                if (c < PNV) fin[c] = sum;
-                else if (c == PNV) lins_fin = sum;
-                if (c < PK) hfin[c] = (int)hsum;
-                else if (c == PK) kfin = hsum;
-                else if (c == PK + 1) linn_fin = hsum;
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+                const int c = w + i * SSN_WAVES_PER_BLOCK;
+                long long hsum = 0;
+#pragma unroll
+                for (int j = 0; j < BPL; ++j) hsum += lane + j * SSN_WAVE < nb ? hv[i][j] : 0;
+                hsum = wave_sum_ll(hsum);       // integer sums: exact in any order
+                if (lane == 0) {
+                    if (c < PK) hfin[c] = (int)hsum;
+                    else if (c == PK) kfin = hsum;
+                    else if (c == PK + 1) linn_fin = hsum;
+                }
             }
         }
     }
@@ -432,10 +471,12 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
 
 void launch_proj_pass(const double* v, const int8_t* y, int64_t n, double C, ProjState* st,
                       double* part, unsigned* counter, hipStream_t s) {
+    (void)counter;
     // doubles for the g-values, then ints for the histogram, in one scratch
     int* hpart = reinterpret_cast<int*>(part + (int64_t)PCOL * PROJ_GRID_MAX);
-    hipLaunchKernelGGL(k_proj_pass, dim3(proj_grid(n)), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, part,
-                       hpart, counter);
+    const unsigned g = proj_grid(n);
+    hipLaunchKernelGGL(k_proj_pass, dim3(g), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, part, hpart);
+    hipLaunchKernelGGL(k_proj_decide, dim3(1), dim3(SSN_BLOCK), 0, s, C, st, part, hpart, (int)g);
 }
 
 // ------------------------------------------------------------------ apply
@@ -447,10 +488,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_apply(const double* __restri
                                                           double C, const ProjState* st,
                                                           double* __restrict__ x,
                                                           uint8_t* __restrict__ mask,
-                                                          Scalars* sc, double* __restrict__ part,
-                                                          unsigned* counter) {
+                                                          double* __restrict__ part) {
     __shared__ long long shl[SSN_WAVES_PER_BLOCK];
-    __shared__ double shd[SSN_WAVES_PER_BLOCK];
     const double lam = st->lam;
     long long p = 0, nsv = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -469,21 +508,20 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_apply(const double* __restri
         part[blockIdx.x * 2 + 0] = (double)bp;
         part[blockIdx.x * 2 + 1] = (double)bs;
     }
-    if (last_block_arrives(counter)) {
-        const double a = grid_colsum(part, gridDim.x, 2, 0, shd);
-        const double b = grid_colsum(part, gridDim.x, 2, 1, shd);
-        if (threadIdx.x == 0) {
-            sc->p = (long long)a;
-            sc->nsv = (long long)b;
-        }
-    }
 }
 
 void launch_proj_apply(const double* v, const int8_t* y, int64_t n, double C, const ProjState* st,
                        double* x, uint8_t* mask, Scalars* sc, double* part, unsigned* counter,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_proj_apply, dim3(proj_grid(n)), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, x,
-                       mask, sc, part, counter);
+    (void)counter;
+    const unsigned g = proj_grid(n);
+    hipLaunchKernelGGL(k_proj_apply, dim3(g), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, x, mask, part);
+    ColSumDst d = colsum_dst();
+    d.p[0] = &sc->p;
+    d.as_ll[0] = 1;
+    d.p[1] = &sc->nsv;
+    d.as_ll[1] = 1;
+    launch_colsum_fin(part, (int)g, 2, 2, d, s);
 }
 
 // ------------------------------------------------------------------ line search
@@ -507,8 +545,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_ls_finalize(
     const double* __restrict__ v, const double* __restrict__ u_base,
     const double* __restrict__ td, double as, const int8_t* __restrict__ y, int64_t n, double C,
     const ProjState* st, const ProjState* st_base, const double* __restrict__ xk,
-    double* __restrict__ x, uint8_t* __restrict__ mask, Scalars* sc, double* __restrict__ part,
-    unsigned* counter) {
+    double* __restrict__ x, uint8_t* __restrict__ mask, double* __restrict__ part) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     __shared__ long long shl[SSN_WAVES_PER_BLOCK];
     const double lam = st->lam, lamb = st_base->lam, dl = lam - lamb;
@@ -540,26 +577,24 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_ls_finalize(
         part[blockIdx.x * 4 + 2] = (double)bp;
         part[blockIdx.x * 4 + 3] = (double)bs;
     }
-    if (last_block_arrives(counter)) {
-        const double a = grid_colsum(part, gridDim.x, 4, 0, shd);
-        const double b = grid_colsum(part, gridDim.x, 4, 1, shd);
-        const double c = grid_colsum(part, gridDim.x, 4, 2, shd);
-        const double d = grid_colsum(part, gridDim.x, 4, 3, shd);
-        if (threadIdx.x == 0) {
-            sc->dh = a;
-            sc->dist2 = b;
-            sc->p = (long long)c;
-            sc->nsv = (long long)d;
-        }
-    }
 }
 
 void launch_ls_finalize(const double* v, const double* u_base, const double* td, double as,
                         const int8_t* y, int64_t n, double C, const ProjState* st,
                         const ProjState* st_base, const double* xk, double* x, uint8_t* mask,
                         Scalars* sc, double* part, unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_ls_finalize, dim3(proj_grid(n)), dim3(SSN_BLOCK), 0, s, v, u_base, td, as,
-                       y, n, C, st, st_base, xk, x, mask, sc, part, counter);
+    (void)counter;
+    const unsigned g = proj_grid(n);
+    hipLaunchKernelGGL(k_ls_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, u_base, td, as, y, n, C, st,
+                       st_base, xk, x, mask, part);
+    ColSumDst d = colsum_dst();
+    d.p[0] = &sc->dh;
+    d.p[1] = &sc->dist2;
+    d.p[2] = &sc->p;
+    d.as_ll[2] = 1;
+    d.p[3] = &sc->nsv;
+    d.as_ll[3] = 1;
+    launch_colsum_fin(part, (int)g, 4, 4, d, s);
 }
 
 // ------------------------------------------------------------------ KKT
@@ -577,9 +612,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_kkt_finalize(const double* __rest
                                                             const double* __restrict__ x,
                                                             const int8_t* __restrict__ y,
                                                             int64_t n, double C,
-                                                            const ProjState* st, Scalars* sc,
-                                                            double* __restrict__ part,
-                                                            unsigned* counter) {
+                                                            const ProjState* st,
+                                                            double* __restrict__ part) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     const double lam = st->lam;
     double r2 = 0.0, x2 = 0.0, sx = 0.0;
@@ -600,23 +634,19 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_kkt_finalize(const double* __rest
         part[blockIdx.x * 3 + 1] = b;
         part[blockIdx.x * 3 + 2] = c;
     }
-    if (last_block_arrives(counter)) {
-        const double s0 = grid_colsum(part, gridDim.x, 3, 0, shd);
-        const double s1 = grid_colsum(part, gridDim.x, 3, 1, shd);
-        const double s2 = grid_colsum(part, gridDim.x, 3, 2, shd);
-        if (threadIdx.x == 0) {
-            sc->res2 = s0;
-            sc->x2 = s1;
-            sc->sumx = s2;
-        }
-    }
 }
 
 void launch_kkt_finalize(const double* v, const double* x, const int8_t* y, int64_t n, double C,
                          const ProjState* st, Scalars* sc, double* part, unsigned* counter,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_kkt_finalize, dim3(proj_grid(n)), dim3(SSN_BLOCK), 0, s, v, x, y, n, C, st,
-                       sc, part, counter);
+    (void)counter;
+    const unsigned g = proj_grid(n);
+    hipLaunchKernelGGL(k_kkt_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, x, y, n, C, st, part);
+    ColSumDst d = colsum_dst();
+    d.p[0] = &sc->res2;
+    d.p[1] = &sc->x2;
+    d.p[2] = &sc->sumx;
+    launch_colsum_fin(part, (int)g, 3, 3, d, s);
 }
 
 // ------------------------------------------------------------------ compaction
@@ -628,9 +658,7 @@ constexpr int CMP_EPT = 16;
 constexpr int CMP_CH = SSN_BLOCK * CMP_EPT;
 
 __global__ __launch_bounds__(SSN_BLOCK) void k_compact_count(const uint8_t* __restrict__ mask,
-                                                             int64_t n, int* blk,
-                                                             long long* total,
-                                                             unsigned* counter) {
+                                                             int64_t n, int* blk) {
     __shared__ long long shl[SSN_WAVES_PER_BLOCK];
     const int64_t base = (int64_t)blockIdx.x * CMP_CH + (int64_t)threadIdx.x * CMP_EPT;
     long long c = 0;
@@ -639,36 +667,19 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_compact_count(const uint8_t* __re
         if (base + e < n) c += mask[base + e] ? 1 : 0;
     const long long bc = block_sum_ll(c, shl);
     if (threadIdx.x == 0) blk[blockIdx.x] = (int)bc;
-    if (last_block_arrives(counter)) {
-        // exclusive scan of the block counts: thread t owns a contiguous run
-        __shared__ long long run_sh[SSN_BLOCK];
-        const int nb = gridDim.x;
-        const int per = (nb + SSN_BLOCK - 1) / SSN_BLOCK;
-        const int b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
-        long long loc = 0;
-        for (int b = b0; b < b1; ++b) loc += ld_grid(&blk[b]);
-        run_sh[threadIdx.x] = loc;
-        __syncthreads();
-        for (int off = 1; off < SSN_BLOCK; off <<= 1) {
-            const long long t = threadIdx.x >= off ? run_sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            run_sh[threadIdx.x] += t;
-            __syncthreads();
-        }
-        long long run = run_sh[threadIdx.x] - loc;
-        for (int b = b0; b < b1; ++b) {
-            const int cb = ld_grid(&blk[b]);
-            blk[b] = (int)run;
-            run += cb;
-        }
-        if (threadIdx.x == SSN_BLOCK - 1) *total = run_sh[SSN_BLOCK - 1];
-    }
 }
-
+// Every block sums the counts of the blocks before it (its offset; exact
+// integers) and writes its indices there in order; the last block also
+// writes the total.
 __global__ __launch_bounds__(SSN_BLOCK) void k_compact_write(const uint8_t* __restrict__ mask,
                                                              int64_t n, const int* __restrict__ blk,
-                                                             int32_t* __restrict__ list) {
+                                                             int32_t* __restrict__ list,
+                                                             long long* total) {
     __shared__ int sh[SSN_BLOCK];
+    __shared__ long long shl[SSN_WAVES_PER_BLOCK];
+    long long before = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += blockDim.x) before += blk[b];
+    const long long off = block_sum_ll(before, shl);
     const int64_t base = (int64_t)blockIdx.x * CMP_CH + (int64_t)threadIdx.x * CMP_EPT;
     int c = 0;
 #pragma unroll
@@ -677,24 +688,24 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_compact_write(const uint8_t* __re
     sh[threadIdx.x] = c;
     __syncthreads();
     // inclusive scan over the block (Hillis-Steele, fixed and exact: integers)
-    for (int off = 1; off < SSN_BLOCK; off <<= 1) {
-        const int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    for (int o = 1; o < SSN_BLOCK; o <<= 1) {
+        const int t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
         __syncthreads();
         sh[threadIdx.x] += t;
         __syncthreads();
     }
-    int pos = blk[blockIdx.x] + sh[threadIdx.x] - c;
+    int64_t pos = off + sh[threadIdx.x] - c;
 #pragma unroll
     for (int e = 0; e < CMP_EPT; ++e)
         if (base + e < n && mask[base + e]) list[pos++] = (int32_t)(base + e);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SSN_BLOCK - 1) *total = off + sh[SSN_BLOCK - 1];
 }
-
 void launch_compact(const uint8_t* mask, int64_t n, int32_t* list, long long* count, int* blk,
                     unsigned* counter, hipStream_t s) {
+    (void)counter;
     const unsigned nb = (unsigned)((n + CMP_CH - 1) / CMP_CH);
-    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk, count,
-                       counter);
-    hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk, list);
+    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk);
+    hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk, list, count);
 }
 
 int compact_blocks(int64_t n) { return (int)((n + CMP_CH - 1) / CMP_CH); }

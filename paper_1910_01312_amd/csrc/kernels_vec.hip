@@ -12,16 +12,44 @@ static inline unsigned vec_grid(int64_t len) {
     return (unsigned)b;
 }
 
+// Sums of up to four columns of block partials (part[b * stride + c],
+// b < nb) in block order, by one block, into the destinations of d.
+__global__ __launch_bounds__(SSN_BLOCK) void k_colsum_fin(const double* __restrict__ part, int nb,
+                                                          int stride, int ncols, ColSumDst d) {
+    __shared__ double shd[SSN_WAVES_PER_BLOCK];
+    if (d.skip && ld_grid(d.skip)) return;
+    for (int c = 0; c < ncols; ++c) {
+        const double t = grid_colsum(part, nb, stride, c, shd);
+        if (threadIdx.x == 0 && d.p[c]) {
+            if (d.as_ll[c]) *(long long*)d.p[c] = (long long)t;
+            else *(double*)d.p[c] = t * d.scale[c];
+        }
+    }
+}
+void launch_colsum_fin(const double* part, int nb, int stride, int ncols, const ColSumDst& d,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum_fin, dim3(1), dim3(SSN_BLOCK), 0, s, part, nb, stride, ncols, d);
+}
+ColSumDst colsum_dst() {
+    ColSumDst d;
+    for (int c = 0; c < 4; ++c) {
+        d.p[c] = nullptr;
+        d.as_ll[c] = 0;
+        d.scale[c] = 1.0;
+    }
+    d.skip = nullptr;
+    return d;
+}
+
 // r_k = a_k . b_k for up to three pairs.  Block partials in part[3*b + k],
-// combined in block order by the last block.
+// combined in block order by a one-block finishing kernel.
 __global__ __launch_bounds__(SSN_BLOCK) void k_dots(int npair, const double* __restrict__ a0,
-                                                    const double* __restrict__ b0, double* r0,
+                                                    const double* __restrict__ b0,
                                                     const double* __restrict__ a1,
-                                                    const double* __restrict__ b1, double* r1,
+                                                    const double* __restrict__ b1,
                                                     const double* __restrict__ a2,
-                                                    const double* __restrict__ b2, double* r2,
-                                                    int64_t len, double* __restrict__ part,
-                                                    unsigned* counter) {
+                                                    const double* __restrict__ b2, int64_t len,
+                                                    double* __restrict__ part) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -38,23 +66,20 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_dots(int npair, const double* __r
         part[blockIdx.x * 3 + 1] = t1;
         part[blockIdx.x * 3 + 2] = t2;
     }
-    if (last_block_arrives(counter)) {
-        const double u0 = grid_colsum(part, gridDim.x, 3, 0, shd);
-        const double u1 = npair > 1 ? grid_colsum(part, gridDim.x, 3, 1, shd) : 0.0;
-        const double u2 = npair > 2 ? grid_colsum(part, gridDim.x, 3, 2, shd) : 0.0;
-        if (threadIdx.x == 0) {
-            *r0 = u0;
-            if (npair > 1) *r1 = u1;
-            if (npair > 2) *r2 = u2;
-        }
-    }
 }
 
 void launch_dots(int npair, const double* a0, const double* b0, double* r0, const double* a1,
                  const double* b1, double* r1, const double* a2, const double* b2, double* r2,
                  int64_t len, double* part, unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_dots, dim3(vec_grid(len)), dim3(SSN_BLOCK), 0, s, npair, a0, b0, r0, a1,
-                       b1, r1, a2, b2, r2, len, part, counter);
+    (void)counter;
+    const unsigned g = vec_grid(len);
+    hipLaunchKernelGGL(k_dots, dim3(g), dim3(SSN_BLOCK), 0, s, npair, a0, b0, a1, b1, a2, b2, len,
+                       part);
+    ColSumDst d = colsum_dst();
+    d.p[0] = r0;
+    d.p[1] = npair > 1 ? r1 : nullptr;
+    d.p[2] = npair > 2 ? r2 : nullptr;
+    launch_colsum_fin(part, (int)g, 3, npair, d, s);
 }
 
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t len) {

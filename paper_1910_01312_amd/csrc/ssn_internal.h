@@ -43,6 +43,19 @@ struct Scalars {
     int    cg_done;
 };
 
+// One-block sums of block-partial columns into scalars (kernels_vec.hip):
+// column c goes to p[c] (skipped when null) as a double times scale[c], or
+// as a long long when as_ll[c]; nothing is written when *skip is nonzero.
+struct ColSumDst {
+    void* p[4];
+    int as_ll[4];
+    double scale[4];
+    const int* skip;
+};
+ColSumDst colsum_dst();
+void launch_colsum_fin(const double* part, int nb, int stride, int ncols, const ColSumDst& d,
+                       hipStream_t s);
+
 // Dense matvecs ----------------------------------------------------------
 void launch_amul_dense(int dtype, const void* X, const int8_t* y, const double* v,
                        double* t, int64_t n, int64_t q, hipStream_t s);
