@@ -97,6 +97,7 @@ struct ssnalm_ctx {
     int32_t* jlist = nullptr;
     // compact column-major copy of X_J (sparse PCG), rebuilt per Newton step
     int32_t *jrank = nullptr, *jr = nullptr, *jc = nullptr;
+    int2* jrow = nullptr;            // entry range of each row of J (sparse input)
     void* jv = nullptr;
     int *tcount = nullptr, *toff = nullptr;
     double *wJ = nullptr, *kcarry = nullptr, *cgpart = nullptr;
@@ -362,7 +363,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
     if (c->kind == SSNALM_CSR) {
         // compact X_J for this Newton step, then fence-free PCG on it
         launch_compact(mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
-        launch_rank_from_list(c->jlist, &dsc(c)->p, c->n, c->jrank, c->st);
+        launch_rank_from_list(c->jlist, &dsc(c)->p, c->n, c->jrank, c->fwd.ptr, c->jrow, c->st);
         launch_jcsc_build(c->tr, mask, c->jrank, c->tcount, c->toff, &dsc(c)->nnzj, c->jr, c->jc,
                           c->jv, c->st);
         STCHK(sync_state(c));
@@ -387,7 +388,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         // decision inside; the kernels stop changing x once the tolerance is met).
         auto cg_iteration = [&](int par) {
             prof_begin(c, SSNALM_K_AMUL_J);
-            launch_cg_rows(c->fwd, c->jlist, p, c->cg_p, c->wJ, Pw, c->st);
+            launch_cg_rows(c->fwd, c->jrow, p, c->cg_p, c->wJ, Pw, c->st);
             prof_end(c, SSNALM_K_AMUL_J, (double)nnzj * (vb + 4.0) + 20.0 * p + 8.0 * c->q,
                      2.0 * (double)nnzj);
             prof_begin(c, SSNALM_K_ATMUL_J);
@@ -796,6 +797,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
         if (!c->use_chol) {
             const int64_t nz = std::max<int64_t>(pr->nnz, 1);
             ALLOC(c->jrank, n); ALLOC(c->jr, nz); ALLOC(c->jc, nz); ALLOC(c->wJ, n);
+            ALLOC(c->jrow, n);
             ALLOC(c->tcount, c->tr.ntile + 1); ALLOC(c->toff, c->tr.ntile + 2);
             ALLOC(c->kcarry, 2 * (nz / 128 + 2)); ALLOC(c->cgpart, 1024 + 512 + 1024);
             if (c->dtype == SSNALM_F64) { double* t; ALLOC(t, nz); c->jv = t; }

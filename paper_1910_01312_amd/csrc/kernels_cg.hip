@@ -88,10 +88,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_init(const double* __restrict_
 // w[k] = (X_J v)_k for the k-th row of the ordered J list; Pw[b] = sum w^2.
 // 16 lanes per row; each lane issues its loads four entries at a time.
 template <typename V>
-__global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int32_t* __restrict__ rp,
+__global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ jrow,
                                                        const int32_t* __restrict__ ci,
-                                                       const V* __restrict__ val,
-                                                       const int32_t* __restrict__ list, int64_t p,
+                                                       const V* __restrict__ val, int64_t p,
                                                        const double* __restrict__ v,
                                                        double* __restrict__ w,
                                                        double* __restrict__ Pw) {
@@ -105,8 +104,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int32_t* __restrict
         const int64_t k = base + grp;
         double acc = 0.0;
         if (k < p) {
-            const int32_t r = list[k];
-            const int32_t e0 = rp[r], e1 = rp[r + 1];
+            const int2 er = jrow[k];
+            const int32_t e0 = er.x, e1 = er.y;
             int32_t e = e0 + sub;
             for (; e + 48 < e1; e += 64) {
                 const int32_t c0 = ci[e], c1 = ci[e + 16], c2 = ci[e + 32], c3 = ci[e + 48];
@@ -140,15 +139,15 @@ unsigned cg_rows_grid(int64_t p) {
     return (unsigned)b;
 }
 
-void launch_cg_rows(const SegPlan& F, const int32_t* list, int64_t p, const double* v, double* w,
+void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double* v, double* w,
                     double* Pw, hipStream_t s) {
     const unsigned g = cg_rows_grid(p);
     if (F.val_f64)
-        hipLaunchKernelGGL((k_cg_rows<double>), dim3(g), dim3(SSN_BLOCK), 0, s, F.ptr, F.idx,
-                           (const double*)F.val, list, p, v, w, Pw);
+        hipLaunchKernelGGL((k_cg_rows<double>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
+                           (const double*)F.val, p, v, w, Pw);
     else
-        hipLaunchKernelGGL((k_cg_rows<float>), dim3(g), dim3(SSN_BLOCK), 0, s, F.ptr, F.idx,
-                           (const float*)F.val, list, p, v, w, Pw);
+        hipLaunchKernelGGL((k_cg_rows<float>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
+                           (const float*)F.val, p, v, w, Pw);
 }
 
 // --------------------------------------------------------------- X_J^T w

@@ -227,12 +227,5 @@ void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStr
 
 int seg_entries_per_lane() { return SEG_E; }
 
-void launch_segsum_fix_only(const SegPlan& P, double* out, hipStream_t s) {
-    if (P.nspan > 0) {
-        const unsigned nf = (unsigned)((P.nspan + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
-        hipLaunchKernelGGL(k_segsum_fix, dim3(nf), dim3(SSN_BLOCK), 0, s, P.span_seg, P.span_t0,
-                           P.span_t1, P.nspan, P.tile_first, P.carry, nullptr, nullptr, out);
-    }
-}
 
 }  // namespace ssn

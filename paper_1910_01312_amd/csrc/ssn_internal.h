@@ -179,21 +179,11 @@ void launch_chol_solve_factored(const double* M, const double* inv, const double
 
 // Sparse products restricted to J (kernels_jcsr.hip) --------------------------
 void launch_rank_from_list(const int32_t* list, const long long* pdev, int64_t n, int32_t* rank,
-                           hipStream_t s);
-// w[k] = (X_J v)_k for the k-th listed row; *mean_out = mean of w
-void launch_rows_fwd(const SegPlan& F, const int32_t* list, int64_t p, const double* v, double* w,
-                     double* mean_out, double* part, unsigned* counter, hipStream_t s);
+                           const int32_t* rp, int2* jrow, hipStream_t s);
 // column-major copy of X_J filtered from the full one (entries: rank, column, value)
 void launch_jcsc_build(const SegPlan& T, const uint8_t* mask, const int32_t* rank, int* tcount,
                        int* toff, long long* total, int32_t* jr, int32_t* jc, void* jv,
                        hipStream_t s);
-// out = X_J^T (w - mean) (mode 0), X_J^T 1 (mode 1) or sum_J X_ij^2 (mode 2)
-void launch_jcsc_tr(int mode, const SegPlan& T, const int* toff, const int32_t* jr,
-                    const int32_t* jc, const void* jv, const double* w, const double* mean,
-                    double* out, int64_t q, hipStream_t s);
-// Ap = p + sigma z, pap = p . Ap
-void launch_mop_pap(const double* pd, const double* z, double sigma, double* Ap, int64_t q,
-                    Scalars* sc, double* part, unsigned* counter, hipStream_t s);
 
 // Fence-free CG on the compact X_J (kernels_cg.hip) ----------------------------
 unsigned cg_qgrid(int64_t q);
@@ -201,7 +191,8 @@ unsigned cg_rows_grid(int64_t p);
 void launch_cg_init(const double* g, const double* diag, const double* sv, int64_t q, double* x,
                     double* r, double* z, double* pd, double* Pst, double* Pdir, hipStream_t s);
 void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, hipStream_t s);
-void launch_cg_rows(const SegPlan& F, const int32_t* list, int64_t p, const double* v, double* w,
+// w[k] = (X_J v)_k for the k-th row of J (entry range jrow[k]); Pw: block sums of w^2
+void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double* v, double* w,
                     double* Pw, hipStream_t s);
 void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
                      int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
