@@ -24,8 +24,9 @@
 
 namespace ssn {
 
-constexpr int PK = 64;            // sub-intervals per pass
+constexpr int PK = 64;            // sub-intervals per pass (one per lane of a wave)
 constexpr int PNV = PK + 1;       // partial values per block: PK+1 g-values
+static_assert(PK == SSN_WAVE, "the pass decision takes one candidate per lane");
 constexpr int PROJ_MAXPASS = 48;
 constexpr int PROJ_GRID_MAX = 256;
 constexpr int PASS_CAP = 2048;    // LDS list of elements evaluated at every candidate
@@ -355,6 +356,16 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
         part[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = s;   // [column][block]
     }
     if (threadIdx.x < PK) hpart[(int64_t)threadIdx.x * PROJ_GRID_MAX + blockIdx.x] = hist[threadIdx.x];
+    if (blockIdx.x == 0) {
+        // zero the slots of the blocks nb .. (next multiple of 64) - 1, which
+        // the decision reads without masks
+        const int nbp = (int)gridDim.x, top = (nbp + SSN_WAVE - 1) / SSN_WAVE * SSN_WAVE;
+        for (int e = threadIdx.x; e < (top - nbp) * PCOL; e += blockDim.x) {
+            const int cc = e / (top - nbp), bb = nbp + e % (top - nbp);
+            part[(int64_t)cc * PROJ_GRID_MAX + bb] = 0.0;
+            if (cc < PICOL) hpart[(int64_t)cc * PROJ_GRID_MAX + bb] = 0;
+        }
+    }
     if (threadIdx.x == 0) {
         long long k2 = 0, l2 = 0;
 #pragma unroll
@@ -369,81 +380,93 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
 // by wave c mod 4: lane l owns blocks l, l+64, l+128, l+192.  A separate
 // launch instead of a last-arriving block: the kernel boundary makes the
 // partials visible without a device-wide fence in every block.
-__global__ __launch_bounds__(SSN_BLOCK) void k_proj_decide(double C, ProjState* st,
-                                                           const double* __restrict__ part,
-                                                           const int* __restrict__ hpart, int nb) {
+constexpr int DEC_THREADS = 1024;
+constexpr int DEC_WAVES = DEC_THREADS / SSN_WAVE;
+__global__ __launch_bounds__(DEC_THREADS) void k_proj_decide(double C, ProjState* st,
+                                                             const double* __restrict__ part,
+                                                             const int* __restrict__ hpart, int nb) {
     __shared__ double lam_s[PK + 1];
     __shared__ double fin[PNV];
     __shared__ int hfin[PK];
     __shared__ long long kfin, linn_fin;
     __shared__ double lins_fin;
+    __shared__ double lred[PCOL][SSN_WAVE];
+    __shared__ int lhred[PICOL][SSN_WAVE];
+    __shared__ int jsel;
     if (ld_grid(&st->done)) return;
     pass_candidates(st, C, lam_s);
     const double blo = st->lo;
     const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
     {
-        constexpr int CPW = (PCOL + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
+        // lane l of wave w sums blocks l, l+64, ... (slots up to the next
+        // multiple of 64 past nb hold zeros) of columns w, w+16, ...; the
+        // per-lane sums go through LDS and thread c adds the 64 of column c in
+        // lane order.  Every load of a wave is issued before any sum.
+        constexpr int CPW = (PCOL + DEC_WAVES - 1) / DEC_WAVES;
         constexpr int BPL = PROJ_GRID_MAX / SSN_WAVE;
-        static_assert(PICOL <= CPW * SSN_WAVES_PER_BLOCK, "int columns per wave");
-        // unconditional loads (column clamped into the arrays, entries of
-        // blocks past nb masked afterwards) so that none waits for another
-        {
-            double vals[CPW][BPL];
+        static_assert(PICOL <= CPW * DEC_WAVES, "int columns per wave");
+        const int jmax = (nb + SSN_WAVE - 1) / SSN_WAVE;
+        double vals[CPW][BPL];
+        int hv[CPW][BPL];
 #pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int cc = min(w + i * SSN_WAVES_PER_BLOCK, PCOL - 1);
+        for (int i = 0; i < CPW; ++i) {
+            const int c = w + i * DEC_WAVES;
 #pragma unroll
-                for (int j = 0; j < BPL; ++j)
-                    vals[i][j] = ld_grid(&part[(int64_t)cc * PROJ_GRID_MAX + lane + j * SSN_WAVE]);
-            }
-#pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int c = w + i * SSN_WAVES_PER_BLOCK;
-                double sum = 0.0;
-#pragma unroll
-                for (int j = 0; j < BPL; ++j) sum += lane + j * SSN_WAVE < nb ? vals[i][j] : 0.0;
-                sum = wave_sum(sum);
-                if (lane == 0) {
-                    if (c < PNV) fin[c] = sum;
-                    else if (c == PNV) lins_fin = sum;
+            for (int j = 0; j < BPL; ++j) {
+                vals[i][j] = 0.0;
+                hv[i][j] = 0;
+                if (j < jmax) {                         // uniform over the wave
+                    if (c < PCOL) vals[i][j] = ld_grid(&part[(int64_t)c * PROJ_GRID_MAX + lane + j * SSN_WAVE]);
+                    if (c < PICOL) hv[i][j] = ld_grid(&hpart[(int64_t)c * PROJ_GRID_MAX + lane + j * SSN_WAVE]);
                 }
             }
         }
-        {
-            int hv[CPW][BPL];
 #pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int cc = min(w + i * SSN_WAVES_PER_BLOCK, PICOL - 1);
+        for (int i = 0; i < CPW; ++i) {
+            const int c = w + i * DEC_WAVES;
+            double sum = 0.0;
+            int hsum = 0;
 #pragma unroll
-                for (int j = 0; j < BPL; ++j)
-                    hv[i][j] = ld_grid(&hpart[(int64_t)cc * PROJ_GRID_MAX + lane + j * SSN_WAVE]);
+            for (int j = 0; j < BPL; ++j) {
+                sum += vals[i][j];
+                hsum += hv[i][j];
             }
-#pragma unroll
-            for (int i = 0; i < CPW; ++i) {
-                const int c = w + i * SSN_WAVES_PER_BLOCK;
-                long long hsum = 0;
-#pragma unroll
-                for (int j = 0; j < BPL; ++j) hsum += lane + j * SSN_WAVE < nb ? hv[i][j] : 0;
-                hsum = wave_sum_ll(hsum);       // integer sums: exact in any order
-                if (lane == 0) {
-                    if (c < PK) hfin[c] = (int)hsum;
-                    else if (c == PK) kfin = hsum;
-                    else if (c == PK + 1) linn_fin = hsum;
-                }
-            }
+            if (c < PCOL) lred[c][lane] = sum;
+            if (c < PICOL) lhred[c][lane] = hsum;
+        }
+        __syncthreads();
+        const int c = threadIdx.x;
+        if (c < PCOL) {
+            double sum = 0.0;
+#pragma unroll 16
+            for (int l = 0; l < SSN_WAVE; ++l) sum += lred[c][l];
+            if (c < PNV) fin[c] = sum;
+            else lins_fin = sum;
+        }
+        if (c < PICOL) {
+            long long hsum = 0;
+#pragma unroll 16
+            for (int l = 0; l < SSN_WAVE; ++l) hsum += lhred[c][l];
+            if (c < PK) hfin[c] = (int)hsum;
+            else if (c == PK) kfin = hsum;
+            else linn_fin = hsum;
         }
     }
     __syncthreads();
     if (threadIdx.x <= PK)
         fin[threadIdx.x] += C * (double)kfin + (double)linn_fin * (lam_s[threadIdx.x] - blo) + lins_fin;
     __syncthreads();
+    // kept sub-interval: the last k < PK with g(lam_k) < 0 (0 if none)
+    if (threadIdx.x < SSN_WAVE) {
+        const unsigned long long neg = __ballot(fin[threadIdx.x] < 0.0);
+        if (threadIdx.x == 0) jsel = neg ? SSN_WAVE - 1 - __clzll((long long)neg) : 0;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         const int passes = st->passes + 1;
         st->passes = passes;
         st->mode = 0;
-        int j = 0;
-        for (int k = 0; k < PK; ++k)
-            if (fin[k] < 0.0) j = k;
+        const int j = jsel;
         const double nlo = lam_s[j], nhi = lam_s[j + 1];
         const double g0 = fin[j], g1 = fin[j + 1];
         const int ins = hfin[j];
@@ -463,8 +486,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_decide(double C, ProjState* 
             lam = fmin(fmax(lam, nlo), nhi);
             st->lam = lam;
             st->approx = (ins == 0) ? 0 : 1;
-            __threadfence();
-            atomicExch(&st->done, 1);
+            st->done = 1;                        // read by later launches only
         }
     }
 }
@@ -476,7 +498,7 @@ void launch_proj_pass(const double* v, const int8_t* y, int64_t n, double C, Pro
     int* hpart = reinterpret_cast<int*>(part + (int64_t)PCOL * PROJ_GRID_MAX);
     const unsigned g = proj_grid(n);
     hipLaunchKernelGGL(k_proj_pass, dim3(g), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, part, hpart);
-    hipLaunchKernelGGL(k_proj_decide, dim3(1), dim3(SSN_BLOCK), 0, s, C, st, part, hpart, (int)g);
+    hipLaunchKernelGGL(k_proj_decide, dim3(1), dim3(DEC_THREADS), 0, s, C, st, part, hpart, (int)g);
 }
 
 // ------------------------------------------------------------------ apply
