@@ -72,9 +72,119 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_amul_dense(const T* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------- forward, q <= 64 VEC
+// Rows that fit one 16-byte piece per lane: lane l covers columns
+// [l VEC, l VEC + VEC) of every row, so its slice of v stays in registers.
+// A wave keeps R rows in flight as raw 16-byte pieces (widened only at the
+// FMA), then a reduce-scatter over the R rows (log2 R exchange steps, each
+// halving the live values) followed by plain xor sums leaves the total of
+// row 4 b5 + 2 b4 + b3 (lane bits, for R = 8) in the lanes whose low bits
+// are zero.  Fixed summation order: deterministic.
+template <typename T, int VEC> struct RawPiece;
+template <> struct RawPiece<double, 2> {
+    uint4 u;
+    __device__ __forceinline__ double get(int e) const {
+        return e == 0 ? __hiloint2double((int)u.y, (int)u.x) : __hiloint2double((int)u.w, (int)u.z);
+    }
+};
+template <> struct RawPiece<float, 4> {
+    uint4 u;
+    __device__ __forceinline__ double get(int e) const {
+        const uint32_t w = e == 0 ? u.x : (e == 1 ? u.y : (e == 2 ? u.z : u.w));
+        return (double)__uint_as_float(w);
+    }
+};
+template <> struct RawPiece<bf16_t, 8> {
+    uint4 u;
+    __device__ __forceinline__ double get(int e) const {
+        const uint32_t w = (e >> 1) == 0 ? u.x : ((e >> 1) == 1 ? u.y : ((e >> 1) == 2 ? u.z : u.w));
+        return (double)__uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+};
+
+template <typename T, int VEC, int R>
+__global__ __launch_bounds__(SSN_BLOCK) void k_amul_rows(const T* __restrict__ X,
+                                                         const int8_t* __restrict__ y,
+                                                         const double* __restrict__ v,
+                                                         double* __restrict__ t, int64_t n,
+                                                         int64_t q) {
+    static_assert(R >= 1 && R <= SSN_WAVE && (R & (R - 1)) == 0, "R: power of two");
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    const int64_t c0 = (int64_t)lane * VEC;
+    const bool full = c0 + VEC <= q;              // this lane's piece is whole
+    double vloc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) vloc[e] = c0 + e < q ? v[c0 + e] : 0.0;
+    for (int64_t r0 = wave * R; r0 < n; r0 += nwave * R) {
+        RawPiece<T, VEC> raw[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int64_t row = r0 + u;
+            raw[u].u = make_uint4(0u, 0u, 0u, 0u);
+            if (row < n) {
+                const T* p = X + row * q + c0;
+                if (full) {
+                    raw[u].u = *reinterpret_cast<const uint4*>(p);
+                } else if (c0 < q) {
+                    T tmp[VEC];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) tmp[e] = c0 + e < q ? p[e] : T(0);
+                    raw[u].u = *reinterpret_cast<const uint4*>(tmp);
+                }
+            }
+        }
+        double acc[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            double a = 0.0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) a = fma(raw[u].get(e), vloc[e], a);
+            acc[u] = a;
+        }
+        // reduce-scatter over the R rows
+#pragma unroll
+        for (int h = SSN_WAVE / 2, live = R; live > 1; h >>= 1, live >>= 1) {
+            const bool up = (lane & h) != 0;
+#pragma unroll
+            for (int j = 0; j < live / 2; ++j) {
+                const double lo_v = acc[j], hi_v = acc[j + live / 2];
+                const double send = up ? lo_v : hi_v;
+                const double keep = up ? hi_v : lo_v;
+                acc[j] = keep + __shfl_xor(send, h, SSN_WAVE);
+            }
+        }
+        double sum = acc[0];
+#pragma unroll
+        for (int h = SSN_WAVE / (2 * R); h >= 1; h >>= 1) sum += __shfl_xor(sum, h, SSN_WAVE);
+        // lane bits above log2(64 / R) name the row
+        const int sub = SSN_WAVE / R;
+        if ((lane & (sub - 1)) == 0) {
+            int u = 0;
+#pragma unroll
+            for (int b = 0, h = SSN_WAVE / 2; (1 << b) < R; ++b, h >>= 1)
+                if (lane & h) u |= (R >> (b + 1));
+            const int64_t row = r0 + u;
+            if (row < n) t[row] = (double)y[row] * sum;
+        }
+    }
+}
+
 template <typename T, int VEC>
 static void amul_dispatch_rows(const T* X, const int8_t* y, const double* v, double* t,
                                int64_t n, int64_t q, hipStream_t s) {
+    if constexpr (VEC * sizeof(T) == 16) {
+      if (q <= (int64_t)SSN_WAVE * VEC) {
+        constexpr int R = 8;
+        int64_t blocks = (n + R * SSN_WAVES_PER_BLOCK - 1) / (R * SSN_WAVES_PER_BLOCK);
+        if (blocks > 8192) blocks = 8192;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL((k_amul_rows<T, VEC, R>), dim3((unsigned)blocks), dim3(SSN_BLOCK), 0, s,
+                           X, y, v, t, n, q);
+        return;
+      }
+    }
     const int use_lds = q <= 8192 ? 1 : 0;
     const size_t shm = use_lds ? (size_t)q * sizeof(double) : 0;
     // enough waves to keep every CU busy; each wave walks rows with a stride
