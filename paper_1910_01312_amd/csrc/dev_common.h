@@ -110,6 +110,63 @@ __device__ __forceinline__ double grid_colsum(const double* part, int nb, int st
     return block_sum((a0 + a1) + (a2 + a3), sh);
 }
 
+// Reduce-scatter over the wave: on entry every lane holds a[0..63]; on exit
+// lane l returns the wave total of a[l].  At each step lanes paired by
+// xor h keep one half of their live values (the upper half if bit h is set)
+// and add the partner's copy of that half: 63 exchanges instead of 64 full
+// wave sums, in a fixed order.
+__device__ __forceinline__ double wave_reduce_scatter64(double (&a)[64]) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+#pragma unroll
+    for (int h = 32; h >= 1; h >>= 1) {
+        const bool up = (lane & h) != 0;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const double lo_v = a[j], hi_v = a[j + h];
+            const double send = up ? lo_v : hi_v;
+            const double keep = up ? hi_v : lo_v;
+            a[j] = keep + __shfl_xor(send, h, SSN_WAVE);
+        }
+    }
+    return a[0];
+}
+
+// block_append for U values per thread (value u of thread t is element
+// u * blockDim + t): one pair of barriers for all U, list order = element order
+template <int U>
+__device__ __forceinline__ int block_append_multi(const bool (&take)[U], const double (&val)[U],
+                                                  double* list, int base,
+                                                  int (*wsum)[SSN_WAVES_PER_BLOCK]) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    unsigned long long m[U];
+    int before[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        m[u] = __ballot(take[u]);
+        before[u] = __popcll(m[u] & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) wsum[u][w] = __popcll(m[u]);
+    }
+    __syncthreads();
+    int off = base;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int ou = 0, tu = 0;
+#pragma unroll
+        for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) {
+            const int c = wsum[u][k];
+            if (k < w) ou += c;
+            tu += c;
+        }
+        if (take[u]) list[off + ou + before[u]] = val[u];
+        off += tu;
+    }
+    return off - base;
+}
+
 __device__ __forceinline__ float bf16_to_f32(bf16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);
 }

@@ -371,8 +371,8 @@ ssnalm_status setup(Batch& B, int32_t count, const ssnalm_problem* probs, const 
     BA(B.items, ni); BA(B.prob_d, np); BA(B.par_d, np); BA(B.bs_d, np);
     BLaunch& L = B.L;
     BA(L.A.wl, ni); BA(L.A.wl_n, 1); BA(L.A.ioff, np); BA(L.A.icnt, np);
-    BA(L.part, ni * std::max<int64_t>(q, 65)); BA(L.part2, ni * q);
-    BA(L.ipart, ni * 65); BA(L.ipart2, ni);
+    BA(L.part, ni * std::max<int64_t>(q, 66)); BA(L.part2, ni * q);
+    BA(L.ipart, ni * 66); BA(L.ipart2, ni);
     BA(L.gwl, gcap); BA(L.gwl_n, 1); BA(L.goff, np); BA(L.gcnt, np);
     BA(L.gpart, (int64_t)gcap * q * q);
 #undef BA

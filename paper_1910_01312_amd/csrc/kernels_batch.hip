@@ -464,14 +464,25 @@ __device__ __forceinline__ double bcand(const ProjState& P, double C, int c) {
 // constant (C or 0) or exactly (lam - lo) + (lo - b) over the whole bracket
 // and are summed in closed form; the others are gathered (thread order) into
 // an LDS list and evaluated at every candidate by the whole block.
+// Per item: the item's partial g-values at the BPK + 1 candidates without
+// the closed-form linear part, its breakpoint histogram, and the closed-form
+// counts (constant part kc, linear count and sum of lo - b), combined by
+// kb_proj_sel.  Elements with a breakpoint inside the bracket go to an LDS
+// list (element order) and are evaluated at every candidate; candidates
+// 0..BPK-1 are reduced over each wave by a reduce-scatter.
+constexpr int BPU = 4;                    // elements per thread per sweep step
+constexpr int BPCOL = BPNV + 1;           // doubles per item: g partials, sum of lo - b
+constexpr int BPICOL = BPK + 2;           // ints per item: histogram, constant count, linear count
+static_assert(BPK == SSN_WAVE, "one candidate per lane in the reduce-scatter");
 __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double* __restrict__ v,
                                                           int w, double* __restrict__ part,
                                                           int* __restrict__ hpart) {
     __shared__ double lam_s[BPK + 1];
-    __shared__ double red[SSN_WAVES_PER_BLOCK][BPNV];
+    __shared__ double red[SSN_WAVES_PER_BLOCK][BPCOL];
+    __shared__ long long redl[SSN_WAVES_PER_BLOCK][2];
     __shared__ int hist[BPK];
     __shared__ double list[BRPI];
-    __shared__ int wsum[SSN_WAVES_PER_BLOCK];
+    __shared__ int wsum[BPU][SSN_WAVES_PER_BLOCK];
     const int nw = *A.wl_n;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < nw; it += gridDim.x) {
@@ -486,35 +497,49 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double*
         if (threadIdx.x < BPK) hist[threadIdx.x] = 0;
         __syncthreads();
         const double blo = lam_s[0], bhi = lam_s[BPK];
-        long long kc = 0;                  // C times this count: exact constant part
-        double lin_n = 0.0, lin_s = 0.0;
+        long long kc = 0, lin_n = 0;       // C times kc: exact constant part
+        double lin_s = 0.0;
         int cnt = 0;
-        for (int base = item.y; base < item.z; base += blockDim.x) {
-            const int r = base + threadIdx.x;
-            bool take = false;
-            double b = 0.0;
-            if (r < item.z) {
-                const double vi = v[Pr.off + r];
-                const bool pos = Pr.y[r] > 0;
-                b = pos ? vi - C : -vi;
-                const double bh = b + C;
-                kc -= pos ? 1 : 0;
-                if (bh <= blo) kc += 1;
-                else if (b >= bhi) {}
-                else if (b <= blo && bh >= bhi) { lin_n += 1.0; lin_s += blo - b; }
-                else take = true;
+        for (int base = item.y; base < item.z; base += blockDim.x * BPU) {
+            double vv[BPU];
+            int yy[BPU];
+#pragma unroll
+            for (int u = 0; u < BPU; ++u) {            // every load of the step first
+                const int r = base + u * (int)blockDim.x + threadIdx.x;
+                vv[u] = r < item.z ? v[Pr.off + r] : 0.0;
+                yy[u] = r < item.z ? (int)Pr.y[r] : 0;
             }
-            cnt += block_append(take, b, list, cnt, wsum);
+            bool take[BPU];
+            double bb[BPU];
+#pragma unroll
+            for (int u = 0; u < BPU; ++u) {
+                const int r = base + u * (int)blockDim.x + threadIdx.x;
+                take[u] = false;
+                bb[u] = 0.0;
+                if (r < item.z) {
+                    const bool pos = yy[u] > 0;
+                    const double b = pos ? vv[u] - C : -vv[u];
+                    const double bh = b + C;
+                    kc -= pos ? 1 : 0;
+                    if (bh <= blo) kc += 1;
+                    else if (b >= bhi) {}
+                    else if (b <= blo && bh >= bhi) { lin_n += 1; lin_s += blo - b; }
+                    else { take[u] = true; bb[u] = b; }
+                }
+            }
+            cnt += block_append_multi<BPU>(take, bb, list, cnt, wsum);
         }
         __syncthreads();
-        double acc[BPK + 1];
+        double acc[BPK];
+        double acc_hi = 0.0;
 #pragma unroll
-        for (int c = 0; c <= BPK; ++c) acc[c] = 0.0;
+        for (int c = 0; c < BPK; ++c) acc[c] = 0.0;
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const double b = list[e];
             const double bh = b + C;
 #pragma unroll
-            for (int c = 0; c <= BPK; ++c) acc[c] += clampd(lam_s[c] - b, 0.0, C);
+            for (int c = 0; c < BPK; ++c) acc[c] += clampd(lam_s[c] - b, 0.0, C);
+            acc_hi += clampd(bhi - b, 0.0, C);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const double t = h ? bh : b;
@@ -528,22 +553,35 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double*
                 }
             }
         }
-        __shared__ long long shk[SSN_WAVES_PER_BLOCK];
-        const long long kblk = block_sum_ll(kc, shk);
-#pragma unroll
-        for (int c = 0; c <= BPK; ++c) {
-            const double s = wave_sum(acc[c] + lin_n * (lam_s[c] - blo) + lin_s);
-            if (lane == 0) red[wv][c] = s;
+        double gk = 0.0, ghi = 0.0;
+        if (cnt > wv * SSN_WAVE) {                 // else this wave's acc are zeros
+            gk = wave_reduce_scatter64(acc);
+            ghi = wave_sum(acc_hi);
+        }
+        const double ls = wave_sum(lin_s);
+        const long long kw = wave_sum_ll(kc), lw = wave_sum_ll(lin_n);
+        red[wv][lane] = gk;
+        if (lane == 0) {
+            red[wv][BPK] = ghi;
+            red[wv][BPK + 1] = ls;
+            redl[wv][0] = kw;
+            redl[wv][1] = lw;
         }
         __syncthreads();
-        if (threadIdx.x < BPNV) {
-            double s = 0.0;
+        if (threadIdx.x < BPCOL) {
+            double s2 = 0.0;
 #pragma unroll
-            for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) s += red[ww][threadIdx.x];
-            part[(int64_t)it * BPNV + threadIdx.x] = s;
+            for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) s2 += red[ww][threadIdx.x];
+            part[(int64_t)it * BPCOL + threadIdx.x] = s2;
         }
-        if (threadIdx.x < BPK) hpart[(int64_t)it * (BPK + 1) + threadIdx.x] = hist[threadIdx.x];
-        if (threadIdx.x == 0) hpart[(int64_t)it * (BPK + 1) + BPK] = (int)kblk;
+        if (threadIdx.x < BPK) hpart[(int64_t)it * BPICOL + threadIdx.x] = hist[threadIdx.x];
+        if (threadIdx.x == 0) {
+            long long k2 = 0, l2 = 0;
+#pragma unroll
+            for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) { k2 += redl[ww][0]; l2 += redl[ww][1]; }
+            hpart[(int64_t)it * BPICOL + BPK] = (int)k2;
+            hpart[(int64_t)it * BPICOL + BPK + 1] = (int)l2;
+        }
     }
 }
 
@@ -560,15 +598,20 @@ __global__ __launch_bounds__(128) void kb_proj_sel(BArgs A, const double* __rest
     if (P.done) return;
     const double C = A.prob[k].C;
     const int i0 = A.ioff[k], ni = A.icnt[k];
-    __shared__ int K;
-    for (int c = threadIdx.x; c <= BPK; c += blockDim.x) {
-        const int h = isum_items(hpart + (int64_t)i0 * (BPK + 1) + c, BPK + 1, ni);
+    __shared__ int K, LN;
+    __shared__ double LS;
+    for (int c = threadIdx.x; c < BPICOL; c += blockDim.x) {
+        const int h = isum_items(hpart + (int64_t)i0 * BPICOL + c, BPICOL, ni);
         if (c < BPK) H[c] = h;
-        else K = h;
+        else if (c == BPK) K = h;
+        else LN = h;
     }
+    if (threadIdx.x == 0) LS = sum_items(part + (int64_t)i0 * BPCOL + BPNV, BPCOL, ni);
     __syncthreads();
+    const double blo = bcand(P, C, 0);
     for (int c = threadIdx.x; c < BPNV; c += blockDim.x)
-        G[c] = sum_items(part + (int64_t)i0 * BPNV + c, BPNV, ni) + C * (double)K;
+        G[c] = sum_items(part + (int64_t)i0 * BPCOL + c, BPCOL, ni) + C * (double)K +
+               (double)LN * (bcand(P, C, c) - blo) + LS;
     __syncthreads();
     if (threadIdx.x != 0) return;
     const int passes = P.passes + 1;

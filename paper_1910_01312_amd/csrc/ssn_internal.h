@@ -274,7 +274,7 @@ struct BLaunch {
     BArgs  A;
     int    dtype, vec, unr, grid, ggrid;
     double *part, *part2;      // item partials (max(q, 65) doubles per item)
-    int    *ipart, *ipart2;    // item partials (64 ints per item), item offsets
+    int    *ipart, *ipart2;    // item partials (66 ints per item), item offsets
     int4*  gwl;                // Gram work list and its per-problem offsets / counts
     int*   gwl_n;
     int    *goff, *gcnt;
