@@ -167,6 +167,29 @@ __device__ __forceinline__ int block_append_multi(const bool (&take)[U], const d
     return off - base;
 }
 
+// A 16-byte piece of a row kept raw in registers and widened to fp64 at use.
+template <typename T, int VEC> struct RawPiece;
+template <> struct RawPiece<double, 2> {
+    uint4 u;
+    __device__ __forceinline__ double get(int e) const {
+        return e == 0 ? __hiloint2double((int)u.y, (int)u.x) : __hiloint2double((int)u.w, (int)u.z);
+    }
+};
+template <> struct RawPiece<float, 4> {
+    uint4 u;
+    __device__ __forceinline__ double get(int e) const {
+        const uint32_t w = e == 0 ? u.x : (e == 1 ? u.y : (e == 2 ? u.z : u.w));
+        return (double)__uint_as_float(w);
+    }
+};
+template <> struct RawPiece<bf16_t, 8> {
+    uint4 u;
+    __device__ __forceinline__ double get(int e) const {
+        const uint32_t w = (e >> 1) == 0 ? u.x : ((e >> 1) == 1 ? u.y : ((e >> 1) == 2 ? u.z : u.w));
+        return (double)__uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+};
+
 __device__ __forceinline__ float bf16_to_f32(bf16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);
 }

@@ -189,6 +189,82 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_amul(BArgs A, const double* __re
     }
 }
 
+// Rows of 16-byte-aligned data: P lanes (a power of two) cover a row in
+// 16-byte pieces, G = 64 / P rows per load; a wave keeps R loads (R G rows)
+// in flight as raw pieces, the lane's slice of v_k in registers.  Within each
+// P-lane group a reduce-scatter over the R row sums (log2 R steps) and xor
+// sums over the remaining lanes leave row u's total in the group's lanes
+// whose position is a multiple of P / R.
+template <typename T, int P, int R>
+__global__ __launch_bounds__(SSN_BLOCK) void kb_amul2(BArgs A, const double* __restrict__ V,
+                                                      double* __restrict__ t) {
+    static_assert(R <= P && (P & (P - 1)) == 0 && (R & (R - 1)) == 0, "P, R: powers of two, R <= P");
+    constexpr int VE = BVec<T>::V;
+    constexpr int G = SSN_WAVE / P;
+    const int nw = *A.wl_n, q = A.q;
+    const int lane = threadIdx.x & (SSN_WAVE - 1), wv = threadIdx.x / SSN_WAVE;
+    const int pl = lane & (P - 1), g = lane / P;
+    const int c0 = pl * VE;
+    for (int it = blockIdx.x; it < nw; it += gridDim.x) {
+        const int4 item = A.wl[it];
+        const int k = item.x;
+        const BProb Pr = A.prob[k];
+        double vloc[VE];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) vloc[e] = c0 + e < q ? V[(int64_t)k * q + c0 + e] : 0.0;
+        const T* X = (const T*)Pr.X;
+        for (int r0 = item.y + wv * R * G; r0 < item.z; r0 += SSN_WAVES_PER_BLOCK * R * G) {
+            RawPiece<T, VE> raw[R];
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int row = r0 + u * G + g;
+                raw[u].u = make_uint4(0u, 0u, 0u, 0u);
+                if (row < item.z && c0 < q) {
+                    const T* p = X + (int64_t)row * q + c0;
+                    if (c0 + VE <= q) {
+                        raw[u].u = *reinterpret_cast<const uint4*>(p);
+                    } else {
+                        T tmp[VE];
+#pragma unroll
+                        for (int e = 0; e < VE; ++e) tmp[e] = c0 + e < q ? p[e] : T(0);
+                        raw[u].u = *reinterpret_cast<const uint4*>(tmp);
+                    }
+                }
+            }
+            double acc[R];
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                double a = 0.0;
+#pragma unroll
+                for (int e = 0; e < VE; ++e) a = fma(raw[u].get(e), vloc[e], a);
+                acc[u] = a;
+            }
+#pragma unroll
+            for (int h = P / 2, live = R; live > 1; h >>= 1, live >>= 1) {
+                const bool up = (pl & h) != 0;
+#pragma unroll
+                for (int j = 0; j < live / 2; ++j) {
+                    const double lo_v = acc[j], hi_v = acc[j + live / 2];
+                    const double send = up ? lo_v : hi_v;
+                    const double keep = up ? hi_v : lo_v;
+                    acc[j] = keep + __shfl_xor(send, h, SSN_WAVE);
+                }
+            }
+            double sum = acc[0];
+#pragma unroll
+            for (int h = P / (2 * R); h >= 1; h >>= 1) sum += __shfl_xor(sum, h, SSN_WAVE);
+            if ((pl & (P / R - 1)) == 0) {
+                int u = 0;
+#pragma unroll
+                for (int b = 0; (1 << b) < R; ++b)
+                    if (pl & (P >> (b + 1))) u |= R >> (b + 1);
+                const int row = r0 + u * G + g;
+                if (row < item.z) t[Pr.off + row] = (double)Pr.y[row] * sum;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ A^T z
 // part[it*q + c] = sum over the item's rows of y_r z_r X_rc; part2 likewise
 // with the 0/1 mask (X_J^T 1).  Rows with zero coefficients are skipped.
@@ -1000,8 +1076,30 @@ __global__ __launch_bounds__(1024) void kb_chol(BArgs A, const double* __restric
 }
 
 // ------------------------------------------------------------------ launchers
+template <typename T, int P>
+static void amul2_t(const BLaunch& L, const double* V, double* t) {
+    constexpr int R = P < 8 ? P : 8;
+    hipLaunchKernelGGL((kb_amul2<T, P, R>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
+}
 template <typename T, bool VEC>
 static void amul_t(const BLaunch& L, const double* V, double* t) {
+    if (VEC) {
+        // lanes per row: 16-byte pieces of a row, rounded up to a power of two
+        const int pieces = (L.A.q * (int)sizeof(T) + 15) / 16;
+        int P = 1;
+        while (P < pieces) P <<= 1;
+        if (P <= SSN_WAVE) {
+            switch (P) {
+            case 1: amul2_t<T, 1>(L, V, t); return;
+            case 2: amul2_t<T, 2>(L, V, t); return;
+            case 4: amul2_t<T, 4>(L, V, t); return;
+            case 8: amul2_t<T, 8>(L, V, t); return;
+            case 16: amul2_t<T, 16>(L, V, t); return;
+            case 32: amul2_t<T, 32>(L, V, t); return;
+            default: amul2_t<T, 64>(L, V, t); return;
+            }
+        }
+    }
     if (L.unr == 1)
         hipLaunchKernelGGL((kb_amul<T, VEC, 1>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
     else if (L.unr == 2)

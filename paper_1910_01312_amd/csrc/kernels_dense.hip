@@ -80,28 +80,6 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_amul_dense(const T* __restrict__ 
 // halving the live values) followed by plain xor sums leaves the total of
 // row 4 b5 + 2 b4 + b3 (lane bits, for R = 8) in the lanes whose low bits
 // are zero.  Fixed summation order: deterministic.
-template <typename T, int VEC> struct RawPiece;
-template <> struct RawPiece<double, 2> {
-    uint4 u;
-    __device__ __forceinline__ double get(int e) const {
-        return e == 0 ? __hiloint2double((int)u.y, (int)u.x) : __hiloint2double((int)u.w, (int)u.z);
-    }
-};
-template <> struct RawPiece<float, 4> {
-    uint4 u;
-    __device__ __forceinline__ double get(int e) const {
-        const uint32_t w = e == 0 ? u.x : (e == 1 ? u.y : (e == 2 ? u.z : u.w));
-        return (double)__uint_as_float(w);
-    }
-};
-template <> struct RawPiece<bf16_t, 8> {
-    uint4 u;
-    __device__ __forceinline__ double get(int e) const {
-        const uint32_t w = (e >> 1) == 0 ? u.x : ((e >> 1) == 1 ? u.y : ((e >> 1) == 2 ? u.z : u.w));
-        return (double)__uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
-    }
-};
-
 template <typename T, int VEC, int R>
 __global__ __launch_bounds__(SSN_BLOCK) void k_amul_rows(const T* __restrict__ X,
                                                          const int8_t* __restrict__ y,
