@@ -34,6 +34,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic of a kernel class per launch, from two rocprofv3 --pmc runs of
+# `bench.py --traffic-op CLASS` (FETCH_SIZE, then WRITE_SIZE, KiB summed over
+# the class's kernels and divided by the op calls), each scaled by what the
+# same counter reads for a plain 1 GiB device copy (profiles/ records the
+# commands and readings).  Reported only while the sources of those kernels
+# are byte-identical to the ones measured (sha256 of each file below).
+MEASURED_TRAFFIC = {}
+
+
+def _sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload, cls):
+    m = MEASURED_TRAFFIC.get((workload, cls))
+    if not m:
+        return None
+    for rel, digest in m["files"].items():
+        if _sha256(os.path.join(ROOT, rel)) != digest:
+            return None
+    return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024.0 / m["calls"]
+
+
+# the kernels of each class that a traffic probe sums, and their sources
+TRAFFIC_KERNELS = {
+    "atmul": (["k_mul_y", "k_segsum<float, false>", "k_segsum_fix", "k_scale_copy"],
+              ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/kernels_vec.hip",
+               "paper_1910_01312_amd/csrc/dev_common.h"]),
+}
+
+
 def make_workload(name, C=None):
     import numpy as np
     import synth
@@ -310,6 +343,10 @@ def main():
     ap.add_argument("--count", type=int, default=256, help="batched workload: number of QPs")
     ap.add_argument("--no-seq", action="store_true", help="batched workload: skip the one-by-one solves")
     ap.add_argument("--keep-frac", type=float, default=0.15, help="warm-start workload: rows kept")
+    ap.add_argument("--traffic-op", default=None, choices=[None, "atmul"],
+                    help="run only this kernel class (--reps times after one warm-up) for a "
+                         "rocprofv3 --pmc traffic reading, then exit")
+    ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device 3 times (a plain copy "
                          "kernel of known size, to scale HBM counter readings)")
@@ -355,6 +392,18 @@ def main():
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t
     log(f"[bench] create {create_s:.2f} s")
+    if args.traffic_op:
+        # A^T z with z of the solution's shape (the op reads every entry of X
+        # whatever z holds)
+        z = torch.rand(s.n, dtype=torch.float64, device="cuda")
+        for _ in range(args.reps + 1):
+            s.atmul(z)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_op": args.traffic_op, "calls": args.reps + 1,
+                          "kernels": TRAFFIC_KERNELS[args.traffic_op][0]}), flush=True)
+        s.close()
+        calib(args)
+        return
 
     # Warm-up solves time every kernel class (launched one by one); the timed
     # solves time only the dominant class among those that stay outside the
@@ -404,7 +453,8 @@ def main():
             achieved = k["bytes"] / k["launches"] / avg / 1e9
             roofline = {"bound": "hbm", "kernel": best, "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": None, "bytes_per_launch": k["bytes"] / k["launches"],
+                        "traffic": measured_traffic(args.workload, best),
+                        "bytes_per_launch": k["bytes"] / k["launches"],
                         "avg_launch_us": avg * 1e6, "launches": k["launches"]}
 
     # correctness of the timed result, checked by the oracle's own KKT code
@@ -457,15 +507,22 @@ def main():
     }
     s.close()
     print(json.dumps(out), flush=True)
-    if args.calib_copy_mb:
-        nb = args.calib_copy_mb * (1 << 20)
-        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        src.fill_(1)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copies of {args.calib_copy_mb} MiB done")
+    calib(args)
+
+
+def calib(args):
+    """Plain device-to-device copies of known size (scale of the counters)."""
+    if not args.calib_copy_mb:
+        return
+    import torch
+    nb = args.calib_copy_mb * (1 << 20)
+    src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copies of {args.calib_copy_mb} MiB done")
 
 
 if __name__ == "__main__":

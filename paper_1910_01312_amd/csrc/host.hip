@@ -98,6 +98,8 @@ struct ssnalm_ctx {
     // compact column-major copy of X_J (sparse PCG), rebuilt per Newton step
     int32_t *jrank = nullptr, *jr = nullptr, *jc = nullptr;
     int2* jrow = nullptr;            // entry range of each row of J (sparse input)
+    uint32_t* jbits = nullptr;       // the J mask as bits (sparse input)
+    int32_t* tcol = nullptr;         // column of every entry of the CSC copy (sparse input)
     void* jv = nullptr;
     int *tcount = nullptr, *toff = nullptr;
     double *wJ = nullptr, *kcarry = nullptr, *cgpart = nullptr;
@@ -364,8 +366,8 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         // compact X_J for this Newton step, then fence-free PCG on it
         launch_compact(mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
         launch_rank_from_list(c->jlist, &dsc(c)->p, c->n, c->jrank, c->fwd.ptr, c->jrow, c->st);
-        launch_jcsc_build(c->tr, mask, c->jrank, c->tcount, c->toff, &dsc(c)->nnzj, c->jr, c->jc,
-                          c->jv, c->st);
+        launch_jcsc_build(c->tr, c->tcol, mask, c->n, c->jbits, c->jrank, c->tcount, c->toff,
+                          &dsc(c)->nnzj, c->jr, c->jc, c->jv, c->st);
         STCHK(sync_state(c));
         const int64_t nnzj = c->hs->sc.nnzj;
         const int vf64 = c->dtype == SSNALM_F64;
@@ -672,6 +674,15 @@ static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
             memcpy(cv.data() + vb * d, vals.data() + vb * k, vb);
         }
     STCHK(build_plan(c, &c->tr, q, nnz, cp, ri, cv.data(), vb == 8));
+    // the column of every CSC entry (the J filter copies it per kept entry)
+    {
+        std::vector<int32_t> tc(std::max<int64_t>(nnz, 1), 0);
+        for (int64_t j = 0; j < q; ++j)
+            for (int32_t k = cp[j]; k < cp[j + 1]; ++k) tc[k] = (int32_t)j;
+        STCHK(dalloc(c, &c->tcol, std::max<int64_t>(nnz, 1)));
+        if (hipMemcpy(c->tcol, tc.data(), sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(SSNALM_E_HIP, "upload of the CSC columns failed");
+    }
     return SSNALM_OK;
 }
 
@@ -797,7 +808,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
         if (!c->use_chol) {
             const int64_t nz = std::max<int64_t>(pr->nnz, 1);
             ALLOC(c->jrank, n); ALLOC(c->jr, nz); ALLOC(c->jc, nz); ALLOC(c->wJ, n);
-            ALLOC(c->jrow, n);
+            ALLOC(c->jrow, n); ALLOC(c->jbits, jcsc_bits_words(n));
             ALLOC(c->tcount, c->tr.ntile + 1); ALLOC(c->toff, c->tr.ntile + 2);
             ALLOC(c->kcarry, 2 * (nz / 128 + 2)); ALLOC(c->cgpart, 1024 + 512 + 1024);
             if (c->dtype == SSNALM_F64) { double* t; ALLOC(t, nz); c->jv = t; }

@@ -44,149 +44,251 @@ void launch_rank_from_list(const int32_t* list, const long long* pdev, int64_t n
 }
 
 // ------------------------------------------------------------------ filter
-// Per full tile: number of entries whose row is in J.
+// The J mask as bits (word w holds rows 32w .. 32w+31), so that the filter
+// kernels keep it in LDS: every membership test is an LDS read instead of a
+// scattered global byte load.
+constexpr int JBITS_MAX_WORDS = 40960;         // 160 KiB of LDS: n <= 1310720 rows
+int jcsc_bits_words(int64_t n) { return (int)((n + 31) / 32); }
+bool jcsc_bits_fit(int64_t n) { return jcsc_bits_words(n) <= JBITS_MAX_WORDS; }
+
+__global__ void k_mask_bits(const uint8_t* __restrict__ mask, int64_t n, uint32_t* __restrict__ bits) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w * 32 >= n) return;
+    uint32_t b = 0;
+    const int64_t r0 = w * 32;
+    if (r0 + 32 <= n) {
+        const uint4* p = reinterpret_cast<const uint4*>(mask + r0);   // 32-byte aligned: r0 % 32 == 0
+        const uint4 u0 = p[0], u1 = p[1];
+        const uint32_t v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b |= ((v[i] >> (8 * j)) & 0xffu ? 1u : 0u) << (4 * i + j);
+    } else {
+        for (int64_t r = r0; r < n; ++r) b |= (mask[r] ? 1u : 0u) << (r - r0);
+    }
+    bits[w] = b;
+}
+
+// Stage the bit mask in LDS (dynamic, nw words) by the whole block, or (for
+// masks beyond the LDS) read it from global memory, where it is L2-resident.
+template <bool LDS>
+__device__ __forceinline__ const uint32_t* stage_bits(const uint32_t* __restrict__ bits, int nw,
+                                                      uint32_t* sb) {
+    if (!LDS) return bits;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) sb[i] = bits[i];
+    __syncthreads();
+    return sb;
+}
+__device__ __forceinline__ bool in_j(const uint32_t* mb, int32_t r) {
+    return (mb[r >> 5] >> (r & 31)) & 1u;
+}
+
+// Per full tile: number of entries whose row is in J.  Persistent blocks,
+// each with the mask in LDS; one wave per tile, 8 entries per lane read as
+// two 16-byte loads.
+template <bool LDS>
 __global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_count(const int32_t* __restrict__ ridx,
                                                           int64_t nnz, int64_t ntile,
-                                                          const uint8_t* __restrict__ mask,
+                                                          const uint32_t* __restrict__ bits, int nw,
                                                           int* __restrict__ tcount) {
+    extern __shared__ uint32_t sbuf[];
+    const uint32_t* sb = stage_bits<LDS>(bits, nw, sbuf);
     const int lane = threadIdx.x & (SSN_WAVE - 1);
-    const int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
-    if (t >= ntile) return;
-    const int64_t k0 = t * JTILE + (int64_t)lane * JE;
-    int c = 0;
+    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    for (int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE; t < ntile;
+         t += nwave) {
+        const int64_t k0 = t * JTILE + (int64_t)lane * JE;
+        int32_t row[JE];
+        if (k0 + JE <= nnz) {
+            const int4* ip = reinterpret_cast<const int4*>(ridx + k0);
+            const int4 i0 = ip[0], i1 = ip[1];
+            row[0] = i0.x; row[1] = i0.y; row[2] = i0.z; row[3] = i0.w;
+            row[4] = i1.x; row[5] = i1.y; row[6] = i1.z; row[7] = i1.w;
+        } else {
 #pragma unroll
-    for (int e = 0; e < JE; ++e) {
-        const int64_t k = k0 + e;
-        if (k < nnz) c += mask[ridx[k]] ? 1 : 0;
+            for (int e = 0; e < JE; ++e) row[e] = k0 + e < nnz ? ridx[k0 + e] : -1;
+        }
+        int c = 0;
+#pragma unroll
+        for (int e = 0; e < JE; ++e) c += (row[e] >= 0 && in_j(sb, row[e])) ? 1 : 0;
+#pragma unroll
+        for (int off = SSN_WAVE / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, SSN_WAVE);
+        if (lane == 0) tcount[t] = c;
     }
-    c = (int)wave_sum_ll(c);
-    if (lane == 0) tcount[t] = c;
 }
 
-// Exclusive scan of tcount[0..ntile) into toff[0..ntile] by one block of
-// 1024 threads, 8192 entries per round: a coalesced load into LDS, a
-// sequential scan of 8 entries per thread, a wave scan and a scan of the 16
-// wave totals.  Integer sums: exact.  *total = toff[ntile].
+// Exclusive scan of tcount[0..ntile) into toff[0..ntile]: block b scans tiles
+// [8192 b, 8192 b + 8192) after summing every count before them itself (so
+// no block waits on another), with 1024 threads: a coalesced load into LDS,
+// a sequential scan of 8 entries per thread, a wave scan and a scan of the
+// 16 wave totals.  Integer sums: exact.  The last block writes toff[ntile]
+// and *total.
+constexpr int SCAN_CHUNK = 8192;
 __global__ __launch_bounds__(1024) void k_scan_tiles(const int* __restrict__ tcount, int64_t ntile,
                                                      int* __restrict__ toff, long long* total) {
-    __shared__ int buf[8192];
+    __shared__ int buf[SCAN_CHUNK];
     __shared__ long long wtot[16];
-    __shared__ long long round_tot;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    long long carry = 0;
-    for (int64_t base = 0; base < ntile; base += 8192) {
-        for (int i = tid; i < 8192; i += 1024) {
-            const int64_t k = base + i;
-            buf[i] = k < ntile ? tcount[k] : 0;
-        }
-        __syncthreads();
-        int loc[8];
-        long long s = 0;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            loc[e] = (int)s;
-            s += buf[tid * 8 + e];
+    for (int i = tid; i < SCAN_CHUNK; i += 1024) {
+        const int64_t k = base + i;
+        buf[i] = k < ntile ? tcount[k] : 0;
+    }
+    // the sum of every count before this chunk (base is a multiple of 4:
+    // 16-byte loads of the 16-byte aligned count array)
+    long long pre = 0;
+    {
+        const int4* q4 = reinterpret_cast<const int4*>(tcount);
+        const int64_t n4 = base / 4;
+        for (int64_t i = tid; i < n4; i += 1024) {
+            const int4 v = q4[i];
+            pre += (long long)v.x + v.y + v.z + v.w;
         }
-        long long incl = s;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long o = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += o;
-        }
-        if (lane == 63) wtot[wv] = incl;
+        pre = wave_sum_ll(pre);
+        if (lane == 0) wtot[wv] = pre;
         __syncthreads();
-        if (tid == 0) {
-            long long run = 0;
-            for (int k = 0; k < 16; ++k) {
-                const long long t = wtot[k];
-                wtot[k] = run;
-                run += t;
-            }
-            round_tot = run;
-        }
-        __syncthreads();
-        const long long excl = carry + wtot[wv] + incl - s;
+        pre = 0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t k = base + tid * 8 + e;
-            if (k < ntile) toff[k] = (int)(excl + loc[e]);
-        }
-        carry += round_tot;
+        for (int k = 0; k < 16; ++k) pre += wtot[k];
         __syncthreads();
     }
-    if (tid == 0) {
-        toff[ntile] = (int)carry;
-        *total = carry;
-    }
-}
-
-// Write the kept entries of full tile t at toff[t] + (rank among the tile's
-// kept entries), in the full copy's order (columns ascending).
-template <typename V>
-__global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_write(
-    const int32_t* __restrict__ cptr, const int32_t* __restrict__ ridx, const V* __restrict__ val,
-    int64_t nnz, int64_t ntile, const int32_t* __restrict__ lane_seg,
-    const uint8_t* __restrict__ mask, const int32_t* __restrict__ rank,
-    const int* __restrict__ toff, int32_t* __restrict__ jr, int32_t* __restrict__ jc,
-    V* __restrict__ jv) {
-    const int lane = threadIdx.x & (SSN_WAVE - 1);
-    const int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
-    if (t >= ntile) return;
-    const int64_t k0 = t * JTILE + (int64_t)lane * JE;
-    bool keep[JE];
-    int32_t row[JE];
-    int c = 0;
+    int loc[8];
+    long long s = 0;
 #pragma unroll
-    for (int e = 0; e < JE; ++e) {
-        const int64_t k = k0 + e;
-        row[e] = k < nnz ? ridx[k] : 0;
-        keep[e] = k < nnz && mask[row[e]];
-        c += keep[e] ? 1 : 0;
+    for (int e = 0; e < 8; ++e) {
+        loc[e] = (int)s;
+        s += buf[tid * 8 + e];
     }
-    // exclusive prefix of c over the lanes of the wave
-    int incl = c;
+    long long incl = s;
 #pragma unroll
-    for (int off = 1; off < SSN_WAVE; off <<= 1) {
-        const int o = __shfl_up(incl, off, SSN_WAVE);
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long o = __shfl_up(incl, off, 64);
         if (lane >= off) incl += o;
     }
-    int pos = toff[t] + incl - c;
-    if (c == 0) return;
-    int32_t seg = lane_seg[t * SSN_WAVE + lane];
-    int64_t segend = cptr[seg + 1];
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    long long wbefore = 0, ctot = 0;
 #pragma unroll
-    for (int e = 0; e < JE; ++e) {
-        const int64_t k = k0 + e;
-        if (k >= nnz) break;
-        while (k >= segend) {
-            ++seg;
-            segend = cptr[seg + 1];
+    for (int k = 0; k < 16; ++k) {
+        if (k < wv) wbefore += wtot[k];
+        ctot += wtot[k];
+    }
+    const long long excl = pre + wbefore + incl - s;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t k = base + tid * 8 + e;
+        if (k < ntile) toff[k] = (int)(excl + loc[e]);
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) {
+        toff[ntile] = (int)(pre + ctot);
+        *total = pre + ctot;
+    }
+}
+
+// Write the kept entries of full tile t from toff[t] on, in the full copy's
+// order (columns ascending).  Lane l of the wave takes entries
+// 64 e + l of the tile, so the kept entries of one step e are consecutive in
+// the output: a ballot gives each its place and every store of the step
+// lands in one contiguous run.  Persistent blocks with the mask in LDS, as
+// the count; tcol gives the column of every entry of the full copy.
+template <typename V, bool LDS>
+__global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_write(
+    const int32_t* __restrict__ tcol, const int32_t* __restrict__ ridx, const V* __restrict__ val,
+    int64_t nnz, int64_t ntile, const uint32_t* __restrict__ bits, int nw,
+    const int32_t* __restrict__ rank,
+    const int* __restrict__ toff, int32_t* __restrict__ jr, int32_t* __restrict__ jc,
+    V* __restrict__ jv) {
+    extern __shared__ uint32_t sbuf[];
+    const uint32_t* sb = stage_bits<LDS>(bits, nw, sbuf);
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    for (int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE; t < ntile;
+         t += nwave) {
+        const int64_t k0 = t * JTILE + lane;
+        int32_t row[JE];
+#pragma unroll
+        for (int e = 0; e < JE; ++e) {
+            const int64_t k = k0 + (int64_t)e * SSN_WAVE;
+            row[e] = k < nnz ? ridx[k] : -1;
         }
-        if (keep[e]) {
-            jr[pos] = rank[row[e]];
-            jc[pos] = seg;
-            jv[pos] = val[k];
-            ++pos;
+        int pos = toff[t];
+        bool keep[JE];
+        int at[JE];
+#pragma unroll
+        for (int e = 0; e < JE; ++e) {
+            keep[e] = row[e] >= 0 && in_j(sb, row[e]);
+            const unsigned long long m = __ballot(keep[e]);
+            at[e] = pos + __popcll(m & below);
+            pos += __popcll(m);
+        }
+        // every gather of the tile in flight before the first store
+        int32_t rk[JE], cl[JE];
+        V vv[JE];
+#pragma unroll
+        for (int e = 0; e < JE; ++e) {
+            const int64_t k = k0 + (int64_t)e * SSN_WAVE;
+            rk[e] = keep[e] ? rank[row[e]] : 0;
+            cl[e] = keep[e] ? tcol[k] : 0;
+            vv[e] = keep[e] ? val[k] : V(0);
+        }
+#pragma unroll
+        for (int e = 0; e < JE; ++e) {
+            if (keep[e]) {
+                jr[at[e]] = rk[e];
+                jc[at[e]] = cl[e];
+                jv[at[e]] = vv[e];
+            }
         }
     }
 }
 
-void launch_jcsc_build(const SegPlan& T, const uint8_t* mask, const int32_t* rank, int* tcount,
-                       int* toff, long long* total, int32_t* jr, int32_t* jc, void* jv,
-                       hipStream_t s) {
-    const unsigned nb = (unsigned)((T.ntile + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
-    if (T.ntile == 0) return;
-    hipLaunchKernelGGL(k_jcsc_count, dim3(nb), dim3(SSN_BLOCK), 0, s, T.idx, T.nnz, T.ntile, mask,
-                       tcount);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, tcount, T.ntile, toff, total);
+template <bool LDS>
+static void jcsc_build_t(const SegPlan& T, const int32_t* tcol, const uint32_t* bits, int nw,
+                         const int32_t* rank,
+                         int* tcount, int* toff, long long* total, int32_t* jr, int32_t* jc, void* jv,
+                         hipStream_t s) {
+    const size_t shm = LDS ? (size_t)nw * sizeof(uint32_t) : 0;
+    static bool attr = false;
+    if (LDS && !attr) {
+        const int mx = JBITS_MAX_WORDS * (int)sizeof(uint32_t);
+        hipFuncSetAttribute((const void*)k_jcsc_count<LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        hipFuncSetAttribute((const void*)k_jcsc_write<float, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        hipFuncSetAttribute((const void*)k_jcsc_write<double, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        attr = true;
+    }
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t nb = (T.ntile + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
+    if (nb > 2 * (int64_t)ncu) nb = 2 * (int64_t)ncu;    // each block stages the mask once
+    hipLaunchKernelGGL((k_jcsc_count<LDS>), dim3((unsigned)nb), dim3(SSN_BLOCK), shm, s, T.idx, T.nnz,
+                       T.ntile, bits, nw, tcount);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)((T.ntile + SCAN_CHUNK - 1) / SCAN_CHUNK)), dim3(1024),
+                       0, s, tcount, T.ntile, toff, total);
     if (T.val_f64)
-        hipLaunchKernelGGL((k_jcsc_write<double>), dim3(nb), dim3(SSN_BLOCK), 0, s, T.ptr, T.idx,
-                           (const double*)T.val, T.nnz, T.ntile, T.lane_seg, mask, rank, toff, jr,
-                           jc, (double*)jv);
+        hipLaunchKernelGGL((k_jcsc_write<double, LDS>), dim3((unsigned)nb), dim3(SSN_BLOCK), shm, s,
+                           tcol, T.idx, (const double*)T.val, T.nnz, T.ntile, bits, nw, rank, toff,
+                           jr, jc, (double*)jv);
     else
-        hipLaunchKernelGGL((k_jcsc_write<float>), dim3(nb), dim3(SSN_BLOCK), 0, s, T.ptr, T.idx,
-                           (const float*)T.val, T.nnz, T.ntile, T.lane_seg, mask, rank, toff, jr,
-                           jc, (float*)jv);
+        hipLaunchKernelGGL((k_jcsc_write<float, LDS>), dim3((unsigned)nb), dim3(SSN_BLOCK), shm, s,
+                           tcol, T.idx, (const float*)T.val, T.nnz, T.ntile, bits, nw, rank, toff,
+                           jr, jc, (float*)jv);
+}
+
+void launch_jcsc_build(const SegPlan& T, const int32_t* tcol, const uint8_t* mask, int64_t n,
+                       uint32_t* bits,
+                       const int32_t* rank, int* tcount, int* toff, long long* total, int32_t* jr,
+                       int32_t* jc, void* jv, hipStream_t s) {
+    if (T.ntile == 0) return;
+    const int nw = jcsc_bits_words(n);
+    hipLaunchKernelGGL(k_mask_bits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mask, n, bits);
+    if (jcsc_bits_fit(n))
+        jcsc_build_t<true>(T, tcol, bits, nw, rank, tcount, toff, total, jr, jc, jv, s);
+    else
+        jcsc_build_t<false>(T, tcol, bits, nw, rank, tcount, toff, total, jr, jc, jv, s);
 }
 
 }  // namespace ssn

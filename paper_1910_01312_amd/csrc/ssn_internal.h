@@ -181,9 +181,15 @@ void launch_chol_solve_factored(const double* M, const double* inv, const double
 void launch_rank_from_list(const int32_t* list, const long long* pdev, int64_t n, int32_t* rank,
                            const int32_t* rp, int2* jrow, hipStream_t s);
 // column-major copy of X_J filtered from the full one (entries: rank, column, value)
-void launch_jcsc_build(const SegPlan& T, const uint8_t* mask, const int32_t* rank, int* tcount,
-                       int* toff, long long* total, int32_t* jr, int32_t* jc, void* jv,
-                       hipStream_t s);
+// the J mask is turned into bits (jcsc_bits_words(n) words of scratch in
+// bits), staged in LDS when it fits (jcsc_bits_fit: n <= 1310720 rows)
+int  jcsc_bits_words(int64_t n);
+bool jcsc_bits_fit(int64_t n);
+// tcol: the column of every entry of T
+void launch_jcsc_build(const SegPlan& T, const int32_t* tcol, const uint8_t* mask, int64_t n,
+                       uint32_t* bits,
+                       const int32_t* rank, int* tcount, int* toff, long long* total, int32_t* jr,
+                       int32_t* jc, void* jv, hipStream_t s);
 
 // Fence-free CG on the compact X_J (kernels_cg.hip) ----------------------------
 unsigned cg_qgrid(int64_t q);
