@@ -61,9 +61,11 @@ def measured_traffic(workload, cls):
 
 # the kernels of each class that a traffic probe sums, and their sources
 TRAFFIC_KERNELS = {
-    "atmul": (["k_mul_y", "k_segsum<float, false>", "k_segsum_fix", "k_scale_copy"],
+    "atmul": (["k_mul_y", "k_segsum<float, false>", "k_segsum_fix", "k_reduce_cols"],
               ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/kernels_vec.hip",
-               "paper_1910_01312_amd/csrc/dev_common.h"]),
+               "paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
+    "amul": (["k_segsum<float, false>", "k_segsum_fix"],
+             ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
 }
 
 
@@ -343,7 +345,7 @@ def main():
     ap.add_argument("--count", type=int, default=256, help="batched workload: number of QPs")
     ap.add_argument("--no-seq", action="store_true", help="batched workload: skip the one-by-one solves")
     ap.add_argument("--keep-frac", type=float, default=0.15, help="warm-start workload: rows kept")
-    ap.add_argument("--traffic-op", default=None, choices=[None, "atmul"],
+    ap.add_argument("--traffic-op", default=None, choices=[None, "atmul", "amul"],
                     help="run only this kernel class (--reps times after one warm-up) for a "
                          "rocprofv3 --pmc traffic reading, then exit")
     ap.add_argument("--reps", type=int, default=20)
@@ -393,11 +395,16 @@ def main():
     create_s = time.perf_counter() - t
     log(f"[bench] create {create_s:.2f} s")
     if args.traffic_op:
-        # A^T z with z of the solution's shape (the op reads every entry of X
-        # whatever z holds)
-        z = torch.rand(s.n, dtype=torch.float64, device="cuda")
-        for _ in range(args.reps + 1):
-            s.atmul(z)
+        # A^T z or A v with random vectors (either op reads every entry of X
+        # whatever the vector holds)
+        if args.traffic_op == "atmul":
+            z = torch.rand(s.n, dtype=torch.float64, device="cuda")
+            for _ in range(args.reps + 1):
+                s.atmul(z)
+        else:
+            v = torch.rand(s.q, dtype=torch.float64, device="cuda")
+            for _ in range(args.reps + 1):
+                s.amul(v)
         torch.cuda.synchronize()
         print(json.dumps({"traffic_op": args.traffic_op, "calls": args.reps + 1,
                           "kernels": TRAFFIC_KERNELS[args.traffic_op][0]}), flush=True)

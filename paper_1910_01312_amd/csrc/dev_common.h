@@ -45,6 +45,27 @@ __device__ __forceinline__ double block_sum(double v, double* sh /* >= SSN_WAVES
     for (int i = 0; i < SSN_WAVES_PER_BLOCK; ++i) r += sh[i];
     return r;
 }
+// K block sums at once with one pair of barriers (fixed order: waves in
+// index order).  sh: K * SSN_WAVES_PER_BLOCK doubles of LDS.
+template <int K>
+__device__ __forceinline__ void block_sum_n(double (&v)[K], double* sh) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[k * SSN_WAVES_PER_BLOCK + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < SSN_WAVES_PER_BLOCK; ++i) r += sh[k * SSN_WAVES_PER_BLOCK + i];
+        v[k] = r;
+    }
+}
 __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
     const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
     v = wave_sum_ll(v);

@@ -89,6 +89,9 @@ struct ssnalm_ctx {
     int device = 0;
     // sparse operator plans (forward on CSR rows, transpose on CSC columns)
     SegPlan fwd{}, tr{};
+    SegPlan trb{};                   // CSC cut into row blocks (segment = block * q + column)
+    int trb_parts = 1;               // row blocks of trb (1: trb unused)
+    double* qparts = nullptr;        // trb_parts * q per-block column sums
     std::vector<void*> owned;
     // n-vectors
     double *xk = nullptr, *aw = nullptr, *u = nullptr, *ut = nullptr, *td = nullptr;
@@ -267,12 +270,17 @@ static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const 
     } else {
         // one gathered coefficient per entry: y .* z, formed once
         launch_mul_y(z, c->y, c->yz, c->n, c->st);
-        launch_segsum(c->tr, c->yz, nullptr, nullptr, nullptr, nullptr, c->qv2, c->st);
-        // r = base + sign * qv2
-        if (base) {
-            launch_sub(base, c->qv2, r, c->q, c->st);       // sign is always -1 with a base
+        if (c->trb_parts > 1) {
+            // per-row-block column sums, then r = base + sign * (their sum in
+            // block order); sign is always -1 with a base
+            launch_segsum_parts(c->trb, c->trb_parts, c->yz, c->qparts, c->st);
+            launch_reduce_cols(c->qparts, c->trb_parts, c->q, base, base ? -1.0 : sign, r, c->st);
         } else {
-            launch_scale_copy(r, c->qv2, sign, c->q, c->st);
+            launch_segsum(c->tr, c->yz, nullptr, nullptr, nullptr, nullptr, c->qv2, c->st);
+            if (base)
+                launch_sub(base, c->qv2, r, c->q, c->st);
+            else
+                launch_scale_copy(r, c->qv2, sign, c->q, c->st);
         }
         if (mask) launch_segsum(c->tr, nullptr, nullptr, mask, nullptr, nullptr, s_out, c->st);
     }
@@ -674,6 +682,31 @@ static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
             memcpy(cv.data() + vb * d, vals.data() + vb * k, vb);
         }
     STCHK(build_plan(c, &c->tr, q, nnz, cp, ri, cv.data(), vb == 8));
+    // The CSC cut into row blocks of about equal entry counts, one per XCD,
+    // for A^T z once the gathered n-vector outgrows an XCD's L2
+    const int parts = atmul_row_parts(n, q, nnz);
+    if (parts > 1) {
+        std::vector<int32_t> rb(parts + 1, 0);
+        for (int r = 1; r < parts; ++r)
+            rb[r] = (int32_t)(std::lower_bound(rp.begin(), rp.end(), (int64_t)(nnz * (double)r / parts)) - rp.begin());
+        rb[parts] = (int32_t)n;
+        std::vector<int32_t> bp((size_t)parts * q + 1, 0), ri2(std::max<int64_t>(nnz, 1));
+        std::vector<char> cv2(vb * std::max<int64_t>(nnz, 1));
+        for (int r = 0; r < parts; ++r)
+            for (int64_t k = rp[rb[r]]; k < rp[rb[r + 1]]; ++k) bp[(size_t)r * q + ci[k] + 1]++;
+        for (size_t s = 0; s < (size_t)parts * q; ++s) bp[s + 1] += bp[s];
+        std::vector<int32_t> at(bp.begin(), bp.end() - 1);
+        for (int r = 0; r < parts; ++r)
+            for (int64_t i = rb[r]; i < rb[r + 1]; ++i)
+                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                    const int32_t d = at[(size_t)r * q + ci[k]]++;
+                    ri2[d] = (int32_t)i;
+                    memcpy(cv2.data() + vb * d, vals.data() + vb * k, vb);
+                }
+        STCHK(build_plan(c, &c->trb, (int64_t)parts * q, nnz, bp, ri2, cv2.data(), vb == 8));
+        STCHK(dalloc(c, &c->qparts, (int64_t)parts * q));
+        c->trb_parts = parts;
+    }
     // the column of every CSC entry (the J filter copies it per kept entry)
     {
         std::vector<int32_t> tc(std::max<int64_t>(nnz, 1), 0);

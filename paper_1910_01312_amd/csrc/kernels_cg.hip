@@ -41,7 +41,7 @@ __device__ __forceinline__ double red_col(const double* __restrict__ part, int n
 }
 
 static inline unsigned qgrid(int64_t q) {
-    int64_t b = (q + 2047) / 2048;
+    int64_t b = (q + 511) / 512;
     if (b > 256) b = 256;
     if (b < 1) b = 1;
     return (unsigned)b;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_init(const double* __restrict_
                                                        double* __restrict__ pd,
                                                        double* __restrict__ Pst,
                                                        double* __restrict__ Pdir) {
-    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    __shared__ double sh[4 * SSN_WAVES_PER_BLOCK];
     double rz = 0.0, rr = 0.0, pp = 0.0, sp = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
@@ -74,13 +74,13 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_init(const double* __restrict_
         pp = fma(zj, zj, pp);
         sp = fma(sv[j], zj, sp);
     }
-    const double a = block_sum(rz, sh), b = block_sum(rr, sh);
-    const double c = block_sum(pp, sh), d = block_sum(sp, sh);
+    double v[4] = {rz, rr, pp, sp};
+    block_sum_n<4>(v, sh);
     if (threadIdx.x == 0) {
-        Pst[blockIdx.x * 2] = a;
-        Pst[blockIdx.x * 2 + 1] = b;
-        Pdir[blockIdx.x * 2] = c;
-        Pdir[blockIdx.x * 2 + 1] = d;
+        Pst[blockIdx.x * 2] = v[0];
+        Pst[blockIdx.x * 2 + 1] = v[1];
+        Pdir[blockIdx.x * 2] = v[2];
+        Pdir[blockIdx.x * 2 + 1] = v[3];
     }
 }
 
@@ -317,13 +317,19 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_step(
     double* __restrict__ z, int64_t q, double sigma, double inv_p, const double* __restrict__ Pw,
     int nbw, const double* __restrict__ Pdir, const double* __restrict__ Pold,
     double* __restrict__ Pnew, double tol2) {
-    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    __shared__ double sh[5 * SSN_WAVES_PER_BLOCK];
     const int nbq = gridDim.x;
-    const double rz = red_col(Pold, nbq, 2, 0, sh);
-    const double rr = red_col(Pold, nbq, 2, 1, sh);
-    const double pp = red_col(Pdir, nbq, 2, 0, sh);
-    const double sp = red_col(Pdir, nbq, 2, 1, sh);
-    const double ww = red_col(Pw, nbw, 1, 0, sh);
+    // the five partial sums, every load issued before the one block exchange
+    double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nbq; b += blockDim.x) {
+        red[0] += Pold[2 * b];
+        red[1] += Pold[2 * b + 1];
+        red[2] += Pdir[2 * b];
+        red[3] += Pdir[2 * b + 1];
+    }
+    for (int b = threadIdx.x; b < nbw; b += blockDim.x) red[4] += Pw[b];
+    block_sum_n<5>(red, sh);
+    const double rz = red[0], rr = red[1], pp = red[2], sp = red[3], ww = red[4];
     const double pap = pp + sigma * (ww - sp * sp * inv_p);
     const bool done = !(rr > tol2) || !(pap > 0.0) || !(rz > 0.0);
     if (done) {
@@ -347,10 +353,11 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_step(
         a = fma(rj, zj, a);
         b = fma(rj, rj, b);
     }
-    const double sa = block_sum(a, sh), sb = block_sum(b, sh);
+    double ab[2] = {a, b};
+    block_sum_n<2>(ab, sh);
     if (threadIdx.x == 0) {
-        Pnew[blockIdx.x * 2] = sa;
-        Pnew[blockIdx.x * 2 + 1] = sb;
+        Pnew[blockIdx.x * 2] = ab[0];
+        Pnew[blockIdx.x * 2 + 1] = ab[1];
     }
 }
 
@@ -363,11 +370,16 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_dir(double* __restrict__ pd,
                                                       const double* __restrict__ Pnew,
                                                       double* __restrict__ Pdir, double tol2,
                                                       Scalars* sc, double* __restrict__ tz) {
-    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    __shared__ double sh[3 * SSN_WAVES_PER_BLOCK];
     const int nbq = gridDim.x;
-    const double rz_old = red_col(Pold, nbq, 2, 0, sh);
-    const double rz_new = red_col(Pnew, nbq, 2, 0, sh);
-    const double rr_new = red_col(Pnew, nbq, 2, 1, sh);
+    double red[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nbq; b += blockDim.x) {
+        red[0] += Pold[2 * b];
+        red[1] += Pnew[2 * b];
+        red[2] += Pnew[2 * b + 1];
+    }
+    block_sum_n<3>(red, sh);
+    const double rz_old = red[0], rz_new = red[1], rr_new = red[2];
     const bool done = !(rr_new > tol2);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->cg_rr = rr_new;
@@ -388,10 +400,11 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_dir(double* __restrict__ pd,
         pp = fma(pj, pj, pp);
         sp = fma(sv[j], pj, sp);
     }
-    const double a = block_sum(pp, sh), b = block_sum(sp, sh);
+    double ab[2] = {pp, sp};
+    block_sum_n<2>(ab, sh);
     if (threadIdx.x == 0) {
-        Pdir[blockIdx.x * 2] = a;
-        Pdir[blockIdx.x * 2 + 1] = b;
+        Pdir[blockIdx.x * 2] = ab[0];
+        Pdir[blockIdx.x * 2 + 1] = ab[1];
     }
 }
 

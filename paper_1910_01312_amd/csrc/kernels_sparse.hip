@@ -11,6 +11,13 @@
 // adds in tile order.  No floating-point atomics: results are deterministic
 // whatever the segment-length distribution (a column present in nearly
 // every row is simply spread over many tiles).
+//
+// For the transpose of a large X the gathered vector (one double per row)
+// outgrows one XCD's L2, and each gather that misses fetches a whole line
+// from HBM.  The transpose then runs over a CSC copy cut into row blocks
+// (segment = (row block, column)) whose tiles are dealt to the XCDs block by
+// block, so every XCD gathers from its own slice of the vector only; the
+// per-block column sums are added in block order afterwards.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
@@ -28,6 +35,20 @@ __device__ __forceinline__ int32_t pick8(const int32_t (&a)[8], int j) {
     return r;
 }
 
+// eight consecutive values from a 32-byte aligned address, as 16-byte loads
+__device__ __forceinline__ void load8(const float* p, double (&a)[8]) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 u = q[0], v = q[1];
+    a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w;
+    a[4] = v.x; a[5] = v.y; a[6] = v.z; a[7] = v.w;
+}
+__device__ __forceinline__ void load8(const double* p, double (&a)[8]) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 u0 = q[0], u1 = q[1], u2 = q[2], u3 = q[3];
+    a[0] = u0.x; a[1] = u0.y; a[2] = u1.x; a[3] = u1.y;
+    a[4] = u2.x; a[5] = u2.y; a[6] = u3.x; a[7] = u3.y;
+}
+
 template <typename V>
 __device__ __forceinline__ double segval(const V* val, int64_t k, bool sq) {
     const double a = (double)val[k];
@@ -43,9 +64,18 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
     const int32_t* __restrict__ tile_first, double* __restrict__ carry,
     const double* __restrict__ vin, const int8_t* __restrict__ yin,
     const uint8_t* __restrict__ mask, const int8_t* __restrict__ yout,
-    const uint8_t* __restrict__ out_mask, double* __restrict__ out) {
+    const uint8_t* __restrict__ out_mask, double* __restrict__ out, int parts, int64_t tpp) {
     const int lane = threadIdx.x & (SSN_WAVE - 1);
-    const int64_t tile = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    int64_t tile;
+    if (parts > 1) {
+        // block b runs on XCD b % parts: part k of the tiles (tpp of them) goes
+        // to the blocks of XCD k
+        const int64_t lt = (int64_t)(blockIdx.x / parts) * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+        if (lt >= tpp) return;
+        tile = (int64_t)(blockIdx.x % parts) * tpp + lt;
+    } else {
+        tile = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    }
     if (tile >= ntile) return;                    // whole wave leaves together
     const int64_t tb = tile * SEG_TILE;
     const int64_t te = tb + SEG_TILE < nnz ? tb + SEG_TILE : nnz;
@@ -69,8 +99,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
             const int4 i0 = ip[0], i1 = ip[1];
             ii[0] = i0.x; ii[1] = i0.y; ii[2] = i0.z; ii[3] = i0.w;
             ii[4] = i1.x; ii[5] = i1.y; ii[6] = i1.z; ii[7] = i1.w;
-#pragma unroll
-            for (int e = 0; e < SEG_E; ++e) av[e] = (double)val[k0 + e];
+            load8(val + k0, av);
         } else {
 #pragma unroll
             for (int e = 0; e < SEG_E; ++e) {
@@ -197,17 +226,23 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum_fix(
 template <bool SQ>
 static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin,
                           const uint8_t* mask, const int8_t* yout, const uint8_t* out_mask,
-                          double* out, hipStream_t s) {
-    const unsigned nb = (unsigned)((P.ntile + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+                          double* out, hipStream_t s, int parts = 1) {
+    int64_t tpp = 0, nb = (P.ntile + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
+    if (parts > 1) {
+        tpp = (P.ntile + parts - 1) / parts;
+        nb = (int64_t)parts * ((tpp + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+    }
     if (nb > 0) {
         if (P.val_f64)
-            hipLaunchKernelGGL((k_segsum<double, SQ>), dim3(nb), dim3(SSN_BLOCK), 0, s, P.nseg,
-                               P.nnz, P.ptr, P.idx, (const double*)P.val, P.lane_seg, P.ntile,
-                               P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out);
+            hipLaunchKernelGGL((k_segsum<double, SQ>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, s,
+                               P.nseg, P.nnz, P.ptr, P.idx, (const double*)P.val, P.lane_seg,
+                               P.ntile, P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out,
+                               parts, tpp);
         else
-            hipLaunchKernelGGL((k_segsum<float, SQ>), dim3(nb), dim3(SSN_BLOCK), 0, s, P.nseg,
-                               P.nnz, P.ptr, P.idx, (const float*)P.val, P.lane_seg, P.ntile,
-                               P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out);
+            hipLaunchKernelGGL((k_segsum<float, SQ>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, s,
+                               P.nseg, P.nnz, P.ptr, P.idx, (const float*)P.val, P.lane_seg,
+                               P.ntile, P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out,
+                               parts, tpp);
     }
     if (P.nspan > 0) {
         const unsigned nf = (unsigned)((P.nspan + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
@@ -221,11 +256,26 @@ void launch_segsum(const SegPlan& P, const double* vin, const int8_t* yin, const
     segsum_launch<false>(P, vin, yin, mask, yout, out_mask, out, s);
 }
 
+void launch_segsum_parts(const SegPlan& P, int parts, const double* vin, double* out,
+                         hipStream_t s) {
+    segsum_launch<false>(P, vin, nullptr, nullptr, nullptr, nullptr, out, s, parts);
+}
+
 void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStream_t s) {
     segsum_launch<true>(P, nullptr, nullptr, mask, nullptr, nullptr, out, s);
 }
 
 int seg_entries_per_lane() { return SEG_E; }
+
+// Row blocks of the transpose: one per XCD of the MI355X (8) once the
+// gathered vector (8 bytes per row) passes 1 MiB, a quarter of an XCD's L2;
+// segment ids (block * q + column) must stay within int32.
+int atmul_row_parts(int64_t n, int64_t q, int64_t nnz) {
+    const int parts = 8;
+    if (n < (1 << 17) || nnz < (int64_t)parts * SEG_TILE) return 1;
+    if ((int64_t)parts * q + 1 > 0x7fffffffLL) return 1;
+    return parts;
+}
 
 
 }  // namespace ssn

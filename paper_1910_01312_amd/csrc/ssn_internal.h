@@ -95,6 +95,12 @@ int seg_entries_per_lane();
 void launch_segsum(const SegPlan& P, const double* vin, const int8_t* yin,
                    const uint8_t* mask, const int8_t* yout, const uint8_t* out_mask,
                    double* out, hipStream_t s);
+// row blocks of the CSC copy used by A^T z (1: the plain CSC copy)
+int atmul_row_parts(int64_t n, int64_t q, int64_t nnz);
+// out[s] = sum_{k in seg s} val[k] vin[idx[k]], with the tiles dealt to
+// `parts` XCDs in contiguous parts (block b runs on XCD b % parts)
+void launch_segsum_parts(const SegPlan& P, int parts, const double* vin, double* out,
+                         hipStream_t s);
 // out[s] = sum_{k in seg s} val[k]^2 mask(idx[k])
 void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStream_t s);
 
