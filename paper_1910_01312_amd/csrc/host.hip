@@ -106,6 +106,10 @@ struct ssnalm_ctx {
     void* jv = nullptr;
     int *tcount = nullptr, *toff = nullptr;
     double *wJ = nullptr, *kcarry = nullptr, *cgpart = nullptr;
+    int64_t nchmax = 0;              // chunks of the largest compact X_J copy
+    uint8_t* fixflag = nullptr;      // per chunk: a crossing run starts here
+    int* fixblk = nullptr;           // compaction scratch for fixflag
+    KeyedFix fix{};                  // the crossing runs of the current copy
     double* zJ = nullptr;            // n-vector, nonzero on J only (mixed refinement)
     double* yz = nullptr;            // n-vector y .* z for the sparse A^T z
     bool mixed = false;              // bf16 SYRK + refinement
@@ -376,11 +380,18 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         launch_rank_from_list(c->jlist, &dsc(c)->p, c->n, c->jrank, c->fwd.ptr, c->jrow, c->st);
         launch_jcsc_build(c->tr, c->tcol, mask, c->n, c->jbits, c->jrank, c->tcount, c->toff,
                           &dsc(c)->nnzj, c->jr, c->jc, c->jv, c->st);
+        launch_fix_flags(c->jc, &dsc(c)->nnzj, c->nchmax, c->fixflag, c->st);
+        launch_compact(c->fixflag, c->nchmax, c->fix.list, &dsc(c)->nfix, c->fixblk,
+                       cnt(c, CNT_CMP), c->st);
         STCHK(sync_state(c));
         const int64_t nnzj = c->hs->sc.nnzj;
+        c->fix.nfix = c->hs->sc.nfix;
+        launch_fix_ends(c->jc, nnzj, c->fix, c->st);
         const int vf64 = c->dtype == SSNALM_F64;
-        launch_keyed_tr(1, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sv, c->q, c->st);
-        launch_keyed_tr(2, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sq, c->q, c->st);
+        launch_keyed_tr(1, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sv, c->q, c->st,
+                        true, &c->fix);
+        launch_keyed_tr(2, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sq, c->q, c->st,
+                        true, &c->fix);
         launch_jacobi_diag(c->sq, c->sv, sigma, p, c->diag, c->q, c->st);
         const double tol2 = cg_tol * cg_tol;
         double* Pw = c->cgpart;
@@ -403,7 +414,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                      2.0 * (double)nnzj);
             prof_begin(c, SSNALM_K_ATMUL_J);
             launch_keyed_tr(0, c->jr, c->jc, c->jv, vf64, nnzj, c->wJ, c->kcarry, c->qv, c->q,
-                            c->st, false);
+                            c->st, false, &c->fix);
             prof_end(c, SSNALM_K_ATMUL_J, (double)nnzj * (8.0 + vb) + 8.0 * p + 8.0 * c->q,
                      2.0 * (double)nnzj);
             launch_cg_step(c->cg_x, c->cg_r, c->cg_p, c->qv, c->sv, c->diag, c->cg_z, c->q,
@@ -844,6 +855,9 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
             ALLOC(c->jrow, n); ALLOC(c->jbits, jcsc_bits_words(n));
             ALLOC(c->tcount, c->tr.ntile + 1); ALLOC(c->toff, c->tr.ntile + 2);
             ALLOC(c->kcarry, 2 * (nz / 128 + 2)); ALLOC(c->cgpart, 1024 + 512 + 1024);
+            c->nchmax = keyed_chunks(nz);
+            ALLOC(c->fixflag, c->nchmax); ALLOC(c->fixblk, compact_blocks(c->nchmax) + 1);
+            ALLOC(c->fix.list, c->nchmax); ALLOC(c->fix.fend, c->nchmax); ALLOC(c->fix.fcol, c->nchmax);
             if (c->dtype == SSNALM_F64) { double* t; ALLOC(t, nz); c->jv = t; }
             else { float* t; ALLOC(t, nz); c->jv = t; }
         }

@@ -286,9 +286,97 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_keyed_fix(const int32_t* __restri
     if (lane == 0) out[K] = tot;
 }
 
+// ---- the border-crossing runs, listed once per compact copy
+// flag[ch] = 1 where a border-crossing run starts (the test of k_keyed_fix);
+// the chunk count comes from the device-side entry count.
+__global__ void k_fix_flags(const int32_t* __restrict__ jc, const long long* __restrict__ nnzj_dev,
+                            int64_t nchmax, uint8_t* __restrict__ flag) {
+    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= nchmax) return;
+    const int64_t nnzj = *nnzj_dev;
+    const int64_t cb = ch * KCH;
+    uint8_t f = 0;
+    if (cb < nnzj) {
+        const int64_t ce = cb + KCH < nnzj ? cb + KCH : nnzj;
+        const int32_t K = jc[ce - 1];
+        const bool right_out = ce < nnzj && jc[ce] == K;
+        const bool left_in = cb > 0 && jc[cb] == K && jc[cb - 1] == K;
+        f = right_out && !left_in;
+    }
+    flag[ch] = f;
+}
+// For listed run i (starting in chunk list[i]): the chunk where it ends and
+// its column.  One wave per run.
+__global__ __launch_bounds__(SSN_BLOCK) void k_fix_ends(const int32_t* __restrict__ jc,
+                                                        int64_t nnzj, int64_t nch,
+                                                        const int32_t* __restrict__ list,
+                                                        int64_t nfix, int32_t* __restrict__ fend,
+                                                        int32_t* __restrict__ fcol) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t i = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    if (i >= nfix) return;
+    const int64_t ch = list[i];
+    const int64_t ce = (ch + 1) * KCH < nnzj ? (ch + 1) * KCH : nnzj;
+    const int32_t K = jc[ce - 1];
+    int64_t end = nch - 1;
+    for (int64_t base = ch + 1; base < nch; base += SSN_WAVE) {
+        const int64_t c2 = base + lane;
+        bool pass = false;
+        const bool valid = c2 < nch;
+        if (valid) {
+            const int64_t b2 = c2 * KCH;
+            const int64_t e2 = b2 + KCH < nnzj ? b2 + KCH : nnzj;
+            pass = jc[b2] == K && jc[e2 - 1] == K && e2 < nnzj && jc[e2] == K;
+        }
+        const unsigned long long stop = __ballot(valid && !pass);
+        if (stop) {
+            end = base + __ffsll((long long)stop) - 1;
+            break;
+        }
+    }
+    if (lane == 0) {
+        fend[i] = (int32_t)end;
+        fcol[i] = K;
+    }
+}
+// out[fcol[i]] = the run's carries: slot 1 of its first chunk and of every
+// chunk it passes through, slot 0 of the chunk where it ends.  One wave per
+// listed run.
+__global__ __launch_bounds__(SSN_BLOCK) void k_keyed_fix_list(const int32_t* __restrict__ list,
+                                                              const int32_t* __restrict__ fend,
+                                                              const int32_t* __restrict__ fcol,
+                                                              int64_t nfix,
+                                                              const double* __restrict__ carry,
+                                                              double* __restrict__ out) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t i = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    if (i >= nfix) return;
+    const int64_t c0 = list[i], c1 = fend[i];
+    double v = 0.0;
+    for (int64_t c = c0 + 1 + lane; c <= c1; c += SSN_WAVE) v += carry[c * 2 + (c < c1 ? 1 : 0)];
+    v = wave_sum(v);
+    if (lane == 0) out[fcol[i]] = carry[c0 * 2 + 1] + v;
+}
+
+int64_t keyed_chunks(int64_t nnz) { return (nnz + KCH - 1) / KCH; }
+
+void launch_fix_flags(const int32_t* jc, const long long* nnzj_dev, int64_t nchmax, uint8_t* flag,
+                      hipStream_t s) {
+    if (nchmax <= 0) return;
+    hipLaunchKernelGGL(k_fix_flags, dim3((unsigned)((nchmax + 255) / 256)), dim3(256), 0, s, jc,
+                       nnzj_dev, nchmax, flag);
+}
+
+void launch_fix_ends(const int32_t* jc, int64_t nnzj, KeyedFix& fx, hipStream_t s) {
+    if (fx.nfix <= 0) return;
+    const unsigned nb = (unsigned)((fx.nfix + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+    hipLaunchKernelGGL(k_fix_ends, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, keyed_chunks(nnzj),
+                       fx.list, fx.nfix, fx.fend, fx.fcol);
+}
+
 void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
                      int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
-                     hipStream_t s, bool zero_out) {
+                     hipStream_t s, bool zero_out, const KeyedFix* fx) {
     if (zero_out) launch_fill(out, 0.0, q, s);
     if (nnzj <= 0) return;
     const int64_t nch = (nnzj + KCH - 1) / KCH;
@@ -301,7 +389,15 @@ void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void*
         if (mode == 0) KT(float, 0); else if (mode == 1) KT(float, 1); else KT(float, 2);
     }
 #undef KT
-    hipLaunchKernelGGL(k_keyed_fix, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, nch, carry, out);
+    if (fx) {
+        if (fx->nfix > 0) {
+            const unsigned nf = (unsigned)((fx->nfix + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+            hipLaunchKernelGGL(k_keyed_fix_list, dim3(nf), dim3(SSN_BLOCK), 0, s, fx->list, fx->fend,
+                               fx->fcol, fx->nfix, carry, out);
+        }
+    } else {
+        hipLaunchKernelGGL(k_keyed_fix, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, nch, carry, out);
+    }
 }
 
 // --------------------------------------------------------------- step

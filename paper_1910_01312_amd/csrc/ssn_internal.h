@@ -38,6 +38,7 @@ struct Scalars {
     double sumx;          // e^T x
     long long p;          // |J|
     long long nnzj;       // nonzeros of the rows in J (sparse input)
+    long long nfix;       // chunk-crossing column runs of the compact X_J copy
     long long nsv;        // #{x_i > 0}
     int    chol_fail;     // Cholesky met a non-positive pivot
     int    cg_done;
@@ -206,9 +207,26 @@ void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, h
 // w[k] = (X_J v)_k for the k-th row of J (entry range jrow[k]); Pw: block sums of w^2
 void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double* v, double* w,
                     double* Pw, hipStream_t s);
+// The runs of equal column that cross chunk borders of a compact copy:
+// their first chunks (ascending), last chunks and columns; nfix on the host.
+struct KeyedFix {
+    int32_t* list;
+    int32_t* fend;
+    int32_t* fcol;
+    int64_t nfix;
+};
+int64_t keyed_chunks(int64_t nnz);
+// flag[ch] = 1 where a crossing run starts (chunks of the copy with
+// *nnzj_dev entries; nchmax >= its chunk count); compact the flags into
+// KeyedFix::list, then launch_fix_ends fills fend/fcol.
+void launch_fix_flags(const int32_t* jc, const long long* nnzj_dev, int64_t nchmax, uint8_t* flag,
+                      hipStream_t s);
+void launch_fix_ends(const int32_t* jc, int64_t nnzj, KeyedFix& fx, hipStream_t s);
+// with fx, the crossing runs are summed from the list instead of being
+// found by a scan of every chunk
 void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
                      int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
-                     hipStream_t s, bool zero_out = true);
+                     hipStream_t s, bool zero_out = true, const KeyedFix* fx = nullptr);
 void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
                     const double* diag, double* z, int64_t q, double sigma, int64_t p,
                     const double* Pw, int nbw, const double* Pdir, const double* Pold, double* Pnew,
