@@ -89,6 +89,8 @@ struct ssnalm_ctx {
     int device = 0;
     // sparse operator plans (forward on CSR rows, transpose on CSC columns)
     SegPlan fwd{}, tr{};
+    int32_t* qperm = nullptr;        // CSR: internal index of each original column (null: identity)
+    double *qin = nullptr, *qout = nullptr;   // q-vectors crossing the boundary, relabelled
     SegPlan trb{};                   // CSC cut into row blocks (segment = block * q + column)
     int trb_parts = 1;               // row blocks of trb (1: trb unused)
     double* qparts = nullptr;        // trb_parts * q per-block column sums
@@ -293,6 +295,19 @@ static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const 
                  2.0 * (c->kind == SSNALM_DENSE ? (double)c->n * c->q : (double)c->nnz));
     else
         prof_end(c, cls, 0.0, 0.0);
+}
+
+// A user q-vector in the internal column order (CSR contexts relabel their
+// columns; the vector is copied into qin), and an internal one written back
+// in the user's order (nothing to do without relabelling: the internal
+// result was already written to dst).
+static const double* q_in(ssnalm_ctx* c, const double* v) {
+    if (!c->qperm) return v;
+    launch_permute(v, c->qperm, c->qin, c->q, true, c->st);
+    return c->qin;
+}
+static void q_out(ssnalm_ctx* c, const double* src, double* dst) {
+    if (c->qperm) launch_permute(src, c->qperm, dst, c->q, false, c->st);
 }
 
 // ---------------------------------------------------------------- projection
@@ -676,6 +691,29 @@ static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
             if (!std::isfinite(v)) return fail(SSNALM_E_NONFINITE, "non-finite value at entry %lld", (long long)k);
         }
     }
+    // Columns relabelled by decreasing entry count (ties by index), so that
+    // the gathers of a q-vector in X v concentrate on a few cache lines for
+    // the frequent columns; q-vectors are relabelled where they cross the API.
+    {
+        std::vector<int64_t> cnt(q, 0);
+        for (int64_t k = 0; k < nnz; ++k) cnt[ci[k]]++;
+        std::vector<int32_t> order(q);
+        for (int64_t j = 0; j < q; ++j) order[j] = (int32_t)j;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+        std::vector<int32_t> perm(q);
+        bool ident = true;
+        for (int64_t r = 0; r < q; ++r) {
+            perm[order[r]] = (int32_t)r;
+            ident = ident && order[r] == r;
+        }
+        if (!ident) {
+            for (int64_t k = 0; k < nnz; ++k) ci[k] = perm[ci[k]];
+            STCHK(dalloc(c, &c->qperm, q));
+            STCHK(dalloc(c, &c->qin, q));
+            STCHK(dalloc(c, &c->qout, q));
+            HIPCHK(hipMemcpy(c->qperm, perm.data(), sizeof(int32_t) * q, hipMemcpyHostToDevice));
+        }
+    }
     std::vector<int32_t> rp32(n + 1);
     for (int64_t i = 0; i <= n; ++i) rp32[i] = (int32_t)rp[i];
     STCHK(build_plan(c, &c->fwd, n, nnz, rp32, ci, vals.data(), vb == 8));
@@ -1003,7 +1041,10 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     launch_dots(1, c->qv, c->qv, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                 q, c->spart, cnt(c, CNT_DOTS), c->st);
     launch_count_x(x_out, n, c->C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);
-    if (w_out) HIPCHK(hipMemcpyAsync(w_out, c->qv, sizeof(double) * q, hipMemcpyDeviceToDevice, c->st));
+    if (w_out) {
+        if (c->qperm) q_out(c, c->qv, w_out);
+        else HIPCHK(hipMemcpyAsync(w_out, c->qv, sizeof(double) * q, hipMemcpyDeviceToDevice, c->st));
+    }
     HIPCHK(hipGetLastError());
     STCHK(sync_state(c));
     const double sumx = c->hs->sc.sumx;
@@ -1033,7 +1074,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
 extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* t) {
     if (!c || !v || !t) return fail(SSNALM_E_BADARG, "null argument");
     StreamScope scope_(c);
-    op_amul(c, v, t);
+    op_amul(c, q_in(c, v), t);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     return SSNALM_OK;
@@ -1042,7 +1083,8 @@ extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* 
 extern "C" ssnalm_status ssnalm_op_atmul(ssnalm_ctx* c, const double* z, double* r) {
     if (!c || !z || !r) return fail(SSNALM_E_BADARG, "null argument");
     StreamScope scope_(c);
-    op_atmul(c, z, nullptr, nullptr, 1.0, r, nullptr);
+    op_atmul(c, z, nullptr, nullptr, 1.0, c->qperm ? c->qout : r, nullptr);
+    q_out(c, c->qout, r);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     return SSNALM_OK;
@@ -1084,7 +1126,9 @@ extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mas
     }
     STCHK(sync_state(c));
     int cgi = 0;
-    STCHK(newton_dir(c, free_mask, c->hs->sc.p, g, c->sv, sigma, cg_tol, d, &cgi));
+    STCHK(newton_dir(c, free_mask, c->hs->sc.p, q_in(c, g), c->sv, sigma, cg_tol,
+                     c->qperm ? c->qout : d, &cgi));
+    q_out(c, c->qout, d);
     HIPCHK(hipGetLastError());
     STCHK(sync_state(c));
     if (c->use_chol && c->hs->sc.chol_fail) return fail(SSNALM_E_NONFINITE, "Cholesky met a non-positive pivot");

@@ -151,6 +151,17 @@ void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double*
 }
 
 // --------------------------------------------------------------- X_J^T w
+// four consecutive values from a 16-byte aligned address
+__device__ __forceinline__ void load4(const float* p, double (&a)[4]) {
+    const float4 u = *reinterpret_cast<const float4*>(p);
+    a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&a)[4]) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 u = q[0], v = q[1];
+    a[0] = u.x; a[1] = u.y; a[2] = v.x; a[3] = v.y;
+}
+static_assert(KE == 4, "load4 covers one lane chunk");
 // out[c] = sum over compact entries of column c of coef, coef =
 //   MODE 0: val * w[rank];  MODE 1: val;  MODE 2: val^2.
 // Carry slots per chunk: [0] the run that ends here coming from the left,
@@ -179,18 +190,36 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_keyed_tr(const int32_t* __restric
     if (active) {
         int32_t keys[KE];
         double cf[KE];
-#pragma unroll
-        for (int e = 0; e < KE; ++e) {
-            const int64_t k = k0 + e;
-            if (k < k1) {
-                keys[e] = jc[k];
-                const double a = (double)jv[k];
-                if (MODE == 0) cf[e] = a * w[jr[k]];
-                else if (MODE == 1) cf[e] = a;
-                else cf[e] = a * a;
+        if (k1 - k0 == KE) {
+            // a full lane chunk (16-byte aligned: k0 is a multiple of 4)
+            const int4 kc = *reinterpret_cast<const int4*>(jc + k0);
+            keys[0] = kc.x; keys[1] = kc.y; keys[2] = kc.z; keys[3] = kc.w;
+            double a[KE];
+            load4(jv + k0, a);
+            if (MODE == 0) {
+                const int4 rr = *reinterpret_cast<const int4*>(jr + k0);
+                cf[0] = a[0] * w[rr.x];
+                cf[1] = a[1] * w[rr.y];
+                cf[2] = a[2] * w[rr.z];
+                cf[3] = a[3] * w[rr.w];
             } else {
-                keys[e] = -1;
-                cf[e] = 0.0;
+#pragma unroll
+                for (int e = 0; e < KE; ++e) cf[e] = MODE == 1 ? a[e] : a[e] * a[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < KE; ++e) {
+                const int64_t k = k0 + e;
+                if (k < k1) {
+                    keys[e] = jc[k];
+                    const double a = (double)jv[k];
+                    if (MODE == 0) cf[e] = a * w[jr[k]];
+                    else if (MODE == 1) cf[e] = a;
+                    else cf[e] = a * a;
+                } else {
+                    keys[e] = -1;
+                    cf[e] = 0.0;
+                }
             }
         }
         int32_t key = keys[0];

@@ -212,10 +212,19 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum_fix(
     const int64_t w = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
     if (w >= nspan) return;
     const int32_t s = span_seg[w], t0 = span_t0[w], t1 = span_t1[w];
-    double acc = 0.0;
-    for (int64_t t = t0 + lane; t <= t1; t += SSN_WAVE)
-        acc += carry[t * 2 + ((s == tile_first[t]) ? 0 : 1)];
-    acc = wave_sum(acc);
+    // in every tile after t0 the segment is the tile's first one (slot 0);
+    // only t0 needs the test.  Four independent loads per lane per round.
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (lane == 0 && t0 <= t1) a0 = carry[(int64_t)t0 * 2 + ((s == tile_first[t0]) ? 0 : 1)];
+    int64_t t = (int64_t)t0 + 1 + lane;
+    for (; t + 3 * SSN_WAVE <= t1; t += 4 * SSN_WAVE) {
+        a0 += carry[t * 2];
+        a1 += carry[(t + SSN_WAVE) * 2];
+        a2 += carry[(t + 2 * SSN_WAVE) * 2];
+        a3 += carry[(t + 3 * SSN_WAVE) * 2];
+    }
+    for (; t <= t1; t += SSN_WAVE) a0 += carry[t * 2];
+    double acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) {
         double scale = yout ? (double)yout[s] : 1.0;
         if (out_mask && !out_mask[s]) scale = 0.0;

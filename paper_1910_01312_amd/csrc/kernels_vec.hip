@@ -131,6 +131,23 @@ void launch_mul_y(const double* z, const int8_t* y, double* out, int64_t n, hipS
     hipLaunchKernelGGL(k_mul_y, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, y, out, n);
 }
 
+// Column relabelling at the boundary: internal index perm[j] holds
+// original column j.  to_internal: dst[perm[j]] = src[j]; otherwise
+// dst[j] = src[perm[j]].
+__global__ void k_permute(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                          double* __restrict__ dst, int64_t q, int to_internal) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    if (to_internal) dst[perm[j]] = src[j];
+    else dst[j] = src[perm[j]];
+}
+void launch_permute(const double* src, const int32_t* perm, double* dst, int64_t q, bool to_internal,
+                    hipStream_t s) {
+    if (q <= 0) return;
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, src, perm, dst,
+                       q, to_internal ? 1 : 0);
+}
+
 __global__ void k_fill(double* __restrict__ p, double v, int64_t len) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) p[i] = v;

@@ -145,6 +145,10 @@ void launch_u_from(const double* xk, const double* aw, double sigma, double* u, 
                    hipStream_t s);
 void launch_sub(const double* a, const double* b, double* out, int64_t len, hipStream_t s);
 void launch_mul_y(const double* z, const int8_t* y, double* out, int64_t n, hipStream_t s);
+// perm[j] = internal index of original column j; to_internal: dst[perm[j]] =
+// src[j], else dst[j] = src[perm[j]]
+void launch_permute(const double* src, const int32_t* perm, double* dst, int64_t q, bool to_internal,
+                    hipStream_t s);
 void launch_fill(double* p, double v, int64_t len, hipStream_t s);
 void launch_count_x(const double* x, int64_t n, double C, Scalars* sc, double* part,
                     unsigned* counter, hipStream_t s);
