@@ -624,7 +624,9 @@ static ssnalm_status build_plan(ssnalm_ctx* c, SegPlan* P, int64_t nseg, int64_t
             tlast[t] = (int32_t)s;
         }
     }
-    std::vector<int32_t> sseg, st0, st1;
+    // spans: short ones (empty, or at most seg_short_tiles() tiles) first
+    std::vector<int32_t> sseg, st0, st1, lseg, lt0, lt1;
+    const int64_t SHORT = seg_short_tiles();
     for (int64_t s = 0; s < nseg; ++s) {
         const int64_t a = ptr[s], b = ptr[s + 1];
         if (a == b) {                                  // empty: written as 0 by the fix-up
@@ -632,8 +634,14 @@ static ssnalm_status build_plan(ssnalm_ctx* c, SegPlan* P, int64_t nseg, int64_t
             continue;
         }
         const int64_t t0 = a / TILE, t1 = (b - 1) / TILE;
-        if (t0 != t1) { sseg.push_back((int32_t)s); st0.push_back((int32_t)t0); st1.push_back((int32_t)t1); }
+        if (t0 == t1) continue;
+        if (t1 - t0 < SHORT) { sseg.push_back((int32_t)s); st0.push_back((int32_t)t0); st1.push_back((int32_t)t1); }
+        else { lseg.push_back((int32_t)s); lt0.push_back((int32_t)t0); lt1.push_back((int32_t)t1); }
     }
+    P->nshort = (int64_t)sseg.size();
+    sseg.insert(sseg.end(), lseg.begin(), lseg.end());
+    st0.insert(st0.end(), lt0.begin(), lt0.end());
+    st1.insert(st1.end(), lt1.begin(), lt1.end());
     P->nspan = (int64_t)sseg.size();
     STCHK(dalloc(c, &P->ptr, nseg + 1));
     STCHK(dalloc(c, &P->idx, nnz));

@@ -202,20 +202,44 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
 }
 
 // out[s] for segments that cross tile borders (and empty segments, t0 > t1):
-// sum of their per-tile partials in tile order.  One wave per segment.
+// sum of their per-tile partials in tile order.  In every tile after t0 the
+// segment is the tile's first one (slot 0); only t0 needs the test.  The
+// span list holds the short spans (at most SEG_SHORT tiles) first: one
+// thread each, in the first blocks; then the long ones: one wave each.
+constexpr int SEG_SHORT = 4;
+__device__ __forceinline__ void segsum_put(int32_t s, double acc, const int8_t* yout,
+                                           const uint8_t* out_mask, double* out) {
+    double scale = yout ? (double)yout[s] : 1.0;
+    if (out_mask && !out_mask[s]) scale = 0.0;
+    out[s] = scale * acc;
+}
 __global__ __launch_bounds__(SSN_BLOCK) void k_segsum_fix(
     const int32_t* __restrict__ span_seg, const int32_t* __restrict__ span_t0,
-    const int32_t* __restrict__ span_t1, int64_t nspan, const int32_t* __restrict__ tile_first,
-    const double* __restrict__ carry, const int8_t* __restrict__ yout,
-    const uint8_t* __restrict__ out_mask, double* __restrict__ out) {
+    const int32_t* __restrict__ span_t1, int64_t nspan, int64_t nshort,
+    const int32_t* __restrict__ tile_first, const double* __restrict__ carry,
+    const int8_t* __restrict__ yout, const uint8_t* __restrict__ out_mask, double* __restrict__ out) {
+    const int64_t nbs = (nshort + SSN_BLOCK - 1) / SSN_BLOCK;
+    if ((int64_t)blockIdx.x < nbs) {
+        const int64_t w = (int64_t)blockIdx.x * SSN_BLOCK + threadIdx.x;
+        if (w >= nshort) return;
+        const int32_t s = span_seg[w], t0 = span_t0[w], t1 = span_t1[w];
+        double acc = 0.0;
+        if (t0 <= t1) {
+            acc = carry[(int64_t)t0 * 2 + ((s == tile_first[t0]) ? 0 : 1)];
+#pragma unroll
+            for (int d = 1; d < SEG_SHORT; ++d)
+                if (t0 + d <= t1) acc += carry[(int64_t)(t0 + d) * 2];
+        }
+        segsum_put(s, acc, yout, out_mask, out);
+        return;
+    }
     const int lane = threadIdx.x & (SSN_WAVE - 1);
-    const int64_t w = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t w = nshort + ((int64_t)blockIdx.x - nbs) * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
     if (w >= nspan) return;
     const int32_t s = span_seg[w], t0 = span_t0[w], t1 = span_t1[w];
-    // in every tile after t0 the segment is the tile's first one (slot 0);
-    // only t0 needs the test.  Four independent loads per lane per round.
+    // four independent loads per lane per round
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    if (lane == 0 && t0 <= t1) a0 = carry[(int64_t)t0 * 2 + ((s == tile_first[t0]) ? 0 : 1)];
+    if (lane == 0) a0 = carry[(int64_t)t0 * 2 + ((s == tile_first[t0]) ? 0 : 1)];
     int64_t t = (int64_t)t0 + 1 + lane;
     for (; t + 3 * SSN_WAVE <= t1; t += 4 * SSN_WAVE) {
         a0 += carry[t * 2];
@@ -224,13 +248,10 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum_fix(
         a3 += carry[(t + 3 * SSN_WAVE) * 2];
     }
     for (; t <= t1; t += SSN_WAVE) a0 += carry[t * 2];
-    double acc = wave_sum((a0 + a1) + (a2 + a3));
-    if (lane == 0) {
-        double scale = yout ? (double)yout[s] : 1.0;
-        if (out_mask && !out_mask[s]) scale = 0.0;
-        out[s] = scale * acc;
-    }
+    const double acc = wave_sum((a0 + a1) + (a2 + a3));
+    if (lane == 0) segsum_put(s, acc, yout, out_mask, out);
 }
+int seg_short_tiles() { return SEG_SHORT; }
 
 template <bool SQ>
 static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin,
@@ -254,9 +275,11 @@ static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin
                                parts, tpp);
     }
     if (P.nspan > 0) {
-        const unsigned nf = (unsigned)((P.nspan + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
-        hipLaunchKernelGGL(k_segsum_fix, dim3(nf), dim3(SSN_BLOCK), 0, s, P.span_seg, P.span_t0,
-                           P.span_t1, P.nspan, P.tile_first, P.carry, yout, out_mask, out);
+        const int64_t nbs = (P.nshort + SSN_BLOCK - 1) / SSN_BLOCK;
+        const int64_t nbl = (P.nspan - P.nshort + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
+        hipLaunchKernelGGL(k_segsum_fix, dim3((unsigned)(nbs + nbl)), dim3(SSN_BLOCK), 0, s,
+                           P.span_seg, P.span_t0, P.span_t1, P.nspan, P.nshort, P.tile_first,
+                           P.carry, yout, out_mask, out);
     }
 }
 

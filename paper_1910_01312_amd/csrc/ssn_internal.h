@@ -88,8 +88,10 @@ struct SegPlan {               // plan of one segmented-sum operator
     int32_t* span_t0;          // their first and last tile (t0 > t1: empty)
     int32_t* span_t1;
     int64_t  nspan;
+    int64_t  nshort;           // spans [0, nshort) cover at most seg_short_tiles() tiles
 };
 int seg_entries_per_lane();
+int seg_short_tiles();
 // out[s] = scale_s * sum_{k in seg s} val[k] * coef(idx[k]); coef(i) =
 // vin[i] * (yin ? yin[i] : 1) * (mask ? mask[i] : 1), or mask[i] when vin is
 // null; scale_s = (yout ? yout[s] : 1) * (out_mask ? out_mask[s] : 1)
