@@ -83,10 +83,33 @@ __device__ __forceinline__ const uint32_t* stage_bits(const uint32_t* __restrict
 __device__ __forceinline__ bool in_j(const uint32_t* mb, int32_t r) {
     return (mb[r >> 5] >> (r & 31)) & 1u;
 }
+// row r >= 0 and in J, without a branch (r < 0 marks entries past the end)
+__device__ __forceinline__ bool keep_row(const uint32_t* mb, int32_t r) {
+    return (r >= 0) & in_j(mb, r < 0 ? 0 : r);
+}
+// Wait for every outstanding global load.  Issued once after a loop's first
+// prefetch so that the loop header starts with no load in flight: the
+// compiler's wait placement at a loop header otherwise assumes the worst for
+// the prefetch registers and waits for the next prefetch as well.
+__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Row indices of entries k0 + 64 e (e < JE) of one lane, -1 past nnz
+// (nnz >= 1).  Every load is issued: an index past the end reads the last
+// entry instead, so that no load sits under a branch and the compiler can
+// count the loads in flight exactly.
+__device__ __forceinline__ void load_rows(const int32_t* __restrict__ ridx, int64_t k0, int64_t nnz,
+                                          int32_t (&row)[JE]) {
+#pragma unroll
+    for (int e = 0; e < JE; ++e) {
+        const int64_t k = k0 + (int64_t)e * SSN_WAVE;
+        const int32_t r = ridx[k < nnz ? k : nnz - 1];
+        row[e] = k < nnz ? r : -1;
+    }
+}
 
 // Per full tile: number of entries whose row is in J.  Persistent blocks,
-// each with the mask in LDS; one wave per tile, 8 entries per lane read as
-// two 16-byte loads.
+// each with the mask in LDS; one wave per tile, lane l reading entries
+// 64 e + l, the next tile's loads issued before this tile's tests.
 template <bool LDS>
 __global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_count(const int32_t* __restrict__ ridx,
                                                           int64_t nnz, int64_t ntile,
@@ -96,25 +119,20 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_count(const int32_t* __restr
     const uint32_t* sb = stage_bits<LDS>(bits, nw, sbuf);
     const int lane = threadIdx.x & (SSN_WAVE - 1);
     const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
-    for (int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE; t < ntile;
-         t += nwave) {
-        const int64_t k0 = t * JTILE + (int64_t)lane * JE;
-        int32_t row[JE];
-        if (k0 + JE <= nnz) {
-            const int4* ip = reinterpret_cast<const int4*>(ridx + k0);
-            const int4 i0 = ip[0], i1 = ip[1];
-            row[0] = i0.x; row[1] = i0.y; row[2] = i0.z; row[3] = i0.w;
-            row[4] = i1.x; row[5] = i1.y; row[6] = i1.z; row[7] = i1.w;
-        } else {
-#pragma unroll
-            for (int e = 0; e < JE; ++e) row[e] = k0 + e < nnz ? ridx[k0 + e] : -1;
-        }
+    int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    if (t >= ntile) return;
+    int32_t row[JE];
+    load_rows(ridx, t * JTILE + lane, nnz, row);
+    wait_loads();
+    for (; t < ntile; t += nwave) {
+        int32_t nxt[JE];
+        load_rows(ridx, (t + nwave) * JTILE + lane, nnz, nxt);   // all -1 past the last tile
         int c = 0;
 #pragma unroll
-        for (int e = 0; e < JE; ++e) c += (row[e] >= 0 && in_j(sb, row[e])) ? 1 : 0;
-#pragma unroll
-        for (int off = SSN_WAVE / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, SSN_WAVE);
+        for (int e = 0; e < JE; ++e) c += __popcll(__ballot(keep_row(sb, row[e])));
         if (lane == 0) tcount[t] = c;
+#pragma unroll
+        for (int e = 0; e < JE; ++e) row[e] = nxt[e];
     }
 }
 
@@ -205,21 +223,21 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_write(
     const int lane = threadIdx.x & (SSN_WAVE - 1);
     const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
-    for (int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE; t < ntile;
-         t += nwave) {
+    const int64_t t0 = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    int32_t cur[JE];
+    load_rows(ridx, t0 * JTILE + lane, nnz, cur);
+    wait_loads();
+    for (int64_t t = t0; t < ntile; t += nwave) {
         const int64_t k0 = t * JTILE + lane;
         int32_t row[JE];
 #pragma unroll
-        for (int e = 0; e < JE; ++e) {
-            const int64_t k = k0 + (int64_t)e * SSN_WAVE;
-            row[e] = k < nnz ? ridx[k] : -1;
-        }
+        for (int e = 0; e < JE; ++e) row[e] = cur[e];
         int pos = toff[t];
         bool keep[JE];
         int at[JE];
 #pragma unroll
         for (int e = 0; e < JE; ++e) {
-            keep[e] = row[e] >= 0 && in_j(sb, row[e]);
+            keep[e] = keep_row(sb, row[e]);
             const unsigned long long m = __ballot(keep[e]);
             at[e] = pos + __popcll(m & below);
             pos += __popcll(m);
@@ -234,6 +252,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_write(
             cl[e] = keep[e] ? tcol[k] : 0;
             vv[e] = keep[e] ? val[k] : V(0);
         }
+        // the next tile's row indices, issued after this tile's gathers so
+        // that the stores below wait for the gathers only
+        load_rows(ridx, (t + nwave) * JTILE + lane, nnz, cur);
 #pragma unroll
         for (int e = 0; e < JE; ++e) {
             if (keep[e]) {
