@@ -424,12 +424,12 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         // decision inside; the kernels stop changing x once the tolerance is met).
         auto cg_iteration = [&](int par) {
             prof_begin(c, SSNALM_K_AMUL_J);
-            launch_cg_rows(c->fwd, c->jrow, p, c->cg_p, c->wJ, Pw, c->st);
+            launch_cg_rows(c->fwd, c->jrow, p, c->cg_p, c->wJ, Pw, dsc(c), c->st);
             prof_end(c, SSNALM_K_AMUL_J, (double)nnzj * (vb + 4.0) + 20.0 * p + 8.0 * c->q,
                      2.0 * (double)nnzj);
             prof_begin(c, SSNALM_K_ATMUL_J);
             launch_keyed_tr(0, c->jr, c->jc, c->jv, vf64, nnzj, c->wJ, c->kcarry, c->qv, c->q,
-                            c->st, false, &c->fix);
+                            c->st, false, &c->fix, &dsc(c)->cg_done);
             prof_end(c, SSNALM_K_ATMUL_J, (double)nnzj * (8.0 + vb) + 8.0 * p + 8.0 * c->q,
                      2.0 * (double)nnzj);
             launch_cg_step(c->cg_x, c->cg_r, c->cg_p, c->qv, c->sv, c->diag, c->cg_z, c->q,
@@ -474,7 +474,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
             it += batch;
             STCHK(sync_state(c));
         }
-        *cg_iters = it;
+        *cg_iters = c->hs->sc.cg_count;     // iterations that did work (a batch may end early)
         HIPCHK(hipMemcpyAsync(d, c->cg_x, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
         return SSNALM_OK;
     }

@@ -93,8 +93,10 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ 
                                                        const V* __restrict__ val, int64_t p,
                                                        const double* __restrict__ v,
                                                        double* __restrict__ w,
-                                                       double* __restrict__ Pw) {
+                                                       double* __restrict__ Pw,
+                                                       const Scalars* __restrict__ sc) {
     __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    if (sc->cg_done) return;                   // converged: the step passes through
     const int lane = threadIdx.x & (SSN_WAVE - 1);
     const int grp = lane >> 4, sub = lane & 15;
     const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
@@ -140,14 +142,14 @@ unsigned cg_rows_grid(int64_t p) {
 }
 
 void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double* v, double* w,
-                    double* Pw, hipStream_t s) {
+                    double* Pw, const Scalars* sc, hipStream_t s) {
     const unsigned g = cg_rows_grid(p);
     if (F.val_f64)
         hipLaunchKernelGGL((k_cg_rows<double>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
-                           (const double*)F.val, p, v, w, Pw);
+                           (const double*)F.val, p, v, w, Pw, sc);
     else
         hipLaunchKernelGGL((k_cg_rows<float>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
-                           (const float*)F.val, p, v, w, Pw);
+                           (const float*)F.val, p, v, w, Pw, sc);
 }
 
 // --------------------------------------------------------------- X_J^T w
@@ -172,7 +174,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_keyed_tr(const int32_t* __restric
                                                         const V* __restrict__ jv, int64_t nnzj,
                                                         const double* __restrict__ w,
                                                         double* __restrict__ carry,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out,
+                                                        const int* __restrict__ skip) {
+    if (skip && *skip) return;
     const int lane = threadIdx.x & (SSN_WAVE - 1);
     const int64_t ch = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
     const int64_t cb = ch * KCH;
@@ -376,7 +380,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_keyed_fix_list(const int32_t* __r
                                                               const int32_t* __restrict__ fcol,
                                                               int64_t nfix,
                                                               const double* __restrict__ carry,
-                                                              double* __restrict__ out) {
+                                                              double* __restrict__ out,
+                                                              const int* __restrict__ skip) {
+    if (skip && *skip) return;
     const int lane = threadIdx.x & (SSN_WAVE - 1);
     const int64_t i = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
     if (i >= nfix) return;
@@ -405,13 +411,13 @@ void launch_fix_ends(const int32_t* jc, int64_t nnzj, KeyedFix& fx, hipStream_t 
 
 void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
                      int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
-                     hipStream_t s, bool zero_out, const KeyedFix* fx) {
+                     hipStream_t s, bool zero_out, const KeyedFix* fx, const int* skip) {
     if (zero_out) launch_fill(out, 0.0, q, s);
     if (nnzj <= 0) return;
     const int64_t nch = (nnzj + KCH - 1) / KCH;
     const unsigned nb = (unsigned)((nch + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
 #define KT(V, M) hipLaunchKernelGGL((k_keyed_tr<V, M>), dim3(nb), dim3(SSN_BLOCK), 0, s, jr, jc, \
-                                    (const V*)jv, nnzj, w, carry, out)
+                                    (const V*)jv, nnzj, w, carry, out, skip)
     if (val_f64) {
         if (mode == 0) KT(double, 0); else if (mode == 1) KT(double, 1); else KT(double, 2);
     } else {
@@ -422,7 +428,7 @@ void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void*
         if (fx->nfix > 0) {
             const unsigned nf = (unsigned)((fx->nfix + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
             hipLaunchKernelGGL(k_keyed_fix_list, dim3(nf), dim3(SSN_BLOCK), 0, s, fx->list, fx->fend,
-                               fx->fcol, fx->nfix, carry, out);
+                               fx->fcol, fx->nfix, carry, out, skip);
         }
     } else {
         hipLaunchKernelGGL(k_keyed_fix, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, nch, carry, out);
@@ -507,6 +513,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_dir(double* __restrict__ pd,
     const double rz_old = red[0], rz_new = red[1], rr_new = red[2];
     const bool done = !(rr_new > tol2);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!sc->cg_done) sc->cg_count += 1;   // this iteration's step did work
         sc->cg_rr = rr_new;
         sc->cg_done = done ? 1 : 0;
     }
@@ -559,6 +566,7 @@ __global__ void k_cg_publish(const double* __restrict__ Pst, int nbq, double tol
     if (threadIdx.x == 0) {
         sc->cg_rr = rr;
         sc->cg_done = rr > tol2 ? 0 : 1;
+        sc->cg_count = 0;
     }
 }
 void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, hipStream_t s) {

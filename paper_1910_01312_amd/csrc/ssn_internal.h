@@ -42,6 +42,7 @@ struct Scalars {
     long long nsv;        // #{x_i > 0}
     int    chol_fail;     // Cholesky met a non-positive pivot
     int    cg_done;
+    int    cg_count;      // CG iterations that changed x since the last start
 };
 
 // One-block sums of block-partial columns into scalars (kernels_vec.hip):
@@ -211,8 +212,9 @@ void launch_cg_init(const double* g, const double* diag, const double* sv, int64
                     double* r, double* z, double* pd, double* Pst, double* Pdir, hipStream_t s);
 void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, hipStream_t s);
 // w[k] = (X_J v)_k for the k-th row of J (entry range jrow[k]); Pw: block sums of w^2
+// returns at once when sc->cg_done is set (the CG has converged)
 void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double* v, double* w,
-                    double* Pw, hipStream_t s);
+                    double* Pw, const Scalars* sc, hipStream_t s);
 // The runs of equal column that cross chunk borders of a compact copy:
 // their first chunks (ascending), last chunks and columns; nfix on the host.
 struct KeyedFix {
@@ -232,7 +234,8 @@ void launch_fix_ends(const int32_t* jc, int64_t nnzj, KeyedFix& fx, hipStream_t 
 // found by a scan of every chunk
 void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
                      int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
-                     hipStream_t s, bool zero_out = true, const KeyedFix* fx = nullptr);
+                     hipStream_t s, bool zero_out = true, const KeyedFix* fx = nullptr,
+                     const int* skip = nullptr);   // skip: no work while *skip is nonzero
 void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
                     const double* diag, double* z, int64_t q, double sigma, int64_t p,
                     const double* Pw, int nbw, const double* Pdir, const double* Pold, double* Pnew,
