@@ -52,11 +52,17 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
     // wave-uniform column group (scalar branches below)
     const int cgu = __builtin_amdgcn_readfirstlane(cg);
     bool bad = false;
+    // 4 groups of 16 columns: the group loop stays a loop so that the code
+    // (16 unrolled steps) fits the instruction cache; fully unrolled, the 64
+    // steps are ~100 KB of straight-line code fetched once each.
+#pragma unroll 1
+    for (int kg = 0; kg < NB / 16; ++kg)
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        double* cr = col[k & 1];
-        double* rb = rowb[k & 1];
-        if (cgu == (k >> 4)) cr[i] = a[k & 15];
+    for (int kk = 0; kk < 16; ++kk) {
+        const int k = kg * 16 + kk;
+        double* cr = col[kk & 1];
+        double* rb = rowb[kk & 1];
+        if (cgu == kg) cr[i] = a[kk];
         if (i == k) {
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) rb[cgu * 16 + jj] = b[jj];
@@ -80,7 +86,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
         const double rk = 1.0 / akk;
         const double rl = rk * lkk;                       // 1 / l_kk
         const double t = i > k ? cik * rk : 0.0;
-        if (cgu == (k >> 4)) a[k & 15] = i > k ? cik * rl : (i == k ? lkk : 0.0);
+        if (cgu == kg) a[kk] = i > k ? cik * rl : (i == k ? lkk : 0.0);
         if (cgu * 16 + 15 > k) {
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
