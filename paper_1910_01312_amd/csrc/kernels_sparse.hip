@@ -84,7 +84,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
     const bool active = k0 < te;
     const int32_t INF = 0x7fffffff;
 
+    const int32_t tfirst = tile_first[tile];
     int32_t F = INF, Lt = INF;
+    int64_t aF = 0, bF = 0, aL = 0, bL = 0;      // entry ranges of segments F and Lt
     double fsum = 0.0, lsum = 0.0;
     if (active) {
         const int32_t seg0 = lane_seg[tile * SSN_WAVE + lane];
@@ -107,10 +109,16 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
                 av[e] = e < ne ? (double)val[k0 + e] : 0.0;
             }
         }
+        // where segment seg0 starts and the next SEG_E segment ends; every load
+        // issued (index clamped to nseg), so none sits under a branch
+        const int64_t p0 = ptr[seg0];
         int32_t ends[SEG_E];
 #pragma unroll
-        for (int j = 0; j < SEG_E; ++j)
-            ends[j] = (seg0 + 1 + j <= nseg) ? ptr[seg0 + 1 + j] : 0x7fffffff;
+        for (int j = 0; j < SEG_E; ++j) {
+            const int64_t sj = (int64_t)seg0 + 1 + j;
+            const int32_t v = ptr[sj <= nseg ? sj : nseg];
+            ends[j] = sj <= nseg ? v : 0x7fffffff;
+        }
         double cfv[SEG_E];
 #pragma unroll
         for (int e = 0; e < SEG_E; ++e) {
@@ -129,7 +137,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
         }
         // walk the lane's entries segment by segment
         int j = 0;                             // current segment = seg0 + j
-        int64_t segend = ends[0];
+        int64_t segend = ends[0], segbeg = p0;
         F = seg0;
         double cur = 0.0;
         bool have_head = false;
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
                 if (sg == F && !have_head) {
                     have_head = true;
                     fsum = cur;
-                    if ((int64_t)ptr[sg] >= k0) {  // complete inside the lane
+                    if (p0 >= k0) {                // complete inside the lane
                         out[sg] = omask ? 0.0 : (yout ? (double)yout[sg] : 1.0) * cur;
                         F = INF - 1;               // head already emitted
                     }
@@ -151,12 +159,17 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
                     out[sg] = omask ? 0.0 : (yout ? (double)yout[sg] : 1.0) * cur;
                 }
                 ++j;
+                segbeg = segend;
                 segend = j < SEG_E ? pick8(ends, j) : ptr[seg0 + 1 + j];
                 cur = 0.0;
             }
             cur += cfv[e];
         }
         Lt = seg0 + j;
+        aL = segbeg;
+        bL = segend;
+        aF = p0;
+        bF = ends[0];
         lsum = (out_mask && !out_mask[Lt]) ? 0.0 : cur;
         if (!have_head) {           // the lane stayed inside one segment: it is the tail
             F = Lt;
@@ -180,24 +193,23 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
     const int32_t F_next = __shfl_down(F, 1, SSN_WAVE);
     const bool has_next = lane + 1 < SSN_WAVE && (k0 + SEG_E) < te;
 
-    auto emit = [&](int32_t s, double v) {
-        const int64_t a = ptr[s], b = ptr[s + 1];
-        double scale = yout ? (double)yout[s] : 1.0;
-        if (out_mask && !out_mask[s]) scale = 0.0;
+    // segment s = [a, b): final when it lies inside the tile, else a carry
+    auto emit = [&](int32_t s, int64_t a, int64_t b, double v) {
         if (a >= tb && b <= te) {
+            double scale = yout ? (double)yout[s] : 1.0;
+            if (out_mask && !out_mask[s]) scale = 0.0;
             out[s] = scale * v;
         } else {
-            const int slot = (s == tile_first[tile]) ? 0 : 1;
-            carry[tile * 2 + slot] = v;
+            carry[tile * 2 + (s == tfirst ? 0 : 1)] = v;
         }
     };
     if (active) {
-        if (F < Lt) {                    // pending head segment F
+        if (F < Lt) {                    // pending head segment F (= the lane's first)
             double tot = fsum;
             if (lane > 0 && Lt_prev == F) tot += S_prev;
-            emit(F, tot);
+            emit(F, aF, bF, tot);
         }
-        if (!has_next || F_next != Lt) emit(Lt, S);
+        if (!has_next || F_next != Lt) emit(Lt, aL, bL, S);
     }
 }
 
