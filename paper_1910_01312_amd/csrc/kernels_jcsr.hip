@@ -20,6 +20,8 @@ namespace ssn {
 
 constexpr int JE = 8;                       // entries per lane, as the full plan
 constexpr int JTILE = JE * SSN_WAVE;        // entries per full tile
+constexpr int JBLOCK = 1024;                // filter blocks: 16 waves, one mask copy in LDS
+constexpr int JWAVES = JBLOCK / SSN_WAVE;
 
 // ------------------------------------------------------------------ ranks
 // rank[list[k]] = k, and jrow[k] = (rp[list[k]], rp[list[k] + 1]): the entry
@@ -111,15 +113,15 @@ __device__ __forceinline__ void load_rows(const int32_t* __restrict__ ridx, int6
 // each with the mask in LDS; one wave per tile, lane l reading entries
 // 64 e + l, the next tile's loads issued before this tile's tests.
 template <bool LDS>
-__global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_count(const int32_t* __restrict__ ridx,
+__global__ __launch_bounds__(JBLOCK) void k_jcsc_count(const int32_t* __restrict__ ridx,
                                                           int64_t nnz, int64_t ntile,
                                                           const uint32_t* __restrict__ bits, int nw,
                                                           int* __restrict__ tcount) {
     extern __shared__ uint32_t sbuf[];
     const uint32_t* sb = stage_bits<LDS>(bits, nw, sbuf);
     const int lane = threadIdx.x & (SSN_WAVE - 1);
-    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
-    int64_t t = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t nwave = (int64_t)gridDim.x * JWAVES;
+    int64_t t = (int64_t)blockIdx.x * JWAVES + threadIdx.x / SSN_WAVE;
     if (t >= ntile) return;
     int32_t row[JE];
     load_rows(ridx, t * JTILE + lane, nnz, row);
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const int* __restrict__ tco
 // lands in one contiguous run.  Persistent blocks with the mask in LDS, as
 // the count; tcol gives the column of every entry of the full copy.
 template <typename V, bool LDS>
-__global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_write(
+__global__ __launch_bounds__(JBLOCK) void k_jcsc_write(
     const int32_t* __restrict__ tcol, const int32_t* __restrict__ ridx, const V* __restrict__ val,
     int64_t nnz, int64_t ntile, const uint32_t* __restrict__ bits, int nw,
     const int32_t* __restrict__ rank,
@@ -222,8 +224,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_jcsc_write(
     const uint32_t* sb = stage_bits<LDS>(bits, nw, sbuf);
     const int lane = threadIdx.x & (SSN_WAVE - 1);
     const unsigned long long below = (1ull << lane) - 1ull;
-    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
-    const int64_t t0 = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t nwave = (int64_t)gridDim.x * JWAVES;
+    const int64_t t0 = (int64_t)blockIdx.x * JWAVES + threadIdx.x / SSN_WAVE;
     int32_t cur[JE];
     load_rows(ridx, t0 * JTILE + lane, nnz, cur);
     wait_loads();
@@ -275,26 +277,30 @@ static void jcsc_build_t(const SegPlan& T, const int32_t* tcol, const uint32_t* 
     static bool attr = false;
     if (LDS && !attr) {
         const int mx = JBITS_MAX_WORDS * (int)sizeof(uint32_t);
-        hipFuncSetAttribute((const void*)k_jcsc_count<LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-        hipFuncSetAttribute((const void*)k_jcsc_write<float, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-        hipFuncSetAttribute((const void*)k_jcsc_write<double, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        (void)hipFuncSetAttribute((const void*)k_jcsc_count<LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        (void)hipFuncSetAttribute((const void*)k_jcsc_write<float, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        (void)hipFuncSetAttribute((const void*)k_jcsc_write<double, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
         attr = true;
     }
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    int64_t nb = (T.ntile + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
-    if (nb > 2 * (int64_t)ncu) nb = 2 * (int64_t)ncu;    // each block stages the mask once
-    hipLaunchKernelGGL((k_jcsc_count<LDS>), dim3((unsigned)nb), dim3(SSN_BLOCK), shm, s, T.idx, T.nnz,
+    // each block stages the mask once: as many blocks as fit the CUs at once
+    // (two per CU by waves, fewer when the mask fills the LDS)
+    int per_cu = 2;
+    if (LDS && shm > 0) per_cu = std::max(1, std::min(2, (int)((160 * 1024) / shm)));
+    int64_t nb = (T.ntile + JWAVES - 1) / JWAVES;
+    if (nb > (int64_t)per_cu * ncu) nb = (int64_t)per_cu * ncu;
+    hipLaunchKernelGGL((k_jcsc_count<LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s, T.idx, T.nnz,
                        T.ntile, bits, nw, tcount);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)((T.ntile + SCAN_CHUNK - 1) / SCAN_CHUNK)), dim3(1024),
                        0, s, tcount, T.ntile, toff, total);
     if (T.val_f64)
-        hipLaunchKernelGGL((k_jcsc_write<double, LDS>), dim3((unsigned)nb), dim3(SSN_BLOCK), shm, s,
+        hipLaunchKernelGGL((k_jcsc_write<double, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
                            tcol, T.idx, (const double*)T.val, T.nnz, T.ntile, bits, nw, rank, toff,
                            jr, jc, (double*)jv);
     else
-        hipLaunchKernelGGL((k_jcsc_write<float, LDS>), dim3((unsigned)nb), dim3(SSN_BLOCK), shm, s,
+        hipLaunchKernelGGL((k_jcsc_write<float, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
                            tcol, T.idx, (const float*)T.val, T.nnz, T.ntile, bits, nw, rank, toff,
                            jr, jc, (float*)jv);
 }
