@@ -104,7 +104,7 @@ struct ssnalm_ctx {
     int32_t *jrank = nullptr, *jr = nullptr, *jc = nullptr;
     int2* jrow = nullptr;            // entry range of each row of J (sparse input)
     uint32_t* jbits = nullptr;       // the J mask as bits (sparse input)
-    int32_t* tcol = nullptr;         // column of every entry of the CSC copy (sparse input)
+    void* tcv = nullptr;             // (column, value) of every entry of the CSC copy (sparse input)
     void* jv = nullptr;
     int *tcount = nullptr, *toff = nullptr;
     double *wJ = nullptr, *kcarry = nullptr, *cgpart = nullptr;
@@ -393,7 +393,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         // compact X_J for this Newton step, then fence-free PCG on it
         launch_compact(mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
         launch_rank_from_list(c->jlist, &dsc(c)->p, c->n, c->jrank, c->fwd.ptr, c->jrow, c->st);
-        launch_jcsc_build(c->tr, c->tcol, mask, c->n, c->jbits, c->jrank, c->tcount, c->toff,
+        launch_jcsc_build(c->tr, c->tcv, mask, c->n, c->jbits, c->jrank, c->tcount, c->toff,
                           &dsc(c)->nnzj, c->jr, c->jc, c->jv, c->st);
         launch_fix_flags(c->jc, &dsc(c)->nnzj, c->nchmax, c->fixflag, c->st);
         launch_compact(c->fixflag, c->nchmax, c->fix.list, &dsc(c)->nfix, c->fixblk,
@@ -764,14 +764,35 @@ static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
         STCHK(dalloc(c, &c->qparts, (int64_t)parts * q));
         c->trb_parts = parts;
     }
-    // the column of every CSC entry (the J filter copies it per kept entry)
+    // the column and value of every CSC entry side by side: the J filter
+    // copies both per kept entry with one load
     {
-        std::vector<int32_t> tc(std::max<int64_t>(nnz, 1), 0);
-        for (int64_t j = 0; j < q; ++j)
-            for (int32_t k = cp[j]; k < cp[j + 1]; ++k) tc[k] = (int32_t)j;
-        STCHK(dalloc(c, &c->tcol, std::max<int64_t>(nnz, 1)));
-        if (hipMemcpy(c->tcol, tc.data(), sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice) != hipSuccess)
-            return fail(SSNALM_E_HIP, "upload of the CSC columns failed");
+        const int64_t m = std::max<int64_t>(nnz, 1);
+        hipError_t e;
+        if (vb == 4) {
+            std::vector<ColValF> t(m, ColValF{0, 0.0f});
+            for (int64_t j = 0; j < q; ++j)
+                for (int32_t k = cp[j]; k < cp[j + 1]; ++k) {
+                    t[k].col = (int32_t)j;
+                    memcpy(&t[k].v, cv.data() + 4 * (size_t)k, 4);
+                }
+            ColValF* d = nullptr;
+            STCHK(dalloc(c, &d, m));
+            c->tcv = d;
+            e = hipMemcpy(d, t.data(), sizeof(ColValF) * m, hipMemcpyHostToDevice);
+        } else {
+            std::vector<ColValD> t(m, ColValD{0, 0, 0.0});
+            for (int64_t j = 0; j < q; ++j)
+                for (int32_t k = cp[j]; k < cp[j + 1]; ++k) {
+                    t[k].col = (int32_t)j;
+                    memcpy(&t[k].v, cv.data() + 8 * (size_t)k, 8);
+                }
+            ColValD* d = nullptr;
+            STCHK(dalloc(c, &d, m));
+            c->tcv = d;
+            e = hipMemcpy(d, t.data(), sizeof(ColValD) * m, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) return fail(SSNALM_E_HIP, "upload of the CSC columns failed");
     }
     return SSNALM_OK;
 }

@@ -212,10 +212,10 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const int* __restrict__ tco
 // 64 e + l of the tile, so the kept entries of one step e are consecutive in
 // the output: a ballot gives each its place and every store of the step
 // lands in one contiguous run.  Persistent blocks with the mask in LDS, as
-// the count; tcol gives the column of every entry of the full copy.
-template <typename V, bool LDS>
+// the count; tcv gives the (column, value) of every entry of the full copy.
+template <typename V, typename CV, bool LDS>
 __global__ __launch_bounds__(JBLOCK) void k_jcsc_write(
-    const int32_t* __restrict__ tcol, const int32_t* __restrict__ ridx, const V* __restrict__ val,
+    const CV* __restrict__ tcv, const int32_t* __restrict__ ridx,
     int64_t nnz, int64_t ntile, const uint32_t* __restrict__ bits, int nw,
     const int32_t* __restrict__ rank,
     const int* __restrict__ toff, int32_t* __restrict__ jr, int32_t* __restrict__ jc,
@@ -251,8 +251,9 @@ __global__ __launch_bounds__(JBLOCK) void k_jcsc_write(
         for (int e = 0; e < JE; ++e) {
             const int64_t k = k0 + (int64_t)e * SSN_WAVE;
             rk[e] = keep[e] ? rank[row[e]] : 0;
-            cl[e] = keep[e] ? tcol[k] : 0;
-            vv[e] = keep[e] ? val[k] : V(0);
+            const CV cv = keep[e] ? tcv[k] : CV{};
+            cl[e] = cv.col;
+            vv[e] = cv.v;
         }
         // the next tile's row indices, issued after this tile's gathers so
         // that the stores below wait for the gathers only
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(JBLOCK) void k_jcsc_write(
 }
 
 template <bool LDS>
-static void jcsc_build_t(const SegPlan& T, const int32_t* tcol, const uint32_t* bits, int nw,
+static void jcsc_build_t(const SegPlan& T, const void* tcv, const uint32_t* bits, int nw,
                          const int32_t* rank,
                          int* tcount, int* toff, long long* total, int32_t* jr, int32_t* jc, void* jv,
                          hipStream_t s) {
@@ -278,8 +279,8 @@ static void jcsc_build_t(const SegPlan& T, const int32_t* tcol, const uint32_t* 
     if (LDS && !attr) {
         const int mx = JBITS_MAX_WORDS * (int)sizeof(uint32_t);
         (void)hipFuncSetAttribute((const void*)k_jcsc_count<LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-        (void)hipFuncSetAttribute((const void*)k_jcsc_write<float, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-        (void)hipFuncSetAttribute((const void*)k_jcsc_write<double, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        (void)hipFuncSetAttribute((const void*)k_jcsc_write<float, ColValF, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        (void)hipFuncSetAttribute((const void*)k_jcsc_write<double, ColValD, LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
         attr = true;
     }
     int dev = 0, ncu = 256;
@@ -296,16 +297,16 @@ static void jcsc_build_t(const SegPlan& T, const int32_t* tcol, const uint32_t* 
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)((T.ntile + SCAN_CHUNK - 1) / SCAN_CHUNK)), dim3(1024),
                        0, s, tcount, T.ntile, toff, total);
     if (T.val_f64)
-        hipLaunchKernelGGL((k_jcsc_write<double, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
-                           tcol, T.idx, (const double*)T.val, T.nnz, T.ntile, bits, nw, rank, toff,
+        hipLaunchKernelGGL((k_jcsc_write<double, ColValD, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
+                           (const ColValD*)tcv, T.idx, T.nnz, T.ntile, bits, nw, rank, toff,
                            jr, jc, (double*)jv);
     else
-        hipLaunchKernelGGL((k_jcsc_write<float, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
-                           tcol, T.idx, (const float*)T.val, T.nnz, T.ntile, bits, nw, rank, toff,
+        hipLaunchKernelGGL((k_jcsc_write<float, ColValF, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
+                           (const ColValF*)tcv, T.idx, T.nnz, T.ntile, bits, nw, rank, toff,
                            jr, jc, (float*)jv);
 }
 
-void launch_jcsc_build(const SegPlan& T, const int32_t* tcol, const uint8_t* mask, int64_t n,
+void launch_jcsc_build(const SegPlan& T, const void* tcv, const uint8_t* mask, int64_t n,
                        uint32_t* bits,
                        const int32_t* rank, int* tcount, int* toff, long long* total, int32_t* jr,
                        int32_t* jc, void* jv, hipStream_t s) {
@@ -313,9 +314,9 @@ void launch_jcsc_build(const SegPlan& T, const int32_t* tcol, const uint8_t* mas
     const int nw = jcsc_bits_words(n);
     hipLaunchKernelGGL(k_mask_bits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mask, n, bits);
     if (jcsc_bits_fit(n))
-        jcsc_build_t<true>(T, tcol, bits, nw, rank, tcount, toff, total, jr, jc, jv, s);
+        jcsc_build_t<true>(T, tcv, bits, nw, rank, tcount, toff, total, jr, jc, jv, s);
     else
-        jcsc_build_t<false>(T, tcol, bits, nw, rank, tcount, toff, total, jr, jc, jv, s);
+        jcsc_build_t<false>(T, tcv, bits, nw, rank, tcount, toff, total, jr, jc, jv, s);
 }
 
 }  // namespace ssn

@@ -199,8 +199,11 @@ void launch_rank_from_list(const int32_t* list, const long long* pdev, int64_t n
 // bits), staged in LDS when it fits (jcsc_bits_fit: n <= 1310720 rows)
 int  jcsc_bits_words(int64_t n);
 bool jcsc_bits_fit(int64_t n);
-// tcol: the column of every entry of T
-void launch_jcsc_build(const SegPlan& T, const int32_t* tcol, const uint8_t* mask, int64_t n,
+// tcv: the (column, value) of every entry of T, ColValF or ColValD by T's
+// value type
+struct alignas(8) ColValF { int32_t col; float v; };
+struct alignas(16) ColValD { int32_t col; int32_t pad; double v; };
+void launch_jcsc_build(const SegPlan& T, const void* tcv, const uint8_t* mask, int64_t n,
                        uint32_t* bits,
                        const int32_t* rank, int* tcount, int* toff, long long* total, int32_t* jr,
                        int32_t* jc, void* jv, hipStream_t s);

@@ -241,8 +241,11 @@ def test_newton_empty_free_set():
     np.testing.assert_array_equal(_np(d), -g)
 
 
-def test_newton_pcg_csr():
+@pytest.mark.parametrize("f64", [False, True])
+def test_newton_pcg_csr(f64):
     vals, ci, rp, y = synth.sparse_text(n=20000, q=3000, seed=12)
+    if f64:
+        vals = vals.astype(np.float64)
     n, q = rp.size - 1, 3000
     Xr = sp.csr_matrix((vals.astype(np.float64), ci, rp), shape=(n, q))
     sigma = 25.0
