@@ -433,7 +433,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
             prof_end(c, SSNALM_K_ATMUL_J, (double)nnzj * (8.0 + vb) + 8.0 * p + 8.0 * c->q,
                      2.0 * (double)nnzj);
             launch_cg_step(c->cg_x, c->cg_r, c->cg_p, c->qv, c->sv, c->diag, c->cg_z, c->q,
-                           sigma, p, Pw, nbw, Pdir, Pst[par], Pst[1 - par], tol2, c->st);
+                           sigma, p, Pw, nbw, Pdir, Pst[par], Pst[1 - par], tol2, dsc(c), c->st);
             launch_cg_dir(c->cg_p, c->cg_z, c->sv, c->q, Pst[par], Pst[1 - par], Pdir, tol2,
                           dsc(c), c->qv, c->st);
         };

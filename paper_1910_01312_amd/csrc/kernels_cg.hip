@@ -447,8 +447,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_step(
     const double* __restrict__ t, const double* __restrict__ sv, const double* __restrict__ diag,
     double* __restrict__ z, int64_t q, double sigma, double inv_p, const double* __restrict__ Pw,
     int nbw, const double* __restrict__ Pdir, const double* __restrict__ Pold,
-    double* __restrict__ Pnew, double tol2) {
+    double* __restrict__ Pnew, double tol2, const Scalars* __restrict__ sc) {
     __shared__ double sh[5 * SSN_WAVES_PER_BLOCK];
+    if (sc->cg_done) return;                   // converged in an earlier iteration
     const int nbq = gridDim.x;
     // the five partial sums, every load issued before the one block exchange
     double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -502,6 +503,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_dir(double* __restrict__ pd,
                                                       double* __restrict__ Pdir, double tol2,
                                                       Scalars* sc, double* __restrict__ tz) {
     __shared__ double sh[3 * SSN_WAVES_PER_BLOCK];
+    // converged in an earlier iteration: nothing changes any more (the next
+    // CG start clears tz itself)
+    if (sc->cg_done) return;
     const int nbq = gridDim.x;
     double red[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nbq; b += blockDim.x) {
@@ -548,9 +552,9 @@ void launch_cg_init(const double* g, const double* diag, const double* sv, int64
 void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
                     const double* diag, double* z, int64_t q, double sigma, int64_t p,
                     const double* Pw, int nbw, const double* Pdir, const double* Pold, double* Pnew,
-                    double tol2, hipStream_t s) {
+                    double tol2, const Scalars* sc, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_step, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, x, r, pd, t, sv, diag, z, q,
-                       sigma, p > 0 ? 1.0 / (double)p : 0.0, Pw, nbw, Pdir, Pold, Pnew, tol2);
+                       sigma, p > 0 ? 1.0 / (double)p : 0.0, Pw, nbw, Pdir, Pold, Pnew, tol2, sc);
 }
 void launch_cg_dir(double* pd, const double* z, const double* sv, int64_t q, const double* Pold,
                    const double* Pnew, double* Pdir, double tol2, Scalars* sc, double* tz,

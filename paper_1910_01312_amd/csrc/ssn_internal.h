@@ -242,7 +242,7 @@ void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void*
 void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
                     const double* diag, double* z, int64_t q, double sigma, int64_t p,
                     const double* Pw, int nbw, const double* Pdir, const double* Pold, double* Pnew,
-                    double tol2, hipStream_t s);
+                    double tol2, const Scalars* sc, hipStream_t s);
 void launch_cg_dir(double* pd, const double* z, const double* sv, int64_t q, const double* Pold,
                    const double* Pnew, double* Pdir, double tol2, Scalars* sc, double* tz,
                    hipStream_t s);
