@@ -42,7 +42,7 @@ def log(*a):
 # are byte-identical to the ones measured (sha256 of each file below).
 MEASURED_TRAFFIC = {
     ("sparse-text", "atmul"): {
-        "fetch_kib": 2827230, "write_kib": 272730, "calls": 21,
+        "fetch_kib": 2827230, "write_kib": 272530, "calls": 21,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "files": {
             "paper_1910_01312_amd/csrc/kernels_sparse.hip":
@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
             "paper_1910_01312_amd/csrc/host.hip":
-                "8fe6368e25c8af23abd2e41276f37cd16dfdb735f54d25ea9ff1af91dad8e811",
+                "6c00393bf004bb367625b148b1cb5db43241ad240e3bfb3a48bf30dee1eb2759",
         },
     },
 }
