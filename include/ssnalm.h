@@ -375,11 +375,13 @@ typedef struct {
  * the rows are ranked by P(x_i* = 0) and about keep_frac n of them, those
  * least surely at 0, are kept (cut on a 4096-bin histogram of
  * -log10(1 - P(x_i* = 0)) over [0, 8), ties in the cut bin kept); the kept
- * rows are solved by ssnalm_solve at tol / 2, the result (zero on the left-out rows)
- * is judged by R_KKT of the FULL problem (eq. Def_Rkkt); rows whose margin
- * y_i (w^T x_i + b) is below 1 are added and the reduced solve repeated
- * from the previous round's solution, at most max_rounds times; otherwise (or when more than half of the rows are
- * kept) the plain cold solve of the full problem runs.  The returned x
+ * rows are solved by ssnalm_solve at tol, the result (zero on the left-out
+ * rows) is judged by R_KKT of the FULL problem (eq. Def_Rkkt); rows whose
+ * margin y_i (w^T x_i + b) is below 1 are added and the reduced solve
+ * repeated from the previous round's solution (at half the previous
+ * tolerance when no row was added), at most max_rounds times; otherwise (or
+ * when more than half of the rows are kept) the plain cold solve of the full
+ * problem runs.  The returned x
  * always satisfies R_KKT <= tol on the full problem when status is OK.
  * x_out: n doubles (device); w_out: q doubles (device) or NULL; info,
  * stats: host pointers or NULL.  Allocates the reduced copies per call.

@@ -1351,11 +1351,18 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
     double t_red = 0.0;
     bool done = false;
     long long prev_m = -1;
+    // The reduced problem is solved at the full problem's tol: with the left-out
+    // rows at 0 and outside the margin their residual terms vanish, so the
+    // full-problem R_KKT is the reduced one.  When it is not (no new margin
+    // violators, R_KKT still above tol), the same rows are solved again from
+    // that solution at half the previous tolerance.
+    double tol_k = c->tol;
     for (int round = 0; round < max_rounds && !done; ++round) {
         launch_compact(keep, n, list, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
         STCHK(sync_state(c));
         const long long m = c->hs->sc.p;
-        if (m == prev_m || m < 2 || 2 * m > n) break;        // nothing new, or not worth it
+        if (m < 2 || 2 * m > n) break;                      // not worth it
+        if (m == prev_m) tol_k *= 0.5;                      // nothing new: tighten instead
         prev_m = m;
         launch_gather_rows(c->dtype, c->X, c->y, list, m, q, Xk, yk, c->st);
         HIPCHK(hipStreamSynchronize(c->st));
@@ -1369,7 +1376,7 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
         pk.X = Xk;
         pk.y = yk;
         pk.C = c->C;
-        pk.tol = 0.5 * c->tol;
+        pk.tol = tol_k;
         ssnalm_options ok = c->opt;
         ok.profile = 0;
         ssnalm_ctx* sub = nullptr;
