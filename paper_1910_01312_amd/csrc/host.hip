@@ -1012,12 +1012,21 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
             for (int m = 0; m <= o.max_backtracks; ++m) {
                 ++ls_trials;
                 STCHK(project_into(c, c->u, c->td, alpha * sigma, c->ut, trial, dps(c, c->base)));
-                STCHK(sync_state(c));
-                STCHK(project_finish(c, c->ut, trial, &more));
+                // the trial's sums are launched before the host knows whether the
+                // first passes finished the projection (they nearly always do):
+                // one host round trip per trial; otherwise more passes and the
+                // sums again
                 launch_ls_finalize(c->ut, c->u, c->td, alpha * sigma, c->y, n, c->C,
                                    dps(c, trial), dps(c, c->base), c->xk, c->xtt, c->jmt,
                                    dsc(c), c->spart, cnt(c, CNT_LS), c->st);
                 STCHK(sync_state(c));
+                STCHK(project_finish(c, c->ut, trial, &more));
+                if (more) {
+                    launch_ls_finalize(c->ut, c->u, c->td, alpha * sigma, c->y, n, c->C,
+                                       dps(c, trial), dps(c, c->base), c->xk, c->xtt, c->jmt,
+                                       dsc(c), c->spart, cnt(c, CNT_LS), c->st);
+                    STCHK(sync_state(c));
+                }
                 c->proj_passes += c->hs->ps[trial].passes;
                 const Scalars& s2 = c->hs->sc;
                 if (m == 0 && s2.gd >= 0.0 && gn > 0.0) {
