@@ -127,6 +127,35 @@ def test_csr_matvec(n, q, seed, f64):
         assert np.all(np.abs(r - r_ref) <= 1e-12 * (absX.T @ np.abs(z)) + 1e-300)
 
 
+@pytest.mark.parametrize("n,f64", [(131073, False), (140000, True), (262144, False)])
+def test_csr_transpose_row_blocks(n, f64):
+    """n >= 2^17 rows: A^T z runs over the CSC copy cut into row blocks (one
+    per XCD) with the per-block column sums added afterwards (a column present
+    in most rows, empty columns); integer data, so every sum is exact."""
+    q = 5000
+    rng = np.random.default_rng(n)
+    lens = rng.poisson(5, size=n)
+    rows = np.repeat(np.arange(n), lens)
+    cols = rng.integers(1, q - 10, size=rows.size)           # the last columns stay empty
+    heavy = np.nonzero(rng.random(n) < 0.8)[0]
+    rows = np.concatenate([rows, heavy])
+    cols = np.concatenate([cols, np.zeros(heavy.size, np.int64)])
+    vals = rng.integers(-3, 4, size=rows.size).astype(np.float64)
+    M = sp.csr_matrix((vals, (rows, cols)), shape=(n, q))
+    M.sum_duplicates()
+    M.sort_indices()
+    data = M.data.astype(np.float64 if f64 else np.float32)
+    y = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    z = rng.integers(-4, 5, size=n).astype(np.float64)
+    v = rng.integers(-4, 5, size=q).astype(np.float64)
+    Xref = sp.csr_matrix((data.astype(np.float64), M.indices, M.indptr), shape=(n, q))
+    with _solver(csr=(data, M.indices.astype(np.int32), M.indptr.astype(np.int64), n, q), y=y) as s:
+        r = _np(s.atmul(z))
+        t = _np(s.amul(v))
+    np.testing.assert_array_equal(r, Xref.T @ (y * z))
+    np.testing.assert_array_equal(t, y * (Xref @ v))
+
+
 def test_csr_text_like_sample():
     """Workload-shaped CSR (Zipf columns, L2-normalised rows), reduced n."""
     vals, ci, rp, y = synth.sparse_text(n=30000, q=8000, seed=11)
