@@ -42,7 +42,7 @@ def log(*a):
 # are byte-identical to the ones measured (sha256 of each file below).
 MEASURED_TRAFFIC = {
     ("sparse-text", "atmul"): {
-        "fetch_kib": 2827230, "write_kib": 272530, "calls": 21,
+        "fetch_kib": 2827230, "write_kib": 273230, "calls": 21,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "files": {
             "paper_1910_01312_amd/csrc/kernels_sparse.hip":
@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
             "paper_1910_01312_amd/csrc/host.hip":
-                "6c00393bf004bb367625b148b1cb5db43241ad240e3bfb3a48bf30dee1eb2759",
+                "29da4f2be3348414e9d7dac4bd1c6c25bcf1ae779e33602f941c177beb8ee104",
         },
     },
 }
