@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
             "paper_1910_01312_amd/csrc/host.hip":
-                "29da4f2be3348414e9d7dac4bd1c6c25bcf1ae779e33602f941c177beb8ee104",
+                "b7e05247096f667048edd73d4bbd2928c563d560788a5abcc96a2a8368201784",
         },
     },
 }

@@ -403,10 +403,10 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         c->fix.nfix = c->hs->sc.nfix;
         launch_fix_ends(c->jc, nnzj, c->fix, c->st);
         const int vf64 = c->dtype == SSNALM_F64;
-        launch_keyed_tr(1, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sv, c->q, c->st,
-                        true, &c->fix);
-        launch_keyed_tr(2, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sq, c->q, c->st,
-                        true, &c->fix);
+        launch_keyed_tr(1, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sv, c->q, c->fix,
+                        c->st);
+        launch_keyed_tr(2, c->jr, c->jc, c->jv, vf64, nnzj, nullptr, c->kcarry, c->sq, c->q, c->fix,
+                        c->st);
         launch_jacobi_diag(c->sq, c->sv, sigma, p, c->diag, c->q, c->st);
         const double tol2 = cg_tol * cg_tol;
         double* Pw = c->cgpart;
@@ -429,7 +429,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                      2.0 * (double)nnzj);
             prof_begin(c, SSNALM_K_ATMUL_J);
             launch_keyed_tr(0, c->jr, c->jc, c->jv, vf64, nnzj, c->wJ, c->kcarry, c->qv, c->q,
-                            c->st, false, &c->fix, &dsc(c)->cg_done);
+                            c->fix, c->st, false, &dsc(c)->cg_done);
             prof_end(c, SSNALM_K_ATMUL_J, (double)nnzj * (8.0 + vb) + 8.0 * p + 8.0 * c->q,
                      2.0 * (double)nnzj);
             launch_cg_step(c->cg_x, c->cg_r, c->cg_p, c->qv, c->sv, c->diag, c->cg_z, c->q,

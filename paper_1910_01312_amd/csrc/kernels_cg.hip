@@ -12,10 +12,11 @@
 // in every block.  All blocks therefore see bit-identical scalars.
 //
 // X_J^T w runs over the compact column-major copy of X_J (entries sorted by
-// column) in fixed chunks of 512 entries (8 per lane, one wave per chunk).
+// column) in fixed chunks of 256 entries (4 per lane, one wave per chunk).
 // Runs of equal column inside a chunk are summed by a segmented scan; a run
-// that reaches a chunk border is left as a carry and the chunk where the
-// run starts adds the carries of the chunks it runs through, in chunk order.
+// that reaches a chunk border is left as a carry per chunk, and the runs that
+// cross borders, listed once per copy (first chunk, last chunk, column), are
+// summed from their carries in chunk order by one wave each.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
@@ -46,7 +47,6 @@ static inline unsigned qgrid(int64_t q) {
     if (b < 1) b = 1;
     return (unsigned)b;
 }
-unsigned cg_qgrid(int64_t q) { return qgrid(q); }
 
 // --------------------------------------------------------------- init
 // x = 0, r = -g, z = r/diag, p = z; partials: Pst = (r.z, r.r), Pdir = (p.p, s.p)
@@ -277,51 +277,11 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_keyed_tr(const int32_t* __restric
     }
 }
 
-// Chunks where a border-crossing run starts (its last run leaves to the
-// right without having come from the left) add the carries of the chunks
-// the run passes through and of the chunk where it ends.  One wave each.
-__global__ __launch_bounds__(SSN_BLOCK) void k_keyed_fix(const int32_t* __restrict__ jc,
-                                                         int64_t nnzj, int64_t nch,
-                                                         const double* __restrict__ carry,
-                                                         double* __restrict__ out) {
-    const int lane = threadIdx.x & (SSN_WAVE - 1);
-    const int64_t ch = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
-    if (ch >= nch) return;
-    const int64_t cb = ch * KCH;
-    const int64_t ce = cb + KCH < nnzj ? cb + KCH : nnzj;
-    const int32_t K = jc[ce - 1];
-    const bool right_out = ce < nnzj && jc[ce] == K;
-    if (!right_out) return;
-    const bool single = jc[cb] == K;
-    const bool left_in = single && cb > 0 && jc[cb - 1] == K;
-    if (left_in) return;                       // not where the run starts
-    double tot = 0.0;
-    if (lane == 0) tot = carry[ch * 2 + 1];
-    int64_t base = ch + 1;
-    for (;;) {
-        const int64_t c2 = base + lane;
-        bool pass = false, valid = c2 < nch;
-        if (valid) {
-            const int64_t b2 = c2 * KCH;
-            const int64_t e2 = b2 + KCH < nnzj ? b2 + KCH : nnzj;
-            pass = jc[b2] == K && jc[e2 - 1] == K && e2 < nnzj && jc[e2] == K;
-        }
-        const unsigned long long stop = __ballot(valid && !pass);
-        const int term = stop ? __ffsll((long long)stop) - 1 : SSN_WAVE;
-        double v = 0.0;
-        if (lane < term && valid) v = carry[c2 * 2 + 1];
-        if (lane == term) v = carry[c2 * 2 + 0];
-        tot += wave_sum(v);
-        if (term < SSN_WAVE) break;
-        base += SSN_WAVE;
-        if (base >= nch) break;
-    }
-    if (lane == 0) out[K] = tot;
-}
-
 // ---- the border-crossing runs, listed once per compact copy
-// flag[ch] = 1 where a border-crossing run starts (the test of k_keyed_fix);
-// the chunk count comes from the device-side entry count.
+// flag[ch] = 1 where a border-crossing run starts: the chunk's last run
+// leaves to the right without having come from the left (a chunk holding
+// one column that both enters and leaves is passed through, not a start).
+// The chunk count comes from the device-side entry count.
 __global__ void k_fix_flags(const int32_t* __restrict__ jc, const long long* __restrict__ nnzj_dev,
                             int64_t nchmax, uint8_t* __restrict__ flag) {
     const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -411,7 +371,7 @@ void launch_fix_ends(const int32_t* jc, int64_t nnzj, KeyedFix& fx, hipStream_t 
 
 void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
                      int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
-                     hipStream_t s, bool zero_out, const KeyedFix* fx, const int* skip) {
+                     const KeyedFix& fx, hipStream_t s, bool zero_out, const int* skip) {
     if (zero_out) launch_fill(out, 0.0, q, s);
     if (nnzj <= 0) return;
     const int64_t nch = (nnzj + KCH - 1) / KCH;
@@ -424,14 +384,10 @@ void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void*
         if (mode == 0) KT(float, 0); else if (mode == 1) KT(float, 1); else KT(float, 2);
     }
 #undef KT
-    if (fx) {
-        if (fx->nfix > 0) {
-            const unsigned nf = (unsigned)((fx->nfix + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
-            hipLaunchKernelGGL(k_keyed_fix_list, dim3(nf), dim3(SSN_BLOCK), 0, s, fx->list, fx->fend,
-                               fx->fcol, fx->nfix, carry, out, skip);
-        }
-    } else {
-        hipLaunchKernelGGL(k_keyed_fix, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, nch, carry, out);
+    if (fx.nfix > 0) {
+        const unsigned nf = (unsigned)((fx.nfix + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
+        hipLaunchKernelGGL(k_keyed_fix_list, dim3(nf), dim3(SSN_BLOCK), 0, s, fx.list, fx.fend,
+                           fx.fcol, fx.nfix, carry, out, skip);
     }
 }
 

@@ -209,7 +209,6 @@ void launch_jcsc_build(const SegPlan& T, const void* tcv, const uint8_t* mask, i
                        int32_t* jc, void* jv, hipStream_t s);
 
 // Fence-free CG on the compact X_J (kernels_cg.hip) ----------------------------
-unsigned cg_qgrid(int64_t q);
 unsigned cg_rows_grid(int64_t p);
 void launch_cg_init(const double* g, const double* diag, const double* sv, int64_t q, double* x,
                     double* r, double* z, double* pd, double* Pst, double* Pdir, hipStream_t s);
@@ -233,11 +232,11 @@ int64_t keyed_chunks(int64_t nnz);
 void launch_fix_flags(const int32_t* jc, const long long* nnzj_dev, int64_t nchmax, uint8_t* flag,
                       hipStream_t s);
 void launch_fix_ends(const int32_t* jc, int64_t nnzj, KeyedFix& fx, hipStream_t s);
-// with fx, the crossing runs are summed from the list instead of being
-// found by a scan of every chunk
+// out = X_J^T coef over the compact copy (mode 0: coef = w[rank], 1: values,
+// 2: squared values); the crossing runs fx are summed by a second kernel
 void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void* jv, int val_f64,
                      int64_t nnzj, const double* w, double* carry, double* out, int64_t q,
-                     hipStream_t s, bool zero_out = true, const KeyedFix* fx = nullptr,
+                     const KeyedFix& fx, hipStream_t s, bool zero_out = true,
                      const int* skip = nullptr);   // skip: no work while *skip is nonzero
 void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
                     const double* diag, double* z, int64_t q, double sigma, int64_t p,
