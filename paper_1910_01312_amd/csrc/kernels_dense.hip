@@ -270,6 +270,81 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_atmul_dense(const T* __restrict__
     }
 }
 
+// The same sums for rows that fit one 16-byte piece per lane (q <= 64 VEC,
+// q VEC-aligned): each wave takes R rows at a time, issues the loads of all
+// of them that carry a nonzero coefficient (raw pieces, widened at the FMA)
+// before the first FMA, and skips the rest; then the block reduction as above.
+template <typename T, int VEC, int R, int MM>
+__global__ __launch_bounds__(SSN_BLOCK) void k_atmul_rows(const T* __restrict__ X,
+                                                          const int8_t* __restrict__ y,
+                                                          const double* __restrict__ z,
+                                                          const uint8_t* __restrict__ mask,
+                                                          int64_t n, int64_t q,
+                                                          int64_t rows_per_blk,
+                                                          double* __restrict__ part,
+                                                          double* __restrict__ part2) {
+    __shared__ double red[SSN_WAVES_PER_BLOCK][SSN_WAVE * VEC];
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int w = threadIdx.x / SSN_WAVE;
+    const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
+    const bool on = (int64_t)lane * VEC < q;
+    double acc[VEC], acc2[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) { acc[e] = 0.0; acc2[e] = 0.0; }
+    for (int64_t base = rb + (int64_t)w * R; base < re; base += (int64_t)SSN_WAVES_PER_BLOCK * R) {
+        // the R coefficients loaded by lanes 0..R-1 at once, then broadcast
+        double mz = 0.0, mm = 0.0;
+        {
+            const int64_t row = base + (lane & (R - 1));
+            if (lane < R && row < re) {
+                if (z) mz = (double)y[row] * z[row];
+                if (MM) mm = (double)mask[row];
+            }
+        }
+        double cf[R], cm[R];
+        bool use[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cf[r] = __shfl(mz, r, SSN_WAVE);
+            cm[r] = MM ? __shfl(mm, r, SSN_WAVE) : 0.0;
+            use[r] = cf[r] != 0.0 || cm[r] != 0.0;          // uniform across the wave
+        }
+        RawPiece<T, VEC> pc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pc[r].u = make_uint4(0u, 0u, 0u, 0u);
+            if (use[r] && on)
+                pc[r].u = *reinterpret_cast<const uint4*>(X + (base + r) * q + (int64_t)lane * VEC);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!use[r]) continue;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const double xv = pc[r].get(e);
+                acc[e] = fma(cf[r], xv, acc[e]);
+                if (MM == 1) acc2[e] = fma(cm[r], xv, acc2[e]);
+                if (MM == 2) acc2[e] = fma(cm[r] * xv, xv, acc2[e]);
+            }
+        }
+    }
+#pragma unroll
+    for (int pass = 0; pass < (MM ? 2 : 1); ++pass) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) red[w][lane * VEC + e] = pass == 0 ? acc[e] : acc2[e];
+        __syncthreads();
+        double* out = pass == 0 ? part : part2;
+        for (int64_t k = threadIdx.x; k < q; k += SSN_BLOCK) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < SSN_WAVES_PER_BLOCK; ++ww) sacc += red[ww][k];
+            out[(int64_t)blockIdx.x * q + k] = sacc;
+        }
+        __syncthreads();
+    }
+}
+
 int atmul_dense_nblk(int64_t n) {
     int64_t nb = (n + 255) / 256;
     if (nb > 1024) nb = 1024;
@@ -283,6 +358,21 @@ static void atmul_dispatch(const T* X, const int8_t* y, const double* z, const u
                            int mm) {
     const int nb = atmul_dense_nblk(n);
     const int64_t rows_per_blk = (n + nb - 1) / nb;
+    if constexpr (VEC * sizeof(T) == 16) {
+        if (q <= (int64_t)SSN_WAVE * VEC) {            // one piece per lane covers a row
+            constexpr int R = 8;
+            if (mask && mm == 2)
+                hipLaunchKernelGGL((k_atmul_rows<T, VEC, R, 2>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
+                                   s, X, y, z, mask, n, q, rows_per_blk, part, part2);
+            else if (mask)
+                hipLaunchKernelGGL((k_atmul_rows<T, VEC, R, 1>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
+                                   s, X, y, z, mask, n, q, rows_per_blk, part, part2);
+            else
+                hipLaunchKernelGGL((k_atmul_rows<T, VEC, R, 0>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
+                                   s, X, y, z, mask, n, q, rows_per_blk, part, part2);
+            return;
+        }
+    }
     constexpr int NCH = (VEC == 1) ? 4 : 2;     // columns per tile: 64*VEC*NCH
     const int64_t tile_cols = (int64_t)SSN_WAVE * VEC * NCH;
     const int64_t ty = (q + tile_cols - 1) / tile_cols;
