@@ -42,7 +42,7 @@ def log(*a):
 # are byte-identical to the ones measured (sha256 of each file below).
 MEASURED_TRAFFIC = {
     ("sparse-text", "atmul"): {
-        "fetch_kib": 2827230, "write_kib": 273230, "calls": 21,
+        "fetch_kib": 2827190, "write_kib": 272830, "calls": 21,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "files": {
             "paper_1910_01312_amd/csrc/kernels_sparse.hip":
@@ -50,7 +50,7 @@ MEASURED_TRAFFIC = {
             "paper_1910_01312_amd/csrc/kernels_vec.hip":
                 "d2593ff52a12f7214c9f9be4269b350a4c1b3ddc9e466db259125b4240e2046e",
             "paper_1910_01312_amd/csrc/kernels_dense.hip":
-                "271a1dcd29394b25b565b26b07e89f862f9dc7d60fd9720887949fc96d127e1f",
+                "0525a806b852e6fe6613027d868baff24b34e9855b73af1fa3c09d599073004e",
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
             "paper_1910_01312_amd/csrc/host.hip":
