@@ -1,4 +1,4 @@
-// Host driver of the SSsNAL solver and the C ABI (include/ssnalm.h).
+// Host side of the SSsNAL solver and the C ABI (include/ssnalm.h).
 //
 // Algorithm 1 (outer augmented Lagrangian loop on the restricted dual (D))
 // and Algorithm 3 (semismooth Newton on psi, eq. Def_psi) run here; every

@@ -1,4 +1,4 @@
-// Host driver of the batched solve (ssnalm_solve_batch, include/ssnalm.h).
+// Host side of the batched solve (ssnalm_solve_batch, include/ssnalm.h).
 //
 // Every problem runs Algorithm 1 (augmented Lagrangian on the restricted
 // dual) with Algorithm 3 (semismooth Newton on psi, Cholesky step) exactly as

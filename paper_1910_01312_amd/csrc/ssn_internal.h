@@ -1,5 +1,5 @@
 // Internal declarations of the SSsNAL library: device state layouts shared
-// between host driver and kernels, and the host-side launchers of every
+// between host code and kernels, and the host-side launchers of every
 // kernel.  Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
