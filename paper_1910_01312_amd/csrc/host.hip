@@ -416,7 +416,8 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                        c->st);
         launch_cg_publish(Pst[0], c->q, tol2, dsc(c), c->st);
         launch_fill(c->qv, 0.0, c->q, c->st);      // later zeroed by the direction kernel
-        STCHK(sync_state(c));
+        // no host check before the first batch: when the start already meets the
+        // tolerance the batch's kernels see the done flag and pass through
         const int nbw = (int)cg_rows_grid(p);
         const double vb = elem_bytes(c->dtype);
         int it = 0;
@@ -443,7 +444,9 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         constexpr int kCgBatch = 8;
         const bool use_graph = !prof_on(c, SSNALM_K_AMUL_J) && !prof_on(c, SSNALM_K_ATMUL_J);
         bool captured = false;
-        while (it < c->opt.max_cg && !c->hs->sc.cg_done) {
+        bool first = true;
+        while (it < c->opt.max_cg && (first || !c->hs->sc.cg_done)) {
+            first = false;
             const int batch = std::min(kCgBatch, c->opt.max_cg - it);
             if (use_graph && batch == kCgBatch) {
                 if (!captured) {
@@ -474,6 +477,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
             it += batch;
             STCHK(sync_state(c));
         }
+        if (first) STCHK(sync_state(c));   // no batch ran (max_cg = 0)
         *cg_iters = c->hs->sc.cg_count;     // iterations that did work (a batch may end early)
         HIPCHK(hipMemcpyAsync(d, c->cg_x, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
         return SSNALM_OK;
