@@ -42,7 +42,7 @@ def log(*a):
 # are byte-identical to the ones measured (sha256 of each file below).
 MEASURED_TRAFFIC = {
     ("sparse-text", "atmul"): {
-        "fetch_kib": 2827190, "write_kib": 272830, "calls": 21,
+        "fetch_kib": 2827190, "write_kib": 273030, "calls": 21,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "files": {
             "paper_1910_01312_amd/csrc/kernels_sparse.hip":
@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
             "paper_1910_01312_amd/csrc/host.hip":
-                "b7e05247096f667048edd73d4bbd2928c563d560788a5abcc96a2a8368201784",
+                "04902bb7ca2f6b1d12629b06681341bea5f94024ef4bdec02c365f92894f41b0",
         },
     },
 }
