@@ -213,23 +213,18 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_amul2(BArgs A, const double* __r
 #pragma unroll
         for (int e = 0; e < VE; ++e) vloc[e] = c0 + e < q ? V[(int64_t)k * q + c0 + e] : 0.0;
         const T* X = (const T*)Pr.X;
+        // every load issued: a row past the item reads the item's last row and a
+        // piece past the row end (P rounded up to a power of two) reads the last
+        // piece; both products are dropped (vloc is 0 there, the store is
+        // skipped).  q is a multiple of VE here, so a piece never straddles it.
+        const int cc = c0 < q ? c0 : q - VE;
         for (int r0 = item.y + wv * R * G; r0 < item.z; r0 += SSN_WAVES_PER_BLOCK * R * G) {
             RawPiece<T, VE> raw[R];
 #pragma unroll
             for (int u = 0; u < R; ++u) {
                 const int row = r0 + u * G + g;
-                raw[u].u = make_uint4(0u, 0u, 0u, 0u);
-                if (row < item.z && c0 < q) {
-                    const T* p = X + (int64_t)row * q + c0;
-                    if (c0 + VE <= q) {
-                        raw[u].u = *reinterpret_cast<const uint4*>(p);
-                    } else {
-                        T tmp[VE];
-#pragma unroll
-                        for (int e = 0; e < VE; ++e) tmp[e] = c0 + e < q ? p[e] : T(0);
-                        raw[u].u = *reinterpret_cast<const uint4*>(tmp);
-                    }
-                }
+                const int rc = row < item.z ? row : item.z - 1;
+                raw[u].u = *reinterpret_cast<const uint4*>(X + (int64_t)rc * q + cc);
             }
             double acc[R];
 #pragma unroll
