@@ -42,7 +42,7 @@ def log(*a):
 # are byte-identical to the ones measured (sha256 of each file below).
 MEASURED_TRAFFIC = {
     ("sparse-text", "atmul"): {
-        "fetch_kib": 2827190, "write_kib": 273030, "calls": 21,
+        "fetch_kib": 2827190, "write_kib": 273130, "calls": 21,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "files": {
             "paper_1910_01312_amd/csrc/kernels_sparse.hip":
@@ -50,7 +50,7 @@ MEASURED_TRAFFIC = {
             "paper_1910_01312_amd/csrc/kernels_vec.hip":
                 "d2593ff52a12f7214c9f9be4269b350a4c1b3ddc9e466db259125b4240e2046e",
             "paper_1910_01312_amd/csrc/kernels_dense.hip":
-                "0525a806b852e6fe6613027d868baff24b34e9855b73af1fa3c09d599073004e",
+                "c8ccb65d530cb18473018fbcade3b41e9021dc52ffd8421f69feb295fe924e7b",
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
             "paper_1910_01312_amd/csrc/host.hip":

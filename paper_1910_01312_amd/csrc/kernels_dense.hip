@@ -91,27 +91,20 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_amul_rows(const T* __restrict__ X
     const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
     const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
     const int64_t c0 = (int64_t)lane * VEC;
-    const bool full = c0 + VEC <= q;              // this lane's piece is whole
     double vloc[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) vloc[e] = c0 + e < q ? v[c0 + e] : 0.0;
+    // q is a multiple of VEC here; every load is issued: a lane past the row
+    // end reads the row's last piece and a row past n reads row n - 1, and
+    // both products are dropped (vloc is 0 there, the store is skipped), so
+    // that no load sits under a branch
+    const int64_t cc = c0 < q ? c0 : q - VEC;
     for (int64_t r0 = wave * R; r0 < n; r0 += nwave * R) {
         RawPiece<T, VEC> raw[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-            const int64_t row = r0 + u;
-            raw[u].u = make_uint4(0u, 0u, 0u, 0u);
-            if (row < n) {
-                const T* p = X + row * q + c0;
-                if (full) {
-                    raw[u].u = *reinterpret_cast<const uint4*>(p);
-                } else if (c0 < q) {
-                    T tmp[VEC];
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) tmp[e] = c0 + e < q ? p[e] : T(0);
-                    raw[u].u = *reinterpret_cast<const uint4*>(tmp);
-                }
-            }
+            const int64_t row = r0 + u < n ? r0 + u : n - 1;
+            raw[u].u = *reinterpret_cast<const uint4*>(X + row * q + cc);
         }
         double acc[R];
 #pragma unroll
