@@ -56,8 +56,10 @@ __device__ __forceinline__ double segval(const V* val, int64_t k, bool sq) {
 }
 
 // coef(i) = vin[i] * (yin ? yin[i] : 1) * (mask ? mask[i] : 1), or mask[i]
-// alone when vin == nullptr.
-template <typename V, bool SQ>
+// alone when vin == nullptr.  CM names the case at compile time, so that the
+// gathers carry no run-time tests and are all in flight together:
+// 0 = vin alone, 1 = mask alone, 2 = any other combination.
+template <typename V, bool SQ, int CM>
 __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
     int64_t nseg, int64_t nnz, const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
     const V* __restrict__ val, const int32_t* __restrict__ lane_seg, int64_t ntile,
@@ -123,7 +125,11 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
 #pragma unroll
         for (int e = 0; e < SEG_E; ++e) {
             double cf = 0.0;
-            if (e < ne) {
+            if constexpr (CM == 0) {
+                cf = vin[ii[e]];                 // ii = 0, av = 0 past the lane's entries
+            } else if constexpr (CM == 1) {
+                cf = (double)mask[ii[e]];
+            } else if (e < ne) {
                 const int32_t i = ii[e];
                 if (vin) {
                     cf = vin[i];
@@ -275,16 +281,17 @@ static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin
         nb = (int64_t)parts * ((tpp + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
     }
     if (nb > 0) {
-        if (P.val_f64)
-            hipLaunchKernelGGL((k_segsum<double, SQ>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, s,
-                               P.nseg, P.nnz, P.ptr, P.idx, (const double*)P.val, P.lane_seg,
-                               P.ntile, P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out,
-                               parts, tpp);
-        else
-            hipLaunchKernelGGL((k_segsum<float, SQ>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, s,
-                               P.nseg, P.nnz, P.ptr, P.idx, (const float*)P.val, P.lane_seg,
-                               P.ntile, P.tile_first, P.carry, vin, yin, mask, yout, out_mask, out,
-                               parts, tpp);
+        const int cm = (vin && !yin && !mask) ? 0 : ((!vin && mask) ? 1 : 2);
+#define SEGSUM(V, CM) hipLaunchKernelGGL((k_segsum<V, SQ, CM>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, \
+                                         s, P.nseg, P.nnz, P.ptr, P.idx, (const V*)P.val, P.lane_seg, \
+                                         P.ntile, P.tile_first, P.carry, vin, yin, mask, yout, \
+                                         out_mask, out, parts, tpp)
+        if (P.val_f64) {
+            if (cm == 0) SEGSUM(double, 0); else if (cm == 1) SEGSUM(double, 1); else SEGSUM(double, 2);
+        } else {
+            if (cm == 0) SEGSUM(float, 0); else if (cm == 1) SEGSUM(float, 1); else SEGSUM(float, 2);
+        }
+#undef SEGSUM
     }
     if (P.nspan > 0) {
         const int64_t nbs = (P.nshort + SSN_BLOCK - 1) / SSN_BLOCK;
