@@ -576,9 +576,12 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_proj_pass(BArgs A, const double*
             int yy[BPU];
 #pragma unroll
             for (int u = 0; u < BPU; ++u) {            // every load of the step first
+                // (a row past the item reads its last row, unused below: no load
+                // sits under a branch, so all of them are in flight together)
                 const int r = base + u * (int)blockDim.x + threadIdx.x;
-                vv[u] = r < item.z ? v[Pr.off + r] : 0.0;
-                yy[u] = r < item.z ? (int)Pr.y[r] : 0;
+                const int rc = r < item.z ? r : item.z - 1;
+                vv[u] = v[Pr.off + rc];
+                yy[u] = (int)Pr.y[rc];
             }
             bool take[BPU];
             double bb[BPU];

@@ -221,9 +221,12 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_proj_pass(const double* __restric
             int yy[PU];
 #pragma unroll
             for (int u = 0; u < PU; ++u) {             // every load of the step first
+                // (an index past n reads element n - 1, unused below: no load
+                // sits under a branch, so all of them are in flight together)
                 const int64_t i = base + u * SSN_BLOCK + threadIdx.x;
-                vv[u] = i < n ? v[i] : 0.0;
-                yy[u] = i < n ? (int)y[i] : 0;
+                const int64_t ic = i < n ? i : n - 1;
+                vv[u] = v[ic];
+                yy[u] = (int)y[ic];
             }
             bool take[PU];
             double bb[PU];
