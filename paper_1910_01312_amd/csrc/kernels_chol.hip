@@ -26,8 +26,10 @@ int64_t chol_inv_size(int64_t q) { return (q + NB - 1) / NB * 2 * NB * NB; }
 
 // Factor diagonal block kb and form X = L_kk^{-1}, both right-looking in
 // registers: thread t keeps row i = t % 64, columns 16 (t / 64) .. +15 of the
-// block (a) and of B (initially I).  Step k publishes column k of a and row k
-// of B through LDS (double buffered, one barrier per step); then
+// block (a), and column j = t % 64, rows 16 (t / 64) .. +15 of B (initially
+// I), so that each thread finds B[k][j] in its own column.  Step k publishes
+// column k of a and row k of B through LDS (double buffered, one barrier per
+// step; row k of B is one vector store by the wave holding it); then
 //   l_kk = sqrt(a_kk),  l_ik = a_ik / l_kk,  X[k][.] = B[k][.] / l_kk,
 //   a_ij -= a_ik a_jk / a_kk  and  B[i][.] -= (a_ik / a_kk) B[k][.]  (i > k),
 // which is forward substitution of L X = I carried along with the
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
     const int o = kb * NB;
     const int m = min(NB, q - o);
     const int i = tid & (NB - 1), cg = tid >> 6;
-    double a[16], b[16];
+    double a[16], b[16];                  // a: A[i][16 cg + jj];  b: B[16 cg + jj][i]
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
         const int j = cg * 16 + jj;
@@ -62,22 +64,18 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
         const int k = kg * 16 + kk;
         double* cr = col[kk & 1];
         double* rb = rowb[kk & 1];
-        if (cgu == kg) cr[i] = a[kk];
-        if (i == k) {
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) rb[cgu * 16 + jj] = b[jj];
+        if (cgu == kg) {
+            cr[i] = a[kk];
+            rb[i] = b[kk];                                // B[k][i], for column i
         }
         __syncthreads();
         // every LDS read of the step is issued here, ahead of the pivot math
         double akk = cr[k];
         const double cik = cr[i];
-        double cj[16], bj[16];
+        const double bki = rb[i];                         // B[k][j] of this thread's column
+        double cj[16];
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) cj[jj] = cr[cgu * 16 + jj];
-        if (cgu * 16 <= k) {
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) bj[jj] = rb[cgu * 16 + jj];
-        }
         if (!(akk > 0.0)) {
             bad = true;
             akk = 1.0;
@@ -94,10 +92,14 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
                 a[jj] = fma(-t, l, a[jj]);
             }
         }
-        if (cgu * 16 <= k) {                              // B[k][c] = 0 for c > k
-            const double f = i == k ? rl : 1.0;
+        if (cgu * 16 + 15 >= k) {                         // rows r < k do not change
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) b[jj] = fma(-t, bj[jj], b[jj]) * f;
+            for (int jj = 0; jj < 16; ++jj) {
+                const int r = cgu * 16 + jj;              // B[r][i] -= (a_rk / a_kk) B[k][i]
+                const double tr = r > k ? cj[jj] * rk : 0.0;
+                const double f = r == k ? rl : 1.0;
+                b[jj] = fma(-tr, bki, b[jj]) * f;
+            }
         }
     }
     if (bad && tid == 0) sc->chol_fail = 1;
@@ -111,9 +113,10 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
             M[(int64_t)(o + i) * q + o + j] = a[jj];
             M[(int64_t)(o + j) * q + o + i] = a[jj];
         }
-        const double x = j <= i ? b[jj] : 0.0;
-        Xo[i * NB + j] = x;
-        XTo[j * NB + i] = x;
+        // b[jj] = B[j][i] (row j = 16 cg + jj, column i)
+        const double x = i <= j ? b[jj] : 0.0;
+        Xo[j * NB + i] = x;
+        XTo[i * NB + j] = x;
     }
 }
 
