@@ -963,10 +963,17 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_gram(BArgs A, const int4* __rest
             for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
         for (int rb = gi.y; rb < gi.z; rb += GST) {
             __syncthreads();
-            for (int e = threadIdx.x; e < GST * BQMAX; e += blockDim.x) {
+            // every load of the stage issued unconditionally (row and column
+            // clamped, the value dropped), so all of them are in flight together
+            static_assert(GST * BQMAX % SSN_BLOCK == 0, "whole stage per thread");
+#pragma unroll
+            for (int h = 0; h < GST * BQMAX / SSN_BLOCK; ++h) {
+                const int e = threadIdx.x + h * SSN_BLOCK;
                 const int rr = e / BQMAX, cc = e % BQMAX;
                 const int r = rb + rr;
-                Xs[rr][cc] = (r < gi.z && cc < q) ? to_f64(X[(int64_t)list[P.off + r] * q + cc]) : 0.0;
+                const int rc = r < gi.z ? r : gi.z - 1, ccc = cc < q ? cc : q - 1;
+                const double xv = to_f64(X[(int64_t)list[P.off + rc] * q + ccc]);
+                Xs[rr][cc] = (r < gi.z && cc < q) ? xv : 0.0;
             }
             __syncthreads();
             const int nr = min(GST, gi.z - rb);
