@@ -279,17 +279,63 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_atmul(BArgs A, const double* __r
         double acc[BSLOT], accm[BSLOT];
 #pragma unroll
         for (int s = 0; s < BSLOT; ++s) acc[s] = accm[s] = 0.0;
-        for (int r = item.y + grp; r < item.z; r += RPB) {
-            const int64_t gi = P.off + r;
-            const double cf = (double)P.y[r] * z[gi];
-            const double cm = MASK ? (double)mask[gi] : 0.0;
-            if (cf == 0.0 && cm == 0.0) continue;
-            double e[BSLOT];
-            bload<T, VEC>(X + (int64_t)r * q, q, j, e);
+        if constexpr (VEC) {
+            // RU rows per group at a time: their coefficients first (a row past
+            // the item reads the item's last row and gets coefficient 0), then
+            // the raw 16-byte pieces of every row with a nonzero coefficient,
+            // widened at the FMA, so that all of a step's loads are in flight
+            constexpr int V = BVec<T>::V, NP = BSLOT / V, RU = 4;
+            for (int r0 = item.y + grp; r0 < item.z; r0 += RPB * RU) {
+                double cf[RU], cm[RU];
+                int rc[RU];
 #pragma unroll
-            for (int s = 0; s < BSLOT; ++s) {
-                acc[s] = fma(cf, e[s], acc[s]);
-                if (MASK) accm[s] = fma(cm, e[s], accm[s]);
+                for (int u = 0; u < RU; ++u) {
+                    const int r = r0 + u * RPB;
+                    const bool in = r < item.z;
+                    rc[u] = in ? r : item.z - 1;
+                    const int64_t gi = P.off + rc[u];
+                    const double a = (double)P.y[rc[u]] * z[gi];
+                    const double b = MASK ? (double)mask[gi] : 0.0;
+                    cf[u] = in ? a : 0.0;
+                    cm[u] = in ? b : 0.0;
+                }
+                // a row with coefficient 0 reads the item's first row instead (a
+                // cache hit, dropped at the FMA), a piece past q the last piece:
+                // the loads carry no branch
+                RawPiece<T, V> pc[RU][NP];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int rl = (cf[u] != 0.0 || cm[u] != 0.0) ? rc[u] : item.y;
+#pragma unroll
+                    for (int g = 0; g < NP; ++g) {
+                        const int c = g * LPR * V + j * V;
+                        pc[u][g].u = *reinterpret_cast<const uint4*>(X + (int64_t)rl * q + (c < q ? c : q - V));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int g = 0; g < NP; ++g)
+#pragma unroll
+                        for (int t = 0; t < V; ++t) {
+                            const double xv = g * LPR * V + j * V < q ? pc[u][g].get(t) : 0.0;
+                            acc[g * V + t] = fma(cf[u], xv, acc[g * V + t]);
+                            if (MASK) accm[g * V + t] = fma(cm[u], xv, accm[g * V + t]);
+                        }
+            }
+        } else {
+            for (int r = item.y + grp; r < item.z; r += RPB) {
+                const int64_t gi = P.off + r;
+                const double cf = (double)P.y[r] * z[gi];
+                const double cm = MASK ? (double)mask[gi] : 0.0;
+                if (cf == 0.0 && cm == 0.0) continue;
+                double e[BSLOT];
+                bload<T, VEC>(X + (int64_t)r * q, q, j, e);
+#pragma unroll
+                for (int s = 0; s < BSLOT; ++s) {
+                    acc[s] = fma(cf, e[s], acc[s]);
+                    if (MASK) accm[s] = fma(cm, e[s], accm[s]);
+                }
             }
         }
         __syncthreads();
