@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
             "paper_1910_01312_amd/csrc/host.hip":
-                "04902bb7ca2f6b1d12629b06681341bea5f94024ef4bdec02c365f92894f41b0",
+                "17d533eb863f3904d866eb5cfa41c348eb401fcf648fa24b2563f96ba99b2044",
         },
     },
 }
