@@ -6,13 +6,13 @@
 //            entries are contiguous in CSR), result as a p-vector.
 //  * X_J^T z: a column-major copy of X_J, rebuilt once per Newton step by
 //            filtering the full column-major copy (CSC) down to the entries
-//            whose row is in J.  The filter keeps the full copy's 512-entry
-//            tile boundaries, so a compact tile t holds exactly the J entries
-//            of full tile t and the full plan's per-tile first/last columns
-//            and its list of tile-spanning columns stay valid; the product
-//            then runs the same segmented reduction as the full operator on
-//            far fewer entries.  Each kept entry stores (rank of its row in
-//            J, column, value); the rank indexes the p-vector directly.
+//            whose row is in J: per 512-entry tile of the full copy a count,
+//            a scan of the counts, then the kept entries of tile t written
+//            from offset t, in order, so the copy stays sorted by column.
+//            Each kept entry stores (rank of its row in J, column, value);
+//            the rank indexes the p-vector directly.  The product itself
+//            (kernels_cg.hip) is a keyed segmented sum over 256-entry chunks
+//            of the copy.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
