@@ -2,11 +2,14 @@
 //
 // Gather-SYRK  G = X_J^T X_J  on the matrix cores: bf16 operands, fp32
 // accumulation (v_mfma_f32_32x32x16_bf16), 128 x 128 output tiles of the
-// lower triangle, split over the row list J.  A block stages 32 gathered
-// rows x 128 columns of each column block in LDS, stored transposed (column
-// major, 8 consecutive rows contiguous) so that each lane's MFMA operand is
-// one 16-byte LDS read.  Four waves each own a 64 x 64 sub-tile (2 x 2 MFMA
-// tiles).  The per-split fp32 partial tiles are summed in split order in fp64.
+// lower triangle, split over the row list J.  A block stages gathered rows x
+// 128 columns of each column block in LDS, stored transposed (column major,
+// 8 consecutive rows contiguous) so that each lane's MFMA operand is one
+// 16-byte LDS read.  Four waves each own a 64 x 64 sub-tile (2 x 2 MFMA
+// tiles).  When q is a multiple of 8, k_syrk_mfma16 stages 64 rows per step
+// with the next step's loads in flight; otherwise k_syrk_mfma stages 32 rows
+// per step with per-element column checks.  The per-split fp32 partial tiles
+// are summed in split order in fp64.
 //
 // Dense X_J v over a row list (one wave per row, fp64 accumulation), used by
 // the exact Newton operator of the iterative refinement.
@@ -133,6 +136,157 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_syrk_mfma(const bf16_t* __restric
             }
 }
 
+// Same product when q is a multiple of 8 (every 8-column piece is one 16-byte
+// load).  64 gathered rows per step; the next step's rows are loaded into
+// registers while the current step's MFMAs run, and the list entries one step
+// further ahead, so a step waits for one memory round trip at most.  Loads are
+// issued unconditionally (row index clamped to the split, column to the last
+// piece) and the values masked afterwards.  Each thread holds 4 consecutive
+// rows of one 8-column piece and writes them to the transposed LDS tile as one
+// 8-byte store per column.  LDS element (col, r) sits at
+//   col * KP2 + (((r >> 3) ^ ((col >> 4) & 7)) << 3) + (r & 7):
+// the 8-row blocks of a column are permuted by bits of the column index so that
+// both the 8-byte stores of a wave and the 16-byte MFMA operand reads of a wave
+// spread over all banks; an operand (8 consecutive rows of one column) stays one
+// aligned 16-byte read.
+constexpr int KC2 = 64;
+constexpr int KP2 = KC2 + 8;     // 144-byte column stride
+
+__device__ __forceinline__ int sw_off(int col, int r) {
+    return col * KP2 + ((((r >> 3) ^ ((col >> 4) & 7))) << 3) + (r & 7);
+}
+
+// rows 4*rq .. 4*rq+3 of piece cg (masked by the validity bits in mk) -> LDS
+__device__ __forceinline__ void put_rows(const uint4 (&u)[4], unsigned mk, int cg, int rq,
+                                         bf16_t* __restrict__ sT) {
+    uint32_t w[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool ok = (mk >> k) & 1u;
+        w[k][0] = ok ? u[k].x : 0u;
+        w[k][1] = ok ? u[k].y : 0u;
+        w[k][2] = ok ? u[k].z : 0u;
+        w[k][3] = ok ? u[k].w : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        uint2 ev, od;
+        ev.x = (w[0][c] & 0xffffu) | (w[1][c] << 16);
+        ev.y = (w[2][c] & 0xffffu) | (w[3][c] << 16);
+        od.x = (w[0][c] >> 16) | (w[1][c] & 0xffff0000u);
+        od.y = (w[2][c] >> 16) | (w[3][c] & 0xffff0000u);
+        const int col = cg * 8 + 2 * c;
+        *reinterpret_cast<uint2*>(sT + sw_off(col, 4 * rq)) = ev;
+        *reinterpret_cast<uint2*>(sT + sw_off(col + 1, 4 * rq)) = od;
+    }
+}
+
+template <bool DIAG>
+__device__ __forceinline__ void syrk16_body(const bf16_t* __restrict__ X, int64_t q,
+                                            const int32_t* __restrict__ list, int64_t r0,
+                                            int64_t r1, int64_t i0, int64_t j0,
+                                            bf16_t* __restrict__ sA, bf16_t* __restrict__ sB,
+                                            f32x16_t (&acc)[2][2]) {
+    const int t = threadIdx.x;
+    const int cg = t & 15, rq = t >> 4;
+    const int lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m = lane & 31, kg = lane >> 5;
+    const int64_t ca = i0 + 8 * cg, cb = j0 + 8 * cg;
+    const bool va = ca < q, vb = cb < q;
+    const bf16_t* Xa = X + (va ? ca : q - 8);
+    const bf16_t* Xb = X + (vb ? cb : q - 8);
+    const int64_t last = r1 - 1;
+    int li[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t row = r0 + 4 * rq + k;
+        li[k] = list[row < last ? row : last];
+    }
+    uint4 ua[4], ub[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ua[k] = *reinterpret_cast<const uint4*>(Xa + (int64_t)li[k] * q);
+        if (!DIAG) ub[k] = *reinterpret_cast<const uint4*>(Xb + (int64_t)li[k] * q);
+    }
+    for (int64_t rb = r0; rb < r1; rb += KC2) {
+        const int64_t rn = rb + KC2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t row = rn + 4 * rq + k;
+            li[k] = list[row < last ? row : last];
+        }
+        unsigned mk = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mk |= (rb + 4 * rq + k < r1 ? 1u : 0u) << k;
+        put_rows(ua, va ? mk : 0u, cg, rq, sA);
+        if (!DIAG) put_rows(ub, vb ? mk : 0u, cg, rq, sB);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            ua[k] = *reinterpret_cast<const uint4*>(Xa + (int64_t)li[k] * q);
+            if (!DIAG) ub[k] = *reinterpret_cast<const uint4*>(Xb + (int64_t)li[k] * q);
+        }
+        const bf16_t* sBp = DIAG ? sA : sB;
+#pragma unroll
+        for (int ks = 0; ks < KC2 / 16; ++ks) {
+            const int r = ks * 16 + kg * 8;
+            bf16x8_t fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                fa[a] = *reinterpret_cast<const bf16x8_t*>(sA + sw_off(wm * 64 + a * 32 + m, r));
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                fb[b] = *reinterpret_cast<const bf16x8_t*>(sBp + sw_off(wn * 64 + b * 32 + m, r));
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(SSN_BLOCK) void k_syrk_mfma16(const bf16_t* __restrict__ X, int64_t q,
+                                                           const int32_t* __restrict__ list,
+                                                           int64_t p, int64_t rows_per_split,
+                                                           float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) bf16_t sA[MT * KP2];
+    __shared__ __attribute__((aligned(16))) bf16_t sB[MT * KP2];
+    int t = blockIdx.x, ti = 0;
+    while (t > ti) { t -= ti + 1; ++ti; }
+    const int tj = t;
+    const int64_t i0 = (int64_t)ti * MT, j0 = (int64_t)tj * MT;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+    const int64_t r1 = r0 + rows_per_split < p ? r0 + rows_per_split : p;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m = lane & 31, kg = lane >> 5;
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
+    if (r0 < r1) {
+        if (ti == tj) syrk16_body<true>(X, q, list, r0, r1, i0, j0, sA, sB, acc);
+        else syrk16_body<false>(X, q, list, r0, r1, i0, j0, sA, sB, acc);
+    }
+    float* out = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * MT * MT;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = wm * 64 + a * 32 + 8 * (e >> 2) + 4 * kg + (e & 3);
+                const int col = wn * 64 + b * 32 + m;
+                out[row * MT + col] = acc[a][b][e];
+            }
+}
+
 // G[i][j] (lower tiles, mirrored) = sum over splits, in split order, in fp64;
 // one element per thread, RED_BLOCKS blocks per 128 x 128 tile
 constexpr int RED_BLOCKS = MT * MT / SSN_BLOCK;
@@ -170,9 +324,15 @@ void launch_syrk_mfma(const void* X, int dtype, int64_t q, const int32_t* list, 
     int64_t ns = mfma_nsplit(q, p);
     while (ns > 1 && ns * ntile * MT * MT > part_cap) --ns;
     int64_t rps = (p + ns - 1) / ns;
-    rps = (rps + KC - 1) / KC * KC;
-    hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
-                       (const bf16_t*)X, q, list, p, rps, part);
+    if (q % 8 == 0) {
+        rps = (rps + KC2 - 1) / KC2 * KC2;
+        hipLaunchKernelGGL(k_syrk_mfma16, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
+                           (const bf16_t*)X, q, list, p, rps, part);
+    } else {
+        rps = (rps + KC - 1) / KC * KC;
+        hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
+                           (const bf16_t*)X, q, list, p, rps, part);
+    }
     hipLaunchKernelGGL(k_syrk_mfma_reduce, dim3((unsigned)(ntile * RED_BLOCKS)), dim3(SSN_BLOCK), 0, s,
                        part, ntile, (int)ns, G, q);
 }
