@@ -10,6 +10,8 @@ Modules:
   projection  - Algorithm 2 breakpoint search, Pi_{K∩L}, HS-Jacobian (Thm 3.1)
   ssnal       - Algorithm 1 + Algorithm 3 in omega-space, Newton solvers,
                 R_KKT (eq. Def_Rkkt), objective, duality gap
+  general     - the same method on the unified problem (P) with Q = B B^T:
+                C-SVC and eps-SVR instances, the SVR primal for duality gaps
   bruteforce  - 3^n active-set enumeration of the QP and of the projection
   literal     - the paper's n-space Newton system and Proposition 5 verbatim
   mlp         - FP64 forward/backward of the warm-start network

@@ -10,6 +10,9 @@ QP is optimal, so all survivors share the optimal value f*.
 
 `projection_by_enumeration` does the same for the projection problem
 eq. Def proj_KL001 with a = y, d = 0, l = 0, u = C.
+
+`general_qp_by_enumeration` does the same for the unified problem (P)
+(eq. Problem_P1_classical1) with general Q, c, a, d, l, u.
 """
 from __future__ import annotations
 
@@ -133,3 +136,71 @@ def projection_by_enumeration(v, y, C, tol=1e-12):
             if best is None or dist < best[0] - 1e-14:
                 best = (dist, x, lam)
     return best[1], best[2]
+
+
+def general_qp_by_enumeration(Q, c, a, d, l, u, tol=1e-9):
+    """Returns (f_star, x_star) for the unified problem (P) of Section 1:
+    min 1/2 x^T Q x + c^T x, a^T x = d, l <= x <= u, by enumerating the 3^n
+    partitions into lower / free / upper and keeping the candidates that
+    satisfy the KKT conditions (r = Q x + c - mu a: r_i >= 0 at a lower
+    bound, <= 0 at an upper bound, = 0 when free).  n <= 8."""
+    Q = np.asarray(Q, np.float64)
+    c = np.asarray(c, np.float64)
+    a = np.asarray(a, np.float64)
+    l = np.asarray(l, np.float64)
+    u = np.asarray(u, np.float64)
+    n = c.size
+    best = None
+    for lab in itertools.product((0, 1, 2), repeat=n):
+        lab = np.array(lab)
+        F = np.flatnonzero(lab == 1)
+        L = np.flatnonzero(lab == 0)
+        U = np.flatnonzero(lab == 2)
+        x = np.where(lab == 2, u, l).astype(np.float64)
+        x[F] = 0.0
+        fixed = np.concatenate([L, U])
+        if F.size == 0:
+            if abs(float(a @ x) - d) > tol * (1.0 + abs(d)):
+                continue
+            base = Q @ x + c
+            lo, hi = -np.inf, np.inf
+            ok = True
+            for i in L:                       # base_i - mu a_i >= 0
+                if a[i] > 0:
+                    hi = min(hi, base[i] / a[i])
+                elif a[i] < 0:
+                    lo = max(lo, base[i] / a[i])
+                elif base[i] < -tol:
+                    ok = False
+            for i in U:                       # base_i - mu a_i <= 0
+                if a[i] > 0:
+                    lo = max(lo, base[i] / a[i])
+                elif a[i] < 0:
+                    hi = min(hi, base[i] / a[i])
+                elif base[i] > tol:
+                    ok = False
+            if not ok or lo > hi + tol:
+                continue
+        else:
+            m = F.size
+            K = np.zeros((m + 1, m + 1))
+            K[:m, :m] = Q[np.ix_(F, F)]
+            K[:m, m] = -a[F]
+            K[m, :m] = a[F]
+            rhs = np.zeros(m + 1)
+            rhs[:m] = -c[F] - Q[np.ix_(F, fixed)] @ x[fixed]
+            rhs[m] = d - float(a[fixed] @ x[fixed])
+            sol, *_ = np.linalg.lstsq(K, rhs, rcond=None)
+            if np.linalg.norm(K @ sol - rhs) > tol * (1.0 + np.linalg.norm(rhs)):
+                continue
+            xF, mu = sol[:m], sol[m]
+            if np.any(xF < l[F] - tol) or np.any(xF > u[F] + tol):
+                continue
+            x[F] = np.clip(xF, l[F], u[F])
+            r = Q @ x + c - mu * a
+            if np.any(r[L] < -10 * tol) or np.any(r[U] > 10 * tol):
+                continue
+        f = 0.5 * float(x @ Q @ x) + float(c @ x)
+        if best is None or f < best[0] - 1e-12:
+            best = (f, x.copy())
+    return best

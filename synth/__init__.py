@@ -254,3 +254,29 @@ def mlp_init(seed: int = 0, sizes=(66, 256, 256, 4)) -> np.ndarray:
         parts.append((rng.standard_normal((a, b)) * np.sqrt(2.0 / (a + b))).ravel())
         parts.append(np.zeros(b))
     return np.concatenate(parts).astype(np.float32)
+
+
+def tiny_regression(n: int, q: int, seed: int, noise: float = 0.1):
+    """Small random regression set (X Gaussian, y = X beta + Gaussian noise)
+    for eps-SVR checks."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, q))
+    beta = rng.standard_normal(q)
+    y = X @ beta + 0.3 + noise * rng.standard_normal(n)
+    return X, y
+
+
+def tiny_general(n: int, q: int, seed: int, zero_a: int = 0):
+    """Small random instance of the unified problem (P): B (n x q), c, a
+    (mixed signs, `zero_a` entries set to 0), l < u, and d = a^T x for a
+    point x drawn inside the box, so the feasible set is non-empty."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((n, q))
+    c = rng.standard_normal(n)
+    a = rng.uniform(0.5, 2.0, n) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    if zero_a:
+        a[rng.choice(n, zero_a, replace=False)] = 0.0
+    l = rng.uniform(-1.0, 0.5, n)
+    u = l + rng.uniform(0.2, 2.0, n)
+    d = float(a @ rng.uniform(l, u))
+    return B, c, a, d, l, u
