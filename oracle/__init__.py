@@ -12,6 +12,8 @@ Modules:
                 R_KKT (eq. Def_Rkkt), objective, duality gap
   general     - the same method on the unified problem (P) with Q = B B^T:
                 C-SVC and eps-SVR instances, the SVR primal for duality gaps
+  features    - random Fourier and Nystroem features of the RBF kernel
+                (Section 4), which feed the linear C-SVC unchanged
   bruteforce  - 3^n active-set enumeration of the QP and of the projection
   literal     - the paper's n-space Newton system and Proposition 5 verbatim
   mlp         - FP64 forward/backward of the warm-start network
