@@ -14,6 +14,7 @@ Modules:
                 C-SVC and eps-SVR instances, the SVR primal for duality gaps
   features    - random Fourier and Nystroem features of the RBF kernel
                 (Section 4), which feed the linear C-SVC unchanged
+  kernel      - the C-SVC dual with a nonlinear kernel (explicit Q, small n)
   bruteforce  - 3^n active-set enumeration of the QP and of the projection
   literal     - the paper's n-space Newton system and Proposition 5 verbatim
   mlp         - FP64 forward/backward of the warm-start network
