@@ -29,6 +29,11 @@ def test_general_matches_enumeration(seed):
     np.testing.assert_allclose(r.x, x_star, atol=1e-7)       # Q positive definite: unique
     assert abs(float(prob.a @ r.x) - prob.d) <= 1e-10 * (1 + abs(prob.d))
     assert np.all(r.x >= prob.l) and np.all(r.x <= prob.u)
+    # eq. Def_Rkkt vanishes at the enumerated optimum and not at a feasible non-optimal point
+    assert general.rkkt(prob, x_star) <= 1e-10
+    x_mid = general.projection(prob, 0.5 * (prob.l + prob.u))[0]
+    if general.objective(prob, x_mid) > f_star + 1e-6:
+        assert general.rkkt(prob, x_mid) > 1e-6
 
 
 @pytest.mark.parametrize("seed", range(4))
