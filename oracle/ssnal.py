@@ -153,6 +153,41 @@ def newton_pspace_centered(X, free, g, sigma):
     return -g + Xc.T @ v
 
 
+def newton_lowrank(X, free, g, sigma, prev_free, prev_cho):
+    """The same direction as `newton_qspace`, obtained from the Cholesky
+    factor of the Newton matrix M0 of an earlier step at the same sigma:
+    M = M0 + U S U^T, the columns of U being the rows entering J (weight
+    +sigma), the rows leaving J (-sigma), s0/sqrt(p0) of the earlier J
+    (+sigma) and s/sqrt(p) of the new J (-sigma), S the diagonal of those
+    weights.  By the Woodbury
+    identity M^{-1} g = M0^{-1} g - M0^{-1} U (S^{-1} + U^T M0^{-1} U)^{-1}
+    U^T M0^{-1} g.  prev_cho is scipy's cho_factor of M0; the rank of the
+    correction is (rows that changed) + 2 (the two centring terms)."""
+    idx = np.flatnonzero(free)
+    idx0 = np.flatnonzero(prev_free)
+    add = np.flatnonzero(free & ~prev_free)
+    rem = np.flatnonzero(prev_free & ~free)
+    cols, sgn = [], []
+    Xd = X.toarray() if sp.issparse(X) else X
+    for i in add:
+        cols.append(Xd[i]); sgn.append(sigma)
+    for i in rem:
+        cols.append(Xd[i]); sgn.append(-sigma)
+    if idx0.size:                       # + sigma s0 s0^T / p0 (old centring removed)
+        s0 = Xd[idx0].sum(axis=0)
+        cols.append(s0 / math.sqrt(idx0.size)); sgn.append(sigma)
+    if idx.size:                        # - sigma s s^T / p (new centring)
+        s1 = Xd[idx].sum(axis=0)
+        cols.append(s1 / math.sqrt(idx.size)); sgn.append(-sigma)
+    y0 = sla.cho_solve(prev_cho, g)
+    if not cols:
+        return -y0
+    U = np.array(cols).T                               # q x k
+    Z = sla.cho_solve(prev_cho, U)                     # M0^{-1} U
+    cap = np.diag(1.0 / np.array(sgn)) + U.T @ Z       # S^{-1} + U^T M0^{-1} U
+    return -(y0 - Z @ np.linalg.solve(cap, U.T @ y0))
+
+
 def apply_M(X, y_unused, idx, s, sigma, v):
     """(I + sigma (X_J^T X_J - s s^T / p)) v, matrix-free."""
     p = idx.size

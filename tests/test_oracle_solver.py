@@ -214,3 +214,28 @@ def test_armijo_and_monotone_psi():
     assert r.ls_fail == 0
     rk = [h["rkkt"] for h in r.history]
     assert rk[-1] <= 1e-9
+
+
+def test_newton_lowrank_matches_cholesky():
+    """The Woodbury correction of an earlier step's factor (same sigma) gives
+    the direction of the fresh Cholesky solve, for J changes of a few rows and
+    of many rows, including an empty previous J."""
+    import scipy.linalg as sla
+    X, y = synth.dense_two_gaussians(n=400, q=12, seed=3)
+    rng = np.random.default_rng(0)
+    sigma = 7.0
+    g = rng.standard_normal(12)
+    base = rng.random(400) < 0.3
+    for flips in (0, 1, 5, 60, 400):
+        free = base.copy()
+        free[rng.choice(400, flips, replace=False)] ^= True
+        for prev in (base, np.zeros(400, bool)):
+            idx0 = np.flatnonzero(prev)
+            M0 = np.eye(12)
+            if idx0.size:
+                XJ = X[idx0]
+                s0 = XJ.sum(0)
+                M0 = M0 + sigma * (XJ.T @ XJ - np.outer(s0, s0) / idx0.size)
+            d = ssnal.newton_lowrank(X, free, g, sigma, prev, sla.cho_factor(M0, lower=True))
+            d_ref = ssnal.newton_qspace(X, free, g, sigma)
+            assert np.linalg.norm(d - d_ref) <= 1e-9 * np.linalg.norm(d_ref)
