@@ -157,3 +157,23 @@ def test_planted_mistake_svr_sign_is_caught():
     P = general.svr_primal(X, yr, C, eps, w, b)
     f_true = general.objective(good, r.x)
     assert P + f_true > 1e-3 * (1 + abs(P) + abs(f_true))
+
+
+def test_svr_on_csr_rows():
+    """The eps-SVR instance built from CSR data (B = [X; -X] kept sparse)
+    gives the dense-data solution and a vanishing duality gap."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(11)
+    n, q = 60, 8
+    Xd = rng.standard_normal((n, q)) * (rng.random((n, q)) < 0.4)
+    yr = Xd @ rng.standard_normal(q) + 0.05 * rng.standard_normal(n)
+    C, eps = 1.0, 0.1
+    r_s = general.solve(general.svr_problem(sp.csr_matrix(Xd), yr, C, eps), tol=1e-10)
+    r_d = general.solve(general.svr_problem(Xd, yr, C, eps), tol=1e-10)
+    assert r_s.status == "OK" and r_d.status == "OK"
+    assert r_s.obj == pytest.approx(r_d.obj, abs=1e-9 * (1 + abs(r_d.obj)))
+    x, z = r_s.x[:n], r_s.x[n:]
+    w = general.svr_weights(Xd, x, z)
+    b = general.svr_best_bias(Xd, yr, C, eps, w)
+    gap = general.svr_primal(Xd, yr, C, eps, w, b) + r_s.obj
+    assert -1e-9 <= gap <= 1e-7 * (1 + abs(r_s.obj))
