@@ -19,7 +19,9 @@ oracle, with general data (omega := B^T w, so Q w = B omega):
     u(omega)  = x^k - sigma (B omega + c)                        (eq. Def_psi)
     psi       = 1/2|omega|^2 + (|u|^2 - |u - Pi(u)|^2)/(2 sigma) - |x^k|^2/(2 sigma)
     grad psi  = omega - B^T Pi(u)                  (eq. Def_differential_of_psi)
-    Newton    (I + sigma B^T P B) d = -grad psi     (eq. Newton_Linear_System)
+    Newton    (I + sigma B^T P B) d = -grad psi     (eq. Newton_Linear_System),
+              by Cholesky or (newton="pcg") by Jacobi-preconditioned CG to
+              |M d + g| <= min(eta, |g|^(1+tau))
 with P the HS-Jacobian of Theorem 3.1 at the free set J (eq. Def_HS_P):
     B^T P B = B_J^T B_J - s s^T / (a_J^T a_J),  s = B_J^T a_J    (a_J != 0)
     B^T P B = B_J^T B_J                                          (a_J = 0)
@@ -171,6 +173,47 @@ def newton_direction(prob, free, g, sigma):
     return -sla.cho_solve(sla.cho_factor(M, lower=True), g)
 
 
+def newton_pcg(prob, free, g, sigma, tol, maxit=500):
+    """The same Newton system solved matrix-free by conjugate gradients with
+    the Jacobi preconditioner diag(M) (floored at 1), to |M d + g| <= tol.
+    Returns (d, iterations)."""
+    idx = np.flatnonzero(free)
+    if idx.size == 0:
+        return -g.copy(), 0
+    BJ = prob.B[idx]
+    aJ = prob.a[idx]
+    den = float(aJ @ aJ)
+    s = btmul(BJ, aJ)
+    sq = (np.asarray(BJ.multiply(BJ).sum(axis=0)).ravel() if sp.issparse(BJ)
+          else (BJ * BJ).sum(axis=0))
+    diag = 1.0 + sigma * (sq - (s * s / den if den != 0.0 else 0.0))
+    diag = np.maximum(diag, 1.0)
+
+    def apply(v):
+        out = v + sigma * btmul(BJ, bmul(BJ, v))
+        if den != 0.0:
+            out -= sigma * s * (float(s @ v) / den)
+        return out
+
+    d = np.zeros_like(g)
+    r = -g.copy()
+    z = r / diag
+    pdir = z.copy()
+    rz = float(r @ z)
+    it = 0
+    while it < maxit and math.sqrt(float(r @ r)) > tol:
+        Ap = apply(pdir)
+        alpha = rz / float(pdir @ Ap)
+        d += alpha * pdir
+        r -= alpha * Ap
+        z = r / diag
+        rz_new = float(r @ z)
+        pdir = z + (rz_new / rz) * pdir
+        rz = rz_new
+        it += 1
+    return d, it
+
+
 @dataclass
 class Result:
     x: np.ndarray
@@ -180,6 +223,7 @@ class Result:
     outer: int
     inner: int
     status: str
+    cg_iters: int
     time_s: float
 
 
@@ -195,6 +239,7 @@ def solve(prob, tol=1e-6, x0=None, **kw):
     omega = btmul(B, x)
     sigma = opt.sigma0
     inner_total = 0
+    cg_total = 0
     status = "MAXITER"
     R = math.inf
     best = None                  # (R, x): returned if the iteration cap is hit
@@ -212,7 +257,11 @@ def solve(prob, tol=1e-6, x0=None, **kw):
             crit = min(eps_k, eps_k * float(np.linalg.norm(xt - xk))) / math.sqrt(sigma)
             if gn <= max(crit, opt.floor * (1.0 + float(np.linalg.norm(omega)))):
                 break
-            d = newton_direction(prob, free, g, sigma)
+            if opt.newton == "pcg":
+                d, it = newton_pcg(prob, free, g, sigma, min(opt.eta, gn ** (1.0 + opt.tau)), opt.max_cg)
+                cg_total += it
+            else:
+                d = newton_direction(prob, free, g, sigma)
             inner_total += 1
             t = bmul(B, d)
             gd = float(g @ d)
@@ -241,7 +290,8 @@ def solve(prob, tol=1e-6, x0=None, **kw):
     if status == "MAXITER" and best is not None and best[0] < R:
         R, x = best
     return Result(x=x, omega=omega, obj=objective(prob, x), rkkt=R, outer=outer,
-                  inner=inner_total, status=status, time_s=time.perf_counter() - t_start)
+                  inner=inner_total, status=status, cg_iters=cg_total,
+                  time_s=time.perf_counter() - t_start)
 
 
 def svr_weights(X, x, z):

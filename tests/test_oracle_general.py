@@ -177,3 +177,27 @@ def test_svr_on_csr_rows():
     b = general.svr_best_bias(Xd, yr, C, eps, w)
     gap = general.svr_primal(Xd, yr, C, eps, w, b) + r_s.obj
     assert -1e-9 <= gap <= 1e-7 * (1 + abs(r_s.obj))
+
+
+@pytest.mark.parametrize("zero_a", [0, 3])
+def test_general_pcg_matches_cholesky_direction(zero_a):
+    prob = _prob(40, 6, 800 + zero_a, zero_a=zero_a)
+    sigma = 5.0
+    xk, omega = _state(prob, sigma, zero_a)
+    u = xk - sigma * (prob.B @ omega + prob.c)
+    xt, _, free = general.projection(prob, u)
+    g = omega - prob.B.T @ xt
+    d_ref = general.newton_direction(prob, free, g, sigma)
+    d, it = general.newton_pcg(prob, free, g, sigma, tol=1e-13 * np.linalg.norm(g))
+    assert it <= 12                  # q = 6: q steps in exact arithmetic, a few more in fp64
+    np.testing.assert_allclose(d, d_ref, rtol=1e-9, atol=1e-12)
+
+
+def test_svr_pcg_solve_matches_cholesky_solve():
+    import scipy.sparse as sp
+    X, yr = synth.tiny_regression(80, 6, seed=4)
+    prob = general.svr_problem(sp.csr_matrix(X), yr, 1.0, 0.1)
+    r_c = general.solve(prob, tol=1e-9)
+    r_p = general.solve(prob, tol=1e-9, newton="pcg")
+    assert r_c.status == "OK" and r_p.status == "OK" and r_p.cg_iters > 0
+    assert r_p.obj == pytest.approx(r_c.obj, abs=1e-8 * (1 + abs(r_c.obj)))
