@@ -94,3 +94,32 @@ def test_struct_layouts_match_header():
                       (_lib.Info, "ssnalm_info"), (_lib.KStat, "ssnalm_kstat"),
                       (_lib.WsStats, "ssnalm_ws_stats")]:
         assert [f for f, _ in cls._fields_] == fields(name), name
+
+
+def test_create_rejects_bad_arguments_without_gpu():
+    """ssnalm_create validates its arguments before any device call: each bad
+    field gives SSNALM_E_BADARG and a message naming it, also on a host with
+    no GPU (the pointers below are never dereferenced)."""
+    import ctypes as C
+    from paper_1910_01312_amd import _lib
+    lib = _lib.load()
+    buf = (C.c_byte * 64)()
+    addr = C.addressof(buf)
+
+    def problem(**kw):
+        f = dict(kind=0, dtype=0, n=4, q=2, nnz=0, X=addr, row_ptr=None, col_idx=None,
+                 y=addr, C=1.0, tol=1e-6)
+        f.update(kw)
+        return _lib.Problem(**f)
+
+    ctx = C.c_void_p()
+    assert lib.ssnalm_create(C.byref(ctx), None, None, None) == _lib.E_BADARG
+    cases = [(dict(n=0), b"n and q"), (dict(q=0), b"n and q"), (dict(C=0.0), b"C must"),
+             (dict(C=float("inf")), b"C must"), (dict(tol=0.0), b"tol"), (dict(kind=7), b"kind"),
+             (dict(dtype=9), b"dtype"), (dict(y=None), b"y missing"), (dict(X=None), b"X missing")]
+    for kw, msg in cases:
+        pr = problem(**kw)
+        st = lib.ssnalm_create(C.byref(ctx), C.byref(pr), None, None)
+        assert st == _lib.E_BADARG, kw
+        assert msg in lib.ssnalm_last_error(), (kw, lib.ssnalm_last_error())
+        assert not ctx.value
