@@ -123,3 +123,49 @@ def test_create_rejects_bad_arguments_without_gpu():
         assert st == _lib.E_BADARG, kw
         assert msg in lib.ssnalm_last_error(), (kw, lib.ssnalm_last_error())
         assert not ctx.value
+
+
+def test_solve_batch_rejects_bad_arguments_without_gpu():
+    """ssnalm_solve_batch validates every problem before any device call."""
+    import ctypes as C
+    from paper_1910_01312_amd import _lib
+    lib = _lib.load()
+    buf = (C.c_byte * 64)()
+    addr = C.addressof(buf)
+
+    def probs(k_bad=None, **kw):
+        arr = (_lib.Problem * 3)()
+        for k in range(3):
+            f = dict(kind=0, dtype=0, n=4, q=8, nnz=0, X=addr, row_ptr=None, col_idx=None,
+                     y=addr, C=1.0, tol=1e-6)
+            if k == k_bad:
+                f.update(kw)
+            arr[k] = _lib.Problem(**f)
+        return arr
+
+    xs = (C.c_void_p * 3)(addr, addr, addr)
+    infos = (_lib.Info * 3)()
+
+    def call(pr, opt=None, count=3, x_out=xs):
+        return lib.ssnalm_solve_batch(count, pr, C.byref(opt) if opt else None, None, x_out, None, infos)
+
+    assert call(probs(), count=0) == _lib.E_BADARG
+    assert call(probs(), x_out=None) == _lib.E_BADARG
+    cases = [(dict(kind=1), b"problem 1: batched problems must be dense"),
+             (dict(dtype=1), b"problem 1: dtype and q must match"),
+             (dict(q=9), b"problem 1: dtype and q must match"),
+             (dict(n=0), b"problem 1: n must be"),
+             (dict(C=-1.0), b"problem 1: C must"),
+             (dict(tol=0.0), b"problem 1: tol"),
+             (dict(y=None), b"problem 1: X and y")]
+    for kw, msg in cases:
+        assert call(probs(1, **kw)) == _lib.E_BADARG, kw
+        assert msg in lib.ssnalm_last_error(), (kw, lib.ssnalm_last_error())
+    o = _lib.default_options()
+    o.newton = 2
+    assert call(probs(), opt=o) == _lib.E_BADARG
+    assert b"Cholesky" in lib.ssnalm_last_error()
+    o = _lib.default_options()
+    o.precision = 1
+    assert call(probs(), opt=o) == _lib.E_BADARG
+    assert b"fp64" in lib.ssnalm_last_error()
