@@ -169,3 +169,29 @@ def test_solve_batch_rejects_bad_arguments_without_gpu():
     o.precision = 1
     assert call(probs(), opt=o) == _lib.E_BADARG
     assert b"fp64" in lib.ssnalm_last_error()
+
+
+def test_null_handles_and_sizes_without_gpu():
+    """Entry points reject null handles and bad sizes before any device call;
+    the network's parameter count matches the oracle's layout."""
+    import ctypes as C
+    import numpy as np
+    import synth
+    from oracle import mlp as omlp
+    from paper_1910_01312_amd import _lib
+    lib = _lib.load()
+    buf = (C.c_byte * 64)()
+    a = C.addressof(buf)
+    info = _lib.Info()
+    assert lib.ssnalm_solve(None, None, a, None, C.byref(info)) == _lib.E_BADARG
+    assert lib.ssnalm_op_amul(None, a, a) == _lib.E_BADARG
+    assert lib.ssnalm_op_atmul(None, a, a) == _lib.E_BADARG
+    assert lib.ssnalm_ws_x0(None, a, a) == _lib.E_BADARG
+    ks = _lib.KStat()
+    assert lib.ssnalm_batch_kernel_stats(-1, C.byref(ks)) == _lib.E_BADARG
+    n_params = omlp.IN * omlp.HID + omlp.HID + omlp.HID * omlp.HID + omlp.HID + omlp.HID * omlp.OUT + omlp.OUT
+    assert lib.ssnalm_mlp_param_count() == n_params == synth.mlp_init(0).size
+    assert lib.ssnalm_mlp_forward(a, a, 0, a, a, None) == _lib.E_BADARG
+    assert b"n must be" in lib.ssnalm_last_error()
+    assert lib.ssnalm_mlp_forward(None, a, 4, a, a, None) == _lib.E_BADARG
+    assert lib.ssnalm_mlp_adam(None, a, a, a, 4, 1e-3, 0.9, 0.999, 1e-8, 1, None) == _lib.E_BADARG
