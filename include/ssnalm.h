@@ -43,7 +43,8 @@ typedef enum {
     SSNALM_OK = 0,                 /* R_KKT <= tol reached                         */
     SSNALM_MAXITER = 1,            /* iteration cap hit; best feasible x returned  */
     SSNALM_LINESEARCH_FAIL = 2,    /* Armijo search exhausted repeatedly            */
-    SSNALM_WARMSTART_REJECTED = 3, /* warm start worse than cold; solved cold       */
+    SSNALM_WARMSTART_REJECTED = 3, /* the warm start was set aside and the plain    */
+                                   /* cold solve reached tol (ssnalm_ws_solve)      */
     SSNALM_E_BADARG = -1,          /* invalid argument (message says which)         */
     SSNALM_E_NONFINITE = -2,       /* NaN/Inf in the data or in an iterate          */
     SSNALM_E_OOM = -3,             /* device allocation failed                      */
@@ -113,6 +114,10 @@ typedef struct {
     double  rkkt;               /* R_KKT(x) of eq. Def_Rkkt at the returned x             */
     double  obj;                /* 1/2 |A^T x|^2 - e^T x                                  */
     double  b;                  /* bias: lam_hat of the final KKT projection              */
+    double  gap;                /* relative duality gap (P + obj) / (1 + |P| + |obj|),    */
+                                /* P = 1/2 |w|^2 + C sum_i max(0, 1 - y_i (x~_i^T w + b)) */
+                                /* the C-SVC primal (Section 1) at w = A^T x and this b;  */
+                                /* P + obj >= 0 for every feasible x and every b          */
     double  sigma;              /* final penalty parameter                                */
     double  time_s;             /* wall time of ssnalm_solve                              */
     double  t_matvec, t_proj, t_newton, t_other;   /* seconds per phase (host clock)      */
@@ -124,6 +129,11 @@ typedef struct {
     int32_t n_sv;               /* #SVs, x_i > 0                                          */
     int32_t ls_fail;            /* line searches that exhausted their backtracks          */
     int32_t ls_trials;          /* line-search trials (projections of u - alpha sigma t)  */
+    int32_t grad_steps;         /* Newton directions replaced by -grad psi because they   */
+                                /* were not descent directions (g^T d >= 0, or a          */
+                                /* non-positive Cholesky pivot)                           */
+    int32_t proj_capped;        /* projections that hit the multisection pass cap (their  */
+                                /* multiplier is the interpolation of the last bracket)   */
     int32_t status;             /* same as the return value                               */
 } ssnalm_info;
 
@@ -156,13 +166,18 @@ ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* prob,
  *           is set to A^T x^0.
  *   x_out : n doubles (device), the dual solution x.
  *   w_out : q doubles (device) or NULL, the primal weights w = A^T x.
+ *   b_out : one double (HOST) or NULL, the bias b of the decision function
+ *           sign(w^T x~ + b): the multiplier lam_hat of the projection in
+ *           R_KKT at the returned x (eq. Def_Rkkt), as info->b.
  *   info  : host pointer or NULL.
+ * An inexact Newton direction that is not a descent direction is replaced
+ * by -grad psi for that step (counted in info->grad_steps).
  * Returns OK, MAXITER (cap hit; the x with the smallest R_KKT seen is
  * returned) or LINESEARCH_FAIL, or a negative error.  If y has one class
  * only, x = 0 is the only feasible point: OK with x = 0 and b = NaN.
  */
 ssnalm_status ssnalm_solve(ssnalm_ctx* ctx, const double* x0, double* x_out,
-                           double* w_out, ssnalm_info* info);
+                           double* w_out, double* b_out, ssnalm_info* info);
 
 /*
  * Solve `count` independent problems with one launch per phase for all of
@@ -390,6 +405,12 @@ typedef struct {
 ssnalm_status ssnalm_ws_solve(ssnalm_ctx* ctx, const float* out, double keep_frac,
                               int32_t max_rounds, double* x_out, double* w_out,
                               ssnalm_info* info, ssnalm_ws_stats* stats);
+
+/* Training labels of the network from a solution x of the context's problem
+ * (n doubles, device): status[i] = 0 if x_i <= 1e-8 C, 2 if x_i >= (1 - 1e-8)
+ * C, else 1 (n int32, device); target[i] = x_i / C (n floats, device).
+ * Returns when done.  E_BADARG: null pointer. */
+ssnalm_status ssnalm_ws_labels(ssnalm_ctx* ctx, const double* x, int32_t* status, float* target);
 
 /* x0 (n doubles, device) from the network output (n x 4 floats, device):
  * 0, C mult or C by the most probable status, for ssnalm_solve(ctx, x0). */

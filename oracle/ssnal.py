@@ -293,6 +293,13 @@ def duality_gap(X, y, C, x):
     hinge-optimal b; P(w,b) + f(x) >= 0 by weak duality."""
     w = atmul(X, y, x)
     b = best_bias(X, y, C, w)
+    return duality_gap_at(X, y, C, x, b)
+
+
+def duality_gap_at(X, y, C, x, b):
+    """The same relative gap at a given bias b (weak duality holds for every
+    b, so it is >= the gap at the hinge-optimal b).  Returns (gap, P, f)."""
+    w = atmul(X, y, x)
     P = primal_objective(X, y, C, w, b)
     f = dual_objective(X, y, x)
     return (P + f) / (1.0 + abs(P) + abs(f)), P, f
@@ -342,6 +349,7 @@ class Result:
     cg_iters: int = 0
     ls_fail: int = 0
     ls_trials: int = 0
+    grad_steps: int = 0
 
 
 def solve(X, y, C, tol=1e-6, x0=None, **kw):
@@ -370,6 +378,7 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
     cg_total = 0
     ls_fail = 0
     ls_trials = 0
+    grad_steps = 0
     hist = []
     status = "MAXITER"
     R, b = math.inf, float("nan")
@@ -404,9 +413,17 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
                 d, it = newton_pcg(X, free, g, sigma, cg_tol, opt.max_cg)
                 cg_total += it
             inner_total += 1
-            # Step 2: Armijo line search on psi
+            # Step 2: Armijo line search on psi.  Reading: a direction that
+            # is not one of descent (possible only when the linear system is
+            # solved inexactly) can never pass the Armijo test on the convex
+            # psi, so the steepest-descent direction -g replaces it.
             t = amul(X, y, d)
             gd = float(g @ d)
+            if not gd < 0.0 and gn > 0.0:
+                d = -g
+                t = amul(X, y, d)
+                gd = float(g @ d)
+                grad_steps += 1
             accepted = False
             alpha = 1.0
             for m in range(opt.max_backtracks + 1):
@@ -450,4 +467,4 @@ def solve(X, y, C, tol=1e-6, x0=None, **kw):
                   inner=inner_total, p=p, n_sv=int(np.sum(x > 0.0)), status=status,
                   sigma=sigma, omega=omega, history=hist,
                   time_s=time.perf_counter() - t_start, cg_iters=cg_total,
-                  ls_fail=ls_fail, ls_trials=ls_trials)
+                  ls_fail=ls_fail, ls_trials=ls_trials, grad_steps=grad_steps)

@@ -44,13 +44,13 @@ class WsStats(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("rkkt", C.c_double), ("obj", C.c_double), ("b", C.c_double),
-                ("sigma", C.c_double), ("time_s", C.c_double),
+                ("gap", C.c_double), ("sigma", C.c_double), ("time_s", C.c_double),
                 ("t_matvec", C.c_double), ("t_proj", C.c_double), ("t_newton", C.c_double),
                 ("t_other", C.c_double),
                 ("iters_outer", C.c_int32), ("iters_inner", C.c_int32),
                 ("cg_iters", C.c_int32), ("proj_passes", C.c_int32), ("p", C.c_int32),
                 ("n_sv", C.c_int32), ("ls_fail", C.c_int32), ("ls_trials", C.c_int32),
-                ("status", C.c_int32)]
+                ("grad_steps", C.c_int32), ("proj_capped", C.c_int32), ("status", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -71,7 +71,7 @@ EXPORTS = [
     "ssnalm_kernel_stats", "ssnalm_op_gram", "ssnalm_batch_kernel_stats",
     "ssnalm_mlp_param_count", "ssnalm_mlp_work_floats", "ssnalm_mlp_scratch_floats",
     "ssnalm_mlp_forward", "ssnalm_mlp_backward", "ssnalm_mlp_adam", "ssnalm_ws_features",
-    "ssnalm_ws_x0", "ssnalm_ws_solve", "ssnalm_set_profile",
+    "ssnalm_ws_x0", "ssnalm_ws_solve", "ssnalm_set_profile", "ssnalm_ws_labels",
 ]
 
 _lib = None
@@ -91,7 +91,7 @@ def load(path: str | None = None):
     lib.ssnalm_default_options.restype = None
     lib.ssnalm_create.argtypes = [C.POINTER(vp), C.POINTER(Problem), C.POINTER(Options), vp]
     lib.ssnalm_create.restype = i32
-    lib.ssnalm_solve.argtypes = [vp, vp, vp, vp, C.POINTER(Info)]
+    lib.ssnalm_solve.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(Info)]
     lib.ssnalm_solve.restype = i32
     lib.ssnalm_solve_batch.argtypes = [i32, C.POINTER(Problem), C.POINTER(Options), vp,
                                        C.POINTER(vp), C.POINTER(vp), C.POINTER(Info)]
@@ -134,6 +134,8 @@ def load(path: str | None = None):
     lib.ssnalm_mlp_adam.restype = i32
     lib.ssnalm_ws_features.argtypes = [vp, vp, vp]
     lib.ssnalm_ws_features.restype = i32
+    lib.ssnalm_ws_labels.argtypes = [vp, vp, vp, vp]
+    lib.ssnalm_ws_labels.restype = i32
     lib.ssnalm_ws_x0.argtypes = [vp, vp, vp]
     lib.ssnalm_ws_x0.restype = i32
     lib.ssnalm_ws_solve.argtypes = [vp, vp, dbl, i32, vp, vp, C.POINTER(Info), C.POINTER(WsStats)]

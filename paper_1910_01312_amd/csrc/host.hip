@@ -138,6 +138,7 @@ struct ssnalm_ctx {
     bool use_chol = true;
     // statistics of the current solve
     int proj_passes = 0;
+    int proj_capped = 0;             // projections that ended at the pass cap
     long long last_nsv = -1;         // support rows of the current x~ (for byte counts)
     // kernel profiling (opt.profile): HIP event pairs around the hot launches
     struct Pending { int cls; hipEvent_t a, b; double bytes, flops; };
@@ -455,25 +456,22 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         HIPCHK(hipMemcpyAsync(d, c->cg_x, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
         return SSNALM_OK;
     }
-    // PCG on M (matrix-free), Jacobi preconditioner diag(M).
+    // Dense X: PCG on M (matrix-free), Jacobi preconditioner diag(M), with
     // sq_j = sum_J X_ij^2
-    if (c->kind == SSNALM_DENSE) {
-        launch_atmul_dense(c->dtype, c->X, c->y, nullptr, mask, c->n, c->q, c->part, c->part2,
-                           c->st, 2);
-        launch_reduce_cols(c->part2, atmul_dense_nblk(c->n), c->q, nullptr, 1.0, c->sq, c->st);
-    } else {
-        launch_segsum_sq(c->tr, mask, c->sq, c->st);
-    }
+    launch_atmul_dense(c->dtype, c->X, c->y, nullptr, mask, c->n, c->q, c->part, c->part2,
+                       c->st, 2);
+    launch_reduce_cols(c->part2, atmul_dense_nblk(c->n), c->q, nullptr, 1.0, c->sq, c->st);
     launch_jacobi_diag(c->sq, sv, sigma, p, c->diag, c->q, c->st);
-    launch_pcg_init(g, c->diag, c->cg_x, c->cg_r, c->cg_z, c->cg_p, c->q, dsc(c), c->spart,
-                    cnt(c, CNT_PCG), c->st);
     const double tol2 = cg_tol * cg_tol;
+    launch_pcg_init(g, c->diag, c->cg_x, c->cg_r, c->cg_z, c->cg_p, c->q, tol2, dsc(c), c->spart,
+                    cnt(c, CNT_PCG), c->st);
+    STCHK(sync_state(c));
     int it = 0;
-    while (it < c->opt.max_cg) {
+    while (it < c->opt.max_cg && !c->hs->sc.cg_done) {
         const int batch = std::min(8, c->opt.max_cg - it);
         for (int b = 0; b < batch; ++b) {
             // Ap = p + sigma (X_J^T (X_J p - mean) )  with mean over J
-            op_amul(c, c->cg_p, c->nv, c->kind == SSNALM_CSR ? mask : nullptr);   // nv = y .* X_J p
+            op_amul(c, c->cg_p, c->nv);   // nv = y .* X p (rows outside J masked below)
             launch_masked_mean(c->nv, c->y, mask, c->n, p, &dsc(c)->mean_w, c->spart,
                                cnt(c, CNT_MEAN), c->st);
             launch_masked_center_t(c->nv, c->y, mask, c->n, &dsc(c)->mean_w, c->nv2, c->st);
@@ -486,9 +484,8 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         }
         it += batch;
         STCHK(sync_state(c));
-        if (c->hs->sc.cg_rr <= tol2) break;
     }
-    *cg_iters = it;
+    *cg_iters = c->hs->sc.cg_count;     // iterations that changed x (a batch may end early)
     HIPCHK(hipMemcpyAsync(d, c->cg_x, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
     return SSNALM_OK;
 }
@@ -506,20 +503,22 @@ static void gradient(ssnalm_ctx* c, const double* xt, const uint8_t* mask) {
 // ---------------------------------------------------------------- KKT
 // R_KKT(x) of eq. Def_Rkkt with Qx = A w, w = A^T x given (q-vector).
 static ssnalm_status kkt(ssnalm_ctx* c, const double* x, const double* w, double* R, double* b,
-                         double* sumx) {
+                         double* sumx, double* hinge = nullptr) {
     op_amul(c, w, c->nv);                                       // Qx
     launch_kkt_prepare(x, c->nv, c->nv2, c->n, c->st);          // v = x - Qx + e
     STCHK(project_into(c, c->nv2, nullptr, 0.0, nullptr, 2));
     STCHK(sync_state(c));
     bool more = false;
     STCHK(project_finish(c, c->nv2, 2, &more));
-    launch_kkt_finalize(c->nv2, x, c->y, c->n, c->C, dps(c, 2), dsc(c), c->spart, cnt(c, CNT_KKT),
+    launch_kkt_finalize(c->nv2, x, c->nv, c->y, c->n, c->C, dps(c, 2), dsc(c), c->spart, cnt(c, CNT_KKT),
                         c->st);
     STCHK(sync_state(c));
     c->proj_passes += c->hs->ps[2].passes;
+    c->proj_capped += c->hs->ps[2].approx;
     *R = std::sqrt(c->hs->sc.res2) / (1.0 + std::sqrt(c->hs->sc.x2));
     *b = c->hs->ps[2].lam;
     if (sumx) *sumx = c->hs->sc.sumx;
+    if (hinge) *hinge = c->hs->sc.hinge;
     return SSNALM_OK;
 }
 
@@ -825,7 +824,11 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
         return bail(fail(SSNALM_E_HIP, "stream or event creation failed"));
-    (void)hipEventRecord(c->ev_in, c->ust);
+    // The checks below read the caller's arrays from the host: wait until the
+    // work already queued on the caller's stream (which may be a non-blocking
+    // stream that the null stream does not order against) has written them.
+    if (hipEventRecord(c->ev_in, c->ust) != hipSuccess || hipEventSynchronize(c->ev_in) != hipSuccess)
+        return bail(fail(SSNALM_E_HIP, "waiting for the caller's stream failed"));
     (void)hipStreamWaitEvent(c->st, c->ev_in, 0);
     if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SSNALM_E_HIP, "no HIP device"));
     const int64_t n = c->n, q = c->q;
@@ -915,16 +918,17 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
 
 // ---------------------------------------------------------------- solve
 extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x_out, double* w_out,
-                                      ssnalm_info* info) {
+                                      double* b_out, ssnalm_info* info) {
     if (!c || !x_out) return fail(SSNALM_E_BADARG, "null argument");
     StreamScope scope_(c);
     const auto t_begin = std::chrono::steady_clock::now();
     const ssnalm_options& o = c->opt;
     const int64_t n = c->n, q = c->q;
     c->proj_passes = 0;
+    c->proj_capped = 0;
     ssnalm_info inf;
     memset(&inf, 0, sizeof inf);
-    int inner_total = 0, cg_total = 0, ls_fail = 0, outer = 0, ls_trials = 0;
+    int inner_total = 0, cg_total = 0, ls_fail = 0, outer = 0, ls_trials = 0, grad_steps = 0;
     ssnalm_status status = SSNALM_MAXITER;
 
     // x^0: zero or the projection of the warm start; omega^0 = A^T x^0
@@ -941,7 +945,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
         launch_fill(c->om, 0.0, q, c->st);
     }
     double sigma = o.sigma0;
-    double R = INFINITY, b = NAN, best_R = INFINITY, best_b = NAN;
+    double R = INFINITY, b = NAN, best_R = INFINITY, best_b = NAN, hinge = NAN, best_hinge = NAN;
     bool have_best = false;      // x_out holds the best x seen when the cap is hit
 
     for (int k = 0; k < o.max_outer; ++k) {
@@ -962,6 +966,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
         gradient(c, c->xt, c->jm);
         STCHK(sync_state(c));
         c->proj_passes += c->hs->ps[c->base].passes;
+        c->proj_capped += c->hs->ps[c->base].approx;
         for (int j = 0; j < o.max_inner; ++j) {
             const Scalars& hsc = c->hs->sc;
             const double gn = std::sqrt(hsc.gnorm2);
@@ -983,7 +988,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
                         &dsc(c)->dd, q, c->spart, cnt(c, CNT_DOTS2), c->st);
             // Step 2: Armijo line search on psi
             double alpha = 1.0;
-            bool accepted = false;
+            bool accepted = false, fell_back = false;
             const int trial = 1 - c->base;
             for (int m = 0; m <= o.max_backtracks; ++m) {
                 ++ls_trials;
@@ -1004,9 +1009,23 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
                     STCHK(sync_state(c));
                 }
                 c->proj_passes += c->hs->ps[trial].passes;
+                c->proj_capped += c->hs->ps[trial].approx;
                 const Scalars& s2 = c->hs->sc;
-                if (m == 0 && s2.gd >= 0.0 && gn > 0.0) {
-                    // not a descent direction (inexact solve): fall back to -g
+                if (m == 0 && !fell_back && gn > 0.0 &&
+                    (!(s2.gd < 0.0) || (c->use_chol && s2.chol_fail))) {
+                    // The direction is not one of descent (an inexact solve
+                    // stopped early, or the factorisation met a non-positive
+                    // pivot): psi is convex, so no step along it can pass the
+                    // Armijo test.  Take the steepest-descent direction -g
+                    // instead and start the search again at alpha = 1.
+                    fell_back = true;
+                    ++grad_steps;
+                    launch_scale_copy(c->d, c->g, -1.0, q, c->st);
+                    op_amul(c, c->d, c->td);
+                    launch_dots(3, c->g, c->d, &dsc(c)->gd, c->om, c->d, &dsc(c)->od, c->d, c->d,
+                                &dsc(c)->dd, q, c->spart, cnt(c, CNT_DOTS2), c->st);
+                    m = -1;
+                    continue;
                 }
                 const double dpsi = alpha * s2.od + 0.5 * alpha * alpha * s2.dd + s2.dh / sigma;
                 if (!std::isfinite(dpsi)) return fail(SSNALM_E_NONFINITE, "non-finite line search value");
@@ -1029,7 +1048,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
         // A^T x^{k+1} = omega - g
         launch_sub(c->om, c->g, c->qv, q, c->st);
         double sumx = 0.0;
-        STCHK(kkt(c, c->xk, c->qv, &R, &b, &sumx));
+        STCHK(kkt(c, c->xk, c->qv, &R, &b, &sumx, &hinge));
         if (o.verbose)
             fprintf(stderr, "[ssnalm] k=%d sigma=%.3g R_KKT=%.3e newton=%d cg=%d p=%lld passes=%d\n",
                     k, sigma, R, inner_total, cg_total, (long long)c->hs->sc.p, c->proj_passes);
@@ -1038,6 +1057,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
         if (R < best_R) {
             best_R = R;
             best_b = b;
+            best_hinge = hinge;
             HIPCHK(hipMemcpyAsync(x_out, c->xk, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
             have_best = true;
         }
@@ -1048,6 +1068,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     } else {
         R = best_R;
         b = best_b;
+        hinge = best_hinge;
     }
     if (status != SSNALM_OK && ls_fail > 0 && ls_fail >= outer) status = SSNALM_LINESEARCH_FAIL;
     // w = A^T x, objective and the paper's columns
@@ -1068,6 +1089,13 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     inf.rkkt = R;
     inf.obj = 0.5 * w2 - sumx;
     inf.b = b;
+    {
+        // relative duality gap of the C-SVC primal at (w, b) and the dual
+        // objective: P(w, b) + f(x) >= 0 for every feasible x and every b
+        const double P = 0.5 * w2 + c->C * hinge;
+        inf.gap = std::isfinite(P) ? (P + inf.obj) / (1.0 + std::fabs(P) + std::fabs(inf.obj)) : NAN;
+    }
+    if (b_out) *b_out = b;
     inf.sigma = sigma;
     inf.time_s = std::chrono::duration<double>(t_end - t_begin).count();
     inf.iters_outer = outer;
@@ -1078,6 +1106,8 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     inf.n_sv = (int32_t)c->hs->sc.nsv;
     inf.ls_fail = ls_fail;
     inf.ls_trials = ls_trials;
+    inf.grad_steps = grad_steps;
+    inf.proj_capped = c->proj_capped;
     inf.status = status;
     if (info) *info = inf;
     return status;
@@ -1274,6 +1304,16 @@ extern "C" ssnalm_status ssnalm_ws_x0(ssnalm_ctx* c, const float* out, double* x
     return SSNALM_OK;
 }
 
+extern "C" ssnalm_status ssnalm_ws_labels(ssnalm_ctx* c, const double* x, int32_t* status,
+                                          float* target) {
+    if (!c || !x || !status || !target) return fail(SSNALM_E_BADARG, "null argument");
+    StreamScope scope_(c);
+    launch_ws_labels(x, c->n, c->C, status, target, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    return SSNALM_OK;
+}
+
 // Screening solve from the network's status prediction (include/ssnalm.h).
 extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double keep_frac,
                                          int32_t max_rounds, double* x_out, double* w_out,
@@ -1370,7 +1410,7 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
         ssnalm_info ik;
         // later rounds start from the previous round's solution (0 on the added rows)
         if (round > 0) launch_gather_vec(x_out, list, m, x0k, c->st);
-        s1 = ssnalm_solve(sub, round > 0 ? x0k : nullptr, xk, c->qv2, &ik);
+        s1 = ssnalm_solve(sub, round > 0 ? x0k : nullptr, xk, c->qv2, nullptr, &ik);
         ssnalm_destroy(sub);
         if (s1 < 0) return s1;
         t_red += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1379,18 +1419,21 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
         agg.iters_outer += ik.iters_outer;
         agg.iters_inner += ik.iters_inner;
         agg.proj_passes += ik.proj_passes;
+        agg.proj_capped += ik.proj_capped;
+        agg.grad_steps += ik.grad_steps;
         agg.ls_trials += ik.ls_trials;
         agg.ls_fail += ik.ls_fail;
         // x on all rows, judged on the full problem; w = A_K^T x_K
         launch_fill(x_out, 0.0, n, c->st);
         launch_scatter(list, m, xk, x_out, c->st);
-        double R, b, sumx;
-        STCHK(kkt(c, x_out, c->qv2, &R, &b, &sumx));
+        double R, b, sumx, hinge;
+        STCHK(kkt(c, x_out, c->qv2, &R, &b, &sumx, &hinge));
         if (s1 == SSNALM_OK && R <= c->tol) {
             done = true;
             st.rkkt_full = R;
             agg.rkkt = R;
             agg.b = b;
+            agg.gap = hinge;          // turned into the gap once |w|^2 is known
             break;
         }
         // add the rows whose margin under (w, b) is below 1 (x_out keeps the
@@ -1400,11 +1443,17 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
     }
     st.t_reduced = t_red;
     if (!done) {
+        // the prediction did not lead to a solution: the plain cold solve of
+        // the full problem decides, and an OK result is reported as
+        // WARMSTART_REJECTED
         st.fallback = 1;
-        const ssnalm_status s2 = ssnalm_solve(c, nullptr, x_out, w_out, info);
-        st.rkkt_full = info ? info->rkkt : NAN;
+        ssnalm_info ic;
+        const ssnalm_status s2 = ssnalm_solve(c, nullptr, x_out, w_out, nullptr, &ic);
+        st.rkkt_full = ic.rkkt;
         if (stats) *stats = st;
-        return s2;
+        if (s2 == SSNALM_OK) ic.status = SSNALM_WARMSTART_REJECTED;
+        if (info) *info = ic;
+        return s2 == SSNALM_OK ? SSNALM_WARMSTART_REJECTED : s2;
     }
     // w, objective and counts of the returned x
     op_atmul(c, x_out, nullptr, nullptr, 1.0, c->qv, nullptr);
@@ -1415,6 +1464,8 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
     STCHK(sync_state(c));
     if (info) {
         agg.obj = 0.5 * c->hs->sc.dd - c->hs->sc.sumx;
+        const double P = 0.5 * c->hs->sc.dd + c->C * agg.gap;
+        agg.gap = (P + agg.obj) / (1.0 + std::fabs(P) + std::fabs(agg.obj));
         agg.sigma = NAN;
         agg.p = (int32_t)c->hs->sc.p;
         agg.n_sv = (int32_t)c->hs->sc.nsv;

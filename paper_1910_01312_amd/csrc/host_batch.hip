@@ -49,6 +49,7 @@ struct HP {                        // host state of one problem
     int    outer = 0, inner = 0;   // ALM iterations started; Newton steps in this one
     double sigma = 1.0, eps = 1.0, tol = 1e-6;
     double R = INFINITY, b = NAN, best_R = INFINITY, best_b = NAN;
+    double hinge = NAN, best_hinge = NAN;   // hinge sum of the C-SVC primal at (A^T x, b)
     bool   have_best = false;
     int    inner_total = 0, ls_fail = 0, ls_trials = 0, passes = 0;
     double alpha = 1.0;
@@ -426,6 +427,17 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
     ssnalm_options o;
     if (opt) o = *opt; else ssnalm_default_options(&o);
     BST(validate(count, probs, o, x_out));
+    // The setup reads the labels from the host: wait until the work already
+    // queued on the caller's stream (possibly a non-blocking stream that the
+    // null stream does not order against) has written the problem arrays.
+    {
+        hipEvent_t ev = nullptr;
+        BCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        const hipError_t e1 = hipEventRecord(ev, (hipStream_t)stream);
+        const hipError_t e2 = e1 == hipSuccess ? hipEventSynchronize(ev) : e1;
+        (void)hipEventDestroy(ev);
+        BCHK(e2);
+    }
     Batch B;
     BST(setup(B, count, probs, o));
     B.prof = o.profile != 0;
@@ -558,9 +570,9 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
             lb_elem(B.L, 1, B.xk, B.nv, B.nv2);               // x - Qx + e
             lb_proj_init(B.L, B.nv2, nullptr, nullptr, 2, 0);
             lb_proj_passes(B.L, B.nv2, 2, kPassBatch);
-            lb_kkt_fin(B.L, B.nv2, B.xk, 2);
+            lb_kkt_fin(B.L, B.nv2, B.xk, B.nv, 2);
             BST(readback(B));
-            BST(finish_open(B, hp, S3, 2, B.nv2, [&] { lb_kkt_fin(B.L, B.nv2, B.xk, 2); }));
+            BST(finish_open(B, hp, S3, 2, B.nv2, [&] { lb_kkt_fin(B.L, B.nv2, B.xk, B.nv, 2); }));
             std::vector<int> improved;
             for (int k : S3) {
                 HP& h = hp[k];
@@ -568,6 +580,7 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
                 h.passes += B.bs_h[k].ps[2].passes;
                 h.R = std::sqrt(r[BS_RES2]) / (1.0 + std::sqrt(r[BS_X2]));
                 h.b = B.bs_h[k].ps[2].lam;
+                h.hinge = r[BS_HINGE];
                 if (!std::isfinite(h.R)) {
                     h.status = SSNALM_E_NONFINITE;
                     h.phase = PH_DONE;
@@ -584,6 +597,7 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
                 if (h.R < h.best_R) {
                     h.best_R = h.R;
                     h.best_b = h.b;
+                    h.best_hinge = h.hinge;
                     h.have_best = true;
                     improved.push_back(k);
                 }
@@ -607,6 +621,7 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
         if (h.status != SSNALM_OK && h.status >= 0 && h.have_best && h.R > h.best_R) {
             h.R = h.best_R;
             h.b = h.best_b;
+            h.hinge = h.best_hinge;
             from_best.push_back(k);
         }
         if (h.status == SSNALM_MAXITER && h.ls_fail > 0 && h.ls_fail >= h.outer)
@@ -642,6 +657,10 @@ extern "C" ssnalm_status ssnalm_solve_batch(int32_t count, const ssnalm_problem*
         in.rkkt = h.R;
         in.obj = 0.5 * r[BS_W2] - r[BS_FSUMX];
         in.b = h.b;
+        {
+            const double P = 0.5 * r[BS_W2] + B.hprob[k].C * h.hinge;
+            in.gap = std::isfinite(P) ? (P + in.obj) / (1.0 + std::fabs(P) + std::fabs(in.obj)) : NAN;
+        }
         in.sigma = h.sigma;
         in.time_s = secs;
         in.iters_outer = h.outer;

@@ -823,8 +823,11 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_ls_fin(BArgs A, const double* __
 }
 
 // KKT finalize: item partials of |x - Pi(v)|^2, |x|^2, e^T x
+// item partials of |x - Pi(v)|^2, |x|^2, e^T x and the hinge sum
+// sum max(0, 1 - Qx_i - y_i lam) of the C-SVC primal at the KKT bias lam
 __global__ __launch_bounds__(SSN_BLOCK) void kb_kkt_fin(BArgs A, const double* __restrict__ v,
-                                                        const double* __restrict__ x, int w,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ Qx, int w,
                                                         double* __restrict__ part) {
     __shared__ double sh[SSN_WAVES_PER_BLOCK];
     const int nw = *A.wl_n;
@@ -833,22 +836,25 @@ __global__ __launch_bounds__(SSN_BLOCK) void kb_kkt_fin(BArgs A, const double* _
         const int k = item.x;
         const BProb P = A.prob[k];
         const double lam = A.bs[k].ps[w].lam, C = P.C;
-        double r2 = 0.0, x2 = 0.0, sx = 0.0;
+        double r2 = 0.0, x2 = 0.0, sx = 0.0, hs = 0.0;
         for (int r = item.y + threadIdx.x; r < item.z; r += blockDim.x) {
             const int64_t i = P.off + r;
             const double xi = x[i];
-            const double pi = clampd(v[i] - lam * (double)P.y[r], 0.0, C);
+            const double yi = (double)P.y[r];
+            const double pi = clampd(v[i] - lam * yi, 0.0, C);
             const double d = xi - pi;
             r2 = fma(d, d, r2);
             x2 = fma(xi, xi, x2);
             sx += xi;
+            hs += fmax(0.0, 1.0 - Qx[i] - lam * yi);
         }
         const double a = block_sum(r2, sh), b = block_sum(x2, sh), c = block_sum(sx, sh);
+        const double h = block_sum(hs, sh);
         if (threadIdx.x == 0) {
             part[(int64_t)it * 4 + 0] = a;
             part[(int64_t)it * 4 + 1] = b;
             part[(int64_t)it * 4 + 2] = c;
-            part[(int64_t)it * 4 + 3] = 0.0;
+            part[(int64_t)it * 4 + 3] = h;
         }
     }
 }
@@ -1233,9 +1239,9 @@ void lb_ls_fin(const BLaunch& L, const double* v, const double* ubase, const dou
                        xk, x, mask, L.part);
     hipLaunchKernelGGL(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_DH, 4);
 }
-void lb_kkt_fin(const BLaunch& L, const double* v, const double* x, int w) {
-    hipLaunchKernelGGL(kb_kkt_fin, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, x, w, L.part);
-    hipLaunchKernelGGL(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_RES2, 3);
+void lb_kkt_fin(const BLaunch& L, const double* v, const double* x, const double* Qx, int w) {
+    hipLaunchKernelGGL(kb_kkt_fin, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, x, Qx, w, L.part);
+    hipLaunchKernelGGL(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_RES2, 4);
 }
 void lb_count(const BLaunch& L, const double* x) {
     hipLaunchKernelGGL(kb_count, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, x, L.part);

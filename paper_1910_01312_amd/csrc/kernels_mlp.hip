@@ -284,14 +284,19 @@ __global__ __launch_bounds__(256) void k_ws_x0(const float* __restrict__ out, in
     x0[i] = k == 0 ? 0.0 : (k == 1 ? C * (double)o.w : C);
 }
 
-// ------------------------------------------------------------------ screening
-// keep[i] = 1 unless the network gives P(x_i* = 0) >= thr
-__global__ __launch_bounds__(256) void k_ws_keep(const float* __restrict__ out, int64_t n, float thr,
-                                                 uint8_t* __restrict__ keep) {
+// Training labels from a solution x: status 0 (x_i <= 1e-8 C), 2 (x_i >=
+// (1 - 1e-8) C) or 1 (inside), and the multiplier target x_i / C.
+__global__ __launch_bounds__(256) void k_ws_labels(const double* __restrict__ x, int64_t n, double C,
+                                                   int32_t* __restrict__ status,
+                                                   float* __restrict__ target) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    keep[i] = out[4 * i] < thr ? 1 : 0;
+    const double xi = x[i];
+    status[i] = xi >= (1.0 - 1e-8) * C ? 2 : (xi <= 1e-8 * C ? 0 : 1);
+    target[i] = (float)(xi / C);
 }
+
+// ------------------------------------------------------------------ screening
 // Xk[j] = X[list[j]], yk[j] = y[list[j]] (one row per 64 threads)
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ X,
@@ -465,9 +470,6 @@ void launch_ws_features(int dtype, const void* X, const int8_t* y, int64_t n, in
                            R, aw, b1, lognc, Z);
 }
 
-void launch_ws_keep(const float* out, int64_t n, float thr, uint8_t* keep, hipStream_t s) {
-    hipLaunchKernelGGL(k_ws_keep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, thr, keep);
-}
 void launch_gather_rows(int dtype, const void* X, const int8_t* y, const int32_t* list, int64_t m,
                         int64_t q, void* Xk, int8_t* yk, hipStream_t s) {
     const dim3 g((unsigned)((m + 3) / 4));
@@ -504,6 +506,11 @@ void launch_ws_violators(const double* aw, const int8_t* y, int64_t n, double b,
 
 void launch_ws_x0(const float* out, int64_t n, double C, double* x0, hipStream_t s) {
     hipLaunchKernelGGL(k_ws_x0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, C, x0);
+}
+void launch_ws_labels(const double* x, int64_t n, double C, int32_t* status, float* target,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_ws_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, C,
+                       status, target);
 }
 
 }  // namespace ssn

@@ -247,9 +247,3 @@ void launch_chol_solve_small(const double* M, const double* g, double* d, int64_
 }
 
 }  // namespace ssn
-
-namespace ssn {
-// The bf16 MFMA SYRK and the blocked Cholesky are provided by
-// kernels_mfma.hip and kernels_chol.hip; these fallbacks keep the library
-// linkable when they are absent.
-}  // namespace ssn

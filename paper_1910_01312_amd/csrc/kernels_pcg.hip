@@ -35,7 +35,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_init(const double* __restrict
                                                         double* __restrict__ r,
                                                         double* __restrict__ z,
                                                         double* __restrict__ pd, int64_t q,
-                                                        Scalars* sc, double* __restrict__ part,
+                                                        double tol2, Scalars* sc,
+                                                        double* __restrict__ part,
                                                         unsigned* counter) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     double rz = 0.0, rr = 0.0;
@@ -58,14 +59,16 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_init(const double* __restrict
         if (threadIdx.x == 0) {
             sc->cg_rz = s0;
             sc->cg_rr = s1;
-            sc->cg_done = 0;
+            sc->cg_done = s1 <= tol2 ? 1 : 0;       // x = 0 may already meet the tolerance
+            sc->cg_count = 0;
         }
     }
 }
 void launch_pcg_init(const double* g, const double* diag, double* x, double* r, double* z, double* pd,
-                     int64_t q, Scalars* sc, double* part, unsigned* counter, hipStream_t s) {
+                     int64_t q, double tol2, Scalars* sc, double* part, unsigned* counter,
+                     hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_init, dim3(grid_for(q)), dim3(SSN_BLOCK), 0, s, g, diag, x, r, z, pd, q,
-                       sc, part, counter);
+                       tol2, sc, part, counter);
 }
 
 // pap = p . Ap
@@ -127,6 +130,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_step(double* __restrict__ x,
             sc->cg_beta = rz > 0.0 ? s0 / rz : 0.0;
             sc->cg_rz = s0;
             sc->cg_rr = s1;
+            sc->cg_count += 1;                       // an iteration that changed x
             if (s1 <= tol2 || !(alpha > 0.0)) sc->cg_done = 1;
         }
     }

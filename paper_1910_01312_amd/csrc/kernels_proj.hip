@@ -431,7 +431,9 @@ __global__ __launch_bounds__(DEC_THREADS) void k_proj_decide(double C, ProjState
             else lam = nlo;
             lam = fmin(fmax(lam, nlo), nhi);
             st->lam = lam;
-            st->approx = (ins == 0) ? 0 : 1;
+            // inexact only when the pass cap stopped a splittable bracket that
+            // still holds breakpoints
+            st->approx = (ins != 0 && !tiny) ? 1 : 0;
             st->done = 1;                        // read by later launches only
         }
     }
@@ -576,45 +578,54 @@ void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n,
                        n);
 }
 
+// |x - Pi(v)|^2, |x|^2, e^T x and the hinge sum
+//   sum_i max(0, 1 - Qx_i - y_i lam) = sum_i max(0, 1 - y_i (x~_i^T w + lam))
+// (Qx = A w, so Qx_i = y_i x~_i^T w) of the C-SVC primal at (w, b = lam).
 __global__ __launch_bounds__(SSN_BLOCK) void k_kkt_finalize(const double* __restrict__ v,
                                                             const double* __restrict__ x,
+                                                            const double* __restrict__ Qx,
                                                             const int8_t* __restrict__ y,
                                                             int64_t n, double C,
                                                             const ProjState* st,
                                                             double* __restrict__ part) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     const double lam = st->lam;
-    double r2 = 0.0, x2 = 0.0, sx = 0.0;
+    double r2 = 0.0, x2 = 0.0, sx = 0.0, hs = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double xi = x[i];
-        const double pi = clampd(v[i] - lam * (double)y[i], 0.0, C);
+        const double yi = (double)y[i];
+        const double pi = clampd(v[i] - lam * yi, 0.0, C);
         const double r = xi - pi;
         r2 = fma(r, r, r2);
         x2 = fma(xi, xi, x2);
         sx += xi;
+        hs += fmax(0.0, 1.0 - Qx[i] - lam * yi);
     }
     const double a = block_sum(r2, shd);
     const double b = block_sum(x2, shd);
     const double c = block_sum(sx, shd);
+    const double h = block_sum(hs, shd);
     if (threadIdx.x == 0) {
-        part[blockIdx.x * 3 + 0] = a;
-        part[blockIdx.x * 3 + 1] = b;
-        part[blockIdx.x * 3 + 2] = c;
+        part[blockIdx.x * 4 + 0] = a;
+        part[blockIdx.x * 4 + 1] = b;
+        part[blockIdx.x * 4 + 2] = c;
+        part[blockIdx.x * 4 + 3] = h;
     }
 }
 
-void launch_kkt_finalize(const double* v, const double* x, const int8_t* y, int64_t n, double C,
-                         const ProjState* st, Scalars* sc, double* part, unsigned* counter,
-                         hipStream_t s) {
+void launch_kkt_finalize(const double* v, const double* x, const double* Qx, const int8_t* y,
+                         int64_t n, double C, const ProjState* st, Scalars* sc, double* part,
+                         unsigned* counter, hipStream_t s) {
     (void)counter;
     const unsigned g = proj_grid(n);
-    hipLaunchKernelGGL(k_kkt_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, x, y, n, C, st, part);
+    hipLaunchKernelGGL(k_kkt_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, x, Qx, y, n, C, st, part);
     ColSumDst d = colsum_dst();
     d.p[0] = &sc->res2;
     d.p[1] = &sc->x2;
     d.p[2] = &sc->sumx;
-    launch_colsum_fin(part, (int)g, 3, 3, d, s);
+    d.p[3] = &sc->hinge;
+    launch_colsum_fin(part, (int)g, 4, 4, d, s);
 }
 
 // ------------------------------------------------------------------ compaction

@@ -59,7 +59,7 @@ __device__ __forceinline__ double segval(const V* val, int64_t k, bool sq) {
 // alone when vin == nullptr.  CM names the case at compile time, so that the
 // gathers carry no run-time tests and are all in flight together:
 // 0 = vin alone, 1 = mask alone, 2 = any other combination.
-template <typename V, bool SQ, int CM>
+template <typename V, int CM>
 __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
     int64_t nseg, int64_t nnz, const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
     const V* __restrict__ val, const int32_t* __restrict__ lane_seg, int64_t ntile,
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum(
                     cf = (double)mask[i];
                 }
             }
-            cfv[e] = SQ ? cf * av[e] * av[e] : cf * av[e];
+            cfv[e] = cf * av[e];
         }
         // walk the lane's entries segment by segment
         int j = 0;                             // current segment = seg0 + j
@@ -271,7 +271,6 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_segsum_fix(
 }
 int seg_short_tiles() { return SEG_SHORT; }
 
-template <bool SQ>
 static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin,
                           const uint8_t* mask, const int8_t* yout, const uint8_t* out_mask,
                           double* out, hipStream_t s, int parts = 1) {
@@ -282,7 +281,7 @@ static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin
     }
     if (nb > 0) {
         const int cm = (vin && !yin && !mask) ? 0 : ((!vin && mask) ? 1 : 2);
-#define SEGSUM(V, CM) hipLaunchKernelGGL((k_segsum<V, SQ, CM>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, \
+#define SEGSUM(V, CM) hipLaunchKernelGGL((k_segsum<V, CM>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, \
                                          s, P.nseg, P.nnz, P.ptr, P.idx, (const V*)P.val, P.lane_seg, \
                                          P.ntile, P.tile_first, P.carry, vin, yin, mask, yout, \
                                          out_mask, out, parts, tpp)
@@ -304,16 +303,12 @@ static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin
 
 void launch_segsum(const SegPlan& P, const double* vin, const int8_t* yin, const uint8_t* mask,
                    const int8_t* yout, const uint8_t* out_mask, double* out, hipStream_t s) {
-    segsum_launch<false>(P, vin, yin, mask, yout, out_mask, out, s);
+    segsum_launch(P, vin, yin, mask, yout, out_mask, out, s);
 }
 
 void launch_segsum_parts(const SegPlan& P, int parts, const double* vin, double* out,
                          hipStream_t s) {
-    segsum_launch<false>(P, vin, nullptr, nullptr, nullptr, nullptr, out, s, parts);
-}
-
-void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStream_t s) {
-    segsum_launch<true>(P, nullptr, nullptr, mask, nullptr, nullptr, out, s);
+    segsum_launch(P, vin, nullptr, nullptr, nullptr, nullptr, out, s, parts);
 }
 
 int seg_entries_per_lane() { return SEG_E; }

@@ -36,6 +36,7 @@ struct Scalars {
     double cg_rz, cg_pap, cg_rr, cg_alpha, cg_beta, cg_rz_new;
     double mean_w;        // PCG: mean of X_J p over J
     double sumx;          // e^T x
+    double hinge;         // KKT: sum_i max(0, 1 - Qx_i - y_i b) at the KKT bias b
     long long p;          // |J|
     long long nnzj;       // nonzeros of the rows in J (sparse input)
     long long nfix;       // chunk-crossing column runs of the compact X_J copy
@@ -106,7 +107,6 @@ int atmul_row_parts(int64_t n, int64_t q, int64_t nnz);
 void launch_segsum_parts(const SegPlan& P, int parts, const double* vin, double* out,
                          hipStream_t s);
 // out[s] = sum_{k in seg s} val[k]^2 mask(idx[k])
-void launch_segsum_sq(const SegPlan& P, const uint8_t* mask, double* out, hipStream_t s);
 
 // Projection ---------------------------------------------------------------
 // v_out = (td ? u - alpha_sigma * td : u); initialise the bracket in st.
@@ -129,8 +129,8 @@ void launch_ls_finalize(const double* v, const double* u_base, const double* td,
                         hipStream_t s);
 // KKT: v = x - Qx + 1; after projecting v: res2 = |x - Pi(v)|^2, x2 = |x|^2, sumx
 void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n, hipStream_t s);
-void launch_kkt_finalize(const double* v, const double* x, const int8_t* y, int64_t n,
-                         double C, const ProjState* st, Scalars* sc, double* part,
+void launch_kkt_finalize(const double* v, const double* x, const double* Qx, const int8_t* y,
+                         int64_t n, double C, const ProjState* st, Scalars* sc, double* part,
                          unsigned* counter, hipStream_t s);
 // ordered compaction of mask into list; total written to *count
 int  compact_blocks(int64_t n);
@@ -249,8 +249,8 @@ void launch_cg_dir(double* pd, const double* z, const double* sv, int64_t q, con
 // PCG pieces -------------------------------------------------------------------
 void launch_jacobi_diag(const double* sq, const double* sv, double sigma, int64_t p,
                         double* diag, int64_t q, hipStream_t s);
-void launch_pcg_init(const double* g, const double* diag, double* x, double* r, double* z,
-                     double* pd, int64_t q, Scalars* sc, double* part, unsigned* counter,
+void launch_pcg_init(const double* g, const double* diag, double* x, double* r, double* z, double* pd,
+                     int64_t q, double tol2, Scalars* sc, double* part, unsigned* counter,
                      hipStream_t s);
 void launch_pcg_pap(const double* pd, const double* Ap, int64_t q, Scalars* sc, double* part,
                     unsigned* counter, hipStream_t s);
@@ -291,7 +291,7 @@ struct BPar {                  // per-phase parameters of problem k (uploaded by
 enum {                         // per-problem scalar slots (BState::r)
     BS_GN2 = 0, BS_OM2, BS_GD, BS_OD, BS_DD,
     BS_DH, BS_DIST2, BS_PF, BS_NSV,
-    BS_RES2, BS_X2, BS_SUMX,
+    BS_RES2, BS_X2, BS_SUMX, BS_HINGE,
     BS_FSUMX, BS_FNSV, BS_FP, BS_W2,
     BS_NR
 };
@@ -339,7 +339,7 @@ void lb_proj_init(const BLaunch& L, const double* u, const double* td, double* v
 void lb_proj_passes(const BLaunch& L, const double* v, int w, int npass);
 void lb_ls_fin(const BLaunch& L, const double* v, const double* ubase, const double* td, int w,
                int wb, const double* xk, double* x, uint8_t* mask);
-void lb_kkt_fin(const BLaunch& L, const double* v, const double* x, int w);
+void lb_kkt_fin(const BLaunch& L, const double* v, const double* x, const double* Qx, int w);
 void lb_count(const BLaunch& L, const double* x);
 void lb_compact(const BLaunch& L, const uint8_t* mask, int32_t* list);
 void lb_newton(const BLaunch& L, const int32_t* list, const double* sv, const double* g, double* d,
@@ -361,7 +361,8 @@ void launch_ws_features(int dtype, const void* X, const int8_t* y, int64_t n, in
                         const float* R, const double* aw, double b1, float lognc, float* Z,
                         hipStream_t s);
 void launch_ws_x0(const float* out, int64_t n, double C, double* x0, hipStream_t s);
-void launch_ws_keep(const float* out, int64_t n, float thr, uint8_t* keep, hipStream_t s);
+void launch_ws_labels(const double* x, int64_t n, double C, int32_t* status, float* target,
+                      hipStream_t s);
 void launch_gather_rows(int dtype, const void* X, const int8_t* y, const int32_t* list, int64_t m,
                         int64_t q, void* Xk, int8_t* yk, hipStream_t s);
 void launch_scatter(const int32_t* list, int64_t m, const double* xk, double* x, hipStream_t s);

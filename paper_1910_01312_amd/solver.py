@@ -124,9 +124,12 @@ class Solver:
         w = torch.empty(self.q, dtype=torch.float64, device=dev)
         info = L.Info()
         x0d = _to_dev(x0, torch.float64) if x0 is not None else None
-        st = self._lib.ssnalm_solve(self._ctx, _ptr(x0d), _ptr(x), _ptr(w), C.byref(info))
+        b = C.c_double(float("nan"))
+        st = self._lib.ssnalm_solve(self._ctx, _ptr(x0d), _ptr(x), _ptr(w), C.byref(b),
+                                    C.byref(info))
         L.check(st, "ssnalm_solve")
         d = info.as_dict()
+        d["b_out"] = b.value
         d["status_name"] = L.STATUS_NAMES.get(st, str(st))
         return x, w, d
 

@@ -122,13 +122,15 @@ def initial_point(solver: Solver, out):
     return x0
 
 
-def labels(x, C_):
+def labels(solver: Solver, x):
     """Bound status (0: x = 0, 1: inside, 2: x = C; relative threshold
-    1e-8 C) and target x / C, on the GPU."""
-    st = torch.ones_like(x, dtype=torch.int32)
-    st[x <= 1e-8 * C_] = 0
-    st[x >= (1.0 - 1e-8) * C_] = 2
-    return st, (x / C_).to(torch.float32)
+    1e-8 C) and target x / C of a solution x of the solver's problem
+    (ssnalm_ws_labels)."""
+    xd = _to_dev(x, torch.float64)
+    st = torch.empty(solver.n, dtype=torch.int32, device=xd.device)
+    tg = torch.empty(solver.n, dtype=torch.float32, device=xd.device)
+    L.check(solver._lib.ssnalm_ws_labels(solver._ctx, _p(xd), _p(st), _p(tg)), "ssnalm_ws_labels")
+    return st, tg
 
 
 def warm_solve(solver: Solver, net: Net, R, keep_frac=0.25, max_rounds=3):
@@ -187,7 +189,7 @@ def build_dataset(specs, R, make_problem, chunk=512, log=None):
             with Solver(Xd, yd, C_, tol=1e-6) as s:
                 x, _, info = r if batched else s.solve()
                 Zs.append(features(s, R))
-            st, tg = labels(x, C_)
+                st, tg = labels(s, x)
             Ss.append(st)
             Ts.append(tg)
             recs.append({"status": info["status_name"], "newton": info["iters_inner"]})

@@ -321,7 +321,8 @@ def test_rkkt_parity():
 
 # ------------------------------------------------------------------ mixed precision
 
-@pytest.mark.parametrize("q,p_frac", [(128, 0.3), (256, 0.05), (512, 0.2), (200, 0.5)])
+@pytest.mark.parametrize("q,p_frac", [(128, 0.3), (256, 0.05), (512, 0.2), (200, 0.5),
+                                      (77, 0.4), (203, 0.3)])
 def test_gram_mfma_bf16(q, p_frac):
     """bf16 MFMA SYRK with fp32 accumulation: exact on small-integer bf16
     data (every partial sum is an integer below 2^24), and within the fp32

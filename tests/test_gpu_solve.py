@@ -4,8 +4,10 @@ x* is generally not unique (rank Q <= q < n), so the comparison uses what is
 unique: the optimal value f*, the primal weights w* = A^T x*, R_KKT
 recomputed by the oracle on the GPU's x, feasibility, and b when p > 0.
 Bars: R_KKT <= 1e-6 and |f - f*| / max(1, |f*|) <= 1e-8 against an oracle
-reference solved to R_KKT <= 1e-8; when the 1e-6 stop leaves the objective
-outside 1e-8 the GPU is re-run at tol 1e-8 for the objective check.
+reference that reached R_KKT <= 1e-8 (status OK asserted).  Both bars are
+checked on ONE solution: the tol-1e-6 solve when its objective already meets
+1e-8, else a tol-1e-8 solve (R_KKT <= 1e-8 <= 1e-6); the tol-1e-6 solve's
+objective error is printed either way.
 """
 import numpy as np
 import pytest
@@ -35,16 +37,19 @@ def _solve(*a, **k):
 
 
 def _ref(X, y, C, **kw):
-    """Oracle reference: R_KKT <= 1e-8, at most 25 ALM iterations (the best x
-    is kept).  In fp64 the method's attainable R_KKT floor at large sigma is
-    a few 1e-9 on some of these problems (1e-10 is not reachable there); at
-    1e-8 the objective already agrees with the best attainable one to ~1e-11
-    relative, three orders inside the 1e-8 objective bar."""
-    return ssnal.solve(X, y, C, tol=1e-8, max_outer=25, **kw)
+    """Oracle reference solved to R_KKT <= 1e-8, which it must reach (status
+    OK).  In fp64 the method's attainable R_KKT floor at large sigma is a few
+    1e-9 on some of these problems, so 1e-10 is not reachable there; at 1e-8
+    the objective agrees with the best attainable one to ~1e-11 relative,
+    three orders inside the 1e-8 objective bar."""
+    r = ssnal.solve(X, y, C, tol=1e-8, **kw)
+    assert r.status == "OK", (r.status, r.rkkt, r.outer)
+    return r
 
 
-def _check_solution(X, y, C, x, w, info, ref, tol=1e-6, rerun=None):
-    yf = y.astype(np.float64)
+def _check_one(X, y, C, x, w, info, tol):
+    """R_KKT (recomputed by the oracle), feasibility and w = A^T x of one
+    returned solution."""
     assert info["status_name"] == "OK", info
     assert np.all(x >= 0.0) and np.all(x <= C)
     R, _ = ssnal.rkkt(X, y, C, x)
@@ -52,12 +57,21 @@ def _check_solution(X, y, C, x, w, info, ref, tol=1e-6, rerun=None):
     assert abs(info["rkkt"] - R) <= 1e-3 * R + 1e-12
     w_ref = ssnal.atmul(X, y, x)
     np.testing.assert_allclose(w, w_ref, rtol=0, atol=1e-10 * (1 + np.abs(w_ref).max()))
+    return R
+
+
+def _check_solution(X, y, C, x, w, info, ref, tol=1e-6, rerun=None):
+    """Both bars on one solution (see the module docstring)."""
+    R = _check_one(X, y, C, x, w, info, tol)
     f = ssnal.dual_objective(X, y, x)
     rel = abs(f - ref.obj) / max(1.0, abs(ref.obj))
+    print(f"tol {tol:g}: R_KKT {R:.2e}, relative objective error {rel:.2e}")
     if rel > 1e-8 and rerun is not None:
-        x2, _, info2 = rerun()
+        x2, w2, info2 = rerun()
+        R2 = _check_one(X, y, C, x2, w2, info2, 1e-8)
         f = ssnal.dual_objective(X, y, x2)
         rel = abs(f - ref.obj) / max(1.0, abs(ref.obj))
+        print(f"tol 1e-08: R_KKT {R2:.2e}, relative objective error {rel:.2e}")
     assert rel <= 1e-8, (f, ref.obj, rel)
     return R
 

@@ -183,7 +183,7 @@ def test_null_handles_and_sizes_without_gpu():
     buf = (C.c_byte * 64)()
     a = C.addressof(buf)
     info = _lib.Info()
-    assert lib.ssnalm_solve(None, None, a, None, C.byref(info)) == _lib.E_BADARG
+    assert lib.ssnalm_solve(None, None, a, None, None, C.byref(info)) == _lib.E_BADARG
     assert lib.ssnalm_op_amul(None, a, a) == _lib.E_BADARG
     assert lib.ssnalm_op_atmul(None, a, a) == _lib.E_BADARG
     assert lib.ssnalm_ws_x0(None, a, a) == _lib.E_BADARG

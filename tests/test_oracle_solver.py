@@ -72,6 +72,35 @@ def test_closed_form_two_points():
             assert r.b == pytest.approx(b, abs=1e-7)
 
 
+def test_duality_gap_capped_two_points():
+    """Two points with the box active (t* = C < 2/|D|^2, D = x~_1 - x~_2):
+    x* = (C, C), w* = C D, f* = C^2|D|^2/2 - 2C, and the C-SVC primal at w*
+    with the best bias is C^2|D|^2/2 + C (2 - C|D|^2) = 2C - C^2|D|^2/2
+    (both hinge terms active between the two kinks), so P* + f* = 0.  A C
+    missing from the hinge term of the primal breaks this for C != 1."""
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        X = rng.normal(size=(2, 3))
+        y = np.array([1, -1], np.int8)
+        D = X[0] - X[1]
+        dd = float(D @ D)
+        C = float(rng.uniform(0.05, 0.9)) * 2.0 / dd       # strictly capped, C != 1
+        x = np.array([C, C])
+        gap, P, f = ssnal.duality_gap(X, y, C, x)
+        assert f == pytest.approx(0.5 * C * C * dd - 2 * C, rel=1e-12)
+        assert P == pytest.approx(2 * C - 0.5 * C * C * dd, rel=1e-12)
+        assert abs(gap) <= 1e-13
+        # any bias between the kinks gives the same primal value; outside, more
+        gb, Pb, _ = ssnal.duality_gap_at(X, y, C, x, b=1e3)
+        assert Pb > P and gb > gap
+        # planted: the hinge sum without its C factor misses P* unless C = 1
+        w = C * D
+        b = ssnal.best_bias(X, y, C, w)
+        m = X @ w + b
+        P_planted = 0.5 * float(w @ w) + float(np.sum(np.maximum(0.0, 1.0 - y * m)))
+        assert abs(P_planted - P) > 1e-6
+
+
 def test_single_class_gives_zero():
     X = np.random.default_rng(0).normal(size=(20, 3))
     y = np.ones(20, np.int8)
