@@ -239,6 +239,25 @@ ssnalm_status ssnalm_op_project(ssnalm_ctx* ctx, const double* v, double* x,
                                 uint8_t* free_mask, double* lam, int64_t* p,
                                 int32_t* passes);
 
+/* The projection of ssnalm_op_project without a context and without any
+ * device allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Its
+ * scratch (search state, block partials, counts; ssnalm_noalloc_scratch_bytes()
+ * bytes, about 260 KB) is a device array inside the library that each GPU
+ * holds until the process ends.  Calls that overlap on one GPU share that
+ * array and race: the caller must order them.
+ *   v: n doubles, y: n labels (+1 / -1), x: n doubles, free_mask: n bytes or
+ *   NULL (as ssnalm_op_project), all device; lam (the multiplier), p (|J|):
+ *   host or NULL; stream: hipStream_t or NULL.  Returns after the stream
+ *   has finished the call's work.
+ * E_BADARG: null v, y or x; n < 1 or n > ssnalm_noalloc_max_n(); C <= 0 or
+ * non-finite.  Labels are not checked (they must be exactly +1 or -1). */
+ssnalm_status ssnalm_project_noalloc(const double* v, const int8_t* y, int64_t n, double C,
+                                     double* x, uint8_t* free_mask, double* lam, int64_t* p,
+                                     void* stream);
+int64_t ssnalm_noalloc_max_n(void);
+int64_t ssnalm_noalloc_scratch_bytes(void);
+
 /* Newton direction of Algorithm 3, step 1, in omega-space:
  * d = -(I + sigma (X_J^T X_J - s s^T / p))^{-1} g,  s = X_J^T 1,  p = |J|
  * (Proposition 5 with L = A; d = -g when p = 0).  free_mask: n bytes

@@ -72,6 +72,7 @@ EXPORTS = [
     "ssnalm_mlp_param_count", "ssnalm_mlp_work_floats", "ssnalm_mlp_scratch_floats",
     "ssnalm_mlp_forward", "ssnalm_mlp_backward", "ssnalm_mlp_adam", "ssnalm_ws_features",
     "ssnalm_ws_x0", "ssnalm_ws_solve", "ssnalm_set_profile", "ssnalm_ws_labels",
+    "ssnalm_project_noalloc", "ssnalm_noalloc_max_n", "ssnalm_noalloc_scratch_bytes",
 ]
 
 _lib = None
@@ -134,6 +135,13 @@ def load(path: str | None = None):
     lib.ssnalm_mlp_adam.restype = i32
     lib.ssnalm_ws_features.argtypes = [vp, vp, vp]
     lib.ssnalm_ws_features.restype = i32
+    lib.ssnalm_project_noalloc.argtypes = [vp, vp, i64, dbl, vp, vp, C.POINTER(dbl),
+                                           C.POINTER(i64), vp]
+    lib.ssnalm_project_noalloc.restype = i32
+    lib.ssnalm_noalloc_max_n.argtypes = []
+    lib.ssnalm_noalloc_max_n.restype = i64
+    lib.ssnalm_noalloc_scratch_bytes.argtypes = []
+    lib.ssnalm_noalloc_scratch_bytes.restype = i64
     lib.ssnalm_ws_labels.argtypes = [vp, vp, vp, vp]
     lib.ssnalm_ws_labels.restype = i32
     lib.ssnalm_ws_x0.argtypes = [vp, vp, vp]
