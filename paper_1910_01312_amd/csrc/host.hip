@@ -252,15 +252,14 @@ static Scalars* dsc(ssnalm_ctx* c) { return &c->ds->sc; }
 static unsigned* cnt(ssnalm_ctx* c, int k) { return c->counters + k; }
 
 // ---------------------------------------------------------------- operators
-// t = A v (rows restricted to out_mask when given: X_J v inside the Newton operator)
-static void op_amul(ssnalm_ctx* c, const double* v, double* t, const uint8_t* out_mask = nullptr) {
-    prof_begin(c, out_mask ? SSNALM_K_AMUL_J : SSNALM_K_AMUL);
+// t = A v over all rows
+static void op_amul(ssnalm_ctx* c, const double* v, double* t) {
+    prof_begin(c, SSNALM_K_AMUL);
     if (c->kind == SSNALM_DENSE)
         launch_amul_dense(c->dtype, c->X, c->y, v, t, c->n, c->q, c->st);
     else
-        launch_segsum(c->fwd, v, nullptr, nullptr, c->y, out_mask, t, c->st);
-    if (out_mask) prof_end(c, SSNALM_K_AMUL_J, 0.0, 0.0);
-    else prof_end(c, SSNALM_K_AMUL, bytes_amul(c), 2.0 * (c->kind == SSNALM_DENSE ? (double)c->n * c->q : (double)c->nnz));
+        launch_segsum(c->fwd, v, nullptr, nullptr, c->y, nullptr, t, c->st);
+    prof_end(c, SSNALM_K_AMUL, bytes_amul(c), 2.0 * (c->kind == SSNALM_DENSE ? (double)c->n * c->q : (double)c->nnz));
 }
 
 // r = base + sign * A^T z  (z an n-vector; base may be null); when mask is
