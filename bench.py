@@ -129,13 +129,27 @@ def oracle_sample(wl, budget_s, gpu_newton_steps):
         X = wl["X"]
         mode = "qspace"
     proc = psutil.Process()
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover - reporting only
+        blas_threads = None
     c0 = proc.cpu_times()
     t0 = time.perf_counter()
     r = ssnal.solve(X, wl["y"], wl["C"], tol=1e-6, newton=mode, time_budget_s=budget_s,
                     max_cg=2000)
     wall = time.perf_counter() - t0
     c1 = proc.cpu_times()
-    cores = max(1, round(((c1.user - c0.user) + (c1.system - c0.system)) / max(wall, 1e-9)))
+    busy = ((c1.user - c0.user) + (c1.system - c0.system)) / max(wall, 1e-9)
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
     steps = max(r.inner, 1)
     if r.status == "OK":
         est = wall
@@ -146,7 +160,11 @@ def oracle_sample(wl, budget_s, gpu_newton_steps):
         sample = (f"first {wall:.1f} s of the oracle solve of the same workload: {steps} Newton "
                   f"steps ({r.cg_iters} CG iterations, {r.outer} ALM iterations); seconds per "
                   f"Newton step x the {gpu_newton_steps} Newton steps of the GPU solve")
-    return {"value": est, "unit": "s", "cores": int(cores), "kind": "oracle", "sample": sample}
+    return {"value": est, "unit": "s",
+            "cores": int(blas_threads) if blas_threads else max(1, round(busy)),
+            "kind": "oracle", "sample": sample,
+            "nproc": os.cpu_count(), "cpu_model": cpu_model, "blas_threads": blas_threads,
+            "avg_busy_cores": round(busy, 2)}
 
 
 def run_batch(args):
@@ -356,7 +374,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sparse-text")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--C", type=float, default=None)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
@@ -432,12 +450,11 @@ def main():
 
     # Warm-up solves time every kernel class; the timed solves time only the
     # dominant class (largest summed time), so the roofline comes from the
-    # timed region itself.  The sparse CG's X_J classes are left out: about a
-    # fifth of their launches pass through after convergence (their per-launch
-    # algorithmic bytes would be overstated), and events around their ~1700
-    # launches per solve would add ~10 ms to the timed solves.
+    # timed region itself.  The library leaves out of a class's statistics the
+    # CG launches that passed through after convergence, so bytes and time
+    # cover the same launches.
     K_NAMES = _lib.K_NAMES
-    untimed = {"amul_J", "atmul_J"} if "csr" in kw else set()
+    untimed = set()
     ks_all = None
     for i in range(max(args.warmup, 1)):
         s.set_profile(1)

@@ -310,8 +310,12 @@ typedef struct {
 } ssnalm_kstat;
 
 /* Per-class kernel statistics accumulated by ssnalm_solve while
- * opt.profile = 1.  which: SSNALM_K_*; out: host pointer.  reset != 0
- * clears all classes after reading. */
+ * opt.profile = 1.  A launch's time is the sum of its kernels' execution
+ * times, each taken by an event pair attached to the kernel's dispatch.  The
+ * sparse CG's classes (SSNALM_K_AMUL_J, SSNALM_K_ATMUL_J) are sampled: one
+ * CG iteration in eight is timed, and launches after the CG met its
+ * tolerance (which pass through) are not counted.  which: SSNALM_K_*; out:
+ * host pointer.  reset != 0 clears all classes after reading. */
 ssnalm_status ssnalm_kernel_stats(ssnalm_ctx* ctx, int32_t which, ssnalm_kstat* out,
                                   int32_t reset);
 
@@ -328,6 +332,38 @@ ssnalm_status ssnalm_batch_kernel_stats(int32_t which, ssnalm_kstat* out);
  * the bias lam of its projection.  rkkt, b: host doubles. */
 ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* ctx, const double* x, double* rkkt,
                              double* b);
+
+/* ------------------------------------------------------------------------
+ * RBF kernels through explicit features (Section 4, the approximations of
+ * Tables 3_1 and 3_2).  With k(x, z) = exp(-|x - z|^2 / (2 alpha)) the
+ * C-SVC dual has Q = diag(y) K diag(y); a feature matrix Z with Z Z^T ~ K
+ * makes it the linear problem of this library with X = Z: pass Z (dense,
+ * fp64 or fp32) to ssnalm_create.  X: n x q row-major (dtype F64, F32 or
+ * BF16), Z: output, row-major, z_dtype F64 or F32; all device pointers.
+ * Both calls run on `stream` (hipStream_t or NULL) and return when done.
+ * ---------------------------------------------------------------------- */
+
+/* Random Fourier features: W holds N frequencies (N x q doubles, device),
+ * drawn by the caller from the Gaussian with covariance I / alpha (the
+ * spectral density of k).  Z is n x 2N with Z[i][2k] = cos(w_k^T x_i) /
+ * sqrt(N) and Z[i][2k+1] = sin(w_k^T x_i) / sqrt(N), so that Z Z^T is the
+ * average of the N sampled kernels.  Products and cos / sin in fp64.
+ * E_BADARG: null pointer, n, q < 1, N outside [1, 4194240], bad dtype. */
+ssnalm_status ssnalm_rff_features(const void* X, int32_t dtype, int64_t n, int64_t q,
+                                  const double* W, int64_t N, void* Z, int32_t z_dtype,
+                                  void* stream);
+
+/* Nystroem features: landmarks holds r row indices of X (int32, device; the
+ * paper picks them by k-means, any choice is accepted).  Z is n x r with
+ * Z = K_nr L^{-T}, K_nr[i][j] = k(x_i, x_{l_j}), K_rr + shift I = L L^T
+ * (the paper's shift is 1e-3), so Z Z^T = K_nr (K_rr + shift I)^{-1}
+ * K_nr^T.  fp64 throughout (blocked Cholesky, blocked triangular solve).
+ * Allocates its workspace (about 8 (n + r) r bytes) per call.
+ * E_BADARG: null pointer, r outside [1, 2048], alpha <= 0, shift < 0, a
+ * landmark outside [0, n), K_rr + shift I not positive definite. */
+ssnalm_status ssnalm_nystroem_features(const void* X, int32_t dtype, int64_t n, int64_t q,
+                                       const int32_t* landmarks, int64_t r, double alpha,
+                                       double shift, void* Z, int32_t z_dtype, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned warm start.  The paper starts its exact-kernel solves from a

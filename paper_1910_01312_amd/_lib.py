@@ -73,6 +73,7 @@ EXPORTS = [
     "ssnalm_mlp_forward", "ssnalm_mlp_backward", "ssnalm_mlp_adam", "ssnalm_ws_features",
     "ssnalm_ws_x0", "ssnalm_ws_solve", "ssnalm_set_profile", "ssnalm_ws_labels",
     "ssnalm_project_noalloc", "ssnalm_noalloc_max_n", "ssnalm_noalloc_scratch_bytes",
+    "ssnalm_rff_features", "ssnalm_nystroem_features",
 ]
 
 _lib = None
@@ -142,6 +143,10 @@ def load(path: str | None = None):
     lib.ssnalm_noalloc_max_n.restype = i64
     lib.ssnalm_noalloc_scratch_bytes.argtypes = []
     lib.ssnalm_noalloc_scratch_bytes.restype = i64
+    lib.ssnalm_rff_features.argtypes = [vp, i32, i64, i64, vp, i64, vp, i32, vp]
+    lib.ssnalm_rff_features.restype = i32
+    lib.ssnalm_nystroem_features.argtypes = [vp, i32, i64, i64, vp, i64, dbl, dbl, vp, i32, vp]
+    lib.ssnalm_nystroem_features.restype = i32
     lib.ssnalm_ws_labels.argtypes = [vp, vp, vp, vp]
     lib.ssnalm_ws_labels.restype = i32
     lib.ssnalm_ws_x0.argtypes = [vp, vp, vp]

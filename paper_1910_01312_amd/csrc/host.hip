@@ -29,6 +29,10 @@
 
 using namespace ssn;
 
+namespace ssn {
+thread_local KTimeSink* g_ktime = nullptr;
+}
+
 // ---------------------------------------------------------------- errors
 static thread_local std::string g_err;
 
@@ -141,10 +145,18 @@ struct ssnalm_ctx {
     int proj_capped = 0;             // projections that ended at the pass cap
     long long last_nsv = -1;         // support rows of the current x~ (for byte counts)
     // kernel profiling (opt.profile): HIP event pairs around the hot launches
-    struct Pending { int cls; hipEvent_t a, b; double bytes, flops; };
+    // one timed kernel: its event pair; `first` marks the first kernel of a
+    // class launch, which carries the launch's bytes and flops
+    struct Pending { int cls; hipEvent_t a, b; double bytes, flops; int cg_iter; bool first; };
+    int cg_iter = -1;                // CG iteration being launched (-1: outside a CG solve)
+    struct Sink : KTimeSink {
+        ssnalm_ctx* c = nullptr;
+        int cls = 0;
+        size_t group = 0;            // index in pend of the class launch's first kernel
+        void pair(hipEvent_t* start, hipEvent_t* stop) override;
+    } sink;
     std::vector<hipEvent_t> ev_free;
     std::vector<Pending> pend;
-    hipEvent_t ev_cur = nullptr;
     ssnalm_kstat kst[SSNALM_K_COUNT] = {};
 };
 
@@ -191,46 +203,81 @@ static ssnalm_status sync_state(ssnalm_ctx* c) {
 static hipEvent_t ev_get(ssnalm_ctx* c) {
     if (c->ev_free.empty()) {
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         return e;
     }
     hipEvent_t e = c->ev_free.back();
     c->ev_free.pop_back();
     return e;
 }
+// After a CG solve whose first `worked` iterations changed x: launches of
+// its later iterations passed through (the kernels saw the converged flag)
+// and are dropped from the statistics, so a class's bytes and time cover
+// only launches that did the work counted in their bytes.
+static void prof_drop_idle_cg(ssnalm_ctx* c, int worked) {
+    std::vector<ssnalm_ctx::Pending> keep;
+    keep.reserve(c->pend.size());
+    for (auto& p : c->pend) {
+        if (p.cg_iter >= worked) {
+            if (p.a) c->ev_free.push_back(p.a);
+            if (p.b) c->ev_free.push_back(p.b);
+        } else {
+            p.cg_iter = -1;
+            keep.push_back(p);
+        }
+    }
+    c->pend.swap(keep);
+}
+// A class launch's time is the sum of its kernels' execution times (each
+// kernel bracketed by its own dispatch-attached event pair); gaps between
+// the kernels are not counted.
 static void prof_harvest(ssnalm_ctx* c) {
     for (auto& p : c->pend) {
         float ms = 0.f;
-        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        if (p.a && p.b && hipEventSynchronize(p.b) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             ssnalm_kstat& k = c->kst[p.cls];
-            k.launches += 1;
+            if (p.first) k.launches += 1;
             k.seconds += 1e-3 * (double)ms;
             k.bytes += p.bytes;
             k.flops += p.flops;
         }
-        c->ev_free.push_back(p.a);
-        c->ev_free.push_back(p.b);
+        if (p.a) c->ev_free.push_back(p.a);
+        if (p.b) c->ev_free.push_back(p.b);
     }
     c->pend.clear();
 }
+void ssnalm_ctx::Sink::pair(hipEvent_t* start, hipEvent_t* stop) {
+    *start = ev_get(c);
+    *stop = ev_get(c);
+    c->pend.push_back({cls, *start, *stop, 0.0, 0.0, c->cg_iter, c->pend.size() == group});
+}
 // opt.profile: 1 times every class; a value > 1 is a mask, bit (k + 1) for class k.
+// The CG's classes are sampled, one iteration in eight (iterations 3, 11,
+// ...): an event pair costs a few microseconds on a ~15 us kernel, and
+// timing all ~1700 launches per solve would slow the solve by ~15%.
 static bool prof_on(const ssnalm_ctx* c, int cls) {
     const int p = c->opt.profile;
-    return p == 1 || (p > 1 && ((p >> (cls + 1)) & 1));
+    const bool on = p == 1 || (p > 1 && ((p >> (cls + 1)) & 1));
+    if (on && c->cg_iter >= 0 && (cls == SSNALM_K_AMUL_J || cls == SSNALM_K_ATMUL_J))
+        return (c->cg_iter & 7) == 3;
+    return on;
 }
 static void prof_begin(ssnalm_ctx* c, int cls) {
     if (!prof_on(c, cls)) return;
-    c->ev_cur = ev_get(c);
-    if (c->ev_cur) hipEventRecord(c->ev_cur, c->st);
+    c->sink.c = c;
+    c->sink.cls = cls;
+    c->sink.group = c->pend.size();
+    g_ktime = &c->sink;
 }
 static void prof_end(ssnalm_ctx* c, int cls, double bytes, double flops) {
-    if (!prof_on(c, cls) || !c->ev_cur) return;
-    hipEvent_t b = ev_get(c);
-    if (!b) return;
-    hipEventRecord(b, c->st);
-    c->pend.push_back({cls, c->ev_cur, b, bytes, flops});
-    c->ev_cur = nullptr;
-    if (c->pend.size() >= 8192) prof_harvest(c);
+    if (!prof_on(c, cls) || g_ktime != &c->sink) return;
+    g_ktime = nullptr;
+    if (c->pend.size() > c->sink.group) {
+        c->pend[c->sink.group].bytes += bytes;
+        c->pend[c->sink.group].flops += flops;
+    }
+    if (c->pend.size() >= 8192 && c->cg_iter < 0) prof_harvest(c);
 }
 static double elem_bytes(int dtype) { return dtype == SSNALM_F64 ? 8.0 : (dtype == SSNALM_F32 ? 4.0 : 2.0); }
 // algorithmic bytes of A v over all rows and of A^T z over `rows` rows
@@ -446,12 +493,17 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         while (it < c->opt.max_cg && (first || !c->hs->sc.cg_done)) {
             first = false;
             const int batch = std::min(kCgBatch, c->opt.max_cg - it);
-            for (int b = 0; b < batch; ++b) cg_iteration(b & 1);
+            for (int b = 0; b < batch; ++b) {
+                c->cg_iter = it + b;
+                cg_iteration(b & 1);
+            }
             it += batch;
+            c->cg_iter = -1;
             STCHK(sync_state(c));
         }
         if (first) STCHK(sync_state(c));   // no batch ran (max_cg = 0)
         *cg_iters = c->hs->sc.cg_count;     // iterations that did work (a batch may end early)
+        prof_drop_idle_cg(c, *cg_iters);
         HIPCHK(hipMemcpyAsync(d, c->cg_x, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
         return SSNALM_OK;
     }

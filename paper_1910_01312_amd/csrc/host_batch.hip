@@ -89,7 +89,7 @@ struct Batch {
     std::vector<char> built;       // active set of the current work list (empty: none)
     // HIP-event timing of the full-pass A v launches (profile = 1)
     bool prof = false;
-    struct Pend { hipEvent_t a, b; double bytes; };
+    struct Pend { hipEvent_t a, b; double bytes; int first; };
     std::vector<Pend> pend;
     std::vector<hipEvent_t> evpool;
     ~Batch() {
@@ -156,7 +156,7 @@ ssnalm_status readback(Batch& B) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, p.a, p.b);
         ssnalm_kstat& k = g_bks[SSNALM_K_AMUL];
-        k.launches += 1;
+        k.launches += p.first;
         k.seconds += 1e-3 * ms;
         k.bytes += p.bytes;
         B.evpool.push_back(p.a);
@@ -173,7 +173,7 @@ hipEvent_t ev_get(Batch& B) {
         return e;
     }
     hipEvent_t e = nullptr;
-    hipEventCreate(&e);
+    hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
 }
 
@@ -188,11 +188,25 @@ void timed_amul(Batch& B, const std::vector<char>& act, const double* V, double*
     double bytes = 0.0;
     for (int k = 0; k < B.nprob; ++k)
         if (act[k]) bytes += (double)B.hprob[k].n * (B.q * esz + 1.0 + 8.0) + 8.0 * B.q;
-    Batch::Pend p{ev_get(B), ev_get(B), bytes};
-    hipEventRecord(p.a, B.s);
+    // each kernel of the launch gets a dispatch-attached event pair (its own
+    // execution time); the launch's bytes ride on the first pair
+    struct S : KTimeSink {
+        Batch* B;
+        double bytes;
+        int first = 1;
+        void pair(hipEvent_t* a, hipEvent_t* b) override {
+            *a = ev_get(*B);
+            *b = ev_get(*B);
+            B->pend.push_back(Batch::Pend{*a, *b, bytes, first});
+            bytes = 0.0;
+            first = 0;
+        }
+    } sink;
+    sink.B = &B;
+    sink.bytes = bytes;
+    g_ktime = &sink;
     lb_amul(B.L, V, t);
-    hipEventRecord(p.b, B.s);
-    B.pend.push_back(p);
+    g_ktime = nullptr;
 }
 
 // Newton direction for the active problems: J compaction, Gram, M,

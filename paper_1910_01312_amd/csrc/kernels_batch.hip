@@ -1136,7 +1136,7 @@ __global__ __launch_bounds__(1024) void kb_chol(BArgs A, const double* __restric
 template <typename T, int P>
 static void amul2_t(const BLaunch& L, const double* V, double* t) {
     constexpr int R = P < 8 ? P : 8;
-    hipLaunchKernelGGL((kb_amul2<T, P, R>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
+    SSN_LAUNCH((kb_amul2<T, P, R>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
 }
 template <typename T, bool VEC>
 static void amul_t(const BLaunch& L, const double* V, double* t) {
@@ -1158,19 +1158,19 @@ static void amul_t(const BLaunch& L, const double* V, double* t) {
         }
     }
     if (L.unr == 1)
-        hipLaunchKernelGGL((kb_amul<T, VEC, 1>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
+        SSN_LAUNCH((kb_amul<T, VEC, 1>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
     else if (L.unr == 2)
-        hipLaunchKernelGGL((kb_amul<T, VEC, 2>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
+        SSN_LAUNCH((kb_amul<T, VEC, 2>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
     else
-        hipLaunchKernelGGL((kb_amul<T, VEC, 4>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
+        SSN_LAUNCH((kb_amul<T, VEC, 4>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, V, t);
 }
 template <typename T, bool VEC>
 static void atmul_t(const BLaunch& L, const double* z, const uint8_t* mask) {
     if (mask)
-        hipLaunchKernelGGL((kb_atmul<T, VEC, true>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, z,
+        SSN_LAUNCH((kb_atmul<T, VEC, true>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, z,
                            mask, L.part, L.part2);
     else
-        hipLaunchKernelGGL((kb_atmul<T, VEC, false>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, z,
+        SSN_LAUNCH((kb_atmul<T, VEC, false>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, z,
                            mask, L.part, L.part2);
 }
 #define BDISPATCH(FN, ...)                                                                  \
@@ -1187,70 +1187,70 @@ static void atmul_t(const BLaunch& L, const double* z, const uint8_t* mask) {
 static inline unsigned pgrid(int n) { return (unsigned)((n + 63) / 64); }
 
 void lb_build_wl(const BLaunch& L, const int4* items) {
-    hipLaunchKernelGGL(kb_wl_scan, dim3(1), dim3(1024), 0, L.s, L.A);
-    hipLaunchKernelGGL(kb_wl_copy, dim3(L.A.nprob), dim3(256), 0, L.s, L.A, items);
+    SSN_LAUNCH(kb_wl_scan, dim3(1), dim3(1024), 0, L.s, L.A);
+    SSN_LAUNCH(kb_wl_copy, dim3(L.A.nprob), dim3(256), 0, L.s, L.A, items);
 }
 void lb_amul(const BLaunch& L, const double* V, double* t) { BDISPATCH(amul_t, L, V, t); }
 void lb_atmul(const BLaunch& L, const double* z, const uint8_t* mask, const double* base,
               double sign, double* out, double* out2) {
     BDISPATCH(atmul_t, L, z, mask);
-    hipLaunchKernelGGL(kb_atmul_fin, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, L.part,
+    SSN_LAUNCH(kb_atmul_fin, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, L.part,
                        mask ? L.part2 : nullptr, base, sign, out, mask ? out2 : nullptr);
 }
 void lb_elem(const BLaunch& L, int mode, const double* a, const double* b, double* o) {
-    hipLaunchKernelGGL(kb_elem, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, mode, a, b, o);
+    SSN_LAUNCH(kb_elem, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, mode, a, b, o);
 }
 void lb_accept(const BLaunch& L, double* om, const double* d, double* aw, const double* td,
                double* u, const double* ut, double* xt, const double* xtt, uint8_t* jm,
                const uint8_t* jmt) {
-    hipLaunchKernelGGL(kb_qvec, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, 0, om, d, om);
-    hipLaunchKernelGGL(kb_accept_n, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, aw, td, u, ut, xt,
+    SSN_LAUNCH(kb_qvec, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, 0, om, d, om);
+    SSN_LAUNCH(kb_accept_n, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, aw, td, u, ut, xt,
                        xtt, jm, jmt);
 }
 void lb_qvec(const BLaunch& L, int mode, const double* a, const double* b, double* o) {
-    hipLaunchKernelGGL(kb_qvec, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, mode, a, b, o);
+    SSN_LAUNCH(kb_qvec, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, mode, a, b, o);
 }
 void lb_qdots(const BLaunch& L, int npair, const double* a0, const double* b0, const double* a1,
               const double* b1, const double* a2, const double* b2, int f0) {
-    hipLaunchKernelGGL(kb_qdots, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, npair, a0, b0, a1, b1,
+    SSN_LAUNCH(kb_qdots, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, npair, a0, b0, a1, b1,
                        a2, b2, f0);
 }
 void lb_proj_init(const BLaunch& L, const double* u, const double* td, double* vout, int w,
                   int use_hint) {
     if (td)
-        hipLaunchKernelGGL((kb_proj_init<true>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, u, td,
+        SSN_LAUNCH((kb_proj_init<true>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, u, td,
                            vout, L.part);
     else
-        hipLaunchKernelGGL((kb_proj_init<false>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, u, td,
+        SSN_LAUNCH((kb_proj_init<false>), dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, u, td,
                            vout, L.part);
-    hipLaunchKernelGGL(kb_proj_init_fin, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, w,
+    SSN_LAUNCH(kb_proj_init_fin, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, w,
                        use_hint);
 }
 void lb_proj_passes(const BLaunch& L, const double* v, int w, int npass) {
     for (int i = 0; i < npass; ++i) {
-        hipLaunchKernelGGL(kb_proj_pass, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, w, L.part,
+        SSN_LAUNCH(kb_proj_pass, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, w, L.part,
                            L.ipart);
-        hipLaunchKernelGGL(kb_proj_sel, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, L.part, L.ipart, w);
+        SSN_LAUNCH(kb_proj_sel, dim3(L.A.nprob), dim3(128), 0, L.s, L.A, L.part, L.ipart, w);
     }
 }
 void lb_ls_fin(const BLaunch& L, const double* v, const double* ubase, const double* td, int w,
                int wb, const double* xk, double* x, uint8_t* mask) {
-    hipLaunchKernelGGL(kb_ls_fin, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, ubase, td, w, wb,
+    SSN_LAUNCH(kb_ls_fin, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, ubase, td, w, wb,
                        xk, x, mask, L.part);
-    hipLaunchKernelGGL(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_DH, 4);
+    SSN_LAUNCH(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_DH, 4);
 }
 void lb_kkt_fin(const BLaunch& L, const double* v, const double* x, const double* Qx, int w) {
-    hipLaunchKernelGGL(kb_kkt_fin, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, x, Qx, w, L.part);
-    hipLaunchKernelGGL(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_RES2, 4);
+    SSN_LAUNCH(kb_kkt_fin, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, v, x, Qx, w, L.part);
+    SSN_LAUNCH(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_RES2, 4);
 }
 void lb_count(const BLaunch& L, const double* x) {
-    hipLaunchKernelGGL(kb_count, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, x, L.part);
-    hipLaunchKernelGGL(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_FSUMX, 3);
+    SSN_LAUNCH(kb_count, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, x, L.part);
+    SSN_LAUNCH(kb_sum4, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.part, (int)BS_FSUMX, 3);
 }
 void lb_compact(const BLaunch& L, const uint8_t* mask, int32_t* list) {
-    hipLaunchKernelGGL(kb_cmp_count, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, mask, L.ipart);
-    hipLaunchKernelGGL(kb_cmp_scan, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.ipart, L.ipart2);
-    hipLaunchKernelGGL(kb_cmp_write, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, mask, L.ipart2, list);
+    SSN_LAUNCH(kb_cmp_count, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, mask, L.ipart);
+    SSN_LAUNCH(kb_cmp_scan, dim3(pgrid(L.A.nprob)), dim3(64), 0, L.s, L.A, L.ipart, L.ipart2);
+    SSN_LAUNCH(kb_cmp_write, dim3(L.grid), dim3(SSN_BLOCK), 0, L.s, L.A, mask, L.ipart2, list);
 }
 void lb_setup_attributes() {
     static bool done = false;
@@ -1261,19 +1261,19 @@ void lb_setup_attributes() {
 }
 void lb_newton(const BLaunch& L, const int32_t* list, const double* sv, const double* g, double* d,
                double* M) {
-    hipLaunchKernelGGL(kb_gram_plan, dim3(1), dim3(1024), 0, L.s, L.A, L.gwl, L.gwl_n, L.goff, L.gcnt);
+    SSN_LAUNCH(kb_gram_plan, dim3(1), dim3(1024), 0, L.s, L.A, L.gwl, L.gwl_n, L.goff, L.gcnt);
     if (L.dtype == SSNALM_F64)
-        hipLaunchKernelGGL(kb_gram<double>, dim3(L.ggrid), dim3(SSN_BLOCK), 0, L.s, L.A, L.gwl,
+        SSN_LAUNCH(kb_gram<double>, dim3(L.ggrid), dim3(SSN_BLOCK), 0, L.s, L.A, L.gwl,
                            L.gwl_n, list, L.gpart);
     else if (L.dtype == SSNALM_F32)
-        hipLaunchKernelGGL(kb_gram<float>, dim3(L.ggrid), dim3(SSN_BLOCK), 0, L.s, L.A, L.gwl,
+        SSN_LAUNCH(kb_gram<float>, dim3(L.ggrid), dim3(SSN_BLOCK), 0, L.s, L.A, L.gwl,
                            L.gwl_n, list, L.gpart);
     else
-        hipLaunchKernelGGL(kb_gram<bf16_t>, dim3(L.ggrid), dim3(SSN_BLOCK), 0, L.s, L.A, L.gwl,
+        SSN_LAUNCH(kb_gram<bf16_t>, dim3(L.ggrid), dim3(SSN_BLOCK), 0, L.s, L.A, L.gwl,
                            L.gwl_n, list, L.gpart);
-    hipLaunchKernelGGL(kb_gram_fin, dim3(L.A.nprob), dim3(SSN_BLOCK), 0, L.s, L.A, L.gpart, L.goff,
+    SSN_LAUNCH(kb_gram_fin, dim3(L.A.nprob), dim3(SSN_BLOCK), 0, L.s, L.A, L.gpart, L.goff,
                        L.gcnt, sv, M);
-    hipLaunchKernelGGL(kb_chol, dim3(L.A.nprob), dim3(L.A.q <= 64 ? 256 : 1024),
+    SSN_LAUNCH(kb_chol, dim3(L.A.nprob), dim3(L.A.q <= 64 ? 256 : 1024),
                        (size_t)L.A.q * L.A.q * sizeof(double), L.s, L.A, M, g, d);
 }
 

@@ -145,10 +145,10 @@ void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double*
                     double* Pw, const Scalars* sc, hipStream_t s) {
     const unsigned g = cg_rows_grid(p);
     if (F.val_f64)
-        hipLaunchKernelGGL((k_cg_rows<double>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
+        SSN_LAUNCH((k_cg_rows<double>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
                            (const double*)F.val, p, v, w, Pw, sc);
     else
-        hipLaunchKernelGGL((k_cg_rows<float>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
+        SSN_LAUNCH((k_cg_rows<float>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
                            (const float*)F.val, p, v, w, Pw, sc);
 }
 
@@ -358,14 +358,14 @@ int64_t keyed_chunks(int64_t nnz) { return (nnz + KCH - 1) / KCH; }
 void launch_fix_flags(const int32_t* jc, const long long* nnzj_dev, int64_t nchmax, uint8_t* flag,
                       hipStream_t s) {
     if (nchmax <= 0) return;
-    hipLaunchKernelGGL(k_fix_flags, dim3((unsigned)((nchmax + 255) / 256)), dim3(256), 0, s, jc,
+    SSN_LAUNCH(k_fix_flags, dim3((unsigned)((nchmax + 255) / 256)), dim3(256), 0, s, jc,
                        nnzj_dev, nchmax, flag);
 }
 
 void launch_fix_ends(const int32_t* jc, int64_t nnzj, KeyedFix& fx, hipStream_t s) {
     if (fx.nfix <= 0) return;
     const unsigned nb = (unsigned)((fx.nfix + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
-    hipLaunchKernelGGL(k_fix_ends, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, keyed_chunks(nnzj),
+    SSN_LAUNCH(k_fix_ends, dim3(nb), dim3(SSN_BLOCK), 0, s, jc, nnzj, keyed_chunks(nnzj),
                        fx.list, fx.nfix, fx.fend, fx.fcol);
 }
 
@@ -376,7 +376,7 @@ void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void*
     if (nnzj <= 0) return;
     const int64_t nch = (nnzj + KCH - 1) / KCH;
     const unsigned nb = (unsigned)((nch + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
-#define KT(V, M) hipLaunchKernelGGL((k_keyed_tr<V, M>), dim3(nb), dim3(SSN_BLOCK), 0, s, jr, jc, \
+#define KT(V, M) SSN_LAUNCH((k_keyed_tr<V, M>), dim3(nb), dim3(SSN_BLOCK), 0, s, jr, jc, \
                                     (const V*)jv, nnzj, w, carry, out, skip)
     if (val_f64) {
         if (mode == 0) KT(double, 0); else if (mode == 1) KT(double, 1); else KT(double, 2);
@@ -386,7 +386,7 @@ void launch_keyed_tr(int mode, const int32_t* jr, const int32_t* jc, const void*
 #undef KT
     if (fx.nfix > 0) {
         const unsigned nf = (unsigned)((fx.nfix + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK);
-        hipLaunchKernelGGL(k_keyed_fix_list, dim3(nf), dim3(SSN_BLOCK), 0, s, fx.list, fx.fend,
+        SSN_LAUNCH(k_keyed_fix_list, dim3(nf), dim3(SSN_BLOCK), 0, s, fx.list, fx.fend,
                            fx.fcol, fx.nfix, carry, out, skip);
     }
 }
@@ -502,20 +502,20 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_dir(double* __restrict__ pd,
 
 void launch_cg_init(const double* g, const double* diag, const double* sv, int64_t q, double* x,
                     double* r, double* z, double* pd, double* Pst, double* Pdir, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, g, diag, sv, q, x, r, z, pd,
+    SSN_LAUNCH(k_cg_init, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, g, diag, sv, q, x, r, z, pd,
                        Pst, Pdir);
 }
 void launch_cg_step(double* x, double* r, const double* pd, const double* t, const double* sv,
                     const double* diag, double* z, int64_t q, double sigma, int64_t p,
                     const double* Pw, int nbw, const double* Pdir, const double* Pold, double* Pnew,
                     double tol2, const Scalars* sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_step, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, x, r, pd, t, sv, diag, z, q,
+    SSN_LAUNCH(k_cg_step, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, x, r, pd, t, sv, diag, z, q,
                        sigma, p > 0 ? 1.0 / (double)p : 0.0, Pw, nbw, Pdir, Pold, Pnew, tol2, sc);
 }
 void launch_cg_dir(double* pd, const double* z, const double* sv, int64_t q, const double* Pold,
                    const double* Pnew, double* Pdir, double tol2, Scalars* sc, double* tz,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_dir, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, pd, z, sv, q, Pold, Pnew,
+    SSN_LAUNCH(k_cg_dir, dim3(qgrid(q)), dim3(SSN_BLOCK), 0, s, pd, z, sv, q, Pold, Pnew,
                        Pdir, tol2, sc, tz);
 }
 
@@ -530,7 +530,7 @@ __global__ void k_cg_publish(const double* __restrict__ Pst, int nbq, double tol
     }
 }
 void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_publish, dim3(1), dim3(SSN_BLOCK), 0, s, Pst, (int)qgrid(q), tol2, sc);
+    SSN_LAUNCH(k_cg_publish, dim3(1), dim3(SSN_BLOCK), 0, s, Pst, (int)qgrid(q), tol2, sc);
 }
 
 }  // namespace ssn

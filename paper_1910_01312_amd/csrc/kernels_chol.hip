@@ -342,11 +342,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_chol_solve2(const double* __r
 void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s) {
     const int nblk = (int)((q + NB - 1) / NB);
     for (int kb = 0; kb < nblk; ++kb) {
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv, sc);
+        SSN_LAUNCH(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv, sc);
         const int nt = nblk - kb - 1;
         if (nt > 0) {
-            hipLaunchKernelGGL(k_chol_panel, dim3(nt), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv);
-            hipLaunchKernelGGL(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(SSN_BLOCK), 0, s, M,
+            SSN_LAUNCH(k_chol_panel, dim3(nt), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv);
+            SSN_LAUNCH(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(SSN_BLOCK), 0, s, M,
                                (int)q, kb);
         }
     }
@@ -354,7 +354,7 @@ void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, 
 
 void launch_chol_solve_factored(const double* M, const double* inv, const double* g, double* d,
                                 int64_t q, hipStream_t s) {
-    hipLaunchKernelGGL(k_chol_solve2, dim3(1), dim3(SOLVE_THREADS), (size_t)q * sizeof(double), s, M,
+    SSN_LAUNCH(k_chol_solve2, dim3(1), dim3(SOLVE_THREADS), (size_t)q * sizeof(double), s, M,
                        inv, g, d, (int)q);
 }
 

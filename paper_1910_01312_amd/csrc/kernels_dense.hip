@@ -151,7 +151,7 @@ static void amul_dispatch_rows(const T* X, const int8_t* y, const double* v, dou
         int64_t blocks = (n + R * SSN_WAVES_PER_BLOCK - 1) / (R * SSN_WAVES_PER_BLOCK);
         if (blocks > 8192) blocks = 8192;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL((k_amul_rows<T, VEC, R>), dim3((unsigned)blocks), dim3(SSN_BLOCK), 0, s,
+        SSN_LAUNCH((k_amul_rows<T, VEC, R>), dim3((unsigned)blocks), dim3(SSN_BLOCK), 0, s,
                            X, y, v, t, n, q);
         return;
       }
@@ -163,7 +163,7 @@ static void amul_dispatch_rows(const T* X, const int8_t* y, const double* v, dou
     int64_t blocks = (n + rows_per_wave * SSN_WAVES_PER_BLOCK - 1) / (rows_per_wave * SSN_WAVES_PER_BLOCK);
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_amul_dense<T, VEC, 4>), dim3((unsigned)blocks), dim3(SSN_BLOCK), shm, s,
+    SSN_LAUNCH((k_amul_dense<T, VEC, 4>), dim3((unsigned)blocks), dim3(SSN_BLOCK), shm, s,
                        X, y, v, t, n, q, use_lds);
 }
 
@@ -355,13 +355,13 @@ static void atmul_dispatch(const T* X, const int8_t* y, const double* z, const u
         if (q <= (int64_t)SSN_WAVE * VEC) {            // one piece per lane covers a row
             constexpr int R = 8;
             if (mask && mm == 2)
-                hipLaunchKernelGGL((k_atmul_rows<T, VEC, R, 2>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
+                SSN_LAUNCH((k_atmul_rows<T, VEC, R, 2>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
                                    s, X, y, z, mask, n, q, rows_per_blk, part, part2);
             else if (mask)
-                hipLaunchKernelGGL((k_atmul_rows<T, VEC, R, 1>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
+                SSN_LAUNCH((k_atmul_rows<T, VEC, R, 1>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
                                    s, X, y, z, mask, n, q, rows_per_blk, part, part2);
             else
-                hipLaunchKernelGGL((k_atmul_rows<T, VEC, R, 0>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
+                SSN_LAUNCH((k_atmul_rows<T, VEC, R, 0>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0,
                                    s, X, y, z, mask, n, q, rows_per_blk, part, part2);
             return;
         }
@@ -371,13 +371,13 @@ static void atmul_dispatch(const T* X, const int8_t* y, const double* z, const u
     const int64_t ty = (q + tile_cols - 1) / tile_cols;
     dim3 grid((unsigned)nb, (unsigned)ty);
     if (mask && mm == 2)
-        hipLaunchKernelGGL((k_atmul_dense<T, VEC, NCH, 2>), grid, dim3(SSN_BLOCK), 0, s, X, y,
+        SSN_LAUNCH((k_atmul_dense<T, VEC, NCH, 2>), grid, dim3(SSN_BLOCK), 0, s, X, y,
                            z, mask, n, q, rows_per_blk, part, part2);
     else if (mask)
-        hipLaunchKernelGGL((k_atmul_dense<T, VEC, NCH, 1>), grid, dim3(SSN_BLOCK), 0, s, X, y,
+        SSN_LAUNCH((k_atmul_dense<T, VEC, NCH, 1>), grid, dim3(SSN_BLOCK), 0, s, X, y,
                            z, mask, n, q, rows_per_blk, part, part2);
     else
-        hipLaunchKernelGGL((k_atmul_dense<T, VEC, NCH, 0>), grid, dim3(SSN_BLOCK), 0, s, X, y,
+        SSN_LAUNCH((k_atmul_dense<T, VEC, NCH, 0>), grid, dim3(SSN_BLOCK), 0, s, X, y,
                            z, mask, n, q, rows_per_blk, part, part2);
 }
 
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_reduce_cols(const double* __restr
 void launch_reduce_cols(const double* part, int nblk, int64_t q, const double* base, double sign,
                         double* out, hipStream_t s) {
     const unsigned blocks = (unsigned)((q + SSN_WAVE - 1) / SSN_WAVE);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(blocks), dim3(SSN_BLOCK), 0, s, part, nblk, q, base,
+    SSN_LAUNCH(k_reduce_cols, dim3(blocks), dim3(SSN_BLOCK), 0, s, part, nblk, q, base,
                        sign, out);
 }
 

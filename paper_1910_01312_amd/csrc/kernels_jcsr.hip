@@ -41,7 +41,7 @@ void launch_rank_from_list(const int32_t* list, const long long* pdev, int64_t n
                            const int32_t* rp, int2* jrow, hipStream_t s) {
     int64_t b = (n + 255) / 256;
     if (b > 2048) b = 2048;
-    hipLaunchKernelGGL(k_rank_from_list, dim3((unsigned)b), dim3(256), 0, s, list, pdev, rank, rp,
+    SSN_LAUNCH(k_rank_from_list, dim3((unsigned)b), dim3(256), 0, s, list, pdev, rank, rp,
                        jrow);
 }
 
@@ -292,16 +292,16 @@ static void jcsc_build_t(const SegPlan& T, const void* tcv, const uint32_t* bits
     if (LDS && shm > 0) per_cu = std::max(1, std::min(2, (int)((160 * 1024) / shm)));
     int64_t nb = (T.ntile + JWAVES - 1) / JWAVES;
     if (nb > (int64_t)per_cu * ncu) nb = (int64_t)per_cu * ncu;
-    hipLaunchKernelGGL((k_jcsc_count<LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s, T.idx, T.nnz,
+    SSN_LAUNCH((k_jcsc_count<LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s, T.idx, T.nnz,
                        T.ntile, bits, nw, tcount);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)((T.ntile + SCAN_CHUNK - 1) / SCAN_CHUNK)), dim3(1024),
+    SSN_LAUNCH(k_scan_tiles, dim3((unsigned)((T.ntile + SCAN_CHUNK - 1) / SCAN_CHUNK)), dim3(1024),
                        0, s, tcount, T.ntile, toff, total);
     if (T.val_f64)
-        hipLaunchKernelGGL((k_jcsc_write<double, ColValD, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
+        SSN_LAUNCH((k_jcsc_write<double, ColValD, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
                            (const ColValD*)tcv, T.idx, T.nnz, T.ntile, bits, nw, rank, toff,
                            jr, jc, (double*)jv);
     else
-        hipLaunchKernelGGL((k_jcsc_write<float, ColValF, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
+        SSN_LAUNCH((k_jcsc_write<float, ColValF, LDS>), dim3((unsigned)nb), dim3(JBLOCK), shm, s,
                            (const ColValF*)tcv, T.idx, T.nnz, T.ntile, bits, nw, rank, toff,
                            jr, jc, (float*)jv);
 }
@@ -312,7 +312,7 @@ void launch_jcsc_build(const SegPlan& T, const void* tcv, const uint8_t* mask, i
                        int32_t* jc, void* jv, hipStream_t s) {
     if (T.ntile == 0) return;
     const int nw = jcsc_bits_words(n);
-    hipLaunchKernelGGL(k_mask_bits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mask, n, bits);
+    SSN_LAUNCH(k_mask_bits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mask, n, bits);
     if (jcsc_bits_fit(n))
         jcsc_build_t<true>(T, tcv, bits, nw, rank, tcount, toff, total, jr, jc, jv, s);
     else

@@ -326,14 +326,14 @@ void launch_syrk_mfma(const void* X, int dtype, int64_t q, const int32_t* list, 
     int64_t rps = (p + ns - 1) / ns;
     if (q % 8 == 0) {
         rps = (rps + KC2 - 1) / KC2 * KC2;
-        hipLaunchKernelGGL(k_syrk_mfma16, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
+        SSN_LAUNCH(k_syrk_mfma16, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
                            (const bf16_t*)X, q, list, p, rps, part);
     } else {
         rps = (rps + KC - 1) / KC * KC;
-        hipLaunchKernelGGL(k_syrk_mfma, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
+        SSN_LAUNCH(k_syrk_mfma, dim3((unsigned)ntile, (unsigned)ns), dim3(SSN_BLOCK), 0, s,
                            (const bf16_t*)X, q, list, p, rps, part);
     }
-    hipLaunchKernelGGL(k_syrk_mfma_reduce, dim3((unsigned)(ntile * RED_BLOCKS)), dim3(SSN_BLOCK), 0, s,
+    SSN_LAUNCH(k_syrk_mfma_reduce, dim3((unsigned)(ntile * RED_BLOCKS)), dim3(SSN_BLOCK), 0, s,
                        part, ntile, (int)ns, G, q);
 }
 
@@ -388,19 +388,19 @@ void launch_dense_rows(int dtype, const void* X, int64_t q, const int32_t* list,
     const uintptr_t a = (uintptr_t)X;
     if (dtype == SSNALM_F64) {
         if ((q * 8) % 16 == 0 && a % 16 == 0)
-            hipLaunchKernelGGL((k_dense_rows<double, 2>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
+            SSN_LAUNCH((k_dense_rows<double, 2>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
         else
-            hipLaunchKernelGGL((k_dense_rows<double, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
+            SSN_LAUNCH((k_dense_rows<double, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
     } else if (dtype == SSNALM_F32) {
         if ((q * 4) % 16 == 0 && a % 16 == 0)
-            hipLaunchKernelGGL((k_dense_rows<float, 4>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
+            SSN_LAUNCH((k_dense_rows<float, 4>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
         else
-            hipLaunchKernelGGL((k_dense_rows<float, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
+            SSN_LAUNCH((k_dense_rows<float, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
     } else {
         if ((q * 2) % 16 == 0 && a % 16 == 0)
-            hipLaunchKernelGGL((k_dense_rows<bf16_t, 8>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
+            SSN_LAUNCH((k_dense_rows<bf16_t, 8>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
         else
-            hipLaunchKernelGGL((k_dense_rows<bf16_t, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
+            SSN_LAUNCH((k_dense_rows<bf16_t, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
     }
 }
 
@@ -427,7 +427,7 @@ void launch_scatter_centered(const int32_t* list, int64_t p, const double* w, co
     int64_t b = (p + 255) / 256;
     if (b > 1024) b = 1024;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_scatter_centered, dim3((unsigned)b), dim3(SSN_BLOCK), 0, s, list, p, w, Pw,
+    SSN_LAUNCH(k_scatter_centered, dim3((unsigned)b), dim3(SSN_BLOCK), 0, s, list, p, w, Pw,
                        nbw, y, z);
 }
 
@@ -440,7 +440,7 @@ __global__ void k_refine_res(const double* __restrict__ g, const double* __restr
 }
 void launch_refine_res(const double* g, const double* d, const double* t, double sigma, double* rn,
                        int64_t q, hipStream_t s) {
-    hipLaunchKernelGGL(k_refine_res, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, g, d, t,
+    SSN_LAUNCH(k_refine_res, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, g, d, t,
                        sigma, rn, q);
 }
 

@@ -137,15 +137,15 @@ void launch_syrk_gather(int dtype, const void* X, int64_t q, const int32_t* list
     const int64_t rps = (p + nsplit - 1) / nsplit;
     dim3 grid((unsigned)ntile, (unsigned)nsplit);
     if (dtype == SSNALM_F64)
-        hipLaunchKernelGGL((k_syrk_gather<double>), grid, dim3(SSN_BLOCK), 0, s, (const double*)X,
+        SSN_LAUNCH((k_syrk_gather<double>), grid, dim3(SSN_BLOCK), 0, s, (const double*)X,
                            q, list, p, rps, tiles, part);
     else if (dtype == SSNALM_F32)
-        hipLaunchKernelGGL((k_syrk_gather<float>), grid, dim3(SSN_BLOCK), 0, s, (const float*)X, q,
+        SSN_LAUNCH((k_syrk_gather<float>), grid, dim3(SSN_BLOCK), 0, s, (const float*)X, q,
                            list, p, rps, tiles, part);
     else
-        hipLaunchKernelGGL((k_syrk_gather<bf16_t>), grid, dim3(SSN_BLOCK), 0, s, (const bf16_t*)X,
+        SSN_LAUNCH((k_syrk_gather<bf16_t>), grid, dim3(SSN_BLOCK), 0, s, (const bf16_t*)X,
                            q, list, p, rps, tiles, part);
-    hipLaunchKernelGGL(k_syrk_reduce, dim3((unsigned)ntile), dim3(SSN_BLOCK), 0, s, part, ntile,
+    SSN_LAUNCH(k_syrk_reduce, dim3((unsigned)ntile), dim3(SSN_BLOCK), 0, s, part, ntile,
                        (int)nsplit, tiles, G, q);
 }
 
@@ -162,7 +162,7 @@ __global__ void k_form_M(const double* __restrict__ G, const double* __restrict_
 void launch_form_M(const double* G, const double* sv, double sigma, int64_t p, double* M, int64_t q,
                    hipStream_t s) {
     const int64_t tot = q * q;
-    hipLaunchKernelGGL(k_form_M, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, G, sv, sigma,
+    SSN_LAUNCH(k_form_M, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, G, sv, sigma,
                        p > 0 ? 1.0 / (double)p : 0.0, M, q);
 }
 
@@ -242,7 +242,7 @@ void launch_chol_solve_small(const double* M, const double* g, double* d, int64_
                             CHOL_SMALL_MAX * CHOL_SMALL_MAX * (int)sizeof(double));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_chol_solve_small, dim3(1), dim3(q <= 64 ? 256 : 1024), shm, s, M, g, d,
+    SSN_LAUNCH(k_chol_solve_small, dim3(1), dim3(q <= 64 ? 256 : 1024), shm, s, M, g, d,
                        (int)q, sc);
 }
 

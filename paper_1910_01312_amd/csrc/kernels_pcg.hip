@@ -24,7 +24,7 @@ __global__ void k_jacobi_diag(const double* __restrict__ sq, const double* __res
 }
 void launch_jacobi_diag(const double* sq, const double* sv, double sigma, int64_t p, double* diag,
                         int64_t q, hipStream_t s) {
-    hipLaunchKernelGGL(k_jacobi_diag, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, sq, sv,
+    SSN_LAUNCH(k_jacobi_diag, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, sq, sv,
                        sigma, p > 0 ? 1.0 / (double)p : 0.0, diag, q);
 }
 
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_init(const double* __restrict
 void launch_pcg_init(const double* g, const double* diag, double* x, double* r, double* z, double* pd,
                      int64_t q, double tol2, Scalars* sc, double* part, unsigned* counter,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_init, dim3(grid_for(q)), dim3(SSN_BLOCK), 0, s, g, diag, x, r, z, pd, q,
+    SSN_LAUNCH(k_pcg_init, dim3(grid_for(q)), dim3(SSN_BLOCK), 0, s, g, diag, x, r, z, pd, q,
                        tol2, sc, part, counter);
 }
 
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_pap(const double* __restrict_
 }
 void launch_pcg_pap(const double* pd, const double* Ap, int64_t q, Scalars* sc, double* part,
                     unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_pap, dim3(grid_for(q)), dim3(SSN_BLOCK), 0, s, pd, Ap, q, sc, part,
+    SSN_LAUNCH(k_pcg_pap, dim3(grid_for(q)), dim3(SSN_BLOCK), 0, s, pd, Ap, q, sc, part,
                        counter);
 }
 
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_pcg_step(double* __restrict__ x,
 void launch_pcg_step(double* x, double* r, double* pd, const double* Ap, const double* diag,
                      double* z, int64_t q, Scalars* sc, double tol2, double* part,
                      unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_step, dim3(grid_for(q)), dim3(SSN_BLOCK), 0, s, x, r, pd, Ap, diag, z,
+    SSN_LAUNCH(k_pcg_step, dim3(grid_for(q)), dim3(SSN_BLOCK), 0, s, x, r, pd, Ap, diag, z,
                        q, sc, tol2, part, counter);
 }
 
@@ -150,7 +150,7 @@ __global__ void k_pcg_dir(double* __restrict__ pd, const double* __restrict__ z,
     if (j < q) pd[j] = fma(beta, pd[j], z[j]);
 }
 void launch_pcg_dir(double* pd, const double* z, int64_t q, Scalars* sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, pd, z, q, sc);
+    SSN_LAUNCH(k_pcg_dir, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, pd, z, q, sc);
 }
 
 // mean over J of w_i = y_i t_i (t = y .* X p): stored in *mean_out
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_masked_mean(const double* __restr
 }
 void launch_masked_mean(const double* t, const int8_t* y, const uint8_t* mask, int64_t n, int64_t p,
                         double* mean_out, double* part, unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_masked_mean, dim3(grid_for(n)), dim3(SSN_BLOCK), 0, s, t, y, mask, n,
+    SSN_LAUNCH(k_masked_mean, dim3(grid_for(n)), dim3(SSN_BLOCK), 0, s, t, y, mask, n,
                        p > 0 ? 1.0 / (double)p : 0.0, mean_out, part, counter);
 }
 
@@ -191,7 +191,7 @@ __global__ void k_masked_center(const double* __restrict__ t, const int8_t* __re
 }
 void launch_masked_center_t(double* t, const int8_t* y, const uint8_t* mask, int64_t n,
                             const double* mean, double* z, hipStream_t s) {
-    hipLaunchKernelGGL(k_masked_center, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, y,
+    SSN_LAUNCH(k_masked_center, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, y,
                        mask, n, mean, z);
 }
 
@@ -203,7 +203,7 @@ __global__ void k_mop_finish(const double* __restrict__ pd, const double* __rest
 }
 void launch_mop_finish(const double* pd, const double* z, double sigma, const double*, const double*,
                        int64_t, double* Ap, int64_t q, hipStream_t s) {
-    hipLaunchKernelGGL(k_mop_finish, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, pd, z, sigma,
+    SSN_LAUNCH(k_mop_finish, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, pd, z, sigma,
                        Ap, q);
 }
 
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_count_x(const double* __restrict_
 }
 void launch_count_x(const double* x, int64_t n, double C, Scalars* sc, double* part,
                     unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_x, dim3(grid_for(n)), dim3(SSN_BLOCK), 0, s, x, n, C, sc, part,
+    SSN_LAUNCH(k_count_x, dim3(grid_for(n)), dim3(SSN_BLOCK), 0, s, x, n, C, sc, part,
                        counter);
 }
 

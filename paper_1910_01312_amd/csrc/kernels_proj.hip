@@ -139,12 +139,12 @@ void launch_proj_init(const double* u, const double* td, double alpha_sigma, dou
     (void)counter;
     const unsigned g = proj_grid(n);
     if (td)
-        hipLaunchKernelGGL((k_proj_init<true>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, alpha_sigma,
+        SSN_LAUNCH((k_proj_init<true>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, alpha_sigma,
                            v_out, y, n, C, part);
     else
-        hipLaunchKernelGGL((k_proj_init<false>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, 0.0,
+        SSN_LAUNCH((k_proj_init<false>), dim3(g), dim3(SSN_BLOCK), 0, s, u, td, 0.0,
                            v_out, y, n, C, part);
-    hipLaunchKernelGGL(k_proj_init_fin, dim3(1), dim3(SSN_BLOCK), 0, s, n, C, st, part, (int)g, hint);
+    SSN_LAUNCH(k_proj_init_fin, dim3(1), dim3(SSN_BLOCK), 0, s, n, C, st, part, (int)g, hint);
 }
 
 // ------------------------------------------------------------------ pass
@@ -445,8 +445,8 @@ void launch_proj_pass(const double* v, const int8_t* y, int64_t n, double C, Pro
     // doubles for the g-values, then ints for the histogram, in one scratch
     int* hpart = reinterpret_cast<int*>(part + (int64_t)PCOL * PROJ_GRID_MAX);
     const unsigned g = proj_grid(n);
-    hipLaunchKernelGGL(k_proj_pass, dim3(g), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, part, hpart);
-    hipLaunchKernelGGL(k_proj_decide, dim3(1), dim3(DEC_THREADS), 0, s, C, st, part, hpart, (int)g);
+    SSN_LAUNCH(k_proj_pass, dim3(g), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, part, hpart);
+    SSN_LAUNCH(k_proj_decide, dim3(1), dim3(DEC_THREADS), 0, s, C, st, part, hpart, (int)g);
 }
 
 // ------------------------------------------------------------------ apply
@@ -485,7 +485,7 @@ void launch_proj_apply(const double* v, const int8_t* y, int64_t n, double C, co
                        hipStream_t s) {
     (void)counter;
     const unsigned g = proj_grid(n);
-    hipLaunchKernelGGL(k_proj_apply, dim3(g), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, x, mask, part);
+    SSN_LAUNCH(k_proj_apply, dim3(g), dim3(SSN_BLOCK), 0, s, v, y, n, C, st, x, mask, part);
     ColSumDst d = colsum_dst();
     d.p[0] = &sc->p;
     d.as_ll[0] = 1;
@@ -555,7 +555,7 @@ void launch_ls_finalize(const double* v, const double* u_base, const double* td,
                         Scalars* sc, double* part, unsigned* counter, hipStream_t s) {
     (void)counter;
     const unsigned g = proj_grid(n);
-    hipLaunchKernelGGL(k_ls_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, u_base, td, as, y, n, C, st,
+    SSN_LAUNCH(k_ls_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, u_base, td, as, y, n, C, st,
                        st_base, xk, x, mask, part);
     ColSumDst d = colsum_dst();
     d.p[0] = &sc->dh;
@@ -574,7 +574,7 @@ __global__ void k_kkt_prepare(const double* __restrict__ x, const double* __rest
     if (i < n) v[i] = x[i] - Qx[i] + 1.0;
 }
 void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_kkt_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, Qx, v,
+    SSN_LAUNCH(k_kkt_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, Qx, v,
                        n);
 }
 
@@ -619,7 +619,7 @@ void launch_kkt_finalize(const double* v, const double* x, const double* Qx, con
                          unsigned* counter, hipStream_t s) {
     (void)counter;
     const unsigned g = proj_grid(n);
-    hipLaunchKernelGGL(k_kkt_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, x, Qx, y, n, C, st, part);
+    SSN_LAUNCH(k_kkt_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, x, Qx, y, n, C, st, part);
     ColSumDst d = colsum_dst();
     d.p[0] = &sc->res2;
     d.p[1] = &sc->x2;
@@ -683,8 +683,8 @@ void launch_compact(const uint8_t* mask, int64_t n, int32_t* list, long long* co
                     unsigned* counter, hipStream_t s) {
     (void)counter;
     const unsigned nb = (unsigned)((n + CMP_CH - 1) / CMP_CH);
-    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk);
-    hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk, list, count);
+    SSN_LAUNCH(k_compact_count, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk);
+    SSN_LAUNCH(k_compact_write, dim3(nb), dim3(SSN_BLOCK), 0, s, mask, n, blk, list, count);
 }
 
 int compact_blocks(int64_t n) { return (int)((n + CMP_CH - 1) / CMP_CH); }

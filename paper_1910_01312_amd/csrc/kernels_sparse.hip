@@ -281,7 +281,7 @@ static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin
     }
     if (nb > 0) {
         const int cm = (vin && !yin && !mask) ? 0 : ((!vin && mask) ? 1 : 2);
-#define SEGSUM(V, CM) hipLaunchKernelGGL((k_segsum<V, CM>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, \
+#define SEGSUM(V, CM) SSN_LAUNCH((k_segsum<V, CM>), dim3((unsigned)nb), dim3(SSN_BLOCK), 0, \
                                          s, P.nseg, P.nnz, P.ptr, P.idx, (const V*)P.val, P.lane_seg, \
                                          P.ntile, P.tile_first, P.carry, vin, yin, mask, yout, \
                                          out_mask, out, parts, tpp)
@@ -295,7 +295,7 @@ static void segsum_launch(const SegPlan& P, const double* vin, const int8_t* yin
     if (P.nspan > 0) {
         const int64_t nbs = (P.nshort + SSN_BLOCK - 1) / SSN_BLOCK;
         const int64_t nbl = (P.nspan - P.nshort + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK;
-        hipLaunchKernelGGL(k_segsum_fix, dim3((unsigned)(nbs + nbl)), dim3(SSN_BLOCK), 0, s,
+        SSN_LAUNCH(k_segsum_fix, dim3((unsigned)(nbs + nbl)), dim3(SSN_BLOCK), 0, s,
                            P.span_seg, P.span_t0, P.span_t1, P.nspan, P.nshort, P.tile_first,
                            P.carry, yout, out_mask, out);
     }

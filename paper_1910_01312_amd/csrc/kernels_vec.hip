@@ -28,7 +28,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_colsum_fin(const double* __restri
 }
 void launch_colsum_fin(const double* part, int nb, int stride, int ncols, const ColSumDst& d,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum_fin, dim3(1), dim3(SSN_BLOCK), 0, s, part, nb, stride, ncols, d);
+    SSN_LAUNCH(k_colsum_fin, dim3(1), dim3(SSN_BLOCK), 0, s, part, nb, stride, ncols, d);
 }
 ColSumDst colsum_dst() {
     ColSumDst d;
@@ -73,7 +73,7 @@ void launch_dots(int npair, const double* a0, const double* b0, double* r0, cons
                  int64_t len, double* part, unsigned* counter, hipStream_t s) {
     (void)counter;
     const unsigned g = vec_grid(len);
-    hipLaunchKernelGGL(k_dots, dim3(g), dim3(SSN_BLOCK), 0, s, npair, a0, b0, a1, b1, a2, b2, len,
+    SSN_LAUNCH(k_dots, dim3(g), dim3(SSN_BLOCK), 0, s, npair, a0, b0, a1, b1, a2, b2, len,
                        part);
     ColSumDst d = colsum_dst();
     d.p[0] = r0;
@@ -87,7 +87,7 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
     if (i < len) y[i] = fma(a, x[i], y[i]);
 }
 void launch_axpy(double* y, const double* x, double a, int64_t len, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, y, x, a, len);
+    SSN_LAUNCH(k_axpy, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, y, x, a, len);
 }
 
 __global__ void k_scale_copy(double* __restrict__ y, const double* __restrict__ x, double a,
@@ -96,7 +96,7 @@ __global__ void k_scale_copy(double* __restrict__ y, const double* __restrict__ 
     if (i < len) y[i] = a * x[i];
 }
 void launch_scale_copy(double* y, const double* x, double a, int64_t len, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, y, x, a,
+    SSN_LAUNCH(k_scale_copy, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, y, x, a,
                        len);
 }
 
@@ -108,7 +108,7 @@ __global__ void k_u_from(const double* __restrict__ xk, const double* __restrict
 }
 void launch_u_from(const double* xk, const double* aw, double sigma, double* u, int64_t n,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_u_from, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xk, aw, sigma,
+    SSN_LAUNCH(k_u_from, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xk, aw, sigma,
                        u, n);
 }
 
@@ -118,7 +118,7 @@ __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b
     if (i < len) o[i] = a[i] - b[i];
 }
 void launch_sub(const double* a, const double* b, double* out, int64_t len, hipStream_t s) {
-    hipLaunchKernelGGL(k_sub, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, a, b, out, len);
+    SSN_LAUNCH(k_sub, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, a, b, out, len);
 }
 
 // o = y .* z (the coefficients of X^T (y .* z), gathered once per entry)
@@ -128,7 +128,7 @@ __global__ void k_mul_y(const double* __restrict__ z, const int8_t* __restrict__
     if (i < n) o[i] = (double)y[i] * z[i];
 }
 void launch_mul_y(const double* z, const int8_t* y, double* out, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_mul_y, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, y, out, n);
+    SSN_LAUNCH(k_mul_y, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, y, out, n);
 }
 
 // Column relabelling at the boundary: internal index perm[j] holds
@@ -144,7 +144,7 @@ __global__ void k_permute(const double* __restrict__ src, const int32_t* __restr
 void launch_permute(const double* src, const int32_t* perm, double* dst, int64_t q, bool to_internal,
                     hipStream_t s) {
     if (q <= 0) return;
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, src, perm, dst,
+    SSN_LAUNCH(k_permute, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, src, perm, dst,
                        q, to_internal ? 1 : 0);
 }
 
@@ -153,7 +153,7 @@ __global__ void k_fill(double* __restrict__ p, double v, int64_t len) {
     if (i < len) p[i] = v;
 }
 void launch_fill(double* p, double v, int64_t len, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, p, v, len);
+    SSN_LAUNCH(k_fill, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, p, v, len);
 }
 
 }  // namespace ssn

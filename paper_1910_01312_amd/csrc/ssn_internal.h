@@ -2,12 +2,35 @@
 // between host code and kernels, and the host-side launchers of every
 // kernel.  Not part of the public ABI.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/ssnalm.h"
 
 namespace ssn {
+
+// Kernel timing (ssnalm_options.profile): while the host times a kernel
+// class it installs a sink on its thread, and every launch then goes through
+// hipExtLaunchKernelGGL with a start / stop event pair from the sink, which
+// the runtime attaches to that dispatch: the pair measures the kernel's own
+// execution, without the dispatch latency in front of it.
+struct KTimeSink {
+    virtual void pair(hipEvent_t* start, hipEvent_t* stop) = 0;
+    virtual ~KTimeSink() = default;
+};
+extern thread_local KTimeSink* g_ktime;
+
+#define SSN_LAUNCH(K, G, B, SH, ST, ...)                                                 \
+    do {                                                                                \
+        if (::ssn::g_ktime) {                                                           \
+            hipEvent_t e0_ = nullptr, e1_ = nullptr;                                    \
+            ::ssn::g_ktime->pair(&e0_, &e1_);                                           \
+            hipExtLaunchKernelGGL(K, G, B, SH, ST, e0_, e1_, 0, __VA_ARGS__);           \
+        } else {                                                                        \
+            hipLaunchKernelGGL(K, G, B, SH, ST, __VA_ARGS__);                           \
+        }                                                                               \
+    } while (0)
 
 // State of one projection onto {y^T x = 0, 0 <= x <= C}: the bracket of the
 // multiplier, the running flags and the result.  Lives in device memory.
@@ -375,6 +398,25 @@ void launch_ws_violators(const double* aw, const int8_t* y, int64_t n, double b,
 
 // error reporting shared by the host files
 ssnalm_status set_error(ssnalm_status st, const char* fmt, ...);
+
+// RBF feature maps (kernels_features.hip) ----------------------------------
+// Z (n x 2N) = cos / sin pairs of X W^T, scaled by 1/sqrt(N); z_f64: Z is
+// fp64, else fp32.
+void launch_rff(int dtype, const void* X, int64_t n, int64_t q, const double* W, int64_t N, void* Z,
+                int z_f64, hipStream_t s);
+// out[i] = |row rows[i] (or i) of X|^2
+void launch_row_norms(int dtype, const void* X, const int32_t* rows, int64_t n, int64_t q,
+                      double* out, hipStream_t s);
+// K (na x r) of the RBF kernel between rows arows (or all) and the landmarks,
+// + shift on the diagonal when arows is given (the landmark block)
+void launch_rbf_block(int dtype, const void* X, int64_t q, const int32_t* arows, int64_t na,
+                      const double* anorm, const int32_t* lm, int64_t r, const double* lnorm,
+                      double alpha, double shift, double* K, hipStream_t s);
+// Zw (n x r, fp64) = K L^{-T} with the blocked Cholesky factor of the
+// landmark block (lower triangle of F, diagonal-block inverses in inv)
+void launch_nys_solve(const double* K, int64_t n, int64_t r, const double* F, const double* inv,
+                      double* Zw, hipStream_t s);
+void launch_copy_z(const double* Zw, int64_t count, void* Z, int z_f64, hipStream_t s);
 // NaN / Inf scan of `count` elements of X (device) on the host
 ssnalm_status scan_finite(const void* X, int dtype, int64_t count);
 
