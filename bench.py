@@ -463,11 +463,19 @@ def main():
         log(f"[bench] warmup {i}: {info['time_s']:.3f} s status={info['status_name']} "
             f"R_KKT={info['rkkt']:.2e} trials={info['ls_trials']} passes={info['proj_passes']} outer={info['iters_outer']} newton={info['iters_inner']} "
             f"cg={info['cg_iters']} p={info['p']}")
+    # the CG's classes are timed on a sample of their launches (one CG
+    # iteration in eight): their share of the solve is the sampled average
+    # times the CG iterations that did work
+    def class_total(name, k):
+        if name in ("amul_J", "atmul_J") and k["launches"]:
+            return k["seconds"] / k["launches"] * max(info["cg_iters"], k["launches"])
+        return k["seconds"]
+
     best = None
     for name, k in ks_all.items():
         if name in untimed or k["launches"] == 0 or (k["bytes"] <= 0 and k["flops"] <= 0):
             continue
-        if best is None or k["seconds"] > ks_all[best]["seconds"]:
+        if best is None or class_total(name, k) > class_total(best, ks_all[best]):
             best = name
     s.set_profile((1 << (K_NAMES.index(best) + 1)) if best is not None else 0)
     torch.cuda.synchronize()
@@ -547,6 +555,7 @@ def main():
                   "cg": last["cg_iters"], "proj_passes": last["proj_passes"], "p": last["p"],
                   "n_sv": last["n_sv"], "obj": last["obj"], "create_s": create_s},
         "kernels_profiled_warmup": {k: {"launches": v["launches"], "ms": v["seconds"] * 1e3,
+                        "ms_per_solve": class_total(k, v) * 1e3,
                         "GBps": (v["bytes"] / v["seconds"] / 1e9) if v["seconds"] > 0 and v["bytes"] > 0 else None}
                     for k, v in ks_all.items() if v["launches"]},
     }

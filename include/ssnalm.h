@@ -160,6 +160,40 @@ ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* prob,
                             const ssnalm_options* opt, void* stream);
 
 /*
+ * The eps-SVR dual (Section 1, eq. Def_Dual_of_SVR_Problem) as an instance
+ * of the unified problem (P): variables [x; z] in R^{2n},
+ *   min 1/2 |X^T (x - z)|^2 + eps e^T (x + z) + y^T (x - z)
+ *   s.t. e^T x - e^T z = 0,  0 <= x, z <= C,
+ * i.e. Q = B B^T with B = [X; -X], c = [eps e + y; eps e - y], a = [e; -e],
+ * d = 0, l = 0, u = C e.  B is never formed: products with B are products
+ * with X (two signed copies of its rows).
+ *   kind  : SSNALM_DENSE (CSR is not accepted), dtype F64, F32 or BF16.
+ *   X     : n x q row-major (device), borrowed like ssnalm_create's.
+ *   y     : n regression targets (doubles, device), read during the call.
+ * The context then solves with ssnalm_solve: x_out holds 2n doubles [x; z],
+ * w_out the primal weights w = X^T (z - x) of the regression function
+ * w^T x~ + b, b_out (and info->b) its bias b, info->obj the dual objective
+ * above and info->gap the relative gap to the eps-insensitive primal
+ * 1/2 |w|^2 + C sum_i max(0, |y_i - w^T x~_i - b| - eps).  Newton steps
+ * use the Cholesky factorisation (q <= 2048), fp64 precision.
+ * E_BADARG: as ssnalm_create, plus eps < 0 or non-finite, CSR input,
+ * PCG or mixed precision requested, q > 2048.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t dtype;
+    int64_t n, q;
+    const void*   X;
+    const double* y;
+    double C;
+    double eps;
+    double tol;
+} ssnalm_svr_problem;
+
+ssnalm_status ssnalm_create_svr(ssnalm_ctx** out, const ssnalm_svr_problem* prob,
+                                const ssnalm_options* opt, void* stream);
+
+/*
  * Solve (Algorithm 1 with Algorithm 3 as its inner solver).
  *   x0    : optional warm start, n doubles (device) or NULL for x^0 = 0.
  *           It is projected onto {y^T x = 0, 0 <= x <= C} first and omega^0

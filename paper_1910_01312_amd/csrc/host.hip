@@ -118,6 +118,16 @@ struct ssnalm_ctx {
     double* zJ = nullptr;            // n-vector, nonzero on J only (mixed refinement)
     double* yz = nullptr;            // n-vector y .* z for the sparse A^T z
     bool mixed = false;              // bf16 SYRK + refinement
+    // eps-SVR (ssnalm_create_svr): n = 2 nphys variables [x; z] over the
+    // nphys rows of X, B = [X; -X] = diag(a) [X; X] with a = y (the labels
+    // array), linear term c = lin (null: the C-SVC's c = -e)
+    bool svr = false;
+    int64_t nphys = 0;
+    double svr_eps = 0.0;
+    const double* lin = nullptr;
+    int8_t* yphys = nullptr;         // nphys ones: plain products with X
+    double* zc = nullptr;            // z_top - z_bot (nphys)
+    uint8_t* mc = nullptr;           // mask_top + mask_bot (nphys)
     int refine_total = 0;
     // q-vectors
     double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
@@ -282,11 +292,15 @@ static void prof_end(ssnalm_ctx* c, int cls, double bytes, double flops) {
 static double elem_bytes(int dtype) { return dtype == SSNALM_F64 ? 8.0 : (dtype == SSNALM_F32 ? 4.0 : 2.0); }
 // algorithmic bytes of A v over all rows and of A^T z over `rows` rows
 static double bytes_amul(const ssnalm_ctx* c) {
+    if (c->svr)      // one pass over X, the n-vector written twice
+        return (double)c->nphys * c->q * elem_bytes(c->dtype) + 17.0 * c->nphys + 8.0 * c->q;
     if (c->kind == SSNALM_DENSE)
         return (double)c->n * c->q * elem_bytes(c->dtype) + 9.0 * c->n + 8.0 * c->q;
     return (double)c->nnz * (elem_bytes(c->dtype) + 4.0) + 4.0 * (c->n + 1) + 9.0 * c->n + 8.0 * c->q;
 }
 static double bytes_atmul(const ssnalm_ctx* c, long long rows) {
+    if (c->svr)      // the 2n-vector folded, then every row of X with its coefficient
+        return (double)c->nphys * c->q * elem_bytes(c->dtype) + 25.0 * c->nphys + 8.0 * c->q;
     if (c->kind == SSNALM_DENSE) {
         const double r = rows >= 0 ? (double)rows : (double)c->n;
         return r * c->q * elem_bytes(c->dtype) + 9.0 * c->n + 8.0 * c->q;
@@ -302,7 +316,10 @@ static unsigned* cnt(ssnalm_ctx* c, int k) { return c->counters + k; }
 // t = A v over all rows
 static void op_amul(ssnalm_ctx* c, const double* v, double* t) {
     prof_begin(c, SSNALM_K_AMUL);
-    if (c->kind == SSNALM_DENSE)
+    if (c->svr) {
+        launch_amul_dense(c->dtype, c->X, c->yphys, v, t, c->nphys, c->q, c->st);
+        launch_svr_expand(t, c->nphys, c->st);
+    } else if (c->kind == SSNALM_DENSE)
         launch_amul_dense(c->dtype, c->X, c->y, v, t, c->n, c->q, c->st);
     else
         launch_segsum(c->fwd, v, nullptr, nullptr, c->y, nullptr, t, c->st);
@@ -314,7 +331,15 @@ static void op_amul(ssnalm_ctx* c, const double* v, double* t) {
 static void op_atmul(ssnalm_ctx* c, const double* z, const uint8_t* mask, const double* base,
                      double sign, double* r, double* s_out, int cls = SSNALM_K_ATMUL) {
     prof_begin(c, cls);
-    if (c->kind == SSNALM_DENSE) {
+    if (c->svr) {
+        // B^T z = X^T (z_top - z_bot), B_J^T a_J = X^T (mask_top + mask_bot)
+        const int nb = atmul_dense_nblk(c->nphys);
+        launch_svr_fold(z, mask, c->nphys, c->zc, mask ? c->mc : nullptr, c->st);
+        launch_atmul_dense(c->dtype, c->X, c->yphys, c->zc, mask ? c->mc : nullptr, c->nphys, c->q,
+                           c->part, c->part2, c->st);
+        launch_reduce_cols(c->part, nb, c->q, base, sign, r, c->st);
+        if (mask) launch_reduce_cols(c->part2, nb, c->q, nullptr, 1.0, s_out, c->st);
+    } else if (c->kind == SSNALM_DENSE) {
         const int nb = atmul_dense_nblk(c->n);
         launch_atmul_dense(c->dtype, c->X, c->y, z, mask, c->n, c->q, c->part, c->part2, c->st);
         launch_reduce_cols(c->part, nb, c->q, base, sign, r, c->st);
@@ -396,6 +421,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
     if (c->use_chol) {
         long long* pcount = &dsc(c)->p;
         launch_compact(mask, c->n, c->jlist, pcount, c->blk, cnt(c, CNT_CMP), c->st);
+        if (c->svr) launch_list_mod(c->jlist, p, c->nphys, c->st);   // rows of X (repeats allowed)
         prof_begin(c, SSNALM_K_SYRK);
         if (c->mixed)
             launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, c->G, c->mpart, c->mpart_cap, c->st);
@@ -556,13 +582,13 @@ static void gradient(ssnalm_ctx* c, const double* xt, const uint8_t* mask) {
 static ssnalm_status kkt(ssnalm_ctx* c, const double* x, const double* w, double* R, double* b,
                          double* sumx, double* hinge = nullptr) {
     op_amul(c, w, c->nv);                                       // Qx
-    launch_kkt_prepare(x, c->nv, c->nv2, c->n, c->st);          // v = x - Qx + e
+    launch_kkt_prepare(x, c->nv, c->nv2, c->n, c->st, c->lin);  // v = x - Qx - c
     STCHK(project_into(c, c->nv2, nullptr, 0.0, nullptr, 2));
     STCHK(sync_state(c));
     bool more = false;
     STCHK(project_finish(c, c->nv2, 2, &more));
     launch_kkt_finalize(c->nv2, x, c->nv, c->y, c->n, c->C, dps(c, 2), dsc(c), c->spart, cnt(c, CNT_KKT),
-                        c->st);
+                        c->st, c->lin, c->svr ? c->nphys : 0, c->svr_eps);
     STCHK(sync_state(c));
     c->proj_passes += c->hs->ps[2].passes;
     c->proj_capped += c->hs->ps[2].approx;
@@ -846,8 +872,86 @@ ssnalm_status scan_finite(const void* X, int dtype, int64_t total) {
 }
 }  // namespace ssn
 
+// x_rows: rows of the X array (n, or n / 2 for the eps-SVR's two copies).
+static ssnalm_status create_impl(ssnalm_ctx** out, const ssnalm_problem* pr,
+                                 const ssnalm_options* opt, void* stream, int64_t x_rows);
+
 extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* pr,
                                        const ssnalm_options* opt, void* stream) {
+    if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
+    return create_impl(out, pr, opt, stream, pr->n);
+}
+
+extern "C" ssnalm_status ssnalm_create_svr(ssnalm_ctx** out, const ssnalm_svr_problem* pr,
+                                           const ssnalm_options* opt, void* stream) {
+    if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
+    *out = nullptr;
+    if (pr->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "eps-SVR needs dense X");
+    if (pr->n < 1 || pr->q < 1 || 2 * pr->n >= INT32_MAX || pr->q >= INT32_MAX)
+        return fail(SSNALM_E_BADARG, "n must be in [1, 2^30) and q in [1, 2^31)");
+    if (!pr->X || !pr->y) return fail(SSNALM_E_BADARG, "X and y are required");
+    if (!(pr->eps >= 0.0) || !std::isfinite(pr->eps)) return fail(SSNALM_E_BADARG, "eps must be finite and >= 0");
+    ssnalm_options o;
+    if (opt) o = *opt; else ssnalm_default_options(&o);
+    if (o.precision != SSNALM_PREC_FP64) return fail(SSNALM_E_BADARG, "eps-SVR runs in fp64 precision");
+    if (o.newton == SSNALM_NEWTON_PCG) return fail(SSNALM_E_BADARG, "eps-SVR uses the Cholesky Newton step");
+    if (pr->q > std::max(chol_small_max(), chol_blocked_max()))
+        return fail(SSNALM_E_BADARG, "eps-SVR needs q <= %d", std::max(chol_small_max(), chol_blocked_max()));
+    o.newton = SSNALM_NEWTON_CHOL;
+    const int64_t n = pr->n;
+    // the targets are read by a kernel on the caller's stream: the labels a
+    // and the linear term c of the 2n-variable problem
+    int8_t* a = nullptr;
+    double* lin = nullptr;
+    if (hipMalloc(&a, 2 * n) != hipSuccess) return fail(SSNALM_E_OOM, "allocation of the labels failed");
+    if (hipMalloc(&lin, sizeof(double) * 2 * n) != hipSuccess) {
+        (void)hipFree(a);
+        return fail(SSNALM_E_OOM, "allocation of the linear term failed");
+    }
+    launch_svr_setup(pr->y, n, pr->eps, a, lin, (hipStream_t)stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+        (void)hipFree(a);
+        (void)hipFree(lin);
+        return fail(SSNALM_E_HIP, "building the eps-SVR problem failed");
+    }
+    ssnalm_problem p2;
+    memset(&p2, 0, sizeof p2);
+    p2.kind = SSNALM_DENSE;
+    p2.dtype = pr->dtype;
+    p2.n = 2 * n;
+    p2.q = pr->q;
+    p2.X = pr->X;
+    p2.y = a;
+    p2.C = pr->C;
+    p2.tol = pr->tol;
+    ssnalm_ctx* c = nullptr;
+    ssnalm_status s = create_impl(&c, &p2, &o, stream, n);
+    if (s < 0) {
+        (void)hipFree(a);
+        (void)hipFree(lin);
+        return s;
+    }
+    c->owned.push_back(a);
+    c->owned.push_back(lin);
+    c->svr = true;
+    c->nphys = n;
+    c->svr_eps = pr->eps;
+    c->lin = lin;
+    if ((s = dalloc(c, &c->yphys, n)) < 0 || (s = dalloc(c, &c->zc, n)) < 0 ||
+        (s = dalloc(c, &c->mc, n)) < 0) {
+        ssnalm_destroy(c);
+        return s;
+    }
+    if (hipMemsetAsync(c->yphys, 1, n, c->st) != hipSuccess || hipStreamSynchronize(c->st) != hipSuccess) {
+        ssnalm_destroy(c);
+        return fail(SSNALM_E_HIP, "setting up the eps-SVR context failed");
+    }
+    *out = c;
+    return SSNALM_OK;
+}
+
+static ssnalm_status create_impl(ssnalm_ctx** out, const ssnalm_problem* pr,
+                                 const ssnalm_options* opt, void* stream, int64_t x_rows) {
     if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
     *out = nullptr;
     if (pr->n < 1 || pr->q < 1 || pr->n >= INT32_MAX || pr->q >= INT32_MAX)
@@ -959,7 +1063,7 @@ extern "C" ssnalm_status ssnalm_create(ssnalm_ctx** out, const ssnalm_problem* p
             else { float* t; ALLOC(t, nz); c->jv = t; }
         }
     } else if (c->opt.check_finite) {
-        if ((s = scan_finite(pr->X, pr->dtype, n * q)) < 0) return bail(s);
+        if ((s = scan_finite(pr->X, pr->dtype, x_rows * q)) < 0) return bail(s);
     }
 #undef ALLOC
     if (hipStreamSynchronize(c->st) != hipSuccess) return bail(fail(SSNALM_E_HIP, "stream sync failed"));
@@ -1004,7 +1108,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
         const double eps_k = std::pow(o.eps_decay, (double)k);
         // fresh A omega and u for this outer iteration
         op_amul(c, c->om, c->aw);
-        launch_u_from(c->xk, c->aw, sigma, c->u, n, c->st);
+        launch_u_from(c->xk, c->aw, sigma, c->u, n, c->st, c->lin);
         c->base = 0;
         STCHK(project_into(c, c->u, nullptr, 0.0, nullptr, c->base));
         STCHK(sync_state(c));
@@ -1127,8 +1231,12 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     launch_dots(1, c->qv, c->qv, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                 q, c->spart, cnt(c, CNT_DOTS), c->st);
     launch_count_x(x_out, n, c->C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);
+    if (c->lin)
+        launch_dots(1, c->lin, x_out, &dsc(c)->cx, nullptr, nullptr, nullptr, nullptr, nullptr,
+                    nullptr, n, c->spart, cnt(c, CNT_DOTS2), c->st);
     if (w_out) {
-        if (c->qperm) q_out(c, c->qv, w_out);
+        if (c->svr) launch_scale_copy(w_out, c->qv, -1.0, q, c->st);   // w = X^T (z - x)
+        else if (c->qperm) q_out(c, c->qv, w_out);
         else HIPCHK(hipMemcpyAsync(w_out, c->qv, sizeof(double) * q, hipMemcpyDeviceToDevice, c->st));
     }
     HIPCHK(hipGetLastError());
@@ -1138,7 +1246,8 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     const double w2 = c->hs->sc.dd;
     const auto t_end = std::chrono::steady_clock::now();
     inf.rkkt = R;
-    inf.obj = 0.5 * w2 - sumx;
+    inf.obj = 0.5 * w2 + (c->lin ? c->hs->sc.cx : -sumx);
+    if (c->svr) b = -b;          // the regression bias (the tube's center is w^T x + b)
     inf.b = b;
     {
         // relative duality gap of the C-SVC primal at (w, b) and the dual
@@ -1207,6 +1316,7 @@ extern "C" ssnalm_status ssnalm_op_project(ssnalm_ctx* c, const double* v, doubl
 extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mask, const double* g,
                                           double sigma, double cg_tol, double* d, int32_t* cg_iters) {
     if (!c || !free_mask || !g || !d) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->svr) return fail(SSNALM_E_BADARG, "op_newton is for C-SVC contexts");
     StreamScope scope_(c);
     if (!(sigma > 0.0)) return fail(SSNALM_E_BADARG, "sigma must be > 0");
     // s = X_J^T 1 and p
@@ -1233,6 +1343,7 @@ extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mas
 
 extern "C" ssnalm_status ssnalm_op_gram(ssnalm_ctx* c, const uint8_t* free_mask, double* G) {
     if (!c || !free_mask || !G) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->svr) return fail(SSNALM_E_BADARG, "op_gram is for C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE || !c->use_chol) return fail(SSNALM_E_BADARG, "Gram matrix needs a dense Cholesky context");
     launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
@@ -1307,6 +1418,7 @@ extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* 
 // means of x_i^T w1, margins m_i, and the projection X R.
 extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float* Z) {
     if (!c || !R || !Z) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->svr) return fail(SSNALM_E_BADARG, "ws_features is for C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "warm-start features need dense X");
     const int64_t n = c->n, q = c->q;
@@ -1349,6 +1461,7 @@ extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float
 
 extern "C" ssnalm_status ssnalm_ws_x0(ssnalm_ctx* c, const float* out, double* x0) {
     if (!c || !out || !x0) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->svr) return fail(SSNALM_E_BADARG, "ws_x0 is for C-SVC contexts");
     StreamScope scope_(c);
     launch_ws_x0(out, c->n, c->C, x0, c->st);
     HIPCHK(hipGetLastError());
@@ -1358,6 +1471,7 @@ extern "C" ssnalm_status ssnalm_ws_x0(ssnalm_ctx* c, const float* out, double* x
 extern "C" ssnalm_status ssnalm_ws_labels(ssnalm_ctx* c, const double* x, int32_t* status,
                                           float* target) {
     if (!c || !x || !status || !target) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->svr) return fail(SSNALM_E_BADARG, "ws_labels is for C-SVC contexts");
     StreamScope scope_(c);
     launch_ws_labels(x, c->n, c->C, status, target, c->st);
     HIPCHK(hipGetLastError());
@@ -1370,6 +1484,7 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
                                          int32_t max_rounds, double* x_out, double* w_out,
                                          ssnalm_info* info, ssnalm_ws_stats* stats) {
     if (!c || !out || !x_out) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->svr) return fail(SSNALM_E_BADARG, "ws_solve is for C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "screening needs dense X");
     if (!(keep_frac > 0.0) || keep_frac > 1.0) return fail(SSNALM_E_BADARG, "keep_frac must be in (0, 1]");

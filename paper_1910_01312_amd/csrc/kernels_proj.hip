@@ -568,25 +568,34 @@ void launch_ls_finalize(const double* v, const double* u_base, const double* td,
 }
 
 // ------------------------------------------------------------------ KKT
+// v = x - Q x - c (eq. Def_Rkkt); c = -e when lin is null
 __global__ void k_kkt_prepare(const double* __restrict__ x, const double* __restrict__ Qx,
-                              double* __restrict__ v, int64_t n) {
+                              const double* __restrict__ lin, double* __restrict__ v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = x[i] - Qx[i] + 1.0;
+    if (i < n) v[i] = x[i] - Qx[i] - (lin ? lin[i] : -1.0);
 }
-void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n, hipStream_t s) {
-    SSN_LAUNCH(k_kkt_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, Qx, v,
+void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n, hipStream_t s,
+                        const double* lin) {
+    SSN_LAUNCH(k_kkt_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, Qx, lin, v,
                        n);
 }
 
-// |x - Pi(v)|^2, |x|^2, e^T x and the hinge sum
-//   sum_i max(0, 1 - Qx_i - y_i lam) = sum_i max(0, 1 - y_i (x~_i^T w + lam))
-// (Qx = A w, so Qx_i = y_i x~_i^T w) of the C-SVC primal at (w, b = lam).
+// |x - Pi(v)|^2, |x|^2, e^T x (c^T x with a linear term) and the loss sum
+// of the primal at the bias given by lam:
+//   C-SVC  sum_i max(0, 1 - Qx_i - y_i lam) = sum_i max(0, 1 - y_i (x~_i^T w + lam))
+//          (Qx = A w, so Qx_i = y_i x~_i^T w; b = lam);
+//   eps-SVR (svr_n = n / 2 rows of X, lin = c): with w = X^T (z - x) the primal
+//          weights, Qx_i = -x~_i^T w for i < svr_n, and b = -lam,
+//          sum_{i < svr_n} max(0, |y_i - x~_i^T w - b| - eps)
+//          = sum max(0, |c_i - eps + Qx_i + lam| - eps).
 __global__ __launch_bounds__(SSN_BLOCK) void k_kkt_finalize(const double* __restrict__ v,
                                                             const double* __restrict__ x,
                                                             const double* __restrict__ Qx,
                                                             const int8_t* __restrict__ y,
                                                             int64_t n, double C,
                                                             const ProjState* st,
+                                                            const double* __restrict__ lin,
+                                                            int64_t svr_n, double eps,
                                                             double* __restrict__ part) {
     __shared__ double shd[SSN_WAVES_PER_BLOCK];
     const double lam = st->lam;
@@ -599,8 +608,13 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_kkt_finalize(const double* __rest
         const double r = xi - pi;
         r2 = fma(r, r, r2);
         x2 = fma(xi, xi, x2);
-        sx += xi;
-        hs += fmax(0.0, 1.0 - Qx[i] - lam * yi);
+        if (lin) {
+            sx = fma(lin[i], xi, sx);
+            if (i < svr_n) hs += fmax(0.0, fabs(lin[i] - eps + Qx[i] + lam) - eps);
+        } else {
+            sx += xi;
+            hs += fmax(0.0, 1.0 - Qx[i] - lam * yi);
+        }
     }
     const double a = block_sum(r2, shd);
     const double b = block_sum(x2, shd);
@@ -616,10 +630,12 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_kkt_finalize(const double* __rest
 
 void launch_kkt_finalize(const double* v, const double* x, const double* Qx, const int8_t* y,
                          int64_t n, double C, const ProjState* st, Scalars* sc, double* part,
-                         unsigned* counter, hipStream_t s) {
+                         unsigned* counter, hipStream_t s, const double* lin, int64_t svr_n,
+                         double eps) {
     (void)counter;
     const unsigned g = proj_grid(n);
-    SSN_LAUNCH(k_kkt_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, x, Qx, y, n, C, st, part);
+    SSN_LAUNCH(k_kkt_finalize, dim3(g), dim3(SSN_BLOCK), 0, s, v, x, Qx, y, n, C, st, lin, svr_n,
+               eps, part);
     ColSumDst d = colsum_dst();
     d.p[0] = &sc->res2;
     d.p[1] = &sc->x2;

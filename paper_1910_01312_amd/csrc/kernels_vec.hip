@@ -101,15 +101,63 @@ void launch_scale_copy(double* y, const double* x, double a, int64_t len, hipStr
 }
 
 // u = x^k + sigma (e - A omega)   (u(w) of eq. Def_psi with c = -e, Q w = A omega)
+// u = x^k - sigma (A omega + c) (eq. Def_psi); c = -e when lin is null
 __global__ void k_u_from(const double* __restrict__ xk, const double* __restrict__ aw, double sigma,
-                         double* __restrict__ u, int64_t n) {
+                         const double* __restrict__ lin, double* __restrict__ u, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) u[i] = fma(sigma, 1.0 - aw[i], xk[i]);
+    if (i < n) u[i] = fma(sigma, (lin ? -lin[i] : 1.0) - aw[i], xk[i]);
 }
 void launch_u_from(const double* xk, const double* aw, double sigma, double* u, int64_t n,
-                   hipStream_t s) {
+                   hipStream_t s, const double* lin) {
     SSN_LAUNCH(k_u_from, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xk, aw, sigma,
-                       u, n);
+                       lin, u, n);
+}
+
+// ---------------------------------------------------------------- eps-SVR
+// The eps-SVR dual (eq. Def_Dual_of_SVR_Problem) as an instance of (P) over
+// the 2n variables [x; z]: B = [X; -X] = diag(a) [X; X] with a = [e; -e],
+// c = [eps e + y; eps e - y].  Labels a and linear term c from the targets.
+__global__ void k_svr_setup(const double* __restrict__ yr, int64_t n, double eps,
+                            int8_t* __restrict__ a, double* __restrict__ lin) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = yr[i];
+    a[i] = 1;
+    a[n + i] = -1;
+    lin[i] = eps + v;
+    lin[n + i] = eps - v;
+}
+void launch_svr_setup(const double* yr, int64_t n, double eps, int8_t* a, double* lin, hipStream_t s) {
+    SSN_LAUNCH(k_svr_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, yr, n, eps, a, lin);
+}
+// B v from X v (first n entries of t): t[n + i] = -t[i]
+__global__ void k_svr_expand(double* __restrict__ t, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) t[n + i] = -t[i];
+}
+void launch_svr_expand(double* t, int64_t n, hipStream_t s) {
+    SSN_LAUNCH(k_svr_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, n);
+}
+// B^T z = X^T (z_top - z_bot); B_J^T a_J = X^T (mask_top + mask_bot)
+__global__ void k_svr_fold(const double* __restrict__ z, const uint8_t* __restrict__ mask, int64_t n,
+                           double* __restrict__ zc, uint8_t* __restrict__ mc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (zc) zc[i] = z ? z[i] - z[n + i] : 0.0;
+    if (mask) mc[i] = (uint8_t)(mask[i] + mask[n + i]);
+}
+void launch_svr_fold(const double* z, const uint8_t* mask, int64_t n, double* zc, uint8_t* mc,
+                     hipStream_t s) {
+    SSN_LAUNCH(k_svr_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, mask, n, zc, mc);
+}
+// rows of the free list that index the second copy of X map to their row of X
+__global__ void k_list_mod(int32_t* __restrict__ list, int64_t p, int32_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < p && list[k] >= n) list[k] -= n;
+}
+void launch_list_mod(int32_t* list, int64_t p, int64_t n, hipStream_t s) {
+    if (p <= 0) return;
+    SSN_LAUNCH(k_list_mod, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, s, list, p, (int32_t)n);
 }
 
 __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b,

@@ -59,7 +59,8 @@ struct Scalars {
     double cg_rz, cg_pap, cg_rr, cg_alpha, cg_beta, cg_rz_new;
     double mean_w;        // PCG: mean of X_J p over J
     double sumx;          // e^T x
-    double hinge;         // KKT: sum_i max(0, 1 - Qx_i - y_i b) at the KKT bias b
+    double hinge;         // KKT: the primal's loss sum at the KKT bias
+    double cx;            // c^T x of a returned x (problems with a linear term)
     long long p;          // |J|
     long long nnzj;       // nonzeros of the rows in J (sparse input)
     long long nfix;       // chunk-crossing column runs of the compact X_J copy
@@ -151,10 +152,15 @@ void launch_ls_finalize(const double* v, const double* u_base, const double* td,
                         uint8_t* mask, Scalars* sc, double* part, unsigned* counter,
                         hipStream_t s);
 // KKT: v = x - Qx + 1; after projecting v: res2 = |x - Pi(v)|^2, x2 = |x|^2, sumx
-void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n, hipStream_t s);
+void launch_kkt_prepare(const double* x, const double* Qx, double* v, int64_t n, hipStream_t s,
+                        const double* lin = nullptr);
+// |x - Pi(v)|^2, |x|^2, e^T x (c^T x when lin is given) and the primal's
+// loss sum into sc (res2, x2, sumx, hinge); eps-SVR when lin is given
+// (svr_n rows of X, tube width eps)
 void launch_kkt_finalize(const double* v, const double* x, const double* Qx, const int8_t* y,
                          int64_t n, double C, const ProjState* st, Scalars* sc, double* part,
-                         unsigned* counter, hipStream_t s);
+                         unsigned* counter, hipStream_t s, const double* lin = nullptr,
+                         int64_t svr_n = 0, double eps = 0.0);
 // ordered compaction of mask into list; total written to *count
 int  compact_blocks(int64_t n);
 void launch_compact(const uint8_t* mask, int64_t n, int32_t* list, long long* count,
@@ -168,7 +174,7 @@ void launch_dots(int npair, const double* a0, const double* b0, double* r0,
 void launch_axpy(double* y, const double* x, double a, int64_t len, hipStream_t s);
 void launch_scale_copy(double* y, const double* x, double a, int64_t len, hipStream_t s);
 void launch_u_from(const double* xk, const double* aw, double sigma, double* u, int64_t n,
-                   hipStream_t s);
+                   hipStream_t s, const double* lin = nullptr);
 void launch_sub(const double* a, const double* b, double* out, int64_t len, hipStream_t s);
 void launch_mul_y(const double* z, const int8_t* y, double* out, int64_t n, hipStream_t s);
 // perm[j] = internal index of original column j; to_internal: dst[perm[j]] =
@@ -417,6 +423,15 @@ void launch_rbf_block(int dtype, const void* X, int64_t q, const int32_t* arows,
 void launch_nys_solve(const double* K, int64_t n, int64_t r, const double* F, const double* inv,
                       double* Zw, hipStream_t s);
 void launch_copy_z(const double* Zw, int64_t count, void* Z, int z_f64, hipStream_t s);
+
+// eps-SVR as an instance of (P) (kernels_vec.hip): labels a = [e; -e] and
+// c = [eps + y; eps - y] from the targets; B v from X v; the folds giving
+// B^T z and B_J^T a_J as products with X; free-list rows mapped into X
+void launch_svr_setup(const double* yr, int64_t n, double eps, int8_t* a, double* lin, hipStream_t s);
+void launch_svr_expand(double* t, int64_t n, hipStream_t s);
+void launch_svr_fold(const double* z, const uint8_t* mask, int64_t n, double* zc, uint8_t* mc,
+                     hipStream_t s);
+void launch_list_mod(int32_t* list, int64_t p, int64_t n, hipStream_t s);
 // NaN / Inf scan of `count` elements of X (device) on the host
 ssnalm_status scan_finite(const void* X, int dtype, int64_t count);
 

@@ -226,6 +226,33 @@ class Solver:
         self.close()
 
 
+class SVR(Solver):
+    """eps-SVR (ssnalm_create_svr): dense X (n, q), regression targets y (n).
+    solve() returns (xz, w, info) with xz = [x; z] (2n doubles), w the
+    primal weights X^T (z - x) and info["b"] the bias of w^T x + b."""
+
+    def __init__(self, X, y, C_=1.0, eps=0.1, tol=1e-6, *, bf16=False, **opts):
+        lib = L.load()
+        self._keep = []
+        Xd, dt = _dense_dev(X, bf16)
+        yd = _to_dev(y, torch.float64)
+        self._keep += [Xd, yd]
+        n, q = Xd.shape
+        prob = L.SvrProblem()
+        prob.kind, prob.dtype = L.DENSE, dt
+        prob.n, prob.q = int(n), int(q)
+        prob.X, prob.y = Xd.data_ptr(), yd.data_ptr()
+        prob.C, prob.eps, prob.tol = float(C_), float(eps), float(tol)
+        self.n, self.q, self.C, self.tol = 2 * int(n), int(q), float(C_), float(tol)
+        self.problem = prob
+        self.options = make_options(**opts)
+        ctx = C.c_void_p()
+        L.check(lib.ssnalm_create_svr(C.byref(ctx), C.byref(prob), C.byref(self.options),
+                                      _stream_handle()), "ssnalm_create_svr")
+        self._ctx = ctx
+        self._lib = lib
+
+
 def solve(X, y, C_, tol=1e-6, x0=None, **opts):
     """One-shot solve: returns (x, w, info)."""
     with Solver(X, y, C_, tol, **opts) as s:
