@@ -194,6 +194,43 @@ ssnalm_status ssnalm_create_svr(ssnalm_ctx** out, const ssnalm_svr_problem* prob
                                 const ssnalm_options* opt, void* stream);
 
 /*
+ * The unified problem (P) of Section 1 (eq. Problem_P1_classical1) with a
+ * linear kernel:
+ *   min 1/2 x^T B B^T x + c^T x   s.t.  a^T x = d,  l <= x <= u,
+ * for a general B (n x q, dense, rows as given), c, a, l < u (n doubles
+ * each) and d.  The same Algorithms 1 and 3 run in omega = B^T w space; the
+ * projection onto {a^T x = d, l <= x <= u} (Section 3.2.1) finds the
+ * smallest zero of -a^T clip(v - lam a, l, u) + d by multisection over the
+ * breakpoints (v_i - u_i)/a_i, (v_i - l_i)/a_i (a_i = 0 components are
+ * clipped alone); the Newton matrix is I + sigma (B_J^T B_J - s s^T /
+ * (a_J^T a_J)), s = B_J^T a_J (Theorem 3.1; no rank-one term when a_J = 0).
+ * x^0 = 0 when it is feasible, else its projection.  After solving,
+ * info->obj is 1/2 |B^T x|^2 + c^T x, info->b (and b_out) the multiplier
+ * lam of the constraint a^T x = d in the projection of R_KKT, info->gap is
+ * NaN (no primal is defined), w_out = B^T x.
+ *   B: n x q row-major (dtype F64, F32 or BF16), borrowed; c, a, l, u:
+ *   device doubles, borrowed (valid and unchanged until ssnalm_destroy).
+ * E_BADARG: null pointer, kind not dense, n, q out of range, a non-finite
+ * a_i, l_i or u_i, l_i >= u_i, no x in [l, u] with a^T x = d, PCG or mixed
+ * precision requested, q > 2048.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t dtype;
+    int64_t n, q;
+    const void*   B;
+    const double* c;
+    const double* a;
+    const double* l;
+    const double* u;
+    double d;
+    double tol;
+} ssnalm_general_problem;
+
+ssnalm_status ssnalm_create_general(ssnalm_ctx** out, const ssnalm_general_problem* prob,
+                                    const ssnalm_options* opt, void* stream);
+
+/*
  * Solve (Algorithm 1 with Algorithm 3 as its inner solver).
  *   x0    : optional warm start, n doubles (device) or NULL for x^0 = 0.
  *           It is projected onto {y^T x = 0, 0 <= x <= C} first and omega^0

@@ -32,6 +32,12 @@ class SvrProblem(C.Structure):
                 ("tol", C.c_double)]
 
 
+class GeneralProblem(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("n", C.c_int64), ("q", C.c_int64),
+                ("B", C.c_void_p), ("c", C.c_void_p), ("a", C.c_void_p), ("l", C.c_void_p),
+                ("u", C.c_void_p), ("d", C.c_double), ("tol", C.c_double)]
+
+
 class Options(C.Structure):
     _fields_ = [("sigma0", C.c_double), ("rho", C.c_double), ("sigma_max", C.c_double),
                 ("mu", C.c_double), ("ls_delta", C.c_double), ("tau", C.c_double),
@@ -80,6 +86,7 @@ EXPORTS = [
     "ssnalm_ws_x0", "ssnalm_ws_solve", "ssnalm_set_profile", "ssnalm_ws_labels",
     "ssnalm_project_noalloc", "ssnalm_noalloc_max_n", "ssnalm_noalloc_scratch_bytes",
     "ssnalm_rff_features", "ssnalm_nystroem_features", "ssnalm_create_svr",
+    "ssnalm_create_general",
 ]
 
 _lib = None
@@ -149,6 +156,8 @@ def load(path: str | None = None):
     lib.ssnalm_noalloc_max_n.restype = i64
     lib.ssnalm_noalloc_scratch_bytes.argtypes = []
     lib.ssnalm_noalloc_scratch_bytes.restype = i64
+    lib.ssnalm_create_general.argtypes = [C.POINTER(vp), C.POINTER(GeneralProblem), C.POINTER(Options), vp]
+    lib.ssnalm_create_general.restype = i32
     lib.ssnalm_create_svr.argtypes = [C.POINTER(vp), C.POINTER(SvrProblem), C.POINTER(Options), vp]
     lib.ssnalm_create_svr.restype = i32
     lib.ssnalm_rff_features.argtypes = [vp, i32, i64, i64, vp, i64, vp, i32, vp]

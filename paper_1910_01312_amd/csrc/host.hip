@@ -128,6 +128,12 @@ struct ssnalm_ctx {
     int8_t* yphys = nullptr;         // nphys ones: plain products with X
     double* zc = nullptr;            // z_top - z_bot (nphys)
     uint8_t* mc = nullptr;           // mask_top + mask_bot (nphys)
+    // general form (ssnalm_create_general): a, l, u, d of the constraints,
+    // c = lin; the rows of X are B's rows (y holds ones)
+    bool gen = false;
+    GBox gbox{};
+    bool zero_feasible = true;       // x = 0 satisfies the constraints
+    double* gzc = nullptr;           // a_i [i in J], the coefficients of s = B_J^T a_J
     int refine_total = 0;
     // q-vectors
     double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
@@ -387,6 +393,16 @@ static const int kPassBatch = 5;
 // Projection of v (or of u - as*td, materialised into vout) into state k.
 static ssnalm_status project_into(ssnalm_ctx* c, const double* u, const double* td, double as,
                                   double* vout, int k, const ProjState* hint = nullptr) {
+    if (c->gen) {
+        launch_gproj_init(u, td, as, vout, c->gbox, c->n, dps(c, k), c->spart, c->st);
+        const double* v = td ? vout : u;
+        for (int i = 0; i < kPassBatch; ++i) {
+            prof_begin(c, SSNALM_K_PROJ);
+            launch_gproj_pass(v, c->gbox, c->n, dps(c, k), c->spart, c->st);
+            prof_end(c, SSNALM_K_PROJ, 32.0 * c->n, 0.0);
+        }
+        return SSNALM_OK;
+    }
     launch_proj_init(u, td, as, vout, c->y, c->n, c->C, dps(c, k), c->spart,
                      cnt(c, CNT_PROJ_INIT), c->st, hint);
     const double* v = td ? vout : u;
@@ -403,9 +419,37 @@ static ssnalm_status project_finish(ssnalm_ctx* c, const double* v, int k, bool*
     *more = false;
     if (c->hs->ps[k].done) return SSNALM_OK;
     *more = true;
+    if (c->gen) {
+        for (int i = 0; i < gproj_max_passes(); ++i)
+            launch_gproj_pass(v, c->gbox, c->n, dps(c, k), c->spart, c->st);
+        return SSNALM_OK;
+    }
     for (int i = 0; i < proj_max_passes(); ++i)
         launch_proj_pass(v, c->y, c->n, c->C, dps(c, k), c->spart, cnt(c, CNT_PROJ_PASS), c->st);
     return SSNALM_OK;
+}
+
+// x = Pi(v) from the final state k, with the free mask (when given), |J|
+// and the support count into the scalars.
+static void proj_apply(ssnalm_ctx* c, const double* v, int k, double* x, uint8_t* mask) {
+    if (c->gen)
+        launch_gfinalize(v, nullptr, nullptr, 0.0, c->gbox, c->n, dps(c, k), dps(c, k), nullptr, x,
+                         mask, dsc(c), c->spart, c->st);
+    else
+        launch_proj_apply(v, c->y, c->n, c->C, dps(c, k), x, mask, dsc(c), c->spart,
+                          cnt(c, CNT_APPLY), c->st);
+}
+
+// The line-search trial's n-side: x~ = Pi(v) from state k, its free mask,
+// |x~ - xk|^2 and the psi increment against the base state kb (at u_base).
+static void ls_fin(ssnalm_ctx* c, const double* v, const double* u_base, const double* td, double as,
+                   int k, int kb, const double* xk, double* x, uint8_t* mask) {
+    if (c->gen)
+        launch_gfinalize(v, u_base, td, as, c->gbox, c->n, dps(c, k), dps(c, kb), xk, x, mask, dsc(c),
+                         c->spart, c->st);
+    else
+        launch_ls_finalize(v, u_base, td, as, c->y, c->n, c->C, dps(c, k), dps(c, kb), xk, x, mask,
+                           dsc(c), c->spart, cnt(c, CNT_LS), c->st);
 }
 
 // ---------------------------------------------------------------- Newton
@@ -429,7 +473,12 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
             launch_syrk_gather(c->dtype, c->X, c->q, c->jlist, p, c->G, c->part, c->part_cap, c->st);
         prof_end(c, SSNALM_K_SYRK, (double)p * c->q * elem_bytes(c->dtype) + 4.0 * p + 8.0 * c->q * c->q,
                  (double)p * c->q * (c->q + 1));
-        launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
+        if (c->gen) {
+            const double den = c->hs->sc.aja;            // a_J^T a_J (0: no rank-one term)
+            launch_form_M_inv(c->G, sv, sigma, den > 0.0 ? 1.0 / den : 0.0, c->M, c->q, c->st);
+        } else {
+            launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
+        }
         prof_begin(c, SSNALM_K_CHOL);
         if (!c->mixed && c->q <= chol_small_max()) {
             launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
@@ -570,6 +619,16 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
 // ---------------------------------------------------------------- gradient
 // g = omega - A^T xt, s = X_J^T 1 (mask), and |g|^2, |omega|^2 into the scalars.
 static void gradient(ssnalm_ctx* c, const double* xt, const uint8_t* mask) {
+    if (c->gen) {
+        // g = omega - B^T x~; s = B_J^T a_J and a_J^T a_J (the rank-one term
+        // of Theorem 3.1's HS-Jacobian) from the coefficients a_i [i in J]
+        op_atmul(c, xt, nullptr, c->om, -1.0, c->g, nullptr);
+        launch_gcoef(c->gbox.a, mask, c->n, c->gzc, dsc(c), c->spart, c->st);
+        op_atmul(c, c->gzc, nullptr, nullptr, 1.0, c->sv, nullptr);
+        launch_dots(2, c->g, c->g, &dsc(c)->gnorm2, c->om, c->om, &dsc(c)->omega2, nullptr, nullptr,
+                    nullptr, c->q, c->spart, cnt(c, CNT_DOTS), c->st);
+        return;
+    }
     // s = X_J^T 1 rides along the dense transposed product; the sparse path
     // computes it from the compact copy of X_J in the Newton step
     op_atmul(c, xt, c->kind == SSNALM_DENSE ? mask : nullptr, c->om, -1.0, c->g, c->sv);
@@ -587,15 +646,18 @@ static ssnalm_status kkt(ssnalm_ctx* c, const double* x, const double* w, double
     STCHK(sync_state(c));
     bool more = false;
     STCHK(project_finish(c, c->nv2, 2, &more));
-    launch_kkt_finalize(c->nv2, x, c->nv, c->y, c->n, c->C, dps(c, 2), dsc(c), c->spart, cnt(c, CNT_KKT),
-                        c->st, c->lin, c->svr ? c->nphys : 0, c->svr_eps);
+    if (c->gen)
+        launch_gkkt_finalize(c->nv2, x, c->lin, c->gbox, c->n, dps(c, 2), dsc(c), c->spart, c->st);
+    else
+        launch_kkt_finalize(c->nv2, x, c->nv, c->y, c->n, c->C, dps(c, 2), dsc(c), c->spart,
+                            cnt(c, CNT_KKT), c->st, c->lin, c->svr ? c->nphys : 0, c->svr_eps);
     STCHK(sync_state(c));
     c->proj_passes += c->hs->ps[2].passes;
     c->proj_capped += c->hs->ps[2].approx;
     *R = std::sqrt(c->hs->sc.res2) / (1.0 + std::sqrt(c->hs->sc.x2));
     *b = c->hs->ps[2].lam;
     if (sumx) *sumx = c->hs->sc.sumx;
-    if (hinge) *hinge = c->hs->sc.hinge;
+    if (hinge) *hinge = c->gen ? NAN : c->hs->sc.hinge;   // no primal loss for the general form
     return SSNALM_OK;
 }
 
@@ -950,6 +1012,82 @@ extern "C" ssnalm_status ssnalm_create_svr(ssnalm_ctx** out, const ssnalm_svr_pr
     return SSNALM_OK;
 }
 
+extern "C" ssnalm_status ssnalm_create_general(ssnalm_ctx** out, const ssnalm_general_problem* pr,
+                                               const ssnalm_options* opt, void* stream) {
+    if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
+    *out = nullptr;
+    if (pr->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "the general form needs dense B");
+    if (pr->n < 1 || pr->q < 1 || pr->n >= INT32_MAX || pr->q >= INT32_MAX)
+        return fail(SSNALM_E_BADARG, "n and q must be in [1, 2^31)");
+    if (!pr->B || !pr->c || !pr->a || !pr->l || !pr->u)
+        return fail(SSNALM_E_BADARG, "B, c, a, l and u are required");
+    if (!std::isfinite(pr->d)) return fail(SSNALM_E_BADARG, "d must be finite");
+    ssnalm_options o;
+    if (opt) o = *opt; else ssnalm_default_options(&o);
+    if (o.precision != SSNALM_PREC_FP64) return fail(SSNALM_E_BADARG, "the general form runs in fp64 precision");
+    if (o.newton == SSNALM_NEWTON_PCG) return fail(SSNALM_E_BADARG, "the general form uses the Cholesky Newton step");
+    if (pr->q > std::max(chol_small_max(), chol_blocked_max()))
+        return fail(SSNALM_E_BADARG, "the general form needs q <= %d", std::max(chol_small_max(), chol_blocked_max()));
+    o.newton = SSNALM_NEWTON_CHOL;
+    const int64_t n = pr->n;
+    // a, l, u are checked on the host once the caller's stream has written them
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return fail(SSNALM_E_HIP, "waiting for the caller's stream failed");
+    bool zero_ok = pr->d == 0.0;
+    {
+        std::vector<double> ah(n), lh(n), uh(n);
+        if (hipMemcpy(ah.data(), pr->a, 8 * n, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(lh.data(), pr->l, 8 * n, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(uh.data(), pr->u, 8 * n, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(SSNALM_E_HIP, "reading a, l, u failed");
+        double lo = 0.0, hi = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!std::isfinite(ah[i]) || !std::isfinite(lh[i]) || !std::isfinite(uh[i]))
+                return fail(SSNALM_E_BADARG, "a, l, u must be finite (entry %lld)", (long long)i);
+            if (!(lh[i] < uh[i])) return fail(SSNALM_E_BADARG, "l_%lld >= u_%lld", (long long)i, (long long)i);
+            lo += std::min(ah[i] * lh[i], ah[i] * uh[i]);
+            hi += std::max(ah[i] * lh[i], ah[i] * uh[i]);
+            zero_ok = zero_ok && lh[i] <= 0.0 && uh[i] >= 0.0;
+        }
+        const double slack = 1e-12 * (std::fabs(lo) + std::fabs(hi) + 1.0);
+        if (pr->d < lo - slack || pr->d > hi + slack)
+            return fail(SSNALM_E_BADARG, "no x in [l, u] has a^T x = d");
+    }
+    int8_t* ones = nullptr;
+    if (hipMalloc(&ones, n) != hipSuccess) return fail(SSNALM_E_OOM, "allocation failed");
+    if (hipMemset(ones, 1, n) != hipSuccess) {
+        (void)hipFree(ones);
+        return fail(SSNALM_E_HIP, "memset failed");
+    }
+    ssnalm_problem p2;
+    memset(&p2, 0, sizeof p2);
+    p2.kind = SSNALM_DENSE;
+    p2.dtype = pr->dtype;
+    p2.n = n;
+    p2.q = pr->q;
+    p2.X = pr->B;
+    p2.y = ones;
+    p2.C = 1.0;                           // unused: the box is [l, u]
+    p2.tol = pr->tol;
+    ssnalm_ctx* c = nullptr;
+    ssnalm_status s = create_impl(&c, &p2, &o, stream, n);
+    if (s < 0) {
+        (void)hipFree(ones);
+        return s;
+    }
+    c->owned.push_back(ones);
+    c->gen = true;
+    c->gbox = GBox{pr->a, pr->l, pr->u, pr->d};
+    c->lin = pr->c;
+    c->zero_feasible = zero_ok;
+    if ((s = dalloc(c, &c->gzc, n)) < 0) {
+        ssnalm_destroy(c);
+        return s;
+    }
+    *out = c;
+    return SSNALM_OK;
+}
+
 static ssnalm_status create_impl(ssnalm_ctx** out, const ssnalm_problem* pr,
                                  const ssnalm_options* opt, void* stream, int64_t x_rows) {
     if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
@@ -1092,8 +1230,16 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
         STCHK(sync_state(c));
         bool more;
         STCHK(project_finish(c, x0, 3, &more));
-        launch_proj_apply(x0, c->y, n, c->C, dps(c, 3), c->xk, nullptr, dsc(c), c->spart,
-                          cnt(c, CNT_APPLY), c->st);
+        proj_apply(c, x0, 3, c->xk, nullptr);
+        op_atmul(c, c->xk, nullptr, nullptr, 1.0, c->om, nullptr);
+    } else if (!c->zero_feasible) {
+        // x^0 = Pi(0) when 0 violates the constraints (general form)
+        launch_fill(c->nv, 0.0, n, c->st);
+        STCHK(project_into(c, c->nv, nullptr, 0.0, nullptr, 3));
+        STCHK(sync_state(c));
+        bool more;
+        STCHK(project_finish(c, c->nv, 3, &more));
+        proj_apply(c, c->nv, 3, c->xk, nullptr);
         op_atmul(c, c->xk, nullptr, nullptr, 1.0, c->om, nullptr);
     } else {
         launch_fill(c->xk, 0.0, n, c->st);
@@ -1115,9 +1261,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
         bool more;
         STCHK(project_finish(c, c->u, c->base, &more));
         // x~, J and distance to x^k: reuse the line-search finalize with alpha = 0
-        launch_ls_finalize(c->u, c->u, nullptr, 0.0, c->y, n, c->C, dps(c, c->base),
-                           dps(c, c->base), c->xk, c->xt, c->jm, dsc(c), c->spart,
-                           cnt(c, CNT_LS), c->st);
+        ls_fin(c, c->u, c->u, nullptr, 0.0, c->base, c->base, c->xk, c->xt, c->jm);
         gradient(c, c->xt, c->jm);
         STCHK(sync_state(c));
         c->proj_passes += c->hs->ps[c->base].passes;
@@ -1152,15 +1296,11 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
                 // first passes finished the projection (they nearly always do):
                 // one host round trip per trial; otherwise more passes and the
                 // sums again
-                launch_ls_finalize(c->ut, c->u, c->td, alpha * sigma, c->y, n, c->C,
-                                   dps(c, trial), dps(c, c->base), c->xk, c->xtt, c->jmt,
-                                   dsc(c), c->spart, cnt(c, CNT_LS), c->st);
+                ls_fin(c, c->ut, c->u, c->td, alpha * sigma, trial, c->base, c->xk, c->xtt, c->jmt);
                 STCHK(sync_state(c));
                 STCHK(project_finish(c, c->ut, trial, &more));
                 if (more) {
-                    launch_ls_finalize(c->ut, c->u, c->td, alpha * sigma, c->y, n, c->C,
-                                       dps(c, trial), dps(c, c->base), c->xk, c->xtt, c->jmt,
-                                       dsc(c), c->spart, cnt(c, CNT_LS), c->st);
+                    ls_fin(c, c->ut, c->u, c->td, alpha * sigma, trial, c->base, c->xk, c->xtt, c->jmt);
                     STCHK(sync_state(c));
                 }
                 c->proj_passes += c->hs->ps[trial].passes;
@@ -1230,7 +1370,8 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     op_atmul(c, x_out, nullptr, nullptr, 1.0, c->qv, nullptr);
     launch_dots(1, c->qv, c->qv, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                 q, c->spart, cnt(c, CNT_DOTS), c->st);
-    launch_count_x(x_out, n, c->C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);
+    if (c->gen) launch_gcount(x_out, c->gbox, n, dsc(c), c->spart, c->st);
+    else launch_count_x(x_out, n, c->C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);
     if (c->lin)
         launch_dots(1, c->lin, x_out, &dsc(c)->cx, nullptr, nullptr, nullptr, nullptr, nullptr,
                     nullptr, n, c->spart, cnt(c, CNT_DOTS2), c->st);
@@ -1303,8 +1444,7 @@ extern "C" ssnalm_status ssnalm_op_project(ssnalm_ctx* c, const double* v, doubl
     STCHK(sync_state(c));
     bool more;
     STCHK(project_finish(c, v, 3, &more));
-    launch_proj_apply(v, c->y, c->n, c->C, dps(c, 3), x, free_mask, dsc(c), c->spart,
-                      cnt(c, CNT_APPLY), c->st);
+    proj_apply(c, v, 3, x, free_mask);
     HIPCHK(hipGetLastError());
     STCHK(sync_state(c));
     if (lam) *lam = c->hs->ps[3].lam;
@@ -1316,7 +1456,7 @@ extern "C" ssnalm_status ssnalm_op_project(ssnalm_ctx* c, const double* v, doubl
 extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mask, const double* g,
                                           double sigma, double cg_tol, double* d, int32_t* cg_iters) {
     if (!c || !free_mask || !g || !d) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr) return fail(SSNALM_E_BADARG, "op_newton is for C-SVC contexts");
+    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "op_newton is for C-SVC contexts");
     StreamScope scope_(c);
     if (!(sigma > 0.0)) return fail(SSNALM_E_BADARG, "sigma must be > 0");
     // s = X_J^T 1 and p
@@ -1343,7 +1483,7 @@ extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mas
 
 extern "C" ssnalm_status ssnalm_op_gram(ssnalm_ctx* c, const uint8_t* free_mask, double* G) {
     if (!c || !free_mask || !G) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr) return fail(SSNALM_E_BADARG, "op_gram is for C-SVC contexts");
+    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "op_gram is for C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE || !c->use_chol) return fail(SSNALM_E_BADARG, "Gram matrix needs a dense Cholesky context");
     launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
@@ -1376,8 +1516,7 @@ extern "C" ssnalm_status ssnalm_op_linesearch_trial(ssnalm_ctx* c, const double*
     STCHK(sync_state(c));
     bool more;
     STCHK(project_finish(c, c->ut, 1, &more));
-    launch_ls_finalize(c->ut, u, t, alpha * sigma, c->y, c->n, c->C, dps(c, 1), dps(c, 0), c->nv2,
-                       c->xtt, c->jmt, dsc(c), c->spart, cnt(c, CNT_LS), c->st);
+    ls_fin(c, c->ut, u, t, alpha * sigma, 1, 0, c->nv2, c->xtt, c->jmt);
     HIPCHK(hipGetLastError());
     STCHK(sync_state(c));
     if (lam_a) *lam_a = c->hs->ps[1].lam;
@@ -1418,7 +1557,7 @@ extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* 
 // means of x_i^T w1, margins m_i, and the projection X R.
 extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float* Z) {
     if (!c || !R || !Z) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr) return fail(SSNALM_E_BADARG, "ws_features is for C-SVC contexts");
+    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "ws_features is for C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "warm-start features need dense X");
     const int64_t n = c->n, q = c->q;
@@ -1461,7 +1600,7 @@ extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float
 
 extern "C" ssnalm_status ssnalm_ws_x0(ssnalm_ctx* c, const float* out, double* x0) {
     if (!c || !out || !x0) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr) return fail(SSNALM_E_BADARG, "ws_x0 is for C-SVC contexts");
+    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "ws_x0 is for C-SVC contexts");
     StreamScope scope_(c);
     launch_ws_x0(out, c->n, c->C, x0, c->st);
     HIPCHK(hipGetLastError());
@@ -1471,7 +1610,7 @@ extern "C" ssnalm_status ssnalm_ws_x0(ssnalm_ctx* c, const float* out, double* x
 extern "C" ssnalm_status ssnalm_ws_labels(ssnalm_ctx* c, const double* x, int32_t* status,
                                           float* target) {
     if (!c || !x || !status || !target) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr) return fail(SSNALM_E_BADARG, "ws_labels is for C-SVC contexts");
+    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "ws_labels is for C-SVC contexts");
     StreamScope scope_(c);
     launch_ws_labels(x, c->n, c->C, status, target, c->st);
     HIPCHK(hipGetLastError());
@@ -1484,7 +1623,7 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
                                          int32_t max_rounds, double* x_out, double* w_out,
                                          ssnalm_info* info, ssnalm_ws_stats* stats) {
     if (!c || !out || !x_out) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr) return fail(SSNALM_E_BADARG, "ws_solve is for C-SVC contexts");
+    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "ws_solve is for C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "screening needs dense X");
     if (!(keep_frac > 0.0) || keep_frac > 1.0) return fail(SSNALM_E_BADARG, "keep_frac must be in (0, 1]");

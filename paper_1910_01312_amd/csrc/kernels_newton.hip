@@ -159,6 +159,12 @@ __global__ void k_form_M(const double* __restrict__ G, const double* __restrict_
     M[e] = (i == j ? 1.0 : 0.0) + sigma * c;
 }
 
+void launch_form_M_inv(const double* G, const double* sv, double sigma, double inv_den, double* M,
+                       int64_t q, hipStream_t s) {
+    const int64_t tot = q * q;
+    SSN_LAUNCH(k_form_M, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, G, sv, sigma, inv_den,
+               M, q);
+}
 void launch_form_M(const double* G, const double* sv, double sigma, int64_t p, double* M, int64_t q,
                    hipStream_t s) {
     const int64_t tot = q * q;

@@ -46,6 +46,7 @@ struct ProjState {
     int    pad_;
     double hint;          // multiplier of a nearby projection (warm start)
     long long npos;       // number of y_i = +1
+    double gbase;         // general form: sum of the left constants K_i plus d
 };
 
 // Scalars produced by reductions, read back by the host in one copy.
@@ -61,6 +62,7 @@ struct Scalars {
     double sumx;          // e^T x
     double hinge;         // KKT: the primal's loss sum at the KKT bias
     double cx;            // c^T x of a returned x (problems with a linear term)
+    double aja;           // general form: a_J^T a_J
     long long p;          // |J|
     long long nnzj;       // nonzeros of the rows in J (sparse input)
     long long nfix;       // chunk-crossing column runs of the compact X_J copy
@@ -423,6 +425,33 @@ void launch_rbf_block(int dtype, const void* X, int64_t q, const int32_t* arows,
 void launch_nys_solve(const double* K, int64_t n, int64_t r, const double* F, const double* inv,
                       double* Zw, hipStream_t s);
 void launch_copy_z(const double* Zw, int64_t count, void* Z, int z_f64, hipStream_t s);
+
+// General form (P): projection onto {l <= x <= u, a^T x = d} and the
+// general problem's n-vector steps (kernels_gproj.hip)
+struct GBox {
+    const double* a;
+    const double* l;
+    const double* u;
+    double d;
+};
+void launch_gproj_init(const double* u0, const double* td, double as, double* vout, const GBox& box,
+                       int64_t n, ProjState* st, double* part, hipStream_t s);
+void launch_gproj_pass(const double* v, const GBox& box, int64_t n, ProjState* st, double* part,
+                       hipStream_t s);
+int  gproj_max_passes();
+// x = clip(v - lam a, l, u), J mask, |x - xk|^2 (xk), psi increment (u_base), |J|, #(x > l)
+void launch_gfinalize(const double* v, const double* u_base, const double* td, double as,
+                      const GBox& box, int64_t n, const ProjState* st, const ProjState* st_base,
+                      const double* xk, double* x, uint8_t* mask, Scalars* sc, double* part,
+                      hipStream_t s);
+void launch_gkkt_finalize(const double* v, const double* x, const double* c, const GBox& box,
+                          int64_t n, const ProjState* st, Scalars* sc, double* part, hipStream_t s);
+void launch_gcoef(const double* a, const uint8_t* mask, int64_t n, double* zc, Scalars* sc,
+                  double* part, hipStream_t s);
+void launch_gcount(const double* x, const GBox& box, int64_t n, Scalars* sc, double* part,
+                   hipStream_t s);
+void launch_form_M_inv(const double* G, const double* sv, double sigma, double inv_den, double* M,
+                       int64_t q, hipStream_t s);
 
 // eps-SVR as an instance of (P) (kernels_vec.hip): labels a = [e; -e] and
 // c = [eps + y; eps - y] from the targets; B v from X v; the folds giving

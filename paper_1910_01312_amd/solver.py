@@ -253,6 +253,35 @@ class SVR(Solver):
         self._lib = lib
 
 
+class General(Solver):
+    """The unified problem (P) (ssnalm_create_general): min 1/2 |B^T x|^2 +
+    c^T x s.t. a^T x = d, l <= x <= u, with dense B (n, q) and vectors c, a,
+    l, u (n).  solve() returns (x, w = B^T x, info); info["b"] is the
+    multiplier of a^T x = d."""
+
+    def __init__(self, B, c, a, l, u, d=0.0, tol=1e-6, *, bf16=False, **opts):
+        lib = L.load()
+        self._keep = []
+        Bd, dt = _dense_dev(B, bf16)
+        vecs = [_to_dev(v, torch.float64) for v in (c, a, l, u)]
+        self._keep += [Bd, *vecs]
+        n, q = Bd.shape
+        prob = L.GeneralProblem()
+        prob.kind, prob.dtype = L.DENSE, dt
+        prob.n, prob.q = int(n), int(q)
+        prob.B = Bd.data_ptr()
+        prob.c, prob.a, prob.l, prob.u = (v.data_ptr() for v in vecs)
+        prob.d, prob.tol = float(d), float(tol)
+        self.n, self.q, self.C, self.tol = int(n), int(q), float("nan"), float(tol)
+        self.problem = prob
+        self.options = make_options(**opts)
+        ctx = C.c_void_p()
+        L.check(lib.ssnalm_create_general(C.byref(ctx), C.byref(prob), C.byref(self.options),
+                                          _stream_handle()), "ssnalm_create_general")
+        self._ctx = ctx
+        self._lib = lib
+
+
 def solve(X, y, C_, tol=1e-6, x0=None, **opts):
     """One-shot solve: returns (x, w, info)."""
     with Solver(X, y, C_, tol, **opts) as s:
