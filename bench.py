@@ -41,20 +41,18 @@ def log(*a):
 # commands and readings).  Reported only while the sources of those kernels
 # are byte-identical to the ones measured (sha256 of each file below).
 MEASURED_TRAFFIC = {
-    ("sparse-text", "atmul"): {
-        "fetch_kib": 2827190, "write_kib": 272430, "calls": 21,
+    # X_J^T w in the CG (k_keyed_tr<float, 0> + k_keyed_fix_list), sparse text
+    # workload: counters summed over the dispatches of one warm-up and one
+    # timed solve, divided by the 2 x 1328 CG iterations that did work
+    # (profiles/sparse_text_atmul_J_hbm_traffic.md)
+    ("sparse-text", "atmul_J"): {
+        "fetch_kib": 52689265.875 + 1168507.875, "write_kib": 2634931.6875 + 299527.5, "calls": 2656,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "files": {
-            "paper_1910_01312_amd/csrc/kernels_sparse.hip":
-                "19b37f1fba2b5268a213d5bcfc397e7ca8e07157e8afec86b08389d997dc4212",
-            "paper_1910_01312_amd/csrc/kernels_vec.hip":
-                "d2593ff52a12f7214c9f9be4269b350a4c1b3ddc9e466db259125b4240e2046e",
-            "paper_1910_01312_amd/csrc/kernels_dense.hip":
-                "c8ccb65d530cb18473018fbcade3b41e9021dc52ffd8421f69feb295fe924e7b",
+            "paper_1910_01312_amd/csrc/kernels_cg.hip":
+                "db1241779d7540f6fada47c7c73fb03f653414824ff6580943a46db9963b6e0e",
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
-            "paper_1910_01312_amd/csrc/host.hip":
-                "17d533eb863f3904d866eb5cfa41c348eb401fcf648fa24b2563f96ba99b2044",
         },
     },
 }
@@ -78,11 +76,10 @@ def measured_traffic(workload, cls):
 
 # the kernels of each class that a traffic probe sums, and their sources
 TRAFFIC_KERNELS = {
-    "atmul": (["k_mul_y", "k_segsum<float, false, 0>", "k_segsum_fix", "k_reduce_cols"],
+    "atmul": (["k_mul_y", "k_segsum<float, 0>", "k_segsum_fix", "k_reduce_cols"],
               ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/kernels_vec.hip",
-               "paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/dev_common.h",
-               "paper_1910_01312_amd/csrc/host.hip"]),
-    "amul": (["k_segsum<float, false, 0>", "k_segsum_fix"],
+               "paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
+    "amul": (["k_segsum<float, 0>", "k_segsum_fix"],
              ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
 }
 
