@@ -231,6 +231,61 @@ ssnalm_status ssnalm_create_general(ssnalm_ctx** out, const ssnalm_general_probl
                                     const ssnalm_options* opt, void* stream);
 
 /*
+ * The C-SVC dual with a nonlinear kernel (Section 1, eq.
+ * Def_Dual_of_C_SVM_Problem with Q_ij = y_i y_j k(x~_i, x~_j); the problem
+ * of Table 3):
+ *   SSNALM_KERNEL_RBF    : k(x, z) = exp(-|x - z|^2 / (2 alpha)), alpha > 0
+ *                          (the Gaussian kernel of Section 4);
+ *   SSNALM_KERNEL_LINEAR : k(x, z) = x^T z (alpha unused), the linear C-SVC
+ *                          through the same kernel path.
+ * The method runs in the paper's w-space (w in R^n): Q is formed once, in
+ * fp64, from the samples by a tiled kernel-evaluation pass and kept in
+ * device memory (n^2 doubles: n = 20000 takes 3.2 GB, n = 100000 80 GB);
+ * the products Q v read only the rows of Q at the nonzeros of v, and the
+ * Newton step of Algorithm 3 is the p x p system of Proposition 5 on the
+ * free set J (p = |J|), written with the projector
+ * Pi = I - y_J y_J^T / p inside the matrix:
+ *   (I_p + sigma Pi Q_JJ Pi) v = Pi (Q s)_J,   s = w - Pi(u(w)),
+ *   z = sigma Pi v,   d = -s + z on J,   Q d = -Q s + Q_{:,J} z,
+ * solved by Cholesky (p <= 2048) or by Jacobi-preconditioned CG on the same
+ * matrix to |residual| <= min(eta, |grad|^(1+tau)) (p > 2048, or always
+ * with opt.newton = SSNALM_NEWTON_PCG).  Norms of the stopping tests are
+ * Q-norms (|omega| = (w^T Q w)^(1/2), |grad| = (s^T Q s)^(1/2)), the
+ * omega-space norms of the linear path.
+ *   dtype : F64, F32 or BF16 samples (values used in fp64).
+ *   X     : n x q row-major (device), read during ssnalm_create_kernel only.
+ *   y     : n labels +-1 (int8, device), borrowed (valid until destroy).
+ * ssnalm_solve then returns x_out (n), b_out / info->b (the bias of the
+ * decision function sum_i x_i y_i k(x~_i, .) + b, the lam_hat of R_KKT's
+ * projection), info->obj = 1/2 x^T Q x - e^T x and info->gap, the relative
+ * gap to the primal 1/2 x^T Q x + C sum_i max(0, 1 - (Q x)_i - y_i b);
+ * w_out must be NULL (the primal weights live in the kernel's feature
+ * space).  ssnalm_op_amul on such a context computes t = Q v (v, t: n
+ * doubles), ssnalm_op_rkkt, ssnalm_op_project, ssnalm_op_linesearch_trial,
+ * ssnalm_ws_labels and ssnalm_ws_x0 work as for ssnalm_create;
+ * ssnalm_op_kernel_newton takes the Newton step; ssnalm_op_atmul,
+ * ssnalm_op_newton, ssnalm_op_gram, ssnalm_ws_features, ssnalm_ws_solve and
+ * opt.precision = MIXED are rejected.
+ * E_BADARG: null pointer, unknown kernel, n out of [1, 2^31), q < 1,
+ * alpha not finite and > 0 (RBF), labels not +-1, C or tol invalid.
+ * E_OOM: Q does not fit in device memory.
+ */
+enum { SSNALM_KERNEL_RBF = 0, SSNALM_KERNEL_LINEAR = 1 };
+typedef struct {
+    int32_t kernel;
+    int32_t dtype;
+    int64_t n, q;
+    const void*   X;
+    const int8_t* y;
+    double C;
+    double alpha;
+    double tol;
+} ssnalm_kernel_problem;
+
+ssnalm_status ssnalm_create_kernel(ssnalm_ctx** out, const ssnalm_kernel_problem* prob,
+                                   const ssnalm_options* opt, void* stream);
+
+/*
  * Solve (Algorithm 1 with Algorithm 3 as its inner solver).
  *   x0    : optional warm start, n doubles (device) or NULL for x^0 = 0.
  *           It is projected onto {y^T x = 0, 0 <= x <= C} first and omega^0
@@ -339,6 +394,16 @@ ssnalm_status ssnalm_op_newton(ssnalm_ctx* ctx, const uint8_t* free_mask,
                                const double* g, double sigma, double cg_tol,
                                double* d, int32_t* cg_iters);
 
+/* Kernel contexts (ssnalm_create_kernel): the Newton step of Algorithm 3
+ * by Proposition 5's p x p system, as ssnalm_solve takes it.  free_mask: n
+ * bytes (device, 1 = in J); s = w - Pi(u(w)): n doubles (device); d, Qd:
+ * n doubles (device) receive the representative d = -s + z on J and Q d;
+ * dQd: host double (d^T Q d); cg_iters: host or NULL (0 for Cholesky).
+ * cg_tol: the CG tolerance when the step is solved by CG. */
+ssnalm_status ssnalm_op_kernel_newton(ssnalm_ctx* ctx, const uint8_t* free_mask,
+                                      const double* s, double sigma, double cg_tol,
+                                      double* d, double* Qd, double* dQd, int32_t* cg_iters);
+
 /* Gram matrix of the free rows, G = X_J^T X_J (q x q, row-major, full),
  * the product inside A^T P A of Proposition 5 (labels cancel).  Uses the
  * context's SYRK: bf16 operands on the matrix cores with fp32 accumulation
@@ -370,7 +435,10 @@ enum {
     SSNALM_K_PROJ = 4,        /* one multisection pass of the projection             */
     SSNALM_K_SYRK = 5,        /* X_J^T X_J                                           */
     SSNALM_K_CHOL = 6,        /* Cholesky factor + solves                            */
-    SSNALM_K_COUNT = 7
+    SSNALM_K_QCOLS = 7,       /* kernel contexts: Q v over the rows of Q at the      */
+                              /* nonzeros of v (gradient, Newton step, KKT)          */
+    SSNALM_K_QJJ = 8,         /* kernel contexts: the p x p Newton matrix from Q_JJ   */
+    SSNALM_K_COUNT = 9
 };
 typedef struct {
     int64_t launches;         /* timed launches since the last reset                 */

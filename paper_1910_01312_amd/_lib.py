@@ -38,6 +38,15 @@ class GeneralProblem(C.Structure):
                 ("u", C.c_void_p), ("d", C.c_double), ("tol", C.c_double)]
 
 
+KERNEL_RBF, KERNEL_LINEAR = 0, 1
+
+
+class KernelProblem(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("dtype", C.c_int32), ("n", C.c_int64), ("q", C.c_int64),
+                ("X", C.c_void_p), ("y", C.c_void_p), ("C", C.c_double), ("alpha", C.c_double),
+                ("tol", C.c_double)]
+
+
 class Options(C.Structure):
     _fields_ = [("sigma0", C.c_double), ("rho", C.c_double), ("sigma_max", C.c_double),
                 ("mu", C.c_double), ("ls_delta", C.c_double), ("tau", C.c_double),
@@ -73,8 +82,8 @@ class KStat(C.Structure):
                 ("flops", C.c_double)]
 
 
-K_AMUL, K_ATMUL, K_AMUL_J, K_ATMUL_J, K_PROJ, K_SYRK, K_CHOL, K_COUNT = range(8)
-K_NAMES = ["amul", "atmul", "amul_J", "atmul_J", "proj_pass", "syrk", "chol"]
+K_AMUL, K_ATMUL, K_AMUL_J, K_ATMUL_J, K_PROJ, K_SYRK, K_CHOL, K_QCOLS, K_QJJ, K_COUNT = range(10)
+K_NAMES = ["amul", "atmul", "amul_J", "atmul_J", "proj_pass", "syrk", "chol", "qcols", "qjj"]
 
 EXPORTS = [
     "ssnalm_default_options", "ssnalm_create", "ssnalm_solve", "ssnalm_solve_batch",
@@ -86,7 +95,7 @@ EXPORTS = [
     "ssnalm_ws_x0", "ssnalm_ws_solve", "ssnalm_set_profile", "ssnalm_ws_labels",
     "ssnalm_project_noalloc", "ssnalm_noalloc_max_n", "ssnalm_noalloc_scratch_bytes",
     "ssnalm_rff_features", "ssnalm_nystroem_features", "ssnalm_create_svr",
-    "ssnalm_create_general",
+    "ssnalm_create_general", "ssnalm_create_kernel", "ssnalm_op_kernel_newton",
 ]
 
 _lib = None
@@ -170,6 +179,10 @@ def load(path: str | None = None):
     lib.ssnalm_ws_x0.restype = i32
     lib.ssnalm_ws_solve.argtypes = [vp, vp, dbl, i32, vp, vp, C.POINTER(Info), C.POINTER(WsStats)]
     lib.ssnalm_ws_solve.restype = i32
+    lib.ssnalm_create_kernel.argtypes = [C.POINTER(vp), C.POINTER(KernelProblem), C.POINTER(Options), vp]
+    lib.ssnalm_create_kernel.restype = i32
+    lib.ssnalm_op_kernel_newton.argtypes = [vp, vp, vp, dbl, dbl, vp, vp, C.POINTER(dbl), C.POINTER(i32)]
+    lib.ssnalm_op_kernel_newton.restype = i32
     lib.ssnalm_set_profile.argtypes = [vp, i32]
     lib.ssnalm_set_profile.restype = i32
     _lib = lib

@@ -134,6 +134,20 @@ struct ssnalm_ctx {
     GBox gbox{};
     bool zero_feasible = true;       // x = 0 satisfies the constraints
     double* gzc = nullptr;           // a_i [i in J], the coefficients of s = B_J^T a_J
+    // kernel C-SVC (ssnalm_create_kernel): the resident Q (n x n, row stride
+    // kld), the w-space n-vectors and the p-space Newton buffers
+    bool kern = false;
+    double* Qk = nullptr;
+    int64_t kld = 0;
+    double *kw = nullptr, *ks = nullptr, *kqs = nullptr, *kd = nullptr;
+    uint8_t* knz = nullptr;          // nonzero mask of a product's input
+    int32_t* klist = nullptr;        // its support, compacted
+    double *kaJ = nullptr, *kgJ = nullptr, *kr = nullptr, *krhs = nullptr, *kv = nullptr,
+           *kz = nullptr;
+    double *kcx = nullptr, *kcr = nullptr, *kcz = nullptr, *kcp = nullptr, *kcap = nullptr,
+           *kdiag = nullptr, *kt1 = nullptr, *kt2 = nullptr;
+    double* kpart = nullptr;         // kQcolsMaxChunks x n partial rows
+    int64_t kchol = 0;               // largest p solved by Cholesky
     int refine_total = 0;
     // q-vectors
     double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
@@ -638,9 +652,16 @@ static void gradient(ssnalm_ctx* c, const double* xt, const uint8_t* mask) {
 
 // ---------------------------------------------------------------- KKT
 // R_KKT(x) of eq. Def_Rkkt with Qx = A w, w = A^T x given (q-vector).
+// kkt_nv: the same with Q x already in c->nv.
+static ssnalm_status kkt_nv(ssnalm_ctx* c, const double* x, double* R, double* b, double* sumx,
+                            double* hinge = nullptr);
 static ssnalm_status kkt(ssnalm_ctx* c, const double* x, const double* w, double* R, double* b,
                          double* sumx, double* hinge = nullptr) {
     op_amul(c, w, c->nv);                                       // Qx
+    return kkt_nv(c, x, R, b, sumx, hinge);
+}
+static ssnalm_status kkt_nv(ssnalm_ctx* c, const double* x, double* R, double* b, double* sumx,
+                            double* hinge) {
     launch_kkt_prepare(x, c->nv, c->nv2, c->n, c->st, c->lin);  // v = x - Qx - c
     STCHK(project_into(c, c->nv2, nullptr, 0.0, nullptr, 2));
     STCHK(sync_state(c));
@@ -658,6 +679,127 @@ static ssnalm_status kkt(ssnalm_ctx* c, const double* x, const double* w, double
     *b = c->hs->ps[2].lam;
     if (sumx) *sumx = c->hs->sc.sumx;
     if (hinge) *hinge = c->gen ? NAN : c->hs->sc.hinge;   // no primal loss for the general form
+    return SSNALM_OK;
+}
+
+// ---------------------------------------------------------------- kernel C-SVC
+// Products with the resident Q of a kernel context (rows of Q at the listed
+// indices; coefficients v[list_k] when by_row, else v[k]):
+//   out = (base ? base : 0) + sign * sum_k coef_k Q[list_k][:].
+static void qlist_prod(ssnalm_ctx* c, const int32_t* list, int64_t m, const double* v, int by_row,
+                       double* out, const double* base = nullptr, double sign = 1.0) {
+    const int64_t n = c->n;
+    const int nch = qcols_chunks(n, m);
+    prof_begin(c, SSNALM_K_QCOLS);
+    launch_qcols(c->Qk, n, c->kld, list, m, v, by_row, c->kpart, nch, c->st);
+    launch_reduce_cols(c->kpart, nch, n, base, sign, out, c->st);
+    prof_end(c, SSNALM_K_QCOLS, 8.0 * (double)m * n + 12.0 * m + (base ? 16.0 : 8.0) * n,
+             2.0 * (double)m * n);
+}
+
+// out = Q v over the support of v (one host round trip for its size).
+static ssnalm_status qprod(ssnalm_ctx* c, const double* v, double* out) {
+    launch_nz_mask(v, c->n, c->knz, c->st);
+    launch_compact(c->knz, c->n, c->klist, &dsc(c)->km, c->blk, cnt(c, CNT_CMP), c->st);
+    STCHK(sync_state(c));
+    qlist_prod(c, c->klist, c->hs->sc.km, v, 1, out);
+    return SSNALM_OK;
+}
+
+// The w-space gradient: s = w - x~, Q s, and the Q-norms |s|_Q^2 (gnorm2),
+// |w|_Q^2 (omega2) into the scalars.
+static ssnalm_status kernel_gradient(ssnalm_ctx* c, const double* xt) {
+    launch_sub(c->kw, xt, c->ks, c->n, c->st);
+    STCHK(qprod(c, c->ks, c->kqs));
+    launch_dots(2, c->ks, c->kqs, &dsc(c)->gnorm2, c->kw, c->aw, &dsc(c)->omega2, nullptr, nullptr,
+                nullptr, c->n, c->spart, cnt(c, CNT_DOTS), c->st);
+    return SSNALM_OK;
+}
+
+// Newton step of Algorithm 3 by Proposition 5 (p x p system on the free set
+// J of mask, p = |J|), for s and g = Q s:
+//   (I_p + sigma Pi Q_JJ Pi) v = Pi g_J,  Pi = I - a a^T / p,  a = y_J,
+//   z = sigma Pi v,  d = -s + z on J,  t = Q d = -g + sum_b z_b Q[J_b][:].
+// Cholesky when p <= kchol (and opt.newton is not PCG), else Jacobi PCG on
+// the same matrix to |M v - Pi g_J| <= cg_tol.
+static ssnalm_status kernel_newton(ssnalm_ctx* c, const uint8_t* mask, int64_t p, const double* s,
+                                   const double* g, double sigma, double cg_tol, double* d, double* t,
+                                   int* cg_iters, bool* direct_out) {
+    *cg_iters = 0;
+    *direct_out = false;
+    const int64_t n = c->n;
+    if (p == 0) {
+        launch_scale_copy(d, s, -1.0, n, c->st);
+        launch_scale_copy(t, g, -1.0, n, c->st);
+        return SSNALM_OK;
+    }
+    Scalars* ds = dsc(c);
+    launch_compact(mask, n, c->jlist, &ds->p, c->blk, cnt(c, CNT_CMP), c->st);
+    launch_kgather(c->jlist, p, c->y, g, c->kaJ, c->kgJ, c->st);
+    launch_dots(1, c->kaJ, c->kgJ, &ds->kd0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, p,
+                c->spart, cnt(c, CNT_DOTS), c->st);
+    launch_kcenter(c->kgJ, c->kaJ, &ds->kd0, p, 1.0, nullptr, c->krhs, c->st);          // Pi g_J
+    const bool direct = c->opt.newton != SSNALM_NEWTON_PCG && p <= c->kchol;
+    prof_begin(c, SSNALM_K_QJJ);
+    launch_qjj_mv(c->Qk, c->kld, c->jlist, p, c->kaJ, c->kr, c->st);                   // r = Q_JJ a
+    launch_dots(1, c->kaJ, c->kr, &ds->kd1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, p,
+                c->spart, cnt(c, CNT_DOTS), c->st);                                   // rho = a^T r
+    if (direct)
+        launch_qjj_form(c->Qk, c->kld, c->jlist, p, c->kaJ, c->kr, &ds->kd1, sigma, c->M, c->st);
+    else
+        launch_qjj_diag(c->Qk, c->kld, c->jlist, p, c->kaJ, c->kr, &ds->kd1, sigma, c->kdiag, c->st);
+    prof_end(c, SSNALM_K_QJJ, 8.0 * (double)p * p * (direct ? 3.0 : 1.0) + 24.0 * p,
+             (direct ? 8.0 : 2.0) * (double)p * p);
+    const double* vneg;                               // -M^{-1} Pi g_J
+    if (direct) {
+        *direct_out = true;
+        prof_begin(c, SSNALM_K_CHOL);
+        if (p <= chol_small_max()) {
+            launch_chol_solve_small(c->M, c->krhs, c->kv, p, ds, c->st);
+        } else {
+            launch_chol_factor_blocked(c->M, p, c->linv, ds, c->st);
+            launch_chol_solve_factored(c->M, c->linv, c->krhs, c->kv, p, c->st);
+        }
+        prof_end(c, SSNALM_K_CHOL, 8.0 * (double)p * p, (double)p * p * p / 3.0 + 2.0 * (double)p * p);
+        vneg = c->kv;
+    } else {
+        const double tol2 = cg_tol * cg_tol;
+        launch_pcg_init(c->krhs, c->kdiag, c->kcx, c->kcr, c->kcz, c->kcp, p, tol2, ds, c->spart,
+                        cnt(c, CNT_PCG), c->st);
+        STCHK(sync_state(c));
+        int it = 0;
+        while (it < c->opt.max_cg && !c->hs->sc.cg_done) {
+            const int batch = std::min(8, c->opt.max_cg - it);
+            for (int b = 0; b < batch; ++b) {
+                // Ap = p + sigma Pi Q_JJ Pi p
+                launch_dots(1, c->kaJ, c->kcp, &ds->kd2, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, p, c->spart, cnt(c, CNT_DOTS), c->st);
+                launch_kcenter(c->kcp, c->kaJ, &ds->kd2, p, 1.0, nullptr, c->kt1, c->st);
+                prof_begin(c, SSNALM_K_QJJ);
+                launch_qjj_mv(c->Qk, c->kld, c->jlist, p, c->kt1, c->kt2, c->st);
+                prof_end(c, SSNALM_K_QJJ, 8.0 * (double)p * p + 20.0 * p, 2.0 * (double)p * p);
+                launch_dots(1, c->kaJ, c->kt2, &ds->kd2, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, p, c->spart, cnt(c, CNT_DOTS), c->st);
+                launch_kcenter(c->kt2, c->kaJ, &ds->kd2, p, sigma, c->kcp, c->kcap, c->st);
+                launch_pcg_pap(c->kcp, c->kcap, p, ds, c->spart, cnt(c, CNT_PCG2), c->st);
+                launch_pcg_step(c->kcx, c->kcr, c->kcp, c->kcap, c->kdiag, c->kcz, p, ds, tol2, c->spart,
+                                cnt(c, CNT_PCG3), c->st);
+                launch_pcg_dir(c->kcp, c->kcz, p, ds, c->st);
+            }
+            it += batch;
+            STCHK(sync_state(c));
+        }
+        *cg_iters = c->hs->sc.cg_count;
+        vneg = c->kcx;
+    }
+    // z = sigma Pi v = -sigma Pi vneg
+    launch_dots(1, c->kaJ, vneg, &ds->kd2, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, p,
+                c->spart, cnt(c, CNT_DOTS), c->st);
+    launch_kcenter(vneg, c->kaJ, &ds->kd2, p, -sigma, nullptr, c->kz, c->st);
+    launch_scale_copy(d, s, -1.0, n, c->st);
+    launch_scatter_add(c->jlist, p, c->kz, d, c->st);
+    qlist_prod(c, c->jlist, p, c->kz, 0, t);
+    launch_axpy(t, g, -1.0, n, c->st);
     return SSNALM_OK;
 }
 
@@ -1088,6 +1230,79 @@ extern "C" ssnalm_status ssnalm_create_general(ssnalm_ctx** out, const ssnalm_ge
     return SSNALM_OK;
 }
 
+extern "C" ssnalm_status ssnalm_create_kernel(ssnalm_ctx** out, const ssnalm_kernel_problem* pr,
+                                              const ssnalm_options* opt, void* stream) {
+    if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
+    *out = nullptr;
+    if (pr->kernel != SSNALM_KERNEL_RBF && pr->kernel != SSNALM_KERNEL_LINEAR)
+        return fail(SSNALM_E_BADARG, "unknown kernel %d", (int)pr->kernel);
+    if (pr->kernel == SSNALM_KERNEL_RBF && !(pr->alpha > 0.0 && std::isfinite(pr->alpha)))
+        return fail(SSNALM_E_BADARG, "alpha must be finite and > 0");
+    if (!pr->X) return fail(SSNALM_E_BADARG, "X missing");
+    ssnalm_options o;
+    if (opt) o = *opt; else ssnalm_default_options(&o);
+    if (o.precision != SSNALM_PREC_FP64) return fail(SSNALM_E_BADARG, "kernel problems run in fp64 precision");
+    // the base context needs no q x q Newton buffers: built in PCG mode, the
+    // requested mode restored afterwards
+    ssnalm_options o2 = o;
+    o2.newton = SSNALM_NEWTON_PCG;
+    ssnalm_problem p2;
+    memset(&p2, 0, sizeof p2);
+    p2.kind = SSNALM_DENSE;
+    p2.dtype = pr->dtype;
+    p2.n = pr->n;
+    p2.q = pr->q;
+    p2.X = pr->X;
+    p2.y = pr->y;
+    p2.C = pr->C;
+    p2.tol = pr->tol;
+    ssnalm_ctx* c = nullptr;
+    ssnalm_status s = create_impl(&c, &p2, &o2, stream, pr->n);
+    if (s < 0) return s;
+    c->opt.newton = o.newton;
+    c->kern = true;
+    const int64_t n = c->n;
+    auto bail = [&](ssnalm_status st) { ssnalm_destroy(c); return st; };
+    c->kld = (n + 31) / 32 * 32;
+    {
+        void* q = nullptr;
+        const size_t bytes = (size_t)n * (size_t)c->kld * sizeof(double);
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(SSNALM_E_OOM, "Q (%lld x %lld doubles, %zu bytes) does not fit in device memory",
+                             (long long)n, (long long)n, bytes));
+        }
+        c->owned.push_back(q);
+        c->Qk = (double*)q;
+    }
+#define KALLOC(ptr, cnt_)                                         \
+    do {                                                          \
+        if ((s = dalloc(c, &(ptr), (cnt_))) < 0) return bail(s);  \
+    } while (0)
+    c->kchol = std::min<int64_t>(n, chol_blocked_max());
+    KALLOC(c->kw, n); KALLOC(c->ks, n); KALLOC(c->kqs, n); KALLOC(c->kd, n);
+    KALLOC(c->knz, n); KALLOC(c->klist, n);
+    KALLOC(c->kaJ, n); KALLOC(c->kgJ, n); KALLOC(c->kr, n); KALLOC(c->krhs, n); KALLOC(c->kv, n);
+    KALLOC(c->kz, n);
+    KALLOC(c->kcx, n); KALLOC(c->kcr, n); KALLOC(c->kcz, n); KALLOC(c->kcp, n); KALLOC(c->kcap, n);
+    KALLOC(c->kdiag, n); KALLOC(c->kt1, n); KALLOC(c->kt2, n);
+    KALLOC(c->kpart, (int64_t)kQcolsMaxChunks * n);
+    KALLOC(c->M, c->kchol * c->kchol);
+    KALLOC(c->linv, chol_inv_size(c->kchol));
+    double* norms = nullptr;
+    KALLOC(norms, n);
+#undef KALLOC
+    const int rbf = pr->kernel == SSNALM_KERNEL_RBF;
+    if (rbf) launch_row_norms(pr->dtype, pr->X, nullptr, n, pr->q, norms, c->st);
+    launch_kernel_q(pr->dtype, pr->X, n, pr->q, norms, pr->y, rbf, pr->alpha, c->Qk, c->kld, c->st);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->st) != hipSuccess)
+        return bail(fail(SSNALM_E_HIP, "forming Q failed"));
+    // X is not read after this call
+    c->X = nullptr;
+    *out = c;
+    return SSNALM_OK;
+}
+
 static ssnalm_status create_impl(ssnalm_ctx** out, const ssnalm_problem* pr,
                                  const ssnalm_options* opt, void* stream, int64_t x_rows) {
     if (!out || !pr) return fail(SSNALM_E_BADARG, "null argument");
@@ -1210,8 +1425,182 @@ static ssnalm_status create_impl(ssnalm_ctx** out, const ssnalm_problem* pr,
 }
 
 // ---------------------------------------------------------------- solve
+// Algorithm 1 with Algorithm 3 for a kernel context, in w-space: the state
+// is w (kw) with Q w (aw); the gradient is Q s with s = w - Pi(u(w)) (ks,
+// kqs); the Newton step gives d (kd) and Q d (td).  The scalars of the
+// omega-space loop are Q-inner products: |omega|^2 = w^T Q w, |g|^2 =
+// s^T Q s, g^T d = d^T Q s, omega^T d = w^T Q d, d^T d = d^T Q d.
+static ssnalm_status solve_kernel(ssnalm_ctx* c, const double* x0, double* x_out, double* b_out,
+                                  ssnalm_info* info) {
+    const auto t_begin = std::chrono::steady_clock::now();
+    const ssnalm_options& o = c->opt;
+    const int64_t n = c->n;
+    c->proj_passes = 0;
+    c->proj_capped = 0;
+    ssnalm_info inf;
+    memset(&inf, 0, sizeof inf);
+    int inner_total = 0, cg_total = 0, ls_fail = 0, outer = 0, ls_trials = 0, grad_steps = 0;
+    ssnalm_status status = SSNALM_MAXITER;
+    // x^0: zero or the projection of the warm start; w^0 = x^0
+    if (x0) {
+        STCHK(project_into(c, x0, nullptr, 0.0, nullptr, 3));
+        STCHK(sync_state(c));
+        bool more;
+        STCHK(project_finish(c, x0, 3, &more));
+        proj_apply(c, x0, 3, c->xk, nullptr);
+    } else {
+        launch_fill(c->xk, 0.0, n, c->st);
+    }
+    HIPCHK(hipMemcpyAsync(c->kw, c->xk, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+    double sigma = o.sigma0;
+    double R = INFINITY, b = NAN, best_R = INFINITY, best_b = NAN, hinge = NAN, best_hinge = NAN;
+    bool have_best = false;
+    for (int k = 0; k < o.max_outer; ++k) {
+        outer = k + 1;
+        const double eps_k = std::pow(o.eps_decay, (double)k);
+        STCHK(qprod(c, c->kw, c->aw));                       // fresh Q w
+        launch_u_from(c->xk, c->aw, sigma, c->u, n, c->st);
+        c->base = 0;
+        STCHK(project_into(c, c->u, nullptr, 0.0, nullptr, c->base));
+        STCHK(sync_state(c));
+        bool more;
+        STCHK(project_finish(c, c->u, c->base, &more));
+        ls_fin(c, c->u, c->u, nullptr, 0.0, c->base, c->base, c->xk, c->xt, c->jm);
+        STCHK(kernel_gradient(c, c->xt));
+        STCHK(sync_state(c));
+        c->proj_passes += c->hs->ps[c->base].passes;
+        c->proj_capped += c->hs->ps[c->base].approx;
+        for (int j = 0; j < o.max_inner; ++j) {
+            const Scalars& hsc = c->hs->sc;
+            const double gn = std::sqrt(std::max(hsc.gnorm2, 0.0));
+            const double dist = std::sqrt(hsc.dist2);
+            const double crit = std::min(eps_k, eps_k * dist) / std::sqrt(sigma);
+            const double flo = o.floor_rel * (1.0 + std::sqrt(std::max(hsc.omega2, 0.0)));
+            if (!std::isfinite(gn)) return fail(SSNALM_E_NONFINITE, "non-finite gradient");
+            if (gn <= std::max(crit, flo)) break;
+            const int64_t p = hsc.p;
+            int cgi = 0;
+            bool direct = false;
+            const double cg_tol = std::min(o.eta, std::pow(gn, 1.0 + o.tau));
+            STCHK(kernel_newton(c, c->jm, p, c->ks, c->kqs, sigma, cg_tol, c->kd, c->td, &cgi, &direct));
+            cg_total += cgi;
+            ++inner_total;
+            launch_dots(3, c->kd, c->kqs, &dsc(c)->gd, c->kw, c->td, &dsc(c)->od, c->kd, c->td,
+                        &dsc(c)->dd, n, c->spart, cnt(c, CNT_DOTS2), c->st);
+            double alpha = 1.0;
+            bool accepted = false, fell_back = false;
+            const int trial = 1 - c->base;
+            for (int m = 0; m <= o.max_backtracks; ++m) {
+                ++ls_trials;
+                STCHK(project_into(c, c->u, c->td, alpha * sigma, c->ut, trial, dps(c, c->base)));
+                ls_fin(c, c->ut, c->u, c->td, alpha * sigma, trial, c->base, c->xk, c->xtt, c->jmt);
+                STCHK(sync_state(c));
+                STCHK(project_finish(c, c->ut, trial, &more));
+                if (more) {
+                    ls_fin(c, c->ut, c->u, c->td, alpha * sigma, trial, c->base, c->xk, c->xtt, c->jmt);
+                    STCHK(sync_state(c));
+                }
+                c->proj_passes += c->hs->ps[trial].passes;
+                c->proj_capped += c->hs->ps[trial].approx;
+                const Scalars& s2 = c->hs->sc;
+                if (m == 0 && !fell_back && gn > 0.0 && (!(s2.gd < 0.0) || (direct && s2.chol_fail))) {
+                    // not a descent direction (an inexact CG solve): take -grad,
+                    // d = -s with Q d = -Q s, and search again from alpha = 1
+                    fell_back = true;
+                    ++grad_steps;
+                    launch_scale_copy(c->kd, c->ks, -1.0, n, c->st);
+                    launch_scale_copy(c->td, c->kqs, -1.0, n, c->st);
+                    launch_dots(3, c->kd, c->kqs, &dsc(c)->gd, c->kw, c->td, &dsc(c)->od, c->kd, c->td,
+                                &dsc(c)->dd, n, c->spart, cnt(c, CNT_DOTS2), c->st);
+                    m = -1;
+                    continue;
+                }
+                const double dpsi = alpha * s2.od + 0.5 * alpha * alpha * s2.dd + s2.dh / sigma;
+                if (!std::isfinite(dpsi)) return fail(SSNALM_E_NONFINITE, "non-finite line search value");
+                if (dpsi <= o.mu * alpha * s2.gd) { accepted = true; break; }
+                alpha *= o.ls_delta;
+            }
+            if (!accepted) { ++ls_fail; break; }
+            launch_axpy(c->kw, c->kd, alpha, n, c->st);
+            launch_axpy(c->aw, c->td, alpha, n, c->st);
+            std::swap(c->u, c->ut);
+            std::swap(c->xt, c->xtt);
+            std::swap(c->jm, c->jmt);
+            c->base = trial;
+            STCHK(kernel_gradient(c, c->xt));
+            STCHK(sync_state(c));
+        }
+        // x^{k+1} = x~, and Q x^{k+1} = Q w - Q s
+        std::swap(c->xk, c->xt);
+        launch_sub(c->aw, c->kqs, c->nv, n, c->st);
+        double sumx = 0.0;
+        STCHK(kkt_nv(c, c->xk, &R, &b, &sumx, &hinge));
+        if (o.verbose)
+            fprintf(stderr, "[ssnalm] k=%d sigma=%.3g R_KKT=%.3e newton=%d cg=%d p=%lld passes=%d\n", k,
+                    sigma, R, inner_total, cg_total, (long long)c->hs->sc.p, c->proj_passes);
+        if (!std::isfinite(R)) return fail(SSNALM_E_NONFINITE, "non-finite KKT residual");
+        if (R <= c->tol) { status = SSNALM_OK; break; }
+        if (R < best_R) {
+            best_R = R;
+            best_b = b;
+            best_hinge = hinge;
+            HIPCHK(hipMemcpyAsync(x_out, c->xk, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+            have_best = true;
+        }
+        sigma = std::min(o.rho * sigma, o.sigma_max);
+    }
+    if (status == SSNALM_OK || !have_best || R <= best_R) {
+        HIPCHK(hipMemcpyAsync(x_out, c->xk, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        R = best_R;
+        b = best_b;
+        hinge = best_hinge;
+    }
+    if (status != SSNALM_OK && ls_fail > 0 && ls_fail >= outer) status = SSNALM_LINESEARCH_FAIL;
+    // x^T Q x of the returned x and the paper's columns
+    STCHK(qprod(c, x_out, c->nv));
+    launch_dots(1, x_out, c->nv, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, n,
+                c->spart, cnt(c, CNT_DOTS), c->st);
+    launch_count_x(x_out, n, c->C, dsc(c), c->spart, cnt(c, CNT_APPLY), c->st);
+    HIPCHK(hipGetLastError());
+    STCHK(sync_state(c));
+    const double sumx = c->hs->sc.sumx;
+    prof_harvest(c);
+    const double xqx = c->hs->sc.dd;
+    const auto t_end = std::chrono::steady_clock::now();
+    inf.rkkt = R;
+    inf.obj = 0.5 * xqx - sumx;
+    inf.b = b;
+    {
+        const double P = 0.5 * xqx + c->C * hinge;
+        inf.gap = std::isfinite(P) ? (P + inf.obj) / (1.0 + std::fabs(P) + std::fabs(inf.obj)) : NAN;
+    }
+    if (b_out) *b_out = b;
+    inf.sigma = sigma;
+    inf.time_s = std::chrono::duration<double>(t_end - t_begin).count();
+    inf.iters_outer = outer;
+    inf.iters_inner = inner_total;
+    inf.cg_iters = cg_total;
+    inf.proj_passes = c->proj_passes;
+    inf.p = (int32_t)c->hs->sc.p;
+    inf.n_sv = (int32_t)c->hs->sc.nsv;
+    inf.ls_fail = ls_fail;
+    inf.ls_trials = ls_trials;
+    inf.grad_steps = grad_steps;
+    inf.proj_capped = c->proj_capped;
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
+
 extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x_out, double* w_out,
                                       double* b_out, ssnalm_info* info) {
+    if (c && c->kern) {
+        if (!x_out) return fail(SSNALM_E_BADARG, "null argument");
+        if (w_out) return fail(SSNALM_E_BADARG, "kernel contexts have no primal weights: pass w_out = NULL");
+        StreamScope scope_(c);
+        return solve_kernel(c, x0, x_out, b_out, info);
+    }
     if (!c || !x_out) return fail(SSNALM_E_BADARG, "null argument");
     StreamScope scope_(c);
     const auto t_begin = std::chrono::steady_clock::now();
@@ -1419,7 +1808,8 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
 extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* t) {
     if (!c || !v || !t) return fail(SSNALM_E_BADARG, "null argument");
     StreamScope scope_(c);
-    op_amul(c, q_in(c, v), t);
+    if (c->kern) STCHK(qprod(c, v, t));                 // t = Q v
+    else op_amul(c, q_in(c, v), t);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     return SSNALM_OK;
@@ -1427,6 +1817,7 @@ extern "C" ssnalm_status ssnalm_op_amul(ssnalm_ctx* c, const double* v, double* 
 
 extern "C" ssnalm_status ssnalm_op_atmul(ssnalm_ctx* c, const double* z, double* r) {
     if (!c || !z || !r) return fail(SSNALM_E_BADARG, "null argument");
+    if (c->kern) return fail(SSNALM_E_BADARG, "op_atmul needs the samples: not for kernel contexts");
     StreamScope scope_(c);
     op_atmul(c, z, nullptr, nullptr, 1.0, c->qperm ? c->qout : r, nullptr);
     q_out(c, c->qout, r);
@@ -1456,7 +1847,7 @@ extern "C" ssnalm_status ssnalm_op_project(ssnalm_ctx* c, const double* v, doubl
 extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mask, const double* g,
                                           double sigma, double cg_tol, double* d, int32_t* cg_iters) {
     if (!c || !free_mask || !g || !d) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "op_newton is for C-SVC contexts");
+    if (c->svr || c->gen || c->kern) return fail(SSNALM_E_BADARG, "op_newton is for linear C-SVC contexts");
     StreamScope scope_(c);
     if (!(sigma > 0.0)) return fail(SSNALM_E_BADARG, "sigma must be > 0");
     // s = X_J^T 1 and p
@@ -1483,7 +1874,7 @@ extern "C" ssnalm_status ssnalm_op_newton(ssnalm_ctx* c, const uint8_t* free_mas
 
 extern "C" ssnalm_status ssnalm_op_gram(ssnalm_ctx* c, const uint8_t* free_mask, double* G) {
     if (!c || !free_mask || !G) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "op_gram is for C-SVC contexts");
+    if (c->svr || c->gen || c->kern) return fail(SSNALM_E_BADARG, "op_gram is for linear C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE || !c->use_chol) return fail(SSNALM_E_BADARG, "Gram matrix needs a dense Cholesky context");
     launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
@@ -1498,6 +1889,29 @@ extern "C" ssnalm_status ssnalm_op_gram(ssnalm_ctx* c, const uint8_t* free_mask,
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
+    return SSNALM_OK;
+}
+
+extern "C" ssnalm_status ssnalm_op_kernel_newton(ssnalm_ctx* c, const uint8_t* free_mask,
+                                                  const double* sv, double sigma, double cg_tol,
+                                                  double* d, double* Qd, double* dQd, int32_t* cg_iters) {
+    if (!c || !free_mask || !sv || !d || !Qd) return fail(SSNALM_E_BADARG, "null argument");
+    if (!c->kern) return fail(SSNALM_E_BADARG, "op_kernel_newton is for kernel contexts");
+    if (!(sigma > 0.0)) return fail(SSNALM_E_BADARG, "sigma must be > 0");
+    StreamScope scope_(c);
+    launch_compact(free_mask, c->n, c->jlist, &dsc(c)->p, c->blk, cnt(c, CNT_CMP), c->st);
+    HIPCHK(hipMemcpyAsync(c->ks, sv, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->st));
+    STCHK(qprod(c, c->ks, c->kqs));
+    int cgi = 0;
+    bool direct = false;
+    STCHK(kernel_newton(c, free_mask, c->hs->sc.p, c->ks, c->kqs, sigma, cg_tol, d, Qd, &cgi, &direct));
+    launch_dots(1, d, Qd, &dsc(c)->dd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->n,
+                c->spart, cnt(c, CNT_DOTS), c->st);
+    HIPCHK(hipGetLastError());
+    STCHK(sync_state(c));
+    if (direct && c->hs->sc.chol_fail) return fail(SSNALM_E_NONFINITE, "Cholesky met a non-positive pivot");
+    if (dQd) *dQd = c->hs->sc.dd;
+    if (cg_iters) *cg_iters = cgi;
     return SSNALM_OK;
 }
 
@@ -1542,9 +1956,14 @@ extern "C" ssnalm_status ssnalm_set_profile(ssnalm_ctx* c, int32_t profile) {
 extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* rkkt, double* b) {
     if (!c || !x) return fail(SSNALM_E_BADARG, "null argument");
     StreamScope scope_(c);
-    op_atmul(c, x, nullptr, nullptr, 1.0, c->qv, nullptr);
     double R, bb;
-    STCHK(kkt(c, x, c->qv, &R, &bb, nullptr));
+    if (c->kern) {
+        STCHK(qprod(c, x, c->nv));
+        STCHK(kkt_nv(c, x, &R, &bb, nullptr));
+    } else {
+        op_atmul(c, x, nullptr, nullptr, 1.0, c->qv, nullptr);
+        STCHK(kkt(c, x, c->qv, &R, &bb, nullptr));
+    }
     HIPCHK(hipGetLastError());
     if (rkkt) *rkkt = R;
     if (b) *b = bb;
@@ -1557,7 +1976,7 @@ extern "C" ssnalm_status ssnalm_op_rkkt(ssnalm_ctx* c, const double* x, double* 
 // means of x_i^T w1, margins m_i, and the projection X R.
 extern "C" ssnalm_status ssnalm_ws_features(ssnalm_ctx* c, const float* R, float* Z) {
     if (!c || !R || !Z) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "ws_features is for C-SVC contexts");
+    if (c->svr || c->gen || c->kern) return fail(SSNALM_E_BADARG, "ws_features is for linear C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "warm-start features need dense X");
     const int64_t n = c->n, q = c->q;
@@ -1623,7 +2042,7 @@ extern "C" ssnalm_status ssnalm_ws_solve(ssnalm_ctx* c, const float* out, double
                                          int32_t max_rounds, double* x_out, double* w_out,
                                          ssnalm_info* info, ssnalm_ws_stats* stats) {
     if (!c || !out || !x_out) return fail(SSNALM_E_BADARG, "null argument");
-    if (c->svr || c->gen) return fail(SSNALM_E_BADARG, "ws_solve is for C-SVC contexts");
+    if (c->svr || c->gen || c->kern) return fail(SSNALM_E_BADARG, "ws_solve is for linear C-SVC contexts");
     StreamScope scope_(c);
     if (c->kind != SSNALM_DENSE) return fail(SSNALM_E_BADARG, "screening needs dense X");
     if (!(keep_frac > 0.0) || keep_frac > 1.0) return fail(SSNALM_E_BADARG, "keep_frac must be in (0, 1]");

@@ -1,6 +1,8 @@
 // Feature maps that turn the RBF-kernel C-SVC into a linear one (Section 4):
 // random Fourier features and Nystroem features.  The linear solver then
 // runs unchanged on the feature matrix Z (Q ~ diag(y) Z Z^T diag(y)).
+// Also the exact kernel matrix Q of the nonlinear C-SVC (Section 1, eq.
+// Def_Dual_of_C_SVM_Problem), formed once for the w-space solver.
 //
 // RBF kernel (Section 1): k(x, z) = exp(-|x - z|^2 / (2 alpha)).
 //   Random Fourier features: frequencies w_1..w_N drawn by the caller from
@@ -160,6 +162,48 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_rbf_block(const T* __restrict__ X
     }
 }
 
+// Q_ij = y_i y_j k(x_i, x_j) for the kernel C-SVC (all n x n entries, row
+// stride ld, columns n .. ld-1 set to zero): one 64 x 64 tile per block,
+// blockIdx.x the column tile, blockIdx.y the row tile.  Both (i, j) and
+// (j, i) sum their products in the same order, so Q is exactly symmetric;
+// the RBF diagonal is exactly 1.
+template <typename T>
+__global__ __launch_bounds__(SSN_BLOCK) void k_kernel_q(const T* __restrict__ X, int64_t n, int64_t q,
+                                                        const double* __restrict__ norms,
+                                                        const int8_t* __restrict__ y, int rbf,
+                                                        double inv2a, double* __restrict__ Q,
+                                                        int64_t ld) {
+    __shared__ double sA[FK][FT + 1];
+    __shared__ double sB[FK][FT + 1];
+    const int64_t r0 = (int64_t)blockIdx.y * FT, c0 = (int64_t)blockIdx.x * FT;
+    double acc[4][4] = {};
+    RowLoader<T> la{X, nullptr, n, q};
+    if (c0 < n) tile_nt(la, la, r0, c0, q, acc, sA, sB);
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = r0 + 4 * ty + u;
+        if (i >= n) continue;
+        const double yi = (double)y[i];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t j = c0 + 4 * tx + v;
+            if (j >= ld) continue;
+            double kv = 0.0;
+            if (j < n) {
+                if (rbf) {
+                    const double d2 = i == j ? 0.0 : fmax(norms[i] + norms[j] - 2.0 * acc[u][v], 0.0);
+                    kv = exp(-d2 * inv2a);
+                } else {
+                    kv = acc[u][v];
+                }
+                kv *= yi * (double)y[j];
+            }
+            Q[i * ld + j] = kv;
+        }
+    }
+}
+
 // Block column b of Z = K L^{-T} (64 rows of Z per workgroup):
 //   Y = K[:, b] - Z[:, <b] L[b, <b]^T,   Z[:, b] = Y X_b^T,  X_b = L_bb^{-1},
 // with the factor L in the lower triangle of F (r x r, row-major) and X_b
@@ -271,6 +315,18 @@ void launch_rbf_block(int dtype, const void* X, int64_t q, const int32_t* arows,
                       const double* anorm, const int32_t* lm, int64_t r, const double* lnorm,
                       double alpha, double shift, double* K, hipStream_t s) {
     FEAT_DISPATCH_X(dtype, rbf_t, X, q, arows, na, anorm, lm, r, lnorm, alpha, shift, K, s);
+}
+
+template <typename T>
+static void kernel_q_t(const void* X, int64_t n, int64_t q, const double* norms, const int8_t* y,
+                       int rbf, double alpha, double* Q, int64_t ld, hipStream_t s) {
+    const dim3 grid((unsigned)((ld + FT - 1) / FT), (unsigned)((n + FT - 1) / FT));
+    SSN_LAUNCH((k_kernel_q<T>), grid, dim3(SSN_BLOCK), 0, s, (const T*)X, n, q, norms, y, rbf,
+               rbf ? 0.5 / alpha : 0.0, Q, ld);
+}
+void launch_kernel_q(int dtype, const void* X, int64_t n, int64_t q, const double* norms,
+                     const int8_t* y, int rbf, double alpha, double* Q, int64_t ld, hipStream_t s) {
+    FEAT_DISPATCH_X(dtype, kernel_q_t, X, n, q, norms, y, rbf, alpha, Q, ld, s);
 }
 
 void launch_nys_solve(const double* K, int64_t n, int64_t r, const double* F, const double* inv,

@@ -63,6 +63,8 @@ struct Scalars {
     double hinge;         // KKT: the primal's loss sum at the KKT bias
     double cx;            // c^T x of a returned x (problems with a linear term)
     double aja;           // general form: a_J^T a_J
+    double kd0, kd1, kd2; // kernel contexts: a^T g_J, a^T r (Newton matrix), a^T v
+    long long km;         // kernel contexts: support size of a product's input
     long long p;          // |J|
     long long nnzj;       // nonzeros of the rows in J (sparse input)
     long long nfix;       // chunk-crossing column runs of the compact X_J copy
@@ -417,6 +419,28 @@ void launch_row_norms(int dtype, const void* X, const int32_t* rows, int64_t n, 
                       double* out, hipStream_t s);
 // K (na x r) of the RBF kernel between rows arows (or all) and the landmarks,
 // + shift on the diagonal when arows is given (the landmark block)
+// Q_ij = y_i y_j k(x_i, x_j) (rbf: exp(-|x_i - x_j|^2 / (2 alpha)); else
+// x_i^T x_j), n x n with row stride ld (a multiple of 32, zero padding).
+void launch_kernel_q(int dtype, const void* X, int64_t n, int64_t q, const double* norms,
+                     const int8_t* y, int rbf, double alpha, double* Q, int64_t ld, hipStream_t s);
+// Kernel-context products (kernels_kernel.hip)
+constexpr int kQcolsMaxChunks = 256;
+void launch_nz_mask(const double* v, int64_t n, uint8_t* mask, hipStream_t s);
+int  qcols_chunks(int64_t n, int64_t m);
+// part[c * n + j] (c < nchunk) = partial sums of coef_k Q[list_k][j] over the m listed rows
+void launch_qcols(const double* Q, int64_t n, int64_t ld, const int32_t* list, int64_t m, const double* v,
+                  int by_row, double* part, int nchunk, hipStream_t s);
+void launch_qjj_mv(const double* Q, int64_t ld, const int32_t* J, int64_t p, const double* v, double* out,
+                   hipStream_t s);
+void launch_qjj_form(const double* Q, int64_t ld, const int32_t* J, int64_t p, const double* aJ,
+                     const double* r, const double* rho, double sigma, double* M, hipStream_t s);
+void launch_qjj_diag(const double* Q, int64_t ld, const int32_t* J, int64_t p, const double* aJ,
+                     const double* r, const double* rho, double sigma, double* diag, hipStream_t s);
+void launch_kgather(const int32_t* J, int64_t p, const int8_t* y, const double* g, double* aJ, double* gJ,
+                    hipStream_t s);
+void launch_kcenter(const double* u, const double* aJ, const double* dot, int64_t p, double scale,
+                    const double* base, double* out, hipStream_t s);
+void launch_scatter_add(const int32_t* J, int64_t p, const double* z, double* d, hipStream_t s);
 void launch_rbf_block(int dtype, const void* X, int64_t q, const int32_t* arows, int64_t na,
                       const double* anorm, const int32_t* lm, int64_t r, const double* lnorm,
                       double alpha, double shift, double* K, hipStream_t s);

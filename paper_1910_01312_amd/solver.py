@@ -282,6 +282,65 @@ class General(Solver):
         self._lib = lib
 
 
+
+class KernelSVC(Solver):
+    """The C-SVC dual with a nonlinear kernel (ssnalm_create_kernel):
+    Q_ij = y_i y_j k(x_i, x_j) with k = "rbf" (exp(-|x - z|^2 / (2 alpha)))
+    or "linear" (x^T z), formed once on the GPU in fp64 and kept resident.
+    solve() returns (x, None, info); amul(v) is Q v (n -> n); newton_step()
+    is the Proposition 5 step."""
+
+    def __init__(self, X, y, C_=1.0, alpha=1.0, tol=1e-6, *, kernel="rbf", bf16=False, **opts):
+        lib = L.load()
+        self._keep = []
+        Xd, dt = _dense_dev(X, bf16)
+        yd = _to_dev(y, torch.int8)
+        self._keep += [yd]
+        n, q = Xd.shape
+        prob = L.KernelProblem()
+        prob.kernel = {"rbf": L.KERNEL_RBF, "linear": L.KERNEL_LINEAR}[kernel]
+        prob.dtype = dt
+        prob.n, prob.q = int(n), int(q)
+        prob.X, prob.y = Xd.data_ptr(), yd.data_ptr()
+        prob.C, prob.alpha, prob.tol = float(C_), float(alpha), float(tol)
+        self.n, self.q, self.C, self.tol = int(n), int(n), float(C_), float(tol)
+        self.y = yd
+        self.problem = prob
+        self.options = make_options(**opts)
+        ctx = C.c_void_p()
+        L.check(lib.ssnalm_create_kernel(C.byref(ctx), C.byref(prob), C.byref(self.options),
+                                         _stream_handle()), "ssnalm_create_kernel")
+        self._ctx = ctx
+        self._lib = lib
+        del Xd                       # the samples are read only while Q is formed
+
+    def solve(self, x0=None):
+        dev = _dev()
+        x = torch.empty(self.n, dtype=torch.float64, device=dev)
+        info = L.Info()
+        x0d = _to_dev(x0, torch.float64) if x0 is not None else None
+        b = C.c_double(float("nan"))
+        st = self._lib.ssnalm_solve(self._ctx, _ptr(x0d), _ptr(x), None, C.byref(b),
+                                    C.byref(info))
+        L.check(st, "ssnalm_solve")
+        d = info.as_dict()
+        d["b_out"] = b.value
+        d["status_name"] = L.STATUS_NAMES.get(st, str(st))
+        return x, None, d
+
+    def newton_step(self, free_mask, s, sigma, cg_tol=1e-12):
+        """Returns (d, Q d, d^T Q d, cg_iters)."""
+        m = _to_dev(free_mask, torch.uint8)
+        sv = _to_dev(s, torch.float64)
+        d = torch.empty(self.n, dtype=torch.float64, device=sv.device)
+        Qd = torch.empty_like(d)
+        dQd = C.c_double()
+        it = C.c_int32()
+        L.check(self._lib.ssnalm_op_kernel_newton(self._ctx, _ptr(m), _ptr(sv), float(sigma),
+                                                  float(cg_tol), _ptr(d), _ptr(Qd), C.byref(dQd),
+                                                  C.byref(it)), "ssnalm_op_kernel_newton")
+        return d, Qd, dQd.value, it.value
+
 def solve(X, y, C_, tol=1e-6, x0=None, **opts):
     """One-shot solve: returns (x, w, info)."""
     with Solver(X, y, C_, tol, **opts) as s:

@@ -280,3 +280,15 @@ def tiny_general(n: int, q: int, seed: int, zero_a: int = 0):
     u = l + rng.uniform(0.2, 2.0, n)
     d = float(a @ rng.uniform(l, u))
     return B, c, a, d, l, u
+
+
+def rbf_problem(n: int, q: int = 100, seed: int = 0, n_comp: int = 3):
+    """Input of the nonlinear-kernel C-SVC (Table 3's shape): the two-class
+    Gaussian mixture of `mixture_problem`, every feature rescaled to [0, 1]
+    over the samples (the scaling Section 4 applies to the datasets).
+    Returns (X float64 [n,q], y int8 [n])."""
+    X, y = mixture_problem(n, q, seed=seed, n_comp=n_comp, mean_scale=1.0)
+    X = X.astype(np.float64)
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    X = (X - lo) / np.where(hi > lo, hi - lo, 1.0)
+    return X, y
