@@ -247,9 +247,10 @@ ssnalm_status ssnalm_create_general(ssnalm_ctx** out, const ssnalm_general_probl
  * Pi = I - y_J y_J^T / p inside the matrix:
  *   (I_p + sigma Pi Q_JJ Pi) v = Pi (Q s)_J,   s = w - Pi(u(w)),
  *   z = sigma Pi v,   d = -s + z on J,   Q d = -Q s + Q_{:,J} z,
- * solved by Cholesky (p <= 2048) or by Jacobi-preconditioned CG on the same
- * matrix to |residual| <= min(eta, |grad|^(1+tau)) (p > 2048, or always
- * with opt.newton = SSNALM_NEWTON_PCG).  Norms of the stopping tests are
+ * solved by Cholesky (p <= 32768; the p x p matrix takes p^2 doubles of
+ * device memory, allocated for min(n, 32768)) or by Jacobi-preconditioned CG
+ * on the same matrix to |residual| <= min(eta, |grad|^(1+tau)) (p > 32768,
+ * or always with opt.newton = SSNALM_NEWTON_PCG).  Norms of the stopping tests are
  * Q-norms (|omega| = (w^T Q w)^(1/2), |grad| = (s^T Q s)^(1/2)), the
  * omega-space norms of the linear path.
  *   dtype : F64, F32 or BF16 samples (values used in fp64).

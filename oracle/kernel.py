@@ -100,10 +100,17 @@ def newton_pspace(Q, a, free, s, sigma):
     QJJ = Q[np.ix_(J, J)]
     p = J.size
     den = float(aJ @ aJ)
-    Pi = np.eye(p) - (np.outer(aJ, aJ) / den if den != 0.0 else 0.0)
-    M = np.eye(p) + sigma * Pi @ QJJ @ Pi
-    v = sla.cho_solve(sla.cho_factor(M, lower=True), Pi @ g[J])
-    z = sigma * (Pi @ v)
+
+    def proj(V):
+        # Pi V with Pi = I - a_J a_J^T / den applied as a rank-one update
+        if den == 0.0:
+            return V
+        return V - np.multiply.outer(aJ, aJ @ V) / den
+
+    PQP = proj(proj(QJJ).T).T                  # Pi Q_JJ Pi (Pi symmetric)
+    M = np.eye(p) + sigma * PQP
+    v = sla.cho_solve(sla.cho_factor(M, lower=True), proj(g[J]))
+    z = sigma * proj(v)
     d = -s.copy()
     d[J] += z
     Qd = -g + Q[:, J] @ z
@@ -139,7 +146,8 @@ def duality_gap_at_q(Q, y, C, x, b):
 def solve_p5(K, y, C, tol=1e-6, x0=None, **kw):
     """SSsNAL (Algorithm 1 + Algorithm 3) on the kernel C-SVC dual in w-space
     with the Newton step of `newton_pspace`.  Parameters as `ssnal.Options`
-    (direct solves only).  Returns a `general.Result` (omega holds w)."""
+    (direct solves only; time_budget_s > 0 stops with status "BUDGET").
+    Returns a `general.Result` (omega holds w)."""
     import time
     t_start = time.perf_counter()
     opt = Options(tol=tol, **kw)
@@ -155,12 +163,21 @@ def solve_p5(K, y, C, tol=1e-6, x0=None, **kw):
     R = math.inf
     best = None
     outer = 0
+    def over_budget():
+        return opt.time_budget_s > 0 and time.perf_counter() - t_start > opt.time_budget_s
+
     for k in range(opt.max_outer):
         outer = k + 1
         eps_k = opt.eps_decay ** k
         Qw = Q @ w
         xk = x
+        if over_budget():
+            status = "BUDGET"
+            break
         for _ in range(opt.max_inner):
+            if over_budget():
+                status = "BUDGET"
+                break
             u = xk - sigma * (Qw + c)
             xt, lam, free = general.projection(prob, u)
             s = w - xt
@@ -191,6 +208,9 @@ def solve_p5(K, y, C, tol=1e-6, x0=None, **kw):
                 break
             w = w + alpha * d
             Qw = Q @ w
+        if status == "BUDGET":
+            x = xk
+            break
         u = xk - sigma * (Qw + c)
         x = general.projection(prob, u)[0]
         R = rkkt_q(Q, y, C, x)[0]

@@ -683,6 +683,9 @@ static ssnalm_status kkt_nv(ssnalm_ctx* c, const double* x, double* R, double* b
 }
 
 // ---------------------------------------------------------------- kernel C-SVC
+// Largest free set whose p x p Newton matrix is factored (8.6 GB at the cap);
+// larger ones are solved by CG.
+static constexpr int64_t kKernelCholMax = 32768;
 // Products with the resident Q of a kernel context (rows of Q at the listed
 // indices; coefficients v[list_k] when by_row, else v[k]):
 //   out = (base ? base : 0) + sign * sum_k coef_k Q[list_k][:].
@@ -758,17 +761,31 @@ static ssnalm_status kernel_newton(ssnalm_ctx* c, const uint8_t* mask, int64_t p
             launch_chol_solve_small(c->M, c->krhs, c->kv, p, ds, c->st);
         } else {
             launch_chol_factor_blocked(c->M, p, c->linv, ds, c->st);
-            launch_chol_solve_factored(c->M, c->linv, c->krhs, c->kv, p, c->st);
+            if (p <= chol_blocked_max())
+                launch_chol_solve_factored(c->M, c->linv, c->krhs, c->kv, p, c->st);
+            else
+                launch_chol_solve_blocked(c->M, c->linv, c->krhs, c->kv, p, c->st);
         }
         prof_end(c, SSNALM_K_CHOL, 8.0 * (double)p * p, (double)p * p * p / 3.0 + 2.0 * (double)p * p);
         vneg = c->kv;
     } else {
-        const double tol2 = cg_tol * cg_tol;
-        launch_pcg_init(c->krhs, c->kdiag, c->kcx, c->kcr, c->kcz, c->kcp, p, tol2, ds, c->spart,
+        // CG on M v = Pi g_J.  Its residual r maps to the residual of the
+        // omega-space system (I + sigma B^T P B) d = -g as sigma L_J^T Pi r,
+        // of norm sigma ((Pi r)^T Q_JJ (Pi r))^(1/2): the test of Algorithm 3
+        // (|residual| <= cg_tol) is taken on that norm, every 8 iterations.
+        launch_pcg_init(c->krhs, c->kdiag, c->kcx, c->kcr, c->kcz, c->kcp, p, 0.0, ds, c->spart,
                         cnt(c, CNT_PCG), c->st);
-        STCHK(sync_state(c));
         int it = 0;
-        while (it < c->opt.max_cg && !c->hs->sc.cg_done) {
+        for (;;) {
+            launch_dots(1, c->kaJ, c->kcr, &ds->kd2, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                        p, c->spart, cnt(c, CNT_DOTS), c->st);
+            launch_kcenter(c->kcr, c->kaJ, &ds->kd2, p, 1.0, nullptr, c->kt1, c->st);
+            launch_qjj_mv(c->Qk, c->kld, c->jlist, p, c->kt1, c->kt2, c->st);
+            launch_dots(1, c->kt1, c->kt2, &ds->kres, nullptr, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, p, c->spart, cnt(c, CNT_DOTS), c->st);
+            STCHK(sync_state(c));
+            const double res = sigma * std::sqrt(std::max(c->hs->sc.kres, 0.0));
+            if (res <= cg_tol || c->hs->sc.cg_done || it >= c->opt.max_cg) break;
             const int batch = std::min(8, c->opt.max_cg - it);
             for (int b = 0; b < batch; ++b) {
                 // Ap = p + sigma Pi Q_JJ Pi p
@@ -782,12 +799,11 @@ static ssnalm_status kernel_newton(ssnalm_ctx* c, const uint8_t* mask, int64_t p
                             nullptr, p, c->spart, cnt(c, CNT_DOTS), c->st);
                 launch_kcenter(c->kt2, c->kaJ, &ds->kd2, p, sigma, c->kcp, c->kcap, c->st);
                 launch_pcg_pap(c->kcp, c->kcap, p, ds, c->spart, cnt(c, CNT_PCG2), c->st);
-                launch_pcg_step(c->kcx, c->kcr, c->kcp, c->kcap, c->kdiag, c->kcz, p, ds, tol2, c->spart,
+                launch_pcg_step(c->kcx, c->kcr, c->kcp, c->kcap, c->kdiag, c->kcz, p, ds, 0.0, c->spart,
                                 cnt(c, CNT_PCG3), c->st);
                 launch_pcg_dir(c->kcp, c->kcz, p, ds, c->st);
             }
             it += batch;
-            STCHK(sync_state(c));
         }
         *cg_iters = c->hs->sc.cg_count;
         vneg = c->kcx;
@@ -1279,7 +1295,7 @@ extern "C" ssnalm_status ssnalm_create_kernel(ssnalm_ctx** out, const ssnalm_ker
     do {                                                          \
         if ((s = dalloc(c, &(ptr), (cnt_))) < 0) return bail(s);  \
     } while (0)
-    c->kchol = std::min<int64_t>(n, chol_blocked_max());
+    c->kchol = std::min<int64_t>(n, kKernelCholMax);
     KALLOC(c->kw, n); KALLOC(c->ks, n); KALLOC(c->kqs, n); KALLOC(c->kd, n);
     KALLOC(c->knz, n); KALLOC(c->klist, n);
     KALLOC(c->kaJ, n); KALLOC(c->kgJ, n); KALLOC(c->kr, n); KALLOC(c->krhs, n); KALLOC(c->kv, n);

@@ -339,6 +339,82 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_chol_solve2(const double* __r
     for (int i = tid; i < q; i += blockDim.x) d[i] = z[i];
 }
 
+// d = -M^{-1} g from the same factor for any size, spread over the chip:
+// after each diagonal block of the triangular solves the not-yet-solved part
+// is updated by a parallel product with the block's 64 columns of L (forward)
+// or 64 rows of L (backward), so no workgroup walks the whole factor.
+//   forward  L w = -g:  w_B = X_B z_B;   z_i -= sum_k L[i][o + k] w_{o+k}  (i > B)
+//   backward L^T d = w: d_B = X_B^T z_B; z_j -= sum_r L[o + r][j] d_{o+r} (j < B)
+// z lives in d.  Each update reads its rows / columns of the lower triangle
+// once: p^2 doubles per solve in total.
+__global__ void k_trsv_diag(const double* __restrict__ inv, int kb, int m, int transposed,
+                            double* __restrict__ z, int o) {
+    __shared__ double zb[NB];
+    const int r = threadIdx.x;
+    zb[r] = r < m ? z[o + r] : 0.0;
+    __syncthreads();
+    const double* X = inv + (int64_t)kb * 2 * NB * NB + (transposed ? NB * NB : 0);
+    double t = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < NB; ++k) t = fma(X[r * NB + k], zb[k], t);
+    if (r < m) z[o + r] = t;
+}
+
+// rows i in [o + m, q): z_i -= L[i][o .. o+m) . z[o .. o+m), one wave per row
+__global__ __launch_bounds__(SSN_BLOCK) void k_trsv_fupd(const double* __restrict__ M, int q, int o, int m,
+                                                         double* __restrict__ z) {
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t i = (int64_t)o + m + (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    if (i >= q) return;
+    const double t = lane < m ? M[i * q + o + lane] * z[o + lane] : 0.0;
+    const double sum = wave_sum(t);
+    if (lane == 0) z[i] -= sum;
+}
+
+// columns j in [0, o): z_j -= sum_r L[o + r][j] z[o + r], one thread per column
+__global__ __launch_bounds__(SSN_BLOCK) void k_trsv_bupd(const double* __restrict__ M, int q, int o, int m,
+                                                         double* __restrict__ z) {
+    __shared__ double zb[NB];
+    if (threadIdx.x < NB) zb[threadIdx.x] = threadIdx.x < m ? z[o + threadIdx.x] : 0.0;
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * SSN_BLOCK + threadIdx.x;
+    if (j >= o) return;
+    double t0 = 0.0, t1 = 0.0;
+    int r = 0;
+    for (; r + 1 < m; r += 2) {
+        t0 = fma(M[(int64_t)(o + r) * q + j], zb[r], t0);
+        t1 = fma(M[(int64_t)(o + r + 1) * q + j], zb[r + 1], t1);
+    }
+    if (r < m) t0 = fma(M[(int64_t)(o + r) * q + j], zb[r], t0);
+    z[j] -= t0 + t1;
+}
+
+__global__ void k_neg_copy(const double* __restrict__ g, double* __restrict__ d, int q) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < q) d[i] = -g[i];
+}
+
+void launch_chol_solve_blocked(const double* M, const double* inv, const double* g, double* d, int64_t q,
+                               hipStream_t s) {
+    const int nblk = (int)((q + NB - 1) / NB);
+    SSN_LAUNCH(k_neg_copy, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, g, d, (int)q);
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int o = kb * NB, m = (int)std::min<int64_t>(NB, q - o);
+        SSN_LAUNCH(k_trsv_diag, dim3(1), dim3(NB), 0, s, inv, kb, m, 0, d, o);
+        const int64_t rows = q - o - m;
+        if (rows > 0)
+            SSN_LAUNCH(k_trsv_fupd, dim3((unsigned)((rows + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK)),
+                       dim3(SSN_BLOCK), 0, s, M, (int)q, o, m, d);
+    }
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+        const int o = kb * NB, m = (int)std::min<int64_t>(NB, q - o);
+        SSN_LAUNCH(k_trsv_diag, dim3(1), dim3(NB), 0, s, inv, kb, m, 1, d, o);
+        if (o > 0)
+            SSN_LAUNCH(k_trsv_bupd, dim3((unsigned)((o + SSN_BLOCK - 1) / SSN_BLOCK)), dim3(SSN_BLOCK), 0, s,
+                       M, (int)q, o, m, d);
+    }
+}
+
 void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s) {
     const int nblk = (int)((q + NB - 1) / NB);
     for (int kb = 0; kb < nblk; ++kb) {

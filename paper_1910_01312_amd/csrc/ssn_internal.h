@@ -64,6 +64,7 @@ struct Scalars {
     double cx;            // c^T x of a returned x (problems with a linear term)
     double aja;           // general form: a_J^T a_J
     double kd0, kd1, kd2; // kernel contexts: a^T g_J, a^T r (Newton matrix), a^T v
+    double kres;          // kernel contexts: (Pi r)^T Q_JJ (Pi r) of a CG residual r
     long long km;         // kernel contexts: support size of a product's input
     long long p;          // |J|
     long long nnzj;       // nonzeros of the rows in J (sparse input)
@@ -221,6 +222,9 @@ void launch_chol_solve_small(const double* M, const double* g, double* d, int64_
 int     chol_blocked_max();
 int64_t chol_inv_size(int64_t q);
 void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s);
+// d = -M^{-1} g from the blocked factor for any q (multi-workgroup solves)
+void launch_chol_solve_blocked(const double* M, const double* inv, const double* g, double* d, int64_t q,
+                               hipStream_t s);
 void launch_chol_solve_factored(const double* M, const double* inv, const double* g, double* d,
                                 int64_t q, hipStream_t s);
 

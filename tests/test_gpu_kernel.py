@@ -5,13 +5,15 @@ kernel oracle (oracle/kernel.py) (GPU only).
   * Q v for dense, sparse and zero v against the oracle's explicit Q, over
     several 256-column tiles with ragged tails, for fp64 and fp32 samples;
   * the Newton step of Proposition 5 (d, Q d, d^T Q d) against the oracle's
-    p x p step: the single-workgroup and the blocked Cholesky, and the CG
-    solve of the same matrix;
+    p x p step: the single-workgroup Cholesky, the blocked factorisation with
+    the single-workgroup and the multi-workgroup triangular solves, and the
+    CG solve of the same matrix;
   * full solves: equal iteration counts, x and the objective against the
     oracle's w-space solve at the same tolerance, R_KKT recomputed by the
     oracle, the bias and the duality gap;
-  * a solve whose first free sets exceed the Cholesky size (CG steps) against
-    the oracle's optimum, the linear kernel against the linear C-SVC path, a
+  * a solve whose first free sets take the multi-workgroup solves (equal
+    counts), the same solve with CG steps against the oracle's optimum, the
+    linear kernel against the linear C-SVC path, a
     warm start, the iteration cap, one-class labels, n = 1 and the rejected
     arguments.
 """
@@ -76,9 +78,11 @@ def _state(n, q, seed, sigma, C_, alpha, free_frac_high=False):
     return X, y, Q, w, xt, free
 
 
-@pytest.mark.parametrize("n,sigma,high", [(200, 2.0, False), (900, 0.01, True), (2600, 0.3, False)])
+@pytest.mark.parametrize("n,sigma,high", [(200, 2.0, False), (900, 0.01, True), (2600, 0.3, False),
+                                           (2600, 0.001, True)])
 def test_newton_step_cholesky(n, sigma, high):
-    """p = 35 (one workgroup), 891 and 1359 (blocked, ragged last block)."""
+    """p = 35 (one workgroup), 891 and 1359 (blocked factor, ragged last
+    block, one-workgroup solves) and 2201 (multi-workgroup solves)."""
     C_, alpha = 1.0, 1.0
     X, y, Q, w, xt, free = _state(n, 20, 40 + n, sigma, C_, alpha, high)
     s = w - xt
@@ -86,22 +90,19 @@ def test_newton_step_cholesky(n, sigma, high):
     d_ref, Qd_ref, dQd_ref = kernel.newton_pspace(Q, y.astype(np.float64), free, s, sigma)
     with _svc(X, y, C_, alpha) as sv:
         d, Qd, dQd, it = sv.newton_step(free.astype(np.uint8), s, sigma)
-    assert it == 0 and 0 < p <= 2048
+    assert it == 0 and 0 < p
     scale = 1.0 + np.abs(Qd_ref).max()
     np.testing.assert_allclose(Qd.cpu().numpy(), Qd_ref, atol=1e-9 * scale)
     np.testing.assert_allclose(d.cpu().numpy(), d_ref, atol=1e-9 * (1.0 + np.abs(d_ref).max()))
     assert dQd == pytest.approx(dQd_ref, rel=1e-9, abs=1e-12)
 
 
-@pytest.mark.parametrize("n,sigma,mode", [(1500, 0.05, "pcg"), (2600, 0.001, "auto")])
-def test_newton_step_pcg(n, sigma, mode):
-    """The same matrix solved by CG to a tight tolerance: forced, and chosen
-    by the context when p = 2201 exceeds the Cholesky size."""
-    C_, alpha = 1.0, 1.0
-    X, y, Q, w, xt, free = _state(n, 20, 7 if mode == "pcg" else 40 + n, sigma, C_, alpha, True)
+@pytest.mark.parametrize("n,sigma,seed", [(1500, 0.05, 7), (2600, 0.001, 2640)])
+def test_newton_step_pcg(n, sigma, seed):
+    """The same matrix solved by CG (forced) to a tight tolerance."""
+    C_, alpha, mode = 1.0, 1.0, "pcg"
+    X, y, Q, w, xt, free = _state(n, 20, seed, sigma, C_, alpha, True)
     s = w - xt
-    if mode == "auto":
-        assert free.sum() > 2048
     d_ref, Qd_ref, dQd_ref = kernel.newton_pspace(Q, y.astype(np.float64), free, s, sigma)
     with _svc(X, y, C_, alpha, newton=mode, max_cg=2000) as sv:
         d, Qd, dQd, it = sv.newton_step(free.astype(np.uint8), s, sigma, cg_tol=1e-11)
@@ -154,10 +155,11 @@ def test_solve_vs_oracle(n, q, C_):
     assert abs(float(y.astype(np.float64) @ x)) <= 1e-9 * (1.0 + np.abs(x).sum())
 
 
-def test_solve_with_cg_steps():
-    """n = 3000 with every sample free in the first step (p > 2048: CG on
-    the p x p matrix), later steps by Cholesky; the optimum against the
-    oracle's."""
+def test_solve_large_free_sets():
+    """n = 3000 with every sample free in the first step (p > 2048: the
+    multi-workgroup triangular solves): the oracle's iteration counts and
+    optimum; then the same problem with every step solved by CG, against the
+    oracle's optimum."""
     n, q, C_ = 3000, 50, 10.0
     X, y = synth.rbf_problem(n, q, seed=5)
     alpha = 2.5
@@ -168,8 +170,15 @@ def test_solve_with_cg_steps():
     with _svc(X, y, C_, alpha, tol=1e-8) as s:
         x, _, info = s.solve()
     x = x.cpu().numpy()
-    assert info["status_name"] == "OK"
-    assert info["cg_iters"] > 0
+    assert info["status_name"] == "OK" and info["cg_iters"] == 0
+    assert (info["iters_outer"], info["iters_inner"]) == (ref.outer, ref.inner)
+    np.testing.assert_allclose(x, ref.x, atol=1e-7 * C_)
+    assert kernel.rkkt_q(Q, y, C_, x)[0] <= 1e-8
+    assert kernel.objective_q(Q, x) == pytest.approx(ref.obj, rel=1e-9)
+    with _svc(X, y, C_, alpha, tol=1e-8, newton="pcg", max_cg=2000) as s:
+        x, _, info = s.solve()
+    x = x.cpu().numpy()
+    assert info["status_name"] == "OK" and info["cg_iters"] > 0
     assert kernel.rkkt_q(Q, y, C_, x)[0] <= 1e-8
     assert kernel.objective_q(Q, x) == pytest.approx(ref.obj, rel=1e-8)
 
