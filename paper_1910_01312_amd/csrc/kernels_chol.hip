@@ -236,38 +236,25 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ 
         }
 }
 
-// The same trailing update on the matrix cores: v_mfma_f64_16x16x4f64.
-// Each wave owns a 32 x 32 quarter of the 64 x 64 tile (2 x 2 MFMA tiles)
-// and runs the 64-long contraction in 16 steps of 4; lane l supplies row
-// l % 16, column l / 16 of the 16 x 4 operand from Li (rows of block ib) and
-// likewise of the 4 x 16 operand from Lj (rows of block jb, i.e. L_jb^T), and
-// holds rows 4 v + l / 16 (v = 0..3), column l % 16 of the 16 x 16 result.
+// Trailing updates on the matrix cores (v_mfma_f64_16x16x4f64):
+//   A_ib,jb -= sum over k-blocks kb in [k0, k1) of L_ib,kb L_jb,kb^T
+// for the lower tiles jb in [j0, j1), ib in [jb, nblk) (grid x: ib - j0,
+// y: jb - j0; blocks above the diagonal return).  The k-blocks are staged in
+// LDS one at a time and accumulated in registers, so a tile is read and
+// written once per launch whatever the number of k-blocks.  Each wave owns a
+// 32 x 32 quarter of the 64 x 64 tile (2 x 2 MFMA tiles) and runs each
+// 64-long contraction in 16 steps of 4; lane l supplies row l % 16, column
+// l / 16 of the 16 x 4 operand from Li (rows of block ib) and likewise of the
+// 4 x 16 operand from Lj (rows of block jb, i.e. L_jb^T), and holds rows
+// 4 v + l / 16 (v = 0..3), column l % 16 of the 16 x 16 result.
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restrict__ M, int q, int kb) {
+__global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restrict__ M, int q, int k0,
+                                                                int k1, int j0) {
     __shared__ double Li[NB][NB + 1];
     __shared__ double Lj[NB][NB + 1];
-    int t = blockIdx.x, a = 0;
-    while (t > a) { t -= a + 1; ++a; }
-    const int b = t;
-    const int ib = kb + 1 + a, jb = kb + 1 + b;
-    const int o = kb * NB, io = ib * NB, jo = jb * NB;
-    const int m = min(NB, q - o);
-    {
-        double vi[TILE_PER_THREAD], vj[TILE_PER_THREAD];
-#pragma unroll
-        for (int h = 0; h < TILE_PER_THREAD; ++h) {
-            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
-            vi[h] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
-            vj[h] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
-        }
-#pragma unroll
-        for (int h = 0; h < TILE_PER_THREAD; ++h) {
-            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
-            Li[i][k] = vi[h];
-            Lj[i][k] = vj[h];
-        }
-    }
-    __syncthreads();
+    const int ib = j0 + (int)blockIdx.x, jb = j0 + (int)blockIdx.y;
+    if (ib < jb) return;
+    const int io = ib * NB, jo = jb * NB;
     const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     const int r16 = lane & 15, k4 = lane >> 4;
@@ -276,14 +263,35 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restri
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    for (int kb = k0; kb < k1; ++kb) {
+        const int o = kb * NB;
+        const int m = min(NB, q - o);
+        {
+            double vi[TILE_PER_THREAD], vj[TILE_PER_THREAD];
+#pragma unroll
+            for (int h = 0; h < TILE_PER_THREAD; ++h) {
+                const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+                vi[h] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
+                vj[h] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
+            }
+            if (kb > k0) __syncthreads();        // the previous k-block's reads are done
+#pragma unroll
+            for (int h = 0; h < TILE_PER_THREAD; ++h) {
+                const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+                Li[i][k] = vi[h];
+                Lj[i][k] = vj[h];
+            }
+        }
+        __syncthreads();
 #pragma unroll 4
-    for (int k0 = 0; k0 < NB; k0 += 4) {
-        const double a0 = Li[wr + r16][k0 + k4], a1 = Li[wr + 16 + r16][k0 + k4];
-        const double b0 = Lj[wc + r16][k0 + k4], b1 = Lj[wc + 16 + r16][k0 + k4];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        for (int kk = 0; kk < NB; kk += 4) {
+            const double a0 = Li[wr + r16][kk + k4], a1 = Li[wr + 16 + r16][kk + k4];
+            const double b0 = Lj[wc + r16][kk + k4], b1 = Lj[wc + 16 + r16][kk + k4];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -475,16 +483,29 @@ void launch_chol_solve_blocked(const double* M, const double* inv, const double*
     }
 }
 
+// Two-level blocking: the 64-wide block columns are taken in groups of
+// kCholGroup.  Inside a group each block column is factored (diagonal block,
+// panel) and its rank-64 update applied only to the group's later block
+// columns; the trailing matrix right of the group then takes one update of
+// rank 64 kCholGroup, which reads and writes each of its tiles once per group
+// instead of once per block column.
+constexpr int kCholGroup = 4;
 void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s) {
     const int nblk = (int)((q + NB - 1) / NB);
-    for (int kb = 0; kb < nblk; ++kb) {
-        SSN_LAUNCH(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv, sc);
-        const int nt = nblk - kb - 1;
-        if (nt > 0) {
-            SSN_LAUNCH(k_chol_panel, dim3(nt), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv);
-            SSN_LAUNCH(k_chol_update_mfma, dim3(nt * (nt + 1) / 2), dim3(SSN_BLOCK), 0, s, M,
-                               (int)q, kb);
+    for (int K = 0; K < nblk; K += kCholGroup) {
+        const int Kend = std::min(nblk, K + kCholGroup);
+        for (int kb = K; kb < Kend; ++kb) {
+            SSN_LAUNCH(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv, sc);
+            const int nt = nblk - kb - 1;
+            if (nt > 0)
+                SSN_LAUNCH(k_chol_panel, dim3(nt), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv);
+            if (kb + 1 < Kend)            // the group's later block columns, all rows below
+                SSN_LAUNCH(k_chol_update_mfma, dim3(nblk - kb - 1, Kend - kb - 1), dim3(SSN_BLOCK), 0, s,
+                           M, (int)q, kb, kb + 1, kb + 1);
         }
+        if (Kend < nblk)                  // everything right of the group
+            SSN_LAUNCH(k_chol_update_mfma, dim3(nblk - Kend, nblk - Kend), dim3(SSN_BLOCK), 0, s, M,
+                       (int)q, K, Kend, Kend);
     }
 }
 
