@@ -80,9 +80,15 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
             bad = true;
             akk = 1.0;
         }
-        const double lkk = sqrt(akk);
-        const double rk = 1.0 / akk;
-        const double rl = rk * lkk;                       // 1 / l_kk
+        // 1 / sqrt(a_kk) from the hardware estimate and two Newton steps
+        // r <- r (3/2 - a r^2 / 2) (each squares the relative error), which
+        // keeps the pivot's latency (the chain that every step waits on) at a
+        // few dependent operations instead of a square root and a division
+        double rl = __builtin_amdgcn_rsq(akk);
+        rl = rl * fma(-0.5 * akk * rl, rl, 1.5);
+        rl = rl * fma(-0.5 * akk * rl, rl, 1.5);        // 1 / l_kk
+        const double lkk = akk * rl;
+        const double rk = rl * rl;                        // 1 / a_kk
         const double t = i > k ? cik * rk : 0.0;
         if (cgu == kg) a[kk] = i > k ? cik * rl : (i == k ? lkk : 0.0);
         if (cgu * 16 + 15 > k) {
@@ -489,7 +495,10 @@ void launch_chol_solve_blocked(const double* M, const double* inv, const double*
 // columns; the trailing matrix right of the group then takes one update of
 // rank 64 kCholGroup, which reads and writes each of its tiles once per group
 // instead of once per block column.
-constexpr int kCholGroup = 4;
+#ifndef SSN_CHOL_GROUP
+#define SSN_CHOL_GROUP 8
+#endif
+constexpr int kCholGroup = SSN_CHOL_GROUP;
 void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s) {
     const int nblk = (int)((q + NB - 1) / NB);
     for (int K = 0; K < nblk; K += kCholGroup) {
