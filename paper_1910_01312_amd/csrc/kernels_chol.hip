@@ -1,10 +1,12 @@
-// Blocked fp64 Cholesky of the reduced Newton matrix
-//     M = I + sigma (X_J^T X_J - s s^T / p)   (q x q, symmetric positive definite)
-// for q above the LDS-resident kernel's limit, and the two triangular solves
+// Blocked fp64 Cholesky of a symmetric positive definite Newton matrix (the
+// q x q M = I + sigma (X_J^T X_J - s s^T / p) of the linear path, the p x p
+// I + sigma Pi Q_JJ Pi of the kernel path, K_rr + s I of the Nystroem map)
+// above the LDS-resident kernel's limit, and the two triangular solves
 // giving d = -M^{-1} g.  Right-looking with 64 x 64 blocks: for each block
 // column kb, factor the diagonal block and form the inverse of its factor,
 // compute the panel below it as A_panel L_kk^{-T} (a small GEMM), and update
-// the trailing lower tiles.  The factor is kept in the lower triangle of M
+// the trailing lower tiles (on the matrix cores, grouped so that the
+// trailing matrix is rewritten once per eight block columns).  The factor is kept in the lower triangle of M
 // and mirrored into the upper triangle (M[j][i] = L[i][j]), so that both
 // triangular solves read it with consecutive lanes on consecutive addresses;
 // the inverses of the diagonal factors turn the block solves into mat-vecs.
@@ -185,61 +187,6 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_panel(double* __restrict__ M
             }
         }
     }
-}
-
-// Trailing update of the lower tiles (ib >= jb > kb):
-// A_ib,jb -= L_ib,kb L_jb,kb^T.  One 64 x 64 tile per block, 4 x 4 per thread.
-__global__ __launch_bounds__(SSN_BLOCK) void k_chol_update(double* __restrict__ M, int q, int kb) {
-    __shared__ double Li[NB][NB + 1];
-    __shared__ double Lj[NB][NB + 1];
-    // blockIdx.x -> (a, b), a >= b, over the trailing lower triangle
-    int t = blockIdx.x, a = 0;
-    while (t > a) { t -= a + 1; ++a; }
-    const int b = t;
-    const int ib = kb + 1 + a, jb = kb + 1 + b;
-    const int o = kb * NB, io = ib * NB, jo = jb * NB;
-    const int m = min(NB, q - o);
-    {
-        double vi[TILE_PER_THREAD], vj[TILE_PER_THREAD];
-#pragma unroll
-        for (int h = 0; h < TILE_PER_THREAD; ++h) {
-            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
-            vi[h] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
-            vj[h] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
-        }
-#pragma unroll
-        for (int h = 0; h < TILE_PER_THREAD; ++h) {
-            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
-            Li[i][k] = vi[h];
-            Lj[i][k] = vj[h];
-        }
-    }
-    __syncthreads();
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    for (int k = 0; k < m; ++k) {
-        double x[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            x[u] = Li[ty + 16 * u][k];
-            y[u] = Lj[tx + 16 * u][k];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = io + ty + 16 * u, j = jo + tx + 16 * v;
-            if (i < q && j < q && j <= i) M[(int64_t)i * q + j] -= acc[u][v];
-        }
 }
 
 // Trailing updates on the matrix cores (v_mfma_f64_16x16x4f64):
