@@ -29,18 +29,28 @@ int64_t chol_inv_size(int64_t q) { return (q + NB - 1) / NB * 2 * NB * NB; }
 // Factor diagonal block kb and form X = L_kk^{-1}, both right-looking in
 // registers: thread t keeps row i = t % 64, columns 16 (t / 64) .. +15 of the
 // block (a), and column j = t % 64, rows 16 (t / 64) .. +15 of B (initially
-// I), so that each thread finds B[k][j] in its own column.  Step k publishes
-// column k of a and row k of B through LDS (double buffered, one barrier per
-// step; row k of B is one vector store by the wave holding it); then
-//   l_kk = sqrt(a_kk),  l_ik = a_ik / l_kk,  X[k][.] = B[k][.] / l_kk,
-//   a_ij -= a_ik a_jk / a_kk  and  B[i][.] -= (a_ik / a_kk) B[k][.]  (i > k),
-// which is forward substitution of L X = I carried along with the
-// factorisation.  A non-positive pivot is replaced by 1 and reported in
-// sc->chol_fail.  Rows past q are padded with the identity.
+// I), so that each thread finds B[k][j] in its own column; B becomes X by
+// forward substitution of L X = I carried along with the factorisation.  A
+// non-positive pivot is replaced by 1 and reported in sc->chol_fail; rows
+// past q are padded with the identity.  Four columns per step, two barriers
+// per step (32 in all; one column per step with one barrier each took 41 us
+// per block against 29 us).  Step k0 = 4K:
+//   1. the column group holding columns k0..k0+3 publishes them (raw values);
+//   2. every thread factors the 4 x 4 diagonal block D = A[k0..+3][k0..+3]
+//      itself (pivot reciprocal square roots from the hardware estimate and
+//      two Newton steps) and computes its own row's entries of L in the four
+//      columns, l_ic = (a_ic - sum_{m<c} l_im l_cm) / l_cc; wave 0 publishes
+//      them for all 64 rows, and the owner group finishes rows k0..k0+3 of
+//      X = L^{-1} by forward substitution with the 4 x 4 factor, published too;
+//   3. a_ij -= sum_c l_ic l_jc for the thread's columns j > k0 + 3, and
+//      B[r][i] -= sum_c l_rc X[k0+c][i] for its rows r > k0 + 3.
+// The published buffers alternate between steps, so the next step's writes
+// never meet this step's reads.
 __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M, int q, int kb,
-                                                         double* __restrict__ inv, Scalars* sc) {
-    __shared__ double col[2][NB];
-    __shared__ double rowb[2][NB];
+                                                          double* __restrict__ inv, Scalars* sc) {
+    __shared__ double raw[2][4][NB];
+    __shared__ double Lc[2][NB][4];      // row-major: the four entries of a row together
+    __shared__ double Bf[2][4][NB];
     const int tid = threadIdx.x;
     if (kb == 0 && tid == 0) sc->chol_fail = 0;
     const int o = kb * NB;
@@ -53,65 +63,108 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
         a[jj] = (i < m && j < m) ? M[(int64_t)(o + i) * q + o + j] : (i == j ? 1.0 : 0.0);
         b[jj] = i == j ? 1.0 : 0.0;
     }
-    // wave-uniform column group (scalar branches below)
     const int cgu = __builtin_amdgcn_readfirstlane(cg);
     bool bad = false;
-    // 4 groups of 16 columns: the group loop stays a loop so that the code
-    // (16 unrolled steps) fits the instruction cache; fully unrolled, the 64
-    // steps are ~100 KB of straight-line code fetched once each.
 #pragma unroll 1
     for (int kg = 0; kg < NB / 16; ++kg)
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-        const int k = kg * 16 + kk;
-        double* cr = col[kk & 1];
-        double* rb = rowb[kk & 1];
+    for (int c0 = 0; c0 < 16; c0 += 4) {
+        const int k0 = kg * 16 + c0;
+        const int par = (c0 >> 2) & 1;
+        // 1. publish the four raw columns
         if (cgu == kg) {
-            cr[i] = a[kk];
-            rb[i] = b[kk];                                // B[k][i], for column i
+#pragma unroll
+            for (int c = 0; c < 4; ++c) raw[par][c][i] = a[c0 + c];
         }
         __syncthreads();
-        // every LDS read of the step is issued here, ahead of the pivot math
-        double akk = cr[k];
-        const double cik = cr[i];
-        const double bki = rb[i];                         // B[k][j] of this thread's column
-        double cj[16];
+        // 2. the 4 x 4 factor (every thread), this row's L entries
+        double d[4][4];
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) cj[jj] = cr[cgu * 16 + jj];
-        if (!(akk > 0.0)) {
-            bad = true;
-            akk = 1.0;
-        }
-        // 1 / sqrt(a_kk) from the hardware estimate and two Newton steps
-        // r <- r (3/2 - a r^2 / 2) (each squares the relative error), which
-        // keeps the pivot's latency (the chain that every step waits on) at a
-        // few dependent operations instead of a square root and a division
-        double rl = __builtin_amdgcn_rsq(akk);
-        rl = rl * fma(-0.5 * akk * rl, rl, 1.5);
-        rl = rl * fma(-0.5 * akk * rl, rl, 1.5);        // 1 / l_kk
-        const double lkk = akk * rl;
-        const double rk = rl * rl;                        // 1 / a_kk
-        const double t = i > k ? cik * rk : 0.0;
-        if (cgu == kg) a[kk] = i > k ? cik * rl : (i == k ? lkk : 0.0);
-        if (cgu * 16 + 15 > k) {
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const double l = cgu * 16 + jj > k ? cj[jj] : 0.0;
-                a[jj] = fma(-t, l, a[jj]);
+            for (int c = 0; c <= r; ++c) d[r][c] = raw[par][c][k0 + r];
+        double l4[4][4], rl[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double piv = d[c][c];
+#pragma unroll
+            for (int mm = 0; mm < c; ++mm) piv = fma(-l4[c][mm], l4[c][mm], piv);
+            if (!(piv > 0.0)) {
+                bad = true;
+                piv = 1.0;
+            }
+            double r0 = __builtin_amdgcn_rsq(piv);
+            r0 = r0 * fma(-0.5 * piv * r0, r0, 1.5);
+            r0 = r0 * fma(-0.5 * piv * r0, r0, 1.5);
+            rl[c] = r0;
+            l4[c][c] = piv * r0;
+#pragma unroll
+            for (int r = c + 1; r < 4; ++r) {
+                double v = d[r][c];
+#pragma unroll
+                for (int mm = 0; mm < c; ++mm) v = fma(-l4[r][mm], l4[c][mm], v);
+                l4[r][c] = v * r0;
             }
         }
-        if (cgu * 16 + 15 >= k) {                         // rows r < k do not change
+        double li[4];
+        {
+            double ar[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ar[c] = raw[par][c][i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double v = ar[c];
+#pragma unroll
+                for (int mm = 0; mm < c; ++mm) v = fma(-li[mm], l4[c][mm], v);
+                // rows above k0 + c have no entry in column k0 + c
+                li[c] = i > k0 + c ? v * rl[c] : (i == k0 + c ? l4[c][c] : 0.0);
+            }
+        }
+        if (cgu == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Lc[par][i][c] = li[c];
+        }
+        if (cgu == kg) {
+            // rows k0..k0+3 of X: forward substitution with the 4 x 4 factor in column i
+            double x[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double v = b[c0 + c];
+#pragma unroll
+                for (int mm = 0; mm < c; ++mm) v = fma(-l4[c][mm], x[mm], v);
+                x[c] = v * rl[c];
+                b[c0 + c] = x[c];
+                Bf[par][c][i] = x[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) a[c0 + c] = li[c];
+        }
+        __syncthreads();
+        // 3. rank-4 updates of the later columns and of the later rows of B
+        if (cgu * 16 + 15 > k0 + 3) {
+            double bx[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bx[c] = Bf[par][c][i];
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
-                const int r = cgu * 16 + jj;              // B[r][i] -= (a_rk / a_kk) B[k][i]
-                const double tr = r > k ? cj[jj] * rk : 0.0;
-                const double f = r == k ? rl : 1.0;
-                b[jj] = fma(-tr, bki, b[jj]) * f;
+                const int j = cgu * 16 + jj;
+                if (j > k0 + 3) {
+                    double lj[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) lj[c] = Lc[par][j][c];
+                    double av = a[jj], bv = b[jj];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        av = fma(-li[c], lj[c], av);       // a_ij -= l_ic l_jc
+                        bv = fma(-lj[c], bx[c], bv);       // B[j][i] -= l_jc X[k0+c][i]
+                    }
+                    a[jj] = av;
+                    b[jj] = bv;
+                }
             }
         }
     }
     if (bad && tid == 0) sc->chol_fail = 1;
-    // factor back to M (lower entry and its upper mirror), X and X^T to inv
     double* Xo = inv + (int64_t)kb * 2 * NB * NB;
     double* XTo = Xo + NB * NB;
 #pragma unroll
@@ -121,7 +174,6 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
             M[(int64_t)(o + i) * q + o + j] = a[jj];
             M[(int64_t)(o + j) * q + o + i] = a[jj];
         }
-        // b[jj] = B[j][i] (row j = 16 cg + jj, column i)
         const double x = i <= j ? b[jj] : 0.0;
         Xo[j * NB + i] = x;
         XTo[i * NB + j] = x;
