@@ -11,6 +11,9 @@ The references are solved to R_KKT <= 1e-8 (the objective of such a solve
 agrees with the best attainable one to ~1e-11 relative on these families).
 
     python tests/golden/make_refs.py [name ...]      # default: all
+
+Each reference is added to the file when its job ends (the file is read
+again at that moment), so jobs may run in separate processes side by side.
 """
 from __future__ import annotations
 
@@ -108,17 +111,26 @@ JOBS = {
 }
 
 
-def main(names):
+def _store(path, name, value):
+    """Add one reference to the file at path, re-reading it first (several
+    jobs may run side by side, each adding its own entries)."""
     refs = {}
-    if os.path.exists(OUT):
-        with open(OUT) as f:
+    if os.path.exists(path):
+        with open(path) as f:
             refs = json.load(f)
+    refs[name] = value
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(refs, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def main(names):
     for name in names or list(JOBS):
         t = time.perf_counter()
-        refs[name] = JOBS[name]()
+        value = JOBS[name]()
         print(f"{name}: {time.perf_counter() - t:.1f} s", flush=True)
-        with open(OUT, "w") as f:
-            json.dump(refs, f, indent=1, sort_keys=True)
+        _store(OUT, name, value)
 
 
 if __name__ == "__main__":
