@@ -107,6 +107,11 @@ typedef struct {
                                 /* issues the same launches one by one (same results)     */
     int32_t autotune;           /* batched solve: 1 times candidate launch shapes once    */
                                 /* per shape class and keeps the fastest (same results)   */
+    int32_t lowrank;            /* dense Cholesky Newton steps at the sigma of the stored  */
+                                /* factor: 1 (default) updates that factor by the Woodbury */
+                                /* identity when at most 94 rows of J changed (mixed       */
+                                /* precision, whose refinement then uses the updated       */
+                                /* operator), 2 also in fp64, 0 always refactors           */
 } ssnalm_options;
 
 /* What the paper reports per solve (Section 4, Table 2 columns) plus timing. */
@@ -135,6 +140,8 @@ typedef struct {
     int32_t proj_capped;        /* projections that hit the multisection pass cap (their  */
                                 /* multiplier is the interpolation of the last bracket)   */
     int32_t status;             /* same as the return value                               */
+    int32_t lowrank_steps;      /* Newton steps taken by a low-rank update of the stored  */
+                                /* Cholesky factor instead of a new factorisation         */
 } ssnalm_info;
 
 /* Fill *opt with the defaults.  opt: host pointer. */

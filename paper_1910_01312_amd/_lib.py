@@ -55,7 +55,7 @@ class Options(C.Structure):
                 ("max_backtracks", C.c_int32), ("newton", C.c_int32),
                 ("precision", C.c_int32), ("max_cg", C.c_int32), ("verbose", C.c_int32),
                 ("check_finite", C.c_int32), ("profile", C.c_int32),
-                ("batch_graphs", C.c_int32), ("autotune", C.c_int32)]
+                ("batch_graphs", C.c_int32), ("autotune", C.c_int32), ("lowrank", C.c_int32)]
 
 
 class WsStats(C.Structure):
@@ -71,7 +71,8 @@ class Info(C.Structure):
                 ("iters_outer", C.c_int32), ("iters_inner", C.c_int32),
                 ("cg_iters", C.c_int32), ("proj_passes", C.c_int32), ("p", C.c_int32),
                 ("n_sv", C.c_int32), ("ls_fail", C.c_int32), ("ls_trials", C.c_int32),
-                ("grad_steps", C.c_int32), ("proj_capped", C.c_int32), ("status", C.c_int32)]
+                ("grad_steps", C.c_int32), ("proj_capped", C.c_int32), ("status", C.c_int32),
+                ("lowrank_steps", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

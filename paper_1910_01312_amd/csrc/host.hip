@@ -149,6 +149,16 @@ struct ssnalm_ctx {
     double* kpart = nullptr;         // kQcolsMaxChunks x n partial rows
     int64_t kchol = 0;               // largest p solved by Cholesky
     int refine_total = 0;
+    // low-rank updates of the dense Newton factor (kernels_lowrank.hip): the
+    // factor in M / linv is that of (lr_sigma, the J mask jm0, s0v, lr_p0)
+    bool lr_valid = false;
+    double lr_sigma = 0.0;
+    int64_t lr_p0 = 0;
+    int lr_k = 0;                    // rank of the update in force for this step (0: fresh factor)
+    int lowrank_steps = 0;
+    uint8_t *jm0 = nullptr, *chg_mask = nullptr;
+    int32_t *chg_list = nullptr, *lr_piv = nullptr;
+    double *s0v = nullptr, *lrU = nullptr, *lrZ = nullptr, *lrW = nullptr, *lrT = nullptr;
     // q-vectors
     double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
     double *qv = nullptr, *qv2 = nullptr;
@@ -480,27 +490,67 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         long long* pcount = &dsc(c)->p;
         launch_compact(mask, c->n, c->jlist, pcount, c->blk, cnt(c, CNT_CMP), c->st);
         if (c->svr) launch_list_mod(c->jlist, p, c->nphys, c->st);   // rows of X (repeats allowed)
-        prof_begin(c, SSNALM_K_SYRK);
-        if (c->mixed)
-            launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, c->G, c->mpart, c->mpart_cap, c->st);
-        else
-            launch_syrk_gather(c->dtype, c->X, c->q, c->jlist, p, c->G, c->part, c->part_cap, c->st);
-        prof_end(c, SSNALM_K_SYRK, (double)p * c->q * elem_bytes(c->dtype) + 4.0 * p + 8.0 * c->q * c->q,
-                 (double)p * c->q * (c->q + 1));
-        if (c->gen) {
-            const double den = c->hs->sc.aja;            // a_J^T a_J (0: no rank-one term)
-            launch_form_M_inv(c->G, sv, sigma, den > 0.0 ? 1.0 / den : 0.0, c->M, c->q, c->st);
-        } else {
-            launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
+        // A step at the sigma of the stored factor whose J differs from the
+        // factor's in few rows updates that factor (Woodbury) instead of
+        // forming and factoring M again.
+        const bool lr_ok = c->lrU && !c->gen && !c->svr && (c->mixed ? c->opt.lowrank >= 1 : c->opt.lowrank >= 2);
+        c->lr_k = 0;
+        bool took_lr = false;
+        if (lr_ok && c->lr_valid && sigma == c->lr_sigma) {
+            launch_mask_diff(mask, c->jm0, c->n, c->chg_mask, c->st);
+            launch_compact(c->chg_mask, c->n, c->chg_list, &dsc(c)->nchg, c->blk, cnt(c, CNT_CMP), c->st);
+            STCHK(sync_state(c));
+            const int64_t nchg = c->hs->sc.nchg;
+            const int64_t k = nchg + (c->lr_p0 > 0 ? 1 : 0) + (p > 0 ? 1 : 0);
+            if (k <= lowrank_max()) {
+                HIPCHK(hipMemsetAsync(&dsc(c)->chol_fail, 0, sizeof(int), c->st));
+                prof_begin(c, SSNALM_K_CHOL);
+                if (k > 0) {
+                    launch_lr_build(c->dtype, c->X, c->q, c->chg_list, (int)nchg, mask, sigma, c->s0v, c->lr_p0,
+                                    sv, p, c->lrU, c->lrW, (int)k, c->st);
+                    launch_chol_solve_factored_multi(c->M, c->linv, c->lrU, c->lrZ, c->q, k, c->st);
+                    launch_lr_factor(c->lrU, c->lrZ, c->q, (int)k, c->lrW, c->lrT, c->lr_piv, dsc(c), c->st);
+                }
+                launch_chol_solve_factored(c->M, c->linv, g, d, c->q, c->st);
+                if (k > 0) launch_lr_apply(c->lrU, c->lrZ, c->q, (int)k, c->lrT, c->lr_piv, d, d, c->st);
+                prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q + 16.0 * c->q * k,
+                         2.0 * (k + 1) * (double)c->q * c->q + 4.0 * (double)k * k * c->q);
+                c->lr_k = (int)k;
+                ++c->lowrank_steps;
+                took_lr = true;
+            }
         }
-        prof_begin(c, SSNALM_K_CHOL);
-        if (!c->mixed && c->q <= chol_small_max()) {
-            launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
-        } else {
-            launch_chol_factor_blocked(c->M, c->q, c->linv, dsc(c), c->st);
-            launch_chol_solve_factored(c->M, c->linv, g, d, c->q, c->st);
+        if (!took_lr) {
+            prof_begin(c, SSNALM_K_SYRK);
+            if (c->mixed)
+                launch_syrk_mfma(c->X, c->dtype, c->q, c->jlist, p, c->G, c->mpart, c->mpart_cap, c->st);
+            else
+                launch_syrk_gather(c->dtype, c->X, c->q, c->jlist, p, c->G, c->part, c->part_cap, c->st);
+            prof_end(c, SSNALM_K_SYRK, (double)p * c->q * elem_bytes(c->dtype) + 4.0 * p + 8.0 * c->q * c->q,
+                     (double)p * c->q * (c->q + 1));
+            if (c->gen) {
+                const double den = c->hs->sc.aja;            // a_J^T a_J (0: no rank-one term)
+                launch_form_M_inv(c->G, sv, sigma, den > 0.0 ? 1.0 / den : 0.0, c->M, c->q, c->st);
+            } else {
+                launch_form_M(c->G, sv, sigma, p, c->M, c->q, c->st);
+            }
+            prof_begin(c, SSNALM_K_CHOL);
+            if (!c->mixed && c->q <= chol_small_max()) {
+                launch_chol_solve_small(c->M, g, d, c->q, dsc(c), c->st);
+            } else {
+                launch_chol_factor_blocked(c->M, c->q, c->linv, dsc(c), c->st);
+                launch_chol_solve_factored(c->M, c->linv, g, d, c->q, c->st);
+            }
+            prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q, (double)c->q * c->q * c->q / 3.0 + 2.0 * c->q * c->q);
+            if (lr_ok) {
+                // the new factor's (sigma, J, s, p), for later steps' updates
+                HIPCHK(hipMemcpyAsync(c->jm0, mask, c->n, hipMemcpyDeviceToDevice, c->st));
+                HIPCHK(hipMemcpyAsync(c->s0v, sv, sizeof(double) * c->q, hipMemcpyDeviceToDevice, c->st));
+                c->lr_p0 = p;
+                c->lr_sigma = sigma;
+                c->lr_valid = true;
+            }
         }
-        prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q, (double)c->q * c->q * c->q / 3.0 + 2.0 * c->q * c->q);
         if (c->mixed) {
             // iterative refinement with the exact operator
             //   M v = v + sigma X_J^T (X_J v - mean(X_J v) 1)
@@ -519,6 +569,8 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                 ++*cg_iters;
                 if (!(c->hs->sc.cg_rr > tol2)) break;
                 launch_chol_solve_factored(c->M, c->linv, c->qv2, c->qv, c->q, c->st);
+                if (c->lr_k > 0)
+                    launch_lr_apply(c->lrU, c->lrZ, c->q, c->lr_k, c->lrT, c->lr_piv, c->qv, c->qv, c->st);
                 launch_axpy(d, c->qv, 1.0, c->q, c->st);
             }
         }
@@ -845,6 +897,7 @@ void ssnalm_default_options(ssnalm_options* o) {
     o->profile = 0;
     o->batch_graphs = 1;
     o->autotune = 1;
+    o->lowrank = 1;
 }
 
 const char* ssnalm_last_error(void) { return g_err.c_str(); }
@@ -1400,7 +1453,13 @@ static ssnalm_status create_impl(ssnalm_ctx** out, const ssnalm_problem* pr,
         ALLOC(c->G, q * q);
         ALLOC(c->M, q * q);
         c->mixed = c->opt.precision == SSNALM_PREC_MIXED && syrk_mfma_supported(c->dtype, q);
-        if (c->mixed || q > chol_small_max()) ALLOC(c->linv, chol_inv_size(q));
+        if (c->mixed || q > chol_small_max()) {
+            ALLOC(c->linv, chol_inv_size(q));
+            const int lr = lowrank_max();
+            ALLOC(c->jm0, n); ALLOC(c->chg_mask, n); ALLOC(c->chg_list, n);
+            ALLOC(c->s0v, q); ALLOC(c->lrU, q * lr); ALLOC(c->lrZ, q * lr); ALLOC(c->lrW, lr);
+            ALLOC(c->lrT, lr * lr); ALLOC(c->lr_piv, lr);
+        }
         if (c->mixed) {
             ALLOC(c->zJ, n); ALLOC(c->wJ, n); ALLOC(c->cgpart, 1024 + 512 + 1024);
         }
@@ -1605,6 +1664,7 @@ static ssnalm_status solve_kernel(ssnalm_ctx* c, const double* x0, double* x_out
     inf.grad_steps = grad_steps;
     inf.proj_capped = c->proj_capped;
     inf.status = status;
+    inf.lowrank_steps = c->lowrank_steps;
     if (info) *info = inf;
     return status;
 }
@@ -1624,6 +1684,8 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     const int64_t n = c->n, q = c->q;
     c->proj_passes = 0;
     c->proj_capped = 0;
+    c->lr_valid = false;             // repeated solves take identical steps
+    c->lowrank_steps = 0;
     ssnalm_info inf;
     memset(&inf, 0, sizeof inf);
     int inner_total = 0, cg_total = 0, ls_fail = 0, outer = 0, ls_trials = 0, grad_steps = 0;
@@ -1720,6 +1782,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
                     // instead and start the search again at alpha = 1.
                     fell_back = true;
                     ++grad_steps;
+                    c->lr_valid = false;     // the next step factors afresh
                     launch_scale_copy(c->d, c->g, -1.0, q, c->st);
                     op_amul(c, c->d, c->td);
                     launch_dots(3, c->g, c->d, &dsc(c)->gd, c->om, c->d, &dsc(c)->od, c->d, c->d,
@@ -1815,6 +1878,7 @@ extern "C" ssnalm_status ssnalm_solve(ssnalm_ctx* c, const double* x0, double* x
     inf.grad_steps = grad_steps;
     inf.proj_capped = c->proj_capped;
     inf.status = status;
+    inf.lowrank_steps = c->lowrank_steps;
     if (info) *info = inf;
     return status;
 }

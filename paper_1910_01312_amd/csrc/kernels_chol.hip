@@ -371,6 +371,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_chol_solve2(const double* __r
     __shared__ double red[SOLVE_PARTS][NB];
     __shared__ double yb[NB];
     const int tid = threadIdx.x, r = tid & (NB - 1), part = tid >> 6;
+    g += (int64_t)blockIdx.x * q;                    // right-hand side blockIdx.x (one per block)
+    d += (int64_t)blockIdx.x * q;
     for (int i = tid; i < q; i += blockDim.x) z[i] = -g[i];
     const int nblk = (q + NB - 1) / NB;
     for (int B = 0; B < nblk; ++B) {
@@ -521,6 +523,12 @@ void launch_chol_solve_factored(const double* M, const double* inv, const double
                                 int64_t q, hipStream_t s) {
     SSN_LAUNCH(k_chol_solve2, dim3(1), dim3(SOLVE_THREADS), (size_t)q * sizeof(double), s, M,
                        inv, g, d, (int)q);
+}
+void launch_chol_solve_factored_multi(const double* M, const double* inv, const double* G, double* D,
+                                      int64_t q, int64_t k, hipStream_t s) {
+    if (k <= 0) return;
+    SSN_LAUNCH(k_chol_solve2, dim3((unsigned)k), dim3(SOLVE_THREADS), (size_t)q * sizeof(double), s, M,
+               inv, G, D, (int)q);
 }
 
 }  // namespace ssn

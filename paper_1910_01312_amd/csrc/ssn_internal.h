@@ -66,6 +66,7 @@ struct Scalars {
     double kd0, kd1, kd2; // kernel contexts: a^T g_J, a^T r (Newton matrix), a^T v
     double kres;          // kernel contexts: (Pi r)^T Q_JJ (Pi r) of a CG residual r
     long long km;         // kernel contexts: support size of a product's input
+    long long nchg;       // rows of J that changed since the stored Newton factor
     long long p;          // |J|
     long long nnzj;       // nonzeros of the rows in J (sparse input)
     long long nfix;       // chunk-crossing column runs of the compact X_J copy
@@ -222,6 +223,19 @@ void launch_chol_solve_small(const double* M, const double* g, double* d, int64_
 int     chol_blocked_max();
 int64_t chol_inv_size(int64_t q);
 void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, hipStream_t s);
+// D[:, c] = -M^{-1} G[:, c] for k right-hand sides (columns of q doubles), q <= chol_blocked_max()
+void launch_chol_solve_factored_multi(const double* M, const double* inv, const double* G, double* D,
+                                      int64_t q, int64_t k, hipStream_t s);
+// Low-rank (Woodbury) update of the dense Newton step (kernels_lowrank.hip)
+int  lowrank_max();
+void launch_mask_diff(const uint8_t* a, const uint8_t* b, int64_t n, uint8_t* out, hipStream_t s);
+void launch_lr_build(int dtype, const void* X, int64_t q, const int32_t* chg, int nchg, const uint8_t* mask,
+                     double sigma, const double* s0, int64_t p0, const double* s1, int64_t p1, double* U,
+                     double* wgt, int k, hipStream_t s);
+void launch_lr_factor(const double* U, const double* Zn, int64_t q, int k, const double* wgt, double* Tm,
+                      int32_t* piv, Scalars* sc, hipStream_t s);
+void launch_lr_apply(const double* U, const double* Zn, int64_t q, int k, const double* LU, const int32_t* piv,
+                     const double* d0, double* out, hipStream_t s);
 // d = -M^{-1} g from the blocked factor for any q (multi-workgroup solves)
 void launch_chol_solve_blocked(const double* M, const double* inv, const double* g, double* d, int64_t q,
                                hipStream_t s);

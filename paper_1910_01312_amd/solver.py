@@ -40,7 +40,7 @@ def _stream_handle():
 
 _OPT_KEYS = {"sigma0", "rho", "sigma_max", "mu", "ls_delta", "tau", "eta", "eps_decay",
              "floor_rel", "max_outer", "max_inner", "max_backtracks", "newton", "precision",
-             "max_cg", "verbose", "check_finite", "profile", "batch_graphs", "autotune"}
+             "max_cg", "verbose", "check_finite", "profile", "batch_graphs", "autotune", "lowrank"}
 
 
 def make_options(**kw) -> L.Options:
