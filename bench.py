@@ -672,7 +672,8 @@ def main():
         "solve": {"status": last["status_name"], "rkkt": last["rkkt"], "rkkt_oracle": rk_oracle,
                   "outer": last["iters_outer"], "newton": last["iters_inner"],
                   "cg": last["cg_iters"], "proj_passes": last["proj_passes"], "p": last["p"],
-                  "n_sv": last["n_sv"], "obj": last["obj"], "create_s": create_s},
+                  "n_sv": last["n_sv"], "obj": last["obj"], "lowrank_steps": last["lowrank_steps"],
+                  "create_s": create_s},
         "kernels_profiled_warmup": {k: {"launches": v["launches"], "ms": v["seconds"] * 1e3,
                         "ms_per_solve": class_total(k, v) * 1e3,
                         "GBps": (v["bytes"] / v["seconds"] / 1e9) if v["seconds"] > 0 and v["bytes"] > 0 else None}

@@ -96,7 +96,8 @@ typedef struct {
     int32_t newton;             /* SSNALM_NEWTON_*                                        */
     int32_t precision;          /* SSNALM_PREC_*                                          */
     int32_t max_cg;             /* PCG iteration cap per Newton step                      */
-    int32_t verbose;            /* 1: one line per outer iteration on stderr              */
+    int32_t verbose;            /* 1: one line per outer iteration on stderr, 2: also one */
+                                /* per Newton step at the stored factor's sigma           */
     int32_t check_finite;       /* 1: ssnalm_create scans X for NaN/Inf                   */
     int32_t profile;            /* HIP-event timing of the hot kernel classes: 0 off, 1    */
                                 /* all classes, > 1 a mask with bit (k + 1) for class k    */

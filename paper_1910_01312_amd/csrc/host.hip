@@ -502,6 +502,9 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
             STCHK(sync_state(c));
             const int64_t nchg = c->hs->sc.nchg;
             const int64_t k = nchg + (c->lr_p0 > 0 ? 1 : 0) + (p > 0 ? 1 : 0);
+            if (c->opt.verbose >= 2)
+                fprintf(stderr, "[ssnalm]   newton step: sigma=%.3g p=%lld rows changed since the factor=%lld\n",
+                        sigma, (long long)p, (long long)nchg);
             if (k <= lowrank_max()) {
                 HIPCHK(hipMemsetAsync(&dsc(c)->chol_fail, 0, sizeof(int), c->st));
                 prof_begin(c, SSNALM_K_CHOL);
