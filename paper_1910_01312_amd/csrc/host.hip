@@ -157,7 +157,7 @@ struct ssnalm_ctx {
     int lr_k = 0;                    // rank of the update in force for this step (0: fresh factor)
     int lowrank_steps = 0;
     uint8_t *jm0 = nullptr, *chg_mask = nullptr;
-    int32_t *chg_list = nullptr, *lr_piv = nullptr;
+    int32_t *chg_list = nullptr, *lr_perm = nullptr;
     double *s0v = nullptr, *lrU = nullptr, *lrZ = nullptr, *lrW = nullptr, *lrT = nullptr;
     // q-vectors
     double *om = nullptr, *g = nullptr, *sv = nullptr, *sq = nullptr, *d = nullptr;
@@ -512,10 +512,10 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                     launch_lr_build(c->dtype, c->X, c->q, c->chg_list, (int)nchg, mask, sigma, c->s0v, c->lr_p0,
                                     sv, p, c->lrU, c->lrW, (int)k, c->st);
                     launch_chol_solve_factored_multi(c->M, c->linv, c->lrU, c->lrZ, c->q, k, c->st);
-                    launch_lr_factor(c->lrU, c->lrZ, c->q, (int)k, c->lrW, c->lrT, c->lr_piv, dsc(c), c->st);
+                    launch_lr_factor(c->lrU, c->lrZ, c->q, (int)k, c->lrW, c->lrT, c->lr_perm, dsc(c), c->st);
                 }
                 launch_chol_solve_factored(c->M, c->linv, g, d, c->q, c->st);
-                if (k > 0) launch_lr_apply(c->lrU, c->lrZ, c->q, (int)k, c->lrT, c->lr_piv, d, d, c->st);
+                if (k > 0) launch_lr_apply(c->lrU, c->lrZ, c->q, (int)k, c->lrT, c->lr_perm, d, d, c->st);
                 prof_end(c, SSNALM_K_CHOL, 8.0 * c->q * c->q + 16.0 * c->q * k,
                          2.0 * (k + 1) * (double)c->q * c->q + 4.0 * (double)k * k * c->q);
                 c->lr_k = (int)k;
@@ -573,7 +573,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
                 if (!(c->hs->sc.cg_rr > tol2)) break;
                 launch_chol_solve_factored(c->M, c->linv, c->qv2, c->qv, c->q, c->st);
                 if (c->lr_k > 0)
-                    launch_lr_apply(c->lrU, c->lrZ, c->q, c->lr_k, c->lrT, c->lr_piv, c->qv, c->qv, c->st);
+                    launch_lr_apply(c->lrU, c->lrZ, c->q, c->lr_k, c->lrT, c->lr_perm, c->qv, c->qv, c->st);
                 launch_axpy(d, c->qv, 1.0, c->q, c->st);
             }
         }
@@ -1461,7 +1461,7 @@ static ssnalm_status create_impl(ssnalm_ctx** out, const ssnalm_problem* pr,
             const int lr = lowrank_max();
             ALLOC(c->jm0, n); ALLOC(c->chg_mask, n); ALLOC(c->chg_list, n);
             ALLOC(c->s0v, q); ALLOC(c->lrU, q * lr); ALLOC(c->lrZ, q * lr); ALLOC(c->lrW, lr);
-            ALLOC(c->lrT, lr * lr); ALLOC(c->lr_piv, lr);
+            ALLOC(c->lrT, lr * lr); ALLOC(c->lr_perm, lr);
         }
         if (c->mixed) {
             ALLOC(c->zJ, n); ALLOC(c->wJ, n); ALLOC(c->cgpart, 1024 + 512 + 1024);

@@ -7,8 +7,14 @@
 // so by the Woodbury identity, with the factor of M0,
 //   -M^{-1} g = d0 + Z' T^{-1} (U^T d0),  d0 = -M0^{-1} g,  Z' = -M0^{-1} U,
 //   T = S^{-1} + U^T M0^{-1} U = S^{-1} - U^T Z'.
-// T is symmetric but indefinite (S has both signs); it is factored by LU
-// with partial pivoting in one workgroup.
+// T is symmetric but indefinite (S has both signs).  With M0 and M both
+// positive definite, the inertia of T equals that of S^{-1} (Haynsworth's
+// inertia additivity on [[M0, U], [U^T, -S^{-1}]]), so after ordering the
+// columns with S > 0 first, the leading block S_+^{-1} + U_+^T M0^{-1} U_+ is
+// positive definite and its Schur complement negative definite: T = L D L^T
+// exists in that order without pivoting, with D > 0 on the first block and
+// D < 0 on the second.  A pivot of the wrong sign (rounding) is reported as a
+// factorisation failure and the step falls back to -g.
 #include "dev_common.h"
 #include "ssn_internal.h"
 
@@ -76,108 +82,206 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_lr_gram(const double* __restrict_
     if (threadIdx.x == 0) Tm[a * k + b] = (a == b ? 1.0 / wgt[a] : 0.0) - t;
 }
 
-// LU with partial pivoting of T (k x k, row-major) in place, in LDS; piv[r]
-// = the original row now at position r.  One workgroup.
 constexpr int LR_MAX = 96;
-__global__ __launch_bounds__(SSN_BLOCK) void k_lr_lu(double* __restrict__ Tm, int k, int32_t* __restrict__ piv,
-                                                     Scalars* sc) {
-    __shared__ double A[LR_MAX][LR_MAX + 1];
-    __shared__ int P[LR_MAX];
-    __shared__ int pr;
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) A[e / k][e % k] = Tm[e];
-    for (int r = threadIdx.x; r < k; r += blockDim.x) P[r] = r;
-    __syncthreads();
-    bool bad = false;
-    for (int c = 0; c < k; ++c) {
-        if (threadIdx.x == 0) {
-            int best = c;
-            double bv = fabs(A[c][c]);
-            for (int r = c + 1; r < k; ++r)
-                if (fabs(A[r][c]) > bv) { bv = fabs(A[r][c]); best = r; }
-            pr = best;
-        }
-        __syncthreads();
-        const int r0 = pr;
-        if (r0 != c) {
-            for (int j = threadIdx.x; j < k; j += blockDim.x) {
-                const double t = A[c][j];
-                A[c][j] = A[r0][j];
-                A[r0][j] = t;
-            }
-            if (threadIdx.x == 0) { const int t = P[c]; P[c] = P[r0]; P[r0] = t; }
-        }
-        __syncthreads();
-        const double pv = A[c][c];
-        if (!(fabs(pv) > 0.0)) bad = true;
-        // multipliers, then the trailing update (row r, column j > c)
-        for (int r = c + 1 + threadIdx.x; r < k; r += blockDim.x) A[r][c] = pv != 0.0 ? A[r][c] / pv : 0.0;
-        __syncthreads();
-        const int w = k - c - 1;
-        for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-            const int r = c + 1 + e / w, j = c + 1 + e % w;
-            A[r][j] = fma(-A[r][c], A[c][j], A[r][j]);
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) Tm[e] = A[e / k][e % k];
-    for (int r = threadIdx.x; r < k; r += blockDim.x) piv[r] = P[r];
-    if (bad && threadIdx.x == 0) sc->chol_fail = 1;
+constexpr int LR_TG = 16;                   // thread grid 16 x 16 over T
+constexpr int LR_TT = LR_MAX / LR_TG;       // each thread holds a 6 x 6 register tile
+static_assert(LR_TG * LR_TG == SSN_BLOCK, "one thread per tile");
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
 }
 
-// out = d0 + Zn c,  c = T^{-1} (U^T d0), with T's LU and pivots; out may be d0.
-__global__ __launch_bounds__(SSN_BLOCK) void k_lr_apply(const double* __restrict__ U,
-                                                        const double* __restrict__ Zn, int64_t q, int k,
-                                                        const double* __restrict__ LU,
-                                                        const int32_t* __restrict__ piv,
-                                                        const double* d0, double* out) {
-    __shared__ double wv[LR_MAX], cv[LR_MAX];
-    const int lane = threadIdx.x & (SSN_WAVE - 1), wid = threadIdx.x / SSN_WAVE;
-    // w = U^T d0, one wave per column
-    for (int a = wid; a < k; a += SSN_WAVES_PER_BLOCK) {
-        const double* ua = U + (int64_t)a * q;
-        double t = 0.0;
-        for (int64_t j = lane; j < q; j += SSN_WAVE) t = fma(ua[j], d0[j], t);
-        t = wave_sum(t);
-        if (lane == 0) wv[a] = t;
+// T = L D L^T in the order perm (columns with wgt > 0 first, each group in
+// its original order); perm[r] = the column of T at position r.  Output in Tm
+// (k x k, row-major, positions after perm): L[i][c] below the diagonal, D on
+// it.  Thread (tr, tc) holds rows tr + 16a and columns tc + 16b of the
+// permuted T; step c broadcasts column c through LDS (double-buffered, one
+// barrier per column) and every thread applies the rank-one update to its
+// tile; L and D collect in LDS and go to Tm at the end, so no global store is
+// outstanding at a barrier.
+__global__ __launch_bounds__(SSN_BLOCK) void k_lr_ldl(double* __restrict__ Tm, int k,
+                                                      const double* __restrict__ wgt,
+                                                      int32_t* __restrict__ perm, Scalars* sc) {
+    __shared__ double colb[2][LR_MAX];
+    __shared__ double Lsh[LR_MAX][LR_MAX + 1];   // L below the diagonal, D on it
+    __shared__ int pm[LR_MAX];
+    __shared__ int npos_s;
+    const int tid = threadIdx.x, lane = tid & (SSN_WAVE - 1);
+    const int tr = tid / LR_TG, tc = tid % LR_TG;
+    if (tid < SSN_WAVE) {
+        // stable partition by the sign of wgt with two ballots (k <= 128)
+        const bool v0 = lane < k, v1 = lane + SSN_WAVE < k;
+        const bool f0 = v0 && wgt[lane] > 0.0, f1 = v1 && wgt[lane + SSN_WAVE] > 0.0;
+        const unsigned long long b0 = __ballot(f0), b1 = __ballot(f1);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        const int n0 = __popcll(b0), npos = n0 + __popcll(b1);
+        const int r0 = __popcll(b0 & lt), r1 = __popcll(b1 & lt);
+        if (v0) pm[f0 ? r0 : npos + (lane - r0)] = lane;
+        if (v1) pm[f1 ? n0 + r1 : npos + (SSN_WAVE - n0) + (lane - r1)] = lane + SSN_WAVE;
+        if (lane == 0) npos_s = npos;
     }
     __syncthreads();
-    // L y = P w, U c = y: one row per step, summed by wave 0; every wave
-    // takes part in the step's barrier
-    for (int r = 0; r < k; ++r) {
-        if (wid == 0) {
-            double t = 0.0;
-            for (int j = lane; j < r; j += SSN_WAVE) t = fma(LU[r * k + j], cv[j], t);
-            t = wave_sum(t);
-            if (lane == 0) cv[r] = wv[piv[r]] - t;
+    const int npos = npos_s;
+    double A[LR_TT][LR_TT];
+#pragma unroll
+    for (int a = 0; a < LR_TT; ++a) {
+        const int i = tr + LR_TG * a;
+#pragma unroll
+        for (int b = 0; b < LR_TT; ++b) {
+            const int j = tc + LR_TG * b;
+            A[a][b] = (i < k && j < k) ? Tm[pm[i] * k + pm[j]] : 0.0;
+        }
+    }
+    __syncthreads();                 // every read of Tm before its overwrite
+    bool bad = false;
+    for (int c = 0; c < k; ++c) {
+        double* cb = colb[c & 1];
+        if (tc == (c % LR_TG)) {
+            const int bc = c / LR_TG;
+#pragma unroll
+            for (int b = 0; b < LR_TT; ++b)
+                if (b == bc) {
+#pragma unroll
+                    for (int a = 0; a < LR_TT; ++a) cb[tr + LR_TG * a] = A[a][b];
+                }
         }
         __syncthreads();
-    }
-    for (int r = k - 1; r >= 0; --r) {
-        if (wid == 0) {
-            double t = 0.0;
-            for (int j = r + 1 + lane; j < k; j += SSN_WAVE) t = fma(LU[r * k + j], cv[j], t);
-            t = wave_sum(t);
-            if (lane == 0) cv[r] = (cv[r] - t) / LU[r * k + r];
+        const double d = cb[c];
+        if (!(c < npos ? d > 0.0 : d < 0.0)) bad = true;
+        const double inv = d != 0.0 ? 1.0 / d : 0.0;
+        double li[LR_TT], vj[LR_TT];
+#pragma unroll
+        for (int a = 0; a < LR_TT; ++a) {
+            const int i = tr + LR_TG * a;
+            li[a] = i > c && i < k ? cb[i] * inv : 0.0;
         }
-        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < LR_TT; ++b) {
+            const int j = tc + LR_TG * b;
+            vj[b] = j > c && j < k ? cb[j] : 0.0;
+        }
+        if (tc == (c % LR_TG)) {
+#pragma unroll
+            for (int a = 0; a < LR_TT; ++a) {
+                const int i = tr + LR_TG * a;
+                if (i > c && i < k) Lsh[i][c] = li[a];
+            }
+            if (tr == 0) Lsh[c][c] = d;
+        }
+#pragma unroll
+        for (int a = 0; a < LR_TT; ++a)
+#pragma unroll
+            for (int b = 0; b < LR_TT; ++b) A[a][b] = fma(-li[a], vj[b], A[a][b]);
     }
-    for (int64_t j = threadIdx.x; j < q; j += blockDim.x) {
-        double t = d0[j];
-        for (int a = 0; a < k; ++a) t = fma(Zn[(int64_t)a * q + j], cv[a], t);
-        out[j] = t;
+    __syncthreads();
+    for (int e = tid; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e % k;
+        if (j <= i) Tm[e] = Lsh[i][j];
+    }
+    for (int r = tid; r < k; r += blockDim.x) perm[r] = pm[r];
+    if (bad && tid == 0) sc->chol_fail = 1;
+}
+
+// out = d0 + Zn c,  c = T^{-1} (U^T d0) with T = P^T L D L^T P from k_lr_ldl;
+// out may be d0.  One workgroup of 1024 threads, so that the k x q reads of U
+// and Zn have many loads in flight: U^T d0 with LR_CG columns per wave at a
+// time; L (strictly lower, zero elsewhere) staged in LDS; the two triangular
+// solves in wave 0 in column (axpy) form with the right-hand side in
+// registers (lane l holds entries l and l + 64) and each solved entry
+// broadcast by readlane, so no reduction and no barrier per row; then Zn c
+// with the columns split in two halves summed through LDS.
+constexpr int LR_APPLY_BLOCK = 1024;
+constexpr int LR_APPLY_WAVES = LR_APPLY_BLOCK / SSN_WAVE;
+constexpr int LR_CG = 6;
+__global__ __launch_bounds__(LR_APPLY_BLOCK) void k_lr_apply(const double* __restrict__ U,
+                                                             const double* __restrict__ Zn, int64_t q, int k,
+                                                             const double* __restrict__ LD,
+                                                             const int32_t* __restrict__ perm,
+                                                             const double* d0, double* out) {
+    __shared__ double Ls[LR_MAX][LR_MAX + 1];
+    __shared__ double wv[LR_MAX], cv[LR_MAX], dv[LR_MAX];
+    __shared__ int pm[LR_MAX];
+    __shared__ double part[LR_APPLY_BLOCK / 2];
+    const int tid = threadIdx.x, lane = tid & (SSN_WAVE - 1), wid = tid / SSN_WAVE;
+    for (int e = tid; e < LR_MAX * LR_MAX; e += blockDim.x) {
+        const int i = e / LR_MAX, j = e % LR_MAX;
+        Ls[i][j] = (i < k && j < i) ? LD[i * k + j] : 0.0;
+    }
+    for (int r = tid; r < k; r += blockDim.x) {
+        dv[r] = LD[r * k + r];
+        pm[r] = perm[r];
+    }
+    // w = U^T d0 in the original column order; wave w takes columns
+    // w, w + 16, ... in groups of LR_CG
+    for (int a0 = wid; a0 < k; a0 += LR_APPLY_WAVES * LR_CG) {
+        double t[LR_CG];
+#pragma unroll
+        for (int g = 0; g < LR_CG; ++g) t[g] = 0.0;
+        for (int64_t j = lane; j < q; j += SSN_WAVE) {
+            const double dj = d0[j];
+#pragma unroll
+            for (int g = 0; g < LR_CG; ++g) {
+                const int a = a0 + g * LR_APPLY_WAVES;
+                if (a < k) t[g] = fma(U[(int64_t)a * q + j], dj, t[g]);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < LR_CG; ++g) {
+            const int a = a0 + g * LR_APPLY_WAVES;
+            const double v = wave_sum(t[g]);
+            if (a < k && lane == 0) wv[a] = v;
+        }
+    }
+    __syncthreads();
+    if (wid == 0) {
+        const int l1 = lane + SSN_WAVE;
+        double y0 = lane < k ? wv[pm[lane]] : 0.0;
+        double y1 = l1 < k ? wv[pm[l1]] : 0.0;
+        for (int r = 0; r < k; ++r) {                // L y = P w
+            const double cr = r < SSN_WAVE ? readlane_f64(y0, r) : readlane_f64(y1, r - SSN_WAVE);
+            y0 = fma(-Ls[lane][r], cr, y0);
+            if (l1 < LR_MAX) y1 = fma(-Ls[l1][r], cr, y1);
+        }
+        if (lane < k) y0 /= dv[lane];                // D z = y
+        if (l1 < k) y1 /= dv[l1];
+        for (int r = k - 1; r >= 0; --r) {           // L^T (P c) = z
+            const double cr = r < SSN_WAVE ? readlane_f64(y0, r) : readlane_f64(y1, r - SSN_WAVE);
+            y0 = fma(-Ls[r][lane], cr, y0);
+            if (l1 < LR_MAX) y1 = fma(-Ls[r][l1], cr, y1);
+        }
+        if (lane < k) cv[pm[lane]] = y0;
+        if (l1 < k) cv[pm[l1]] = y1;
+    }
+    __syncthreads();
+    // out = d0 + Zn c: threads [0, 512) take columns [0, kh), the others [kh, k)
+    const int half = tid / (LR_APPLY_BLOCK / 2), ht = tid % (LR_APPLY_BLOCK / 2);
+    const int kh = (k + 1) / 2, a_lo = half ? kh : 0, a_hi = half ? k : kh;
+    for (int64_t j0 = 0; j0 < q; j0 += LR_APPLY_BLOCK / 2) {
+        const int64_t j = j0 + ht;
+        double t = 0.0;
+        if (j < q) {
+#pragma unroll 8
+            for (int a = a_lo; a < a_hi; ++a) t = fma(Zn[(int64_t)a * q + j], cv[a], t);
+        }
+        if (half) part[ht] = t;
+        __syncthreads();
+        if (!half && j < q) out[j] = d0[j] + t + part[ht];
+        __syncthreads();
     }
 }
 
 int lowrank_max() { return LR_MAX; }
 
 void launch_lr_factor(const double* U, const double* Zn, int64_t q, int k, const double* wgt, double* Tm,
-                      int32_t* piv, Scalars* sc, hipStream_t s) {
+                      int32_t* perm, Scalars* sc, hipStream_t s) {
     SSN_LAUNCH(k_lr_gram, dim3((unsigned)k, (unsigned)k), dim3(SSN_BLOCK), 0, s, U, Zn, q, k, wgt, Tm);
-    SSN_LAUNCH(k_lr_lu, dim3(1), dim3(SSN_BLOCK), 0, s, Tm, k, piv, sc);
+    SSN_LAUNCH(k_lr_ldl, dim3(1), dim3(SSN_BLOCK), 0, s, Tm, k, wgt, perm, sc);
 }
-void launch_lr_apply(const double* U, const double* Zn, int64_t q, int k, const double* LU, const int32_t* piv,
+void launch_lr_apply(const double* U, const double* Zn, int64_t q, int k, const double* LD, const int32_t* perm,
                      const double* d0, double* out, hipStream_t s) {
-    SSN_LAUNCH(k_lr_apply, dim3(1), dim3(SSN_BLOCK), 0, s, U, Zn, q, k, LU, piv, d0, out);
+    SSN_LAUNCH(k_lr_apply, dim3(1), dim3(LR_APPLY_BLOCK), 0, s, U, Zn, q, k, LD, perm, d0, out);
 }
 
 }  // namespace ssn

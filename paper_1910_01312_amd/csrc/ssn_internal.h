@@ -232,9 +232,10 @@ void launch_mask_diff(const uint8_t* a, const uint8_t* b, int64_t n, uint8_t* ou
 void launch_lr_build(int dtype, const void* X, int64_t q, const int32_t* chg, int nchg, const uint8_t* mask,
                      double sigma, const double* s0, int64_t p0, const double* s1, int64_t p1, double* U,
                      double* wgt, int k, hipStream_t s);
+// T = S^{-1} - U^T Zn, then T = P^T L D L^T P in place (perm: P's order)
 void launch_lr_factor(const double* U, const double* Zn, int64_t q, int k, const double* wgt, double* Tm,
-                      int32_t* piv, Scalars* sc, hipStream_t s);
-void launch_lr_apply(const double* U, const double* Zn, int64_t q, int k, const double* LU, const int32_t* piv,
+                      int32_t* perm, Scalars* sc, hipStream_t s);
+void launch_lr_apply(const double* U, const double* Zn, int64_t q, int k, const double* LD, const int32_t* perm,
                      const double* d0, double* out, hipStream_t s);
 // d = -M^{-1} g from the blocked factor for any q (multi-workgroup solves)
 void launch_chol_solve_blocked(const double* M, const double* inv, const double* g, double* d, int64_t q,
