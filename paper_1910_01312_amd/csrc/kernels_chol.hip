@@ -27,26 +27,31 @@ int chol_blocked_max() { return CHOL_BLOCKED_MAX; }
 int64_t chol_inv_size(int64_t q) { return (q + NB - 1) / NB * 2 * NB * NB; }
 
 // Factor diagonal block kb and form X = L_kk^{-1}, both right-looking in
-// registers: thread t keeps row i = t % 64, columns 16 (t / 64) .. +15 of the
-// block (a), and column j = t % 64, rows 16 (t / 64) .. +15 of B (initially
+// registers: thread t keeps row i = t % 64, columns 8 (t / 64) .. +7 of the
+// block (a), and column j = t % 64, rows 8 (t / 64) .. +7 of B (initially
 // I), so that each thread finds B[k][j] in its own column; B becomes X by
 // forward substitution of L X = I carried along with the factorisation.  A
 // non-positive pivot is replaced by 1 and reported in sc->chol_fail; rows
-// past q are padded with the identity.  Four columns per step, two barriers
-// per step (32 in all; one column per step with one barrier each took 41 us
-// per block against 29 us).  Step k0 = 4K:
+// past q are padded with the identity.  Eight waves, four columns per step,
+// two barriers per step.  Step k0 = 4K:
 //   1. the column group holding columns k0..k0+3 publishes them (raw values);
 //   2. every thread factors the 4 x 4 diagonal block D = A[k0..+3][k0..+3]
 //      itself (pivot reciprocal square roots from the hardware estimate and
 //      two Newton steps) and computes its own row's entries of L in the four
 //      columns, l_ic = (a_ic - sum_{m<c} l_im l_cm) / l_cc; wave 0 publishes
-//      them for all 64 rows, and the owner group finishes rows k0..k0+3 of
-//      X = L^{-1} by forward substitution with the 4 x 4 factor, published too;
-//   3. a_ij -= sum_c l_ic l_jc for the thread's columns j > k0 + 3, and
-//      B[r][i] -= sum_c l_rc X[k0+c][i] for its rows r > k0 + 3.
+//      them for the rows past the block (zero for the rows up to k0 + 3), and
+//      the owner group finishes rows k0..k0+3 of X = L^{-1} by forward
+//      substitution with the 4 x 4 factor, published too;
+//   3. a_ij -= sum_c l_ic l_jc for all the thread's columns j, and
+//      B[j][i] -= sum_c l_jc X[k0+c][i] for all its rows j: the zero rows of
+//      the published L leave the finished columns and rows as they are, so the
+//      update runs without a branch per column (with one, 12 to 20% slower).
 // The published buffers alternate between steps, so the next step's writes
 // never meet this step's reads.
-__global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M, int q, int kb,
+constexpr int DIAG_WAVES = 8;
+constexpr int DIAG_THREADS = DIAG_WAVES * SSN_WAVE;
+constexpr int DIAG_CPT = NB / DIAG_WAVES;     // columns of a (rows of B) per thread
+__global__ __launch_bounds__(DIAG_THREADS) void k_chol_diag(double* __restrict__ M, int q, int kb,
                                                           double* __restrict__ inv, Scalars* sc) {
     __shared__ double raw[2][4][NB];
     __shared__ double Lc[2][NB][4];      // row-major: the four entries of a row together
@@ -56,20 +61,20 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
     const int o = kb * NB;
     const int m = min(NB, q - o);
     const int i = tid & (NB - 1), cg = tid >> 6;
-    double a[16], b[16];                  // a: A[i][16 cg + jj];  b: B[16 cg + jj][i]
+    double a[DIAG_CPT], b[DIAG_CPT];      // a: A[i][8 cg + jj];  b: B[8 cg + jj][i]
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-        const int j = cg * 16 + jj;
+    for (int jj = 0; jj < DIAG_CPT; ++jj) {
+        const int j = cg * DIAG_CPT + jj;
         a[jj] = (i < m && j < m) ? M[(int64_t)(o + i) * q + o + j] : (i == j ? 1.0 : 0.0);
         b[jj] = i == j ? 1.0 : 0.0;
     }
     const int cgu = __builtin_amdgcn_readfirstlane(cg);
     bool bad = false;
 #pragma unroll 1
-    for (int kg = 0; kg < NB / 16; ++kg)
+    for (int kg = 0; kg < DIAG_WAVES; ++kg)
 #pragma unroll
-    for (int c0 = 0; c0 < 16; c0 += 4) {
-        const int k0 = kg * 16 + c0;
+    for (int c0 = 0; c0 < DIAG_CPT; c0 += 4) {
+        const int k0 = kg * DIAG_CPT + c0;
         const int par = (c0 >> 2) & 1;
         // 1. publish the four raw columns
         if (cgu == kg) {
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
         }
         if (cgu == 0) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Lc[par][i][c] = li[c];
+            for (int c = 0; c < 4; ++c) Lc[par][i][c] = i > k0 + 3 ? li[c] : 0.0;
         }
         if (cgu == kg) {
             // rows k0..k0+3 of X: forward substitution with the 4 x 4 factor in column i
@@ -141,14 +146,14 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
         }
         __syncthreads();
         // 3. rank-4 updates of the later columns and of the later rows of B
-        if (cgu * 16 + 15 > k0 + 3) {
+        if (cgu * DIAG_CPT + DIAG_CPT - 1 > k0 + 3) {
             double bx[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) bx[c] = Bf[par][c][i];
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const int j = cgu * 16 + jj;
-                if (j > k0 + 3) {
+            for (int jj = 0; jj < DIAG_CPT; ++jj) {
+                const int j = cgu * DIAG_CPT + jj;
+                {
                     double lj[4];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) lj[c] = Lc[par][j][c];
@@ -168,8 +173,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_diag(double* __restrict__ M,
     double* Xo = inv + (int64_t)kb * 2 * NB * NB;
     double* XTo = Xo + NB * NB;
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-        const int j = cg * 16 + jj;
+    for (int jj = 0; jj < DIAG_CPT; ++jj) {
+        const int j = cg * DIAG_CPT + jj;
         if (j <= i && i < m) {
             M[(int64_t)(o + i) * q + o + j] = a[jj];
             M[(int64_t)(o + j) * q + o + i] = a[jj];
@@ -505,7 +510,7 @@ void launch_chol_factor_blocked(double* M, int64_t q, double* inv, Scalars* sc, 
     for (int K = 0; K < nblk; K += kCholGroup) {
         const int Kend = std::min(nblk, K + kCholGroup);
         for (int kb = K; kb < Kend; ++kb) {
-            SSN_LAUNCH(k_chol_diag, dim3(1), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv, sc);
+            SSN_LAUNCH(k_chol_diag, dim3(1), dim3(DIAG_THREADS), 0, s, M, (int)q, kb, inv, sc);
             const int nt = nblk - kb - 1;
             if (nt > 0)
                 SSN_LAUNCH(k_chol_panel, dim3(nt), dim3(SSN_BLOCK), 0, s, M, (int)q, kb, inv);
