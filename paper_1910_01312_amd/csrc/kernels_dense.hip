@@ -264,9 +264,14 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_atmul_dense(const T* __restrict__
 }
 
 // The same sums for rows that fit one 16-byte piece per lane (q <= 64 VEC,
-// q VEC-aligned): each wave takes R rows at a time, issues the loads of all
-// of them that carry a nonzero coefficient (raw pieces, widened at the FMA)
-// before the first FMA, and skips the rest; then the block reduction as above.
+// q VEC-aligned).  A wave takes 64-row chunks: lane l loads row l's
+// coefficients (those of the next chunk are loaded while this one is
+// processed), a ballot marks the rows with a nonzero one, and the wave walks
+// the marked rows R at a time, issuing all R row loads (raw pieces, widened
+// at the FMA) before the first FMA, with each coefficient broadcast from its
+// lane by readlane.  Rows with zero coefficients are never read, and every
+// batch is R useful rows however sparse the coefficients are.  Then the block
+// reduction as above.
 template <typename T, int VEC, int R, int MM>
 __global__ __launch_bounds__(SSN_BLOCK) void k_atmul_rows(const T* __restrict__ X,
                                                           const int8_t* __restrict__ y,
@@ -282,43 +287,51 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_atmul_rows(const T* __restrict__ 
     const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
     const bool on = (int64_t)lane * VEC < q;
+    const int64_t cstep = (int64_t)SSN_WAVES_PER_BLOCK * SSN_WAVE;
     double acc[VEC], acc2[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) { acc[e] = 0.0; acc2[e] = 0.0; }
-    for (int64_t base = rb + (int64_t)w * R; base < re; base += (int64_t)SSN_WAVES_PER_BLOCK * R) {
-        // the R coefficients loaded by lanes 0..R-1 at once, then broadcast
-        double mz = 0.0, mm = 0.0;
-        {
-            const int64_t row = base + (lane & (R - 1));
-            if (lane < R && row < re) {
-                if (z) mz = (double)y[row] * z[row];
-                if (MM) mm = (double)mask[row];
+    auto coef = [&](int64_t row, double& mz, double& mm) {
+        mz = 0.0;
+        mm = 0.0;
+        if (row < re) {
+            if (z) mz = (double)y[row] * z[row];
+            if (MM) mm = (double)mask[row];
+        }
+    };
+    int64_t cb = rb + (int64_t)w * SSN_WAVE;
+    double mzn, mmn;
+    coef(cb + lane, mzn, mmn);
+    for (; cb < re; cb += cstep) {
+        const double mz = mzn, mm = mmn;
+        coef(cb + cstep + lane, mzn, mmn);          // the next chunk's, in flight meanwhile
+        unsigned long long bits = __ballot(mz != 0.0 || mm != 0.0);
+        while (bits) {                              // uniform across the wave
+            int rr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                rr[r] = bits ? __ffsll((unsigned long long)bits) - 1 : -1;
+                bits &= bits - 1;
             }
-        }
-        double cf[R], cm[R];
-        bool use[R];
+            RawPiece<T, VEC> pc[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cf[r] = __shfl(mz, r, SSN_WAVE);
-            cm[r] = MM ? __shfl(mm, r, SSN_WAVE) : 0.0;
-            use[r] = cf[r] != 0.0 || cm[r] != 0.0;          // uniform across the wave
-        }
-        RawPiece<T, VEC> pc[R];
+            for (int r = 0; r < R; ++r) {
+                pc[r].u = make_uint4(0u, 0u, 0u, 0u);
+                if (rr[r] >= 0 && on)
+                    pc[r].u = *reinterpret_cast<const uint4*>(X + (cb + rr[r]) * q + (int64_t)lane * VEC);
+            }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            pc[r].u = make_uint4(0u, 0u, 0u, 0u);
-            if (use[r] && on)
-                pc[r].u = *reinterpret_cast<const uint4*>(X + (base + r) * q + (int64_t)lane * VEC);
-        }
+            for (int r = 0; r < R; ++r) {
+                if (rr[r] < 0) break;
+                const double cf = readlane_f64(mz, rr[r]);
+                const double cm = MM ? readlane_f64(mm, rr[r]) : 0.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (!use[r]) continue;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const double xv = pc[r].get(e);
-                acc[e] = fma(cf[r], xv, acc[e]);
-                if (MM == 1) acc2[e] = fma(cm[r], xv, acc2[e]);
-                if (MM == 2) acc2[e] = fma(cm[r] * xv, xv, acc2[e]);
+                for (int e = 0; e < VEC; ++e) {
+                    const double xv = pc[r].get(e);
+                    acc[e] = fma(cf, xv, acc[e]);
+                    if (MM == 1) acc2[e] = fma(cm, xv, acc2[e]);
+                    if (MM == 2) acc2[e] = fma(cm * xv, xv, acc2[e]);
+                }
             }
         }
     }

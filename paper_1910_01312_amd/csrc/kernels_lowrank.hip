@@ -87,12 +87,6 @@ constexpr int LR_TG = 16;                   // thread grid 16 x 16 over T
 constexpr int LR_TT = LR_MAX / LR_TG;       // each thread holds a 6 x 6 register tile
 static_assert(LR_TG * LR_TG == SSN_BLOCK, "one thread per tile");
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
 // T = L D L^T in the order perm (columns with wgt > 0 first, each group in
 // its original order); perm[r] = the column of T at position r.  Output in Tm
 // (k x k, row-major, positions after perm): L[i][c] below the diagonal, D on
