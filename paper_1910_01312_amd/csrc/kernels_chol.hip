@@ -273,26 +273,31 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restri
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-    for (int kb = k0; kb < k1; ++kb) {
+    // the tiles of block column kb into registers; the next block column's
+    // loads are issued before this one's products, so that they are in
+    // flight while the matrix cores work
+    double vi[TILE_PER_THREAD], vj[TILE_PER_THREAD];
+    auto load_tiles = [&](int kb) {
         const int o = kb * NB;
         const int m = min(NB, q - o);
-        {
-            double vi[TILE_PER_THREAD], vj[TILE_PER_THREAD];
 #pragma unroll
-            for (int h = 0; h < TILE_PER_THREAD; ++h) {
-                const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
-                vi[h] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
-                vj[h] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
-            }
-            if (kb > k0) __syncthreads();        // the previous k-block's reads are done
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+            vi[h] = (io + i < q && k < m) ? M[(int64_t)(io + i) * q + o + k] : 0.0;
+            vj[h] = (jo + i < q && k < m) ? M[(int64_t)(jo + i) * q + o + k] : 0.0;
+        }
+    };
+    load_tiles(k0);
+    for (int kb = k0; kb < k1; ++kb) {
+        if (kb > k0) __syncthreads();            // the previous k-block's reads are done
 #pragma unroll
-            for (int h = 0; h < TILE_PER_THREAD; ++h) {
-                const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
-                Li[i][k] = vi[h];
-                Lj[i][k] = vj[h];
-            }
+        for (int h = 0; h < TILE_PER_THREAD; ++h) {
+            const int e = threadIdx.x + h * SSN_BLOCK, i = e / NB, k = e % NB;
+            Li[i][k] = vi[h];
+            Lj[i][k] = vj[h];
         }
         __syncthreads();
+        if (kb + 1 < k1) load_tiles(kb + 1);
 #pragma unroll 4
         for (int kk = 0; kk < NB; kk += 4) {
             const double a0 = Li[wr + r16][kk + k4], a1 = Li[wr + 16 + r16][kk + k4];
