@@ -416,35 +416,37 @@ void launch_atmul_dense(int dtype, const void* X, const int8_t* y, const double*
     }
 }
 
-// out[j] = base[j] + sign * sum_b part[b*q + j].  A block owns 64 columns
-// (one per lane); wave w sums the partial rows b = w, w+4, ... and the four
-// wave sums are added in wave order: a fixed order, so the result is
-// deterministic.
-__global__ __launch_bounds__(SSN_BLOCK) void k_reduce_cols(const double* __restrict__ part,
-                                                           int nblk, int64_t q,
-                                                           const double* __restrict__ base,
-                                                           double sign, double* __restrict__ out) {
-    __shared__ double sh[SSN_WAVES_PER_BLOCK][SSN_WAVE];
+// out[j] = base[j] + sign * sum_b part[b*q + j].  A block of 16 waves owns 64
+// columns (one per lane); wave w sums the partial rows b = w, w+16, ... with
+// eight loads in flight, and the 16 wave sums are added in wave order: a fixed
+// order, so the result is deterministic.
+constexpr int RC_WAVES = 16;
+constexpr int RC_UNROLL = 8;
+__global__ __launch_bounds__(RC_WAVES * SSN_WAVE) void k_reduce_cols(const double* __restrict__ part,
+                                                                    int nblk, int64_t q,
+                                                                    const double* __restrict__ base,
+                                                                    double sign, double* __restrict__ out) {
+    __shared__ double sh[RC_WAVES][SSN_WAVE];
     const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
     const int64_t j = (int64_t)blockIdx.x * SSN_WAVE + lane;
     double s = 0.0;
     if (j < q) {
         int b = w;
-        for (; b + 3 * SSN_WAVES_PER_BLOCK < nblk; b += 4 * SSN_WAVES_PER_BLOCK) {
-            const double a0 = part[(int64_t)b * q + j];
-            const double a1 = part[(int64_t)(b + SSN_WAVES_PER_BLOCK) * q + j];
-            const double a2 = part[(int64_t)(b + 2 * SSN_WAVES_PER_BLOCK) * q + j];
-            const double a3 = part[(int64_t)(b + 3 * SSN_WAVES_PER_BLOCK) * q + j];
-            s += a0; s += a1; s += a2; s += a3;
+        for (; b + (RC_UNROLL - 1) * RC_WAVES < nblk; b += RC_UNROLL * RC_WAVES) {
+            double a[RC_UNROLL];
+#pragma unroll
+            for (int u = 0; u < RC_UNROLL; ++u) a[u] = part[(int64_t)(b + u * RC_WAVES) * q + j];
+#pragma unroll
+            for (int u = 0; u < RC_UNROLL; ++u) s += a[u];
         }
-        for (; b < nblk; b += SSN_WAVES_PER_BLOCK) s += part[(int64_t)b * q + j];
+        for (; b < nblk; b += RC_WAVES) s += part[(int64_t)b * q + j];
     }
     sh[w][lane] = s;
     __syncthreads();
     if (w == 0 && j < q) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < SSN_WAVES_PER_BLOCK; ++k) t += sh[k][lane];
+        for (int k = 0; k < RC_WAVES; ++k) t += sh[k][lane];
         out[j] = (base ? base[j] : 0.0) + sign * t;
     }
 }
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_reduce_cols(const double* __restr
 void launch_reduce_cols(const double* part, int nblk, int64_t q, const double* base, double sign,
                         double* out, hipStream_t s) {
     const unsigned blocks = (unsigned)((q + SSN_WAVE - 1) / SSN_WAVE);
-    SSN_LAUNCH(k_reduce_cols, dim3(blocks), dim3(SSN_BLOCK), 0, s, part, nblk, q, base,
+    SSN_LAUNCH(k_reduce_cols, dim3(blocks), dim3(RC_WAVES * SSN_WAVE), 0, s, part, nblk, q, base,
                        sign, out);
 }
 
