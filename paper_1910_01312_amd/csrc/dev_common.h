@@ -11,12 +11,6 @@
 
 typedef uint16_t bf16_t;
 
-// lane l's v, for a wave-uniform l (v_readlane into scalar registers)
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = SSN_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SSN_WAVE);

@@ -9,6 +9,7 @@
 // reduces per row.  Rows whose coefficient is zero are skipped in the
 // transpose, so it reads only the support-vector rows.
 #include "dev_common.h"
+#include "lane_ops.h"
 #include "ssn_internal.h"
 
 namespace ssn {

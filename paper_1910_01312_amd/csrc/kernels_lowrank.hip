@@ -16,6 +16,7 @@
 // D < 0 on the second.  A pivot of the wrong sign (rounding) is reported as a
 // factorisation failure and the step falls back to -g.
 #include "dev_common.h"
+#include "lane_ops.h"
 #include "ssn_internal.h"
 
 namespace ssn {
