@@ -79,10 +79,13 @@ def _state(n, q, seed, sigma, C_, alpha, free_frac_high=False):
 
 
 @pytest.mark.parametrize("n,sigma,high", [(200, 2.0, False), (900, 0.01, True), (2600, 0.3, False),
-                                           (2600, 0.001, True)])
+                                           (2600, 0.001, True), (3600, 0.001, True)])
 def test_newton_step_cholesky(n, sigma, high):
     """p = 35 (one workgroup), 891 and 1359 (blocked factor, ragged last
-    block, one-workgroup solves) and 2201 (multi-workgroup solves)."""
+    block, one-workgroup solves), 2201 (multi-workgroup solves) and 3169
+    (the trailing updates right of the first two groups of eight block
+    columns, 2657 and 2145 rows, in 128 x 128 tiles; the later ones in
+    64 x 64 tiles)."""
     C_, alpha = 1.0, 1.0
     X, y, Q, w, xt, free = _state(n, 20, 40 + n, sigma, C_, alpha, high)
     s = w - xt
