@@ -819,7 +819,7 @@ static ssnalm_status kernel_newton(ssnalm_ctx* c, const uint8_t* mask, int64_t p
             if (p <= chol_blocked_max())
                 launch_chol_solve_factored(c->M, c->linv, c->krhs, c->kv, p, c->st);
             else
-                launch_chol_solve_blocked(c->M, c->linv, c->krhs, c->kv, p, c->st);
+                launch_chol_solve_blocked(c->M, c->linv, c->krhs, c->kv, p, c->kt1, c->st);
         }
         prof_end(c, SSNALM_K_CHOL, 8.0 * (double)p * p, (double)p * p * p / 3.0 + 2.0 * (double)p * p);
         vneg = c->kv;

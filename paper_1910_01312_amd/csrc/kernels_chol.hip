@@ -508,54 +508,78 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_chol_solve2(const double* __r
     for (int i = tid; i < q; i += blockDim.x) d[i] = z[i];
 }
 
-// d = -M^{-1} g from the same factor for any size, spread over the chip:
-// after each diagonal block of the triangular solves the not-yet-solved part
-// is updated by a parallel product with the block's 64 columns of L (forward)
-// or 64 rows of L (backward), so no workgroup walks the whole factor.
-//   forward  L w = -g:  w_B = X_B z_B;   z_i -= sum_k L[i][o + k] w_{o+k}  (i > B)
-//   backward L^T d = w: d_B = X_B^T z_B; z_j -= sum_r L[o + r][j] d_{o+r} (j < B)
-// z lives in d.  Each update reads its rows / columns of the lower triangle
-// once: p^2 doubles per solve in total.
-__global__ void k_trsv_diag(const double* __restrict__ inv, int kb, int m, int transposed,
-                            double* __restrict__ z, int o) {
-    __shared__ double zb[NB];
-    const int r = threadIdx.x;
-    zb[r] = r < m ? z[o + r] : 0.0;
+// d = -M^{-1} g from the same factor for any size, spread over the chip, one
+// launch per diagonal block and direction: every workgroup solves the
+// block's 64 x 64 system itself from the inverse of its diagonal factor (16
+// products per thread, summed through LDS; workgroup 0 stores the result),
+// then updates its part of the not-yet-solved vector with the block's 64
+// columns of L (forward, read from the mirror in the upper triangle) or 64 rows
+// of L (backward, read from the lower triangle), one thread per entry and the
+// 64 loads of a thread in flight sixteen at a time, coalesced across threads:
+//   forward  L w = -g:  w_B = X_B z_B;    z_i -= sum_k L[i][o + k] w_{o+k}  (i past B)
+//   backward L^T d = w: d_B = X_B^T w_B;  w_j -= sum_r L[o + r][j] d_{o+r} (j before B)
+// z lives in d during the forward pass; w is a separate q-vector, so that a
+// block's entries are never written while other workgroups read them.
+// Each pass reads the triangle of L once: p^2 doubles per solve in total.
+__device__ __forceinline__ void trsv_block_solve(const double* __restrict__ Xm, const double* __restrict__ src,
+                                                 int o, int m, double* zb, double (*part)[NB], double* out) {
+    // out[r] = sum_k Xm[k * NB + r] src[o + k], r < m (zero past m)
+    const int tid = threadIdx.x, r = tid & (NB - 1), h = tid / NB;
+    if (tid < NB) zb[tid] = tid < m ? src[o + tid] : 0.0;
     __syncthreads();
-    const double* X = inv + (int64_t)kb * 2 * NB * NB + (transposed ? NB * NB : 0);
     double t = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < NB; ++k) t = fma(X[r * NB + k], zb[k], t);
-    if (r < m) z[o + r] = t;
-}
-
-// rows i in [o + m, q): z_i -= L[i][o .. o+m) . z[o .. o+m), one wave per row
-__global__ __launch_bounds__(SSN_BLOCK) void k_trsv_fupd(const double* __restrict__ M, int q, int o, int m,
-                                                         double* __restrict__ z) {
-    const int lane = threadIdx.x & (SSN_WAVE - 1);
-    const int64_t i = (int64_t)o + m + (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
-    if (i >= q) return;
-    const double t = lane < m ? M[i * q + o + lane] * z[o + lane] : 0.0;
-    const double sum = wave_sum(t);
-    if (lane == 0) z[i] -= sum;
-}
-
-// columns j in [0, o): z_j -= sum_r L[o + r][j] z[o + r], one thread per column
-__global__ __launch_bounds__(SSN_BLOCK) void k_trsv_bupd(const double* __restrict__ M, int q, int o, int m,
-                                                         double* __restrict__ z) {
-    __shared__ double zb[NB];
-    if (threadIdx.x < NB) zb[threadIdx.x] = threadIdx.x < m ? z[o + threadIdx.x] : 0.0;
+#pragma unroll
+    for (int kk = 0; kk < NB / 4; ++kk) {
+        const int k = (NB / 4) * h + kk;
+        t = fma(Xm[k * NB + r], zb[k], t);
+    }
+    part[h][r] = t;
     __syncthreads();
+    if (tid < NB) out[tid] = tid < m ? (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]) : 0.0;
+    __syncthreads();
+}
+
+// sum over k < m of col[k q] v[k]: 16 loads in flight per round
+__device__ __forceinline__ double trsv_dot(const double* __restrict__ col, int q, int m, const double* v) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 15 < m; k += 16) {
+        double x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = col[(int64_t)(k + u) * q];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u & 3] = fma(x[u], v[k + u], a[u & 3]);
+    }
+    for (; k < m; ++k) a[0] = fma(col[(int64_t)k * q], v[k], a[0]);
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+__global__ __launch_bounds__(SSN_BLOCK) void k_trsv_fwd(const double* __restrict__ M,
+                                                        const double* __restrict__ inv, int q, int kb,
+                                                        double* __restrict__ z, double* __restrict__ w) {
+    __shared__ double zb[NB], wb[NB];
+    __shared__ double part[4][NB];
+    const int o = kb * NB, m = min(NB, q - o);
+    // X^T of the block, row-major: element (k, r) is X[r][k]
+    trsv_block_solve(inv + (int64_t)kb * 2 * NB * NB + NB * NB, z, o, m, zb, part, wb);
+    if (blockIdx.x == 0 && threadIdx.x < m) w[o + threadIdx.x] = wb[threadIdx.x];
+    const int64_t i = (int64_t)o + m + (int64_t)blockIdx.x * SSN_BLOCK + threadIdx.x;
+    if (i >= q) return;
+    z[i] -= trsv_dot(M + (int64_t)o * q + i, q, m, wb);   // M[o + k][i] = L[i][o + k]
+}
+
+__global__ __launch_bounds__(SSN_BLOCK) void k_trsv_bwd(const double* __restrict__ M,
+                                                        const double* __restrict__ inv, int q, int kb,
+                                                        double* __restrict__ w, double* __restrict__ d) {
+    __shared__ double zb[NB], db[NB];
+    __shared__ double part[4][NB];
+    const int o = kb * NB, m = min(NB, q - o);
+    // X of the block, row-major: element (k, r) is X[k][r], so the sum is X^T w_B
+    trsv_block_solve(inv + (int64_t)kb * 2 * NB * NB, w, o, m, zb, part, db);
+    if (blockIdx.x == 0 && threadIdx.x < m) d[o + threadIdx.x] = db[threadIdx.x];
     const int64_t j = (int64_t)blockIdx.x * SSN_BLOCK + threadIdx.x;
     if (j >= o) return;
-    double t0 = 0.0, t1 = 0.0;
-    int r = 0;
-    for (; r + 1 < m; r += 2) {
-        t0 = fma(M[(int64_t)(o + r) * q + j], zb[r], t0);
-        t1 = fma(M[(int64_t)(o + r + 1) * q + j], zb[r + 1], t1);
-    }
-    if (r < m) t0 = fma(M[(int64_t)(o + r) * q + j], zb[r], t0);
-    z[j] -= t0 + t1;
+    w[j] -= trsv_dot(M + (int64_t)o * q + j, q, m, db);   // M[o + r][j] = L[o + r][j]
 }
 
 __global__ void k_neg_copy(const double* __restrict__ g, double* __restrict__ d, int q) {
@@ -564,23 +588,19 @@ __global__ void k_neg_copy(const double* __restrict__ g, double* __restrict__ d,
 }
 
 void launch_chol_solve_blocked(const double* M, const double* inv, const double* g, double* d, int64_t q,
-                               hipStream_t s) {
+                               double* w, hipStream_t s) {
     const int nblk = (int)((q + NB - 1) / NB);
     SSN_LAUNCH(k_neg_copy, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, g, d, (int)q);
     for (int kb = 0; kb < nblk; ++kb) {
-        const int o = kb * NB, m = (int)std::min<int64_t>(NB, q - o);
-        SSN_LAUNCH(k_trsv_diag, dim3(1), dim3(NB), 0, s, inv, kb, m, 0, d, o);
+        const int64_t o = (int64_t)kb * NB, m = std::min<int64_t>(NB, q - o);
         const int64_t rows = q - o - m;
-        if (rows > 0)
-            SSN_LAUNCH(k_trsv_fupd, dim3((unsigned)((rows + SSN_WAVES_PER_BLOCK - 1) / SSN_WAVES_PER_BLOCK)),
-                       dim3(SSN_BLOCK), 0, s, M, (int)q, o, m, d);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, (rows + SSN_BLOCK - 1) / SSN_BLOCK);
+        SSN_LAUNCH(k_trsv_fwd, dim3(grid), dim3(SSN_BLOCK), 0, s, M, inv, (int)q, kb, d, w);
     }
     for (int kb = nblk - 1; kb >= 0; --kb) {
-        const int o = kb * NB, m = (int)std::min<int64_t>(NB, q - o);
-        SSN_LAUNCH(k_trsv_diag, dim3(1), dim3(NB), 0, s, inv, kb, m, 1, d, o);
-        if (o > 0)
-            SSN_LAUNCH(k_trsv_bupd, dim3((unsigned)((o + SSN_BLOCK - 1) / SSN_BLOCK)), dim3(SSN_BLOCK), 0, s,
-                       M, (int)q, o, m, d);
+        const int64_t o = (int64_t)kb * NB;
+        const unsigned grid = (unsigned)std::max<int64_t>(1, (o + SSN_BLOCK - 1) / SSN_BLOCK);
+        SSN_LAUNCH(k_trsv_bwd, dim3(grid), dim3(SSN_BLOCK), 0, s, M, inv, (int)q, kb, w, d);
     }
 }
 

@@ -237,9 +237,10 @@ void launch_lr_factor(const double* U, const double* Zn, int64_t q, int k, const
                       int32_t* perm, Scalars* sc, hipStream_t s);
 void launch_lr_apply(const double* U, const double* Zn, int64_t q, int k, const double* LD, const int32_t* perm,
                      const double* d0, double* out, hipStream_t s);
-// d = -M^{-1} g from the blocked factor for any q (multi-workgroup solves)
+// d = -M^{-1} g from the blocked factor for any q (multi-workgroup solves;
+// w: q doubles of scratch for the forward solution)
 void launch_chol_solve_blocked(const double* M, const double* inv, const double* g, double* d, int64_t q,
-                               hipStream_t s);
+                               double* w, hipStream_t s);
 void launch_chol_solve_factored(const double* M, const double* inv, const double* g, double* d,
                                 int64_t q, hipStream_t s);
 
