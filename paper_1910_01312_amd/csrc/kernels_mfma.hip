@@ -375,6 +375,60 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_dense_rows(const T* __restrict__ 
     if (threadIdx.x == 0) Pw[blockIdx.x] = bs;
 }
 
+// The same for rows that fit one 16-byte piece per lane (q <= 64 VEC, q a
+// multiple of VEC): v stays in registers (each lane's VEC entries, loaded once),
+// and a wave takes its rows R at a time, the R row indices loaded by lanes
+// 0..R-1 at once and the R row pieces in flight together.  Rows go to waves,
+// and the per-lane products and wave sums run, in the same order as above, so
+// w and Pw are bit-identical to it.
+template <typename T, int VEC, int R>
+__global__ __launch_bounds__(SSN_BLOCK) void k_dense_rows_r(const T* __restrict__ X, int64_t q,
+                                                            const int32_t* __restrict__ list,
+                                                            int64_t p, const double* __restrict__ v,
+                                                            double* __restrict__ w,
+                                                            double* __restrict__ Pw) {
+    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+    const int lane = threadIdx.x & (SSN_WAVE - 1);
+    const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
+    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    const int64_t c0 = (int64_t)lane * VEC;
+    const bool on = c0 < q;
+    double vl[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) vl[e] = on ? v[c0 + e] : 0.0;
+    double loc = 0.0;
+    for (int64_t k0 = wave; k0 < p; k0 += (int64_t)R * nwave) {
+        int li = 0;
+        {
+            const int64_t kr = k0 + (int64_t)(lane & (R - 1)) * nwave;
+            if (lane < R && kr < p) li = list[kr];
+        }
+        RawPiece<T, VEC> pc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t kr = k0 + (int64_t)r * nwave;
+            const int row = __builtin_amdgcn_readlane(li, r);
+            pc[r].u = make_uint4(0u, 0u, 0u, 0u);
+            if (kr < p && on) pc[r].u = *reinterpret_cast<const uint4*>(X + (int64_t)row * q + c0);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t kr = k0 + (int64_t)r * nwave;
+            if (kr >= p) break;                       // uniform across the wave
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc = fma(pc[r].get(e), vl[e], acc);
+            acc = wave_sum(acc);
+            if (lane == 0) {
+                w[kr] = acc;
+                loc += acc;
+            }
+        }
+    }
+    const double bs = block_sum(loc, sh);
+    if (threadIdx.x == 0) Pw[blockIdx.x] = bs;
+}
+
 unsigned dense_rows_grid(int64_t p) {
     int64_t b = (p + 3) / 4;
     if (b > 1024) b = 1024;
@@ -387,17 +441,23 @@ void launch_dense_rows(int dtype, const void* X, int64_t q, const int32_t* list,
     const unsigned g = dense_rows_grid(p);
     const uintptr_t a = (uintptr_t)X;
     if (dtype == SSNALM_F64) {
-        if ((q * 8) % 16 == 0 && a % 16 == 0)
+        if ((q * 8) % 16 == 0 && a % 16 == 0 && q <= (int64_t)SSN_WAVE * 2)
+            SSN_LAUNCH((k_dense_rows_r<double, 2, 8>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
+        else if ((q * 8) % 16 == 0 && a % 16 == 0)
             SSN_LAUNCH((k_dense_rows<double, 2>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
         else
             SSN_LAUNCH((k_dense_rows<double, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const double*)X, q, list, p, v, w, Pw);
     } else if (dtype == SSNALM_F32) {
-        if ((q * 4) % 16 == 0 && a % 16 == 0)
+        if ((q * 4) % 16 == 0 && a % 16 == 0 && q <= (int64_t)SSN_WAVE * 4)
+            SSN_LAUNCH((k_dense_rows_r<float, 4, 8>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
+        else if ((q * 4) % 16 == 0 && a % 16 == 0)
             SSN_LAUNCH((k_dense_rows<float, 4>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
         else
             SSN_LAUNCH((k_dense_rows<float, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const float*)X, q, list, p, v, w, Pw);
     } else {
-        if ((q * 2) % 16 == 0 && a % 16 == 0)
+        if ((q * 2) % 16 == 0 && a % 16 == 0 && q <= (int64_t)SSN_WAVE * 8)
+            SSN_LAUNCH((k_dense_rows_r<bf16_t, 8, 8>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
+        else if ((q * 2) % 16 == 0 && a % 16 == 0)
             SSN_LAUNCH((k_dense_rows<bf16_t, 8>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);
         else
             SSN_LAUNCH((k_dense_rows<bf16_t, 1>), dim3(g), dim3(SSN_BLOCK), 0, s, (const bf16_t*)X, q, list, p, v, w, Pw);

@@ -522,20 +522,40 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_ls_finalize(
     double dh = 0.0, d2 = 0.0;
     long long p = 0, nsv = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double yi = (double)y[i];
-        const double t = v[i] - lam * yi;
-        const double xi = clampd(t, 0.0, C);
-        const bool fr = (t > 0.0) && (t < C);
-        x[i] = xi;
-        mask[i] = fr ? 1 : 0;
-        p += fr ? 1 : 0;
-        nsv += xi > 0.0 ? 1 : 0;
-        const double dx = xi - xk[i];
-        d2 = fma(dx, dx, d2);
-        const double tb = u_base[i] - lamb * yi;
-        const double dt = td ? fma(-as, td[i], -dl * yi) : -dl * yi;
-        dh += huber_inc(tb, dt, C);
+    // LSU elements per thread per step, every load of the step issued first
+    // (an index past n reads element n - 1, unused); the elements are taken
+    // in the order of a plain strided loop
+    constexpr int LSU = 4;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; base < n; base += LSU * stride) {
+        double vv[LSU], yv[LSU], xkv[LSU], ubv[LSU], tdv[LSU];
+#pragma unroll
+        for (int u = 0; u < LSU; ++u) {
+            const int64_t i = base + u * stride;
+            const int64_t ic = i < n ? i : n - 1;
+            vv[u] = v[ic];
+            yv[u] = (double)y[ic];
+            xkv[u] = xk[ic];
+            ubv[u] = u_base[ic];
+            tdv[u] = td ? td[ic] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < LSU; ++u) {
+            const int64_t i = base + u * stride;
+            if (i >= n) break;
+            const double yi = yv[u];
+            const double t = vv[u] - lam * yi;
+            const double xi = clampd(t, 0.0, C);
+            const bool fr = (t > 0.0) && (t < C);
+            x[i] = xi;
+            mask[i] = fr ? 1 : 0;
+            p += fr ? 1 : 0;
+            nsv += xi > 0.0 ? 1 : 0;
+            const double dx = xi - xkv[u];
+            d2 = fma(dx, dx, d2);
+            const double tb = ubv[u] - lamb * yi;
+            const double dt = td ? fma(-as, tdv[u], -dl * yi) : -dl * yi;
+            dh += huber_inc(tb, dt, C);
+        }
     }
     const double bdh = block_sum(dh, shd);
     const double bd2 = block_sum(d2, shd);
