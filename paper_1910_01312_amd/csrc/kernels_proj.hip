@@ -29,7 +29,7 @@ constexpr int PNV = PK + 1;       // partial values per block: PK+1 g-values
 static_assert(PK == SSN_WAVE, "the pass decision takes one candidate per lane");
 constexpr int PROJ_MAXPASS = 48;
 constexpr int PROJ_GRID_MAX = 256;
-constexpr int PASS_CAP = 2048;    // LDS list of elements evaluated at every candidate
+constexpr int PASS_CAP = 4096;    // LDS list of elements evaluated at every candidate
 
 int proj_max_passes() { return PROJ_MAXPASS; }
 
@@ -163,7 +163,7 @@ __device__ __forceinline__ double cand_geometric(double lo, double hi, double hi
     return fmin(fmax(v, lo), hi);
 }
 
-constexpr int PU = 4;                     // elements per thread per sweep step
+constexpr int PU = 8;                     // elements per thread per sweep step
 constexpr int PCOL = PNV + 1;             // double columns per block: g partials, lin_s
 constexpr int PICOL = PK + 2;             // int columns: histogram, constant count, lin count
 
