@@ -74,13 +74,19 @@ def measured_traffic(workload, cls):
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024.0 / m["calls"]
 
 
-# the kernels of each class that a traffic probe sums, and their sources
+# the kernels of each class that a traffic probe sums, and their sources, for
+# CSR and for dense X
 TRAFFIC_KERNELS = {
     "atmul": (["k_mul_y", "k_segsum<float, 0>", "k_segsum_fix", "k_reduce_cols"],
               ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/kernels_vec.hip",
                "paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
     "amul": (["k_segsum<float, 0>", "k_segsum_fix"],
              ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
+    "atmul-dense": (["k_atmul_rows", "k_reduce_cols"],
+                    ["paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/lane_ops.h",
+                     "paper_1910_01312_amd/csrc/dev_common.h"]),
+    "amul-dense": (["k_amul_rows"],
+                   ["paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
 }
 
 
@@ -562,7 +568,8 @@ def main():
                 s.amul(v)
         torch.cuda.synchronize()
         print(json.dumps({"traffic_op": args.traffic_op, "calls": args.reps + 1,
-                          "kernels": TRAFFIC_KERNELS[args.traffic_op][0]}), flush=True)
+                          "kernels": TRAFFIC_KERNELS[args.traffic_op + ("-dense" if wl.get("X") is not None
+                                                                        else "")][0]}), flush=True)
         s.close()
         calib(args)
         return
