@@ -185,9 +185,13 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_chol_diag(double* __restrict__
     }
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
 // Panel below block kb: L_ib,kb = A_ib,kb X^T, X = L_kb,kb^{-1}, for the
-// 64-row block ib = kb + 1 + blockIdx.x; 4 x 4 outputs per thread, written to
-// the lower part and its upper mirror.
+// 64-row block ib = kb + 1 + blockIdx.x, on the matrix cores
+// (v_mfma_f64_16x16x4f64, each wave a 32 x 32 quarter as 2 x 2 tiles, the
+// lane layout of the trailing update below: operand B[k][j] = X[j][k] read
+// from the rows of X), written to the lower part and its upper mirror.
 __global__ __launch_bounds__(SSN_BLOCK) void k_chol_panel(double* __restrict__ M, int q, int kb,
                                                           const double* __restrict__ inv) {
     __shared__ double Ap[NB][NB + 1];
@@ -214,36 +218,35 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_panel(double* __restrict__ M
         }
     }
     __syncthreads();
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4];
+    const int lane = threadIdx.x & (SSN_WAVE - 1), w = threadIdx.x / SSN_WAVE;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    f64x4_t acc[2][2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    for (int mm = 0; mm < NB; ++mm) {
-        double x[4], w[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            x[u] = Ap[ty + 16 * u][mm];
-            w[u] = Xs[tx + 16 * u][mm];                 // X[j][mm], zero for mm > j
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], w[v], acc[u][v]);
+        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int kk = 0; kk < NB; kk += 4) {
+        const double a0 = Ap[wr + r16][kk + k4], a1 = Ap[wr + 16 + r16][kk + k4];
+        const double b0 = Xs[wc + r16][kk + k4], b1 = Xs[wc + 16 + r16][kk + k4];   // X[j][k], zero for k > j
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int r = ty + 16 * u;
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int j = tx + 16 * v;
-            if (r < rm && j < m) {
-                M[(int64_t)(ro + r) * q + o + j] = acc[u][v];
-                M[(int64_t)(o + j) * q + ro + r] = acc[u][v];
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = wr + 16 * u + 4 * e + k4, j = wc + 16 * v + r16;
+                if (r < rm && j < m) {
+                    M[(int64_t)(ro + r) * q + o + j] = acc[u][v][e];
+                    M[(int64_t)(o + j) * q + ro + r] = acc[u][v][e];
+                }
             }
-        }
-    }
 }
 
 // Trailing updates on the matrix cores (v_mfma_f64_16x16x4f64):
@@ -257,7 +260,6 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_panel(double* __restrict__ M
 // l / 16 of the 16 x 4 operand from Li (rows of block ib) and likewise of the
 // 4 x 16 operand from Lj (rows of block jb, i.e. L_jb^T), and holds rows
 // 4 v + l / 16 (v = 0..3), column l % 16 of the 16 x 16 result.
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restrict__ M, int q, int k0,
                                                                 int k1, int j0) {
     __shared__ double Li[NB][NB + 1];
