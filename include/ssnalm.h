@@ -136,8 +136,9 @@ typedef struct {
     int32_t ls_fail;            /* line searches that exhausted their backtracks          */
     int32_t ls_trials;          /* line-search trials (projections of u - alpha sigma t)  */
     int32_t grad_steps;         /* Newton directions replaced by -grad psi because they   */
-                                /* were not descent directions (g^T d >= 0, or a          */
-                                /* non-positive Cholesky pivot)                           */
+                                /* were not descent directions (g^T d >= 0, a non-        */
+                                /* positive Cholesky pivot, or in a low-rank step a pivot */
+                                /* of the capacitance matrix with the wrong sign)         */
     int32_t proj_capped;        /* projections that hit the multisection pass cap (their  */
                                 /* multiplier is the interpolation of the last bracket)   */
     int32_t status;             /* same as the return value                               */
