@@ -517,7 +517,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_chol_solve2(const double* __r
 // then updates its part of the not-yet-solved vector with the block's 64
 // columns of L (forward, read from the mirror in the upper triangle) or 64 rows
 // of L (backward, read from the lower triangle), one thread per entry and the
-// 64 loads of a thread in flight sixteen at a time, coalesced across threads:
+// 64 loads of a thread in flight together, coalesced across threads:
 //   forward  L w = -g:  w_B = X_B z_B;    z_i -= sum_k L[i][o + k] w_{o+k}  (i past B)
 //   backward L^T d = w: d_B = X_B^T w_B;  w_j -= sum_r L[o + r][j] d_{o+r} (j before B)
 // z lives in d during the forward pass; w is a separate q-vector, so that a
@@ -541,9 +541,18 @@ __device__ __forceinline__ void trsv_block_solve(const double* __restrict__ Xm, 
     __syncthreads();
 }
 
-// sum over k < m of col[k q] v[k]: 16 loads in flight per round
+// sum over k < m of col[k q] v[k]: for a full block all 64 loads in flight
+// at once, else 16 per round
 __device__ __forceinline__ double trsv_dot(const double* __restrict__ col, int q, int m, const double* v) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (m == NB) {
+        double x[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) x[u] = col[(int64_t)u * q];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) a[u & 3] = fma(x[u], v[u], a[u & 3]);
+        return (a[0] + a[1]) + (a[2] + a[3]);
+    }
     int k = 0;
     for (; k + 15 < m; k += 16) {
         double x[16];
