@@ -275,6 +275,19 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restri
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    // this thread's entries of the destination tile, loaded now so that the
+    // final update does not wait for them (the tile is no operand of this
+    // launch and no other workgroup writes it)
+    double dst[2][2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = io + wr + 16 * u + 4 * e + k4, j = jo + wc + 16 * v + r16;
+                dst[u][v][e] = (i < q && j < q && j <= i) ? M[(int64_t)i * q + j] : 0.0;
+            }
     // the tiles of block column kb into registers; the next block column's
     // loads are issued before this one's products, so that they are in
     // flight while the matrix cores work
@@ -317,7 +330,7 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restri
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = io + wr + 16 * u + 4 * e + k4, j = jo + wc + 16 * v + r16;
-                if (i < q && j < q && j <= i) M[(int64_t)i * q + j] -= acc[u][v][e];
+                if (i < q && j < q && j <= i) M[(int64_t)i * q + j] = dst[u][v][e] - acc[u][v][e];
             }
 }
 
