@@ -372,6 +372,18 @@ __global__ __launch_bounds__(UTHREADS) void k_chol_update_mfma128(double* __rest
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    // this thread's entries of the destination tile, loaded at the start (the
+    // tile is no operand of this launch and no other workgroup writes it)
+    double dst[4][2][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = io + wr + 16 * u + 4 * e + k4, j = jo + wc + 16 * v + r16;
+                dst[u][v][e] = (i < q && j < q && j <= i) ? M[(int64_t)i * q + j] : 0.0;
+            }
     double vi[UPT], vj[UPT];
     auto load_chunk = [&](int c0) {
 #pragma unroll
@@ -414,7 +426,7 @@ __global__ __launch_bounds__(UTHREADS) void k_chol_update_mfma128(double* __rest
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = io + wr + 16 * u + 4 * e + k4, j = jo + wc + 16 * v + r16;
-                if (i < q && j < q && j <= i) M[(int64_t)i * q + j] -= acc[u][v][e];
+                if (i < q && j < q && j <= i) M[(int64_t)i * q + j] = dst[u][v][e] - acc[u][v][e];
             }
 }
 
