@@ -86,7 +86,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_init(const double* __restrict_
 
 // --------------------------------------------------------------- X_J v
 // w[k] = (X_J v)_k for the k-th row of the ordered J list; Pw[b] = sum w^2.
-// 16 lanes per row; each lane issues its loads four entries at a time.
+// 16 lanes per row; each lane issues its loads four entries at a time, with no
+// load under a per-lane branch.
 template <typename V>
 __global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ jrow,
                                                        const int32_t* __restrict__ ci,
@@ -108,18 +109,26 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ 
         if (k < p) {
             const int2 er = jrow[k];
             const int32_t e0 = er.x, e1 = er.y;
-            int32_t e = e0 + sub;
-            for (; e + 48 < e1; e += 64) {
-                const int32_t c0 = ci[e], c1 = ci[e + 16], c2 = ci[e + 32], c3 = ci[e + 48];
-                const double a0 = (double)val[e], a1 = (double)val[e + 16];
-                const double a2 = (double)val[e + 32], a3 = (double)val[e + 48];
-                const double v0 = v[c0], v1 = v[c1], v2 = v[c2], v3 = v[c3];
-                acc = fma(a0, v0, acc);
-                acc = fma(a1, v1, acc);
-                acc = fma(a2, v2, acc);
-                acc = fma(a3, v3, acc);
+            // a lane's entries e0 + sub + 16 m, four at a time: the indices and
+            // values of all four loaded at once (an entry past the row reads the
+            // row's first entry and is multiplied by 0), then the four gathers
+            for (int32_t e = e0 + sub; e < e1; e += 64) {
+                int32_t cc[4];
+                double a[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int32_t em = e + 16 * m;
+                    const int32_t ec = em < e1 ? em : e0;
+                    cc[m] = ci[ec];
+                    const double x = (double)val[ec];
+                    a[m] = em < e1 ? x : 0.0;
+                }
+                double vv[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) vv[m] = v[cc[m]];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) acc = fma(a[m], vv[m], acc);
             }
-            for (; e < e1; e += 16) acc = fma((double)val[e], v[ci[e]], acc);
         }
         acc += __shfl_xor(acc, 8, SSN_WAVE);
         acc += __shfl_xor(acc, 4, SSN_WAVE);
