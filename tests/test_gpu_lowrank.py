@@ -45,11 +45,14 @@ def _m0_factor(X, free, sigma):
     return sla.cho_factor(M0, lower=True)
 
 
-@pytest.mark.parametrize("q,nchg", [(160, 0), (160, 5), (512, 60), (200, 94), (200, 95)])
+@pytest.mark.parametrize("q,nchg", [(160, 0), (160, 5), (512, 60), (200, 62), (200, 63), (200, 94),
+                                    (200, 95)])
 def test_lowrank_step_fp64(q, nchg):
     """Second op_newton call at the same sigma: the update of the first
     call's factor (nchg <= 94) or a new factorisation (95: past the cap),
-    either way the oracle's direction."""
+    either way the oracle's direction.  62 and 63 changed rows give a
+    capacitance matrix of order 64 and 65, where its factorisation and
+    solves start using a second entry per lane."""
     X, y = synth.dense_two_gaussians(n=3000, q=q, seed=12)
     sigma = 7.0
     f0, f1 = _masks(X.shape[0], nchg, 3 + q)
