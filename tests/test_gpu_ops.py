@@ -105,6 +105,34 @@ def _csr_case(n, q, seed, heavy=True, integer=False, f64=False):
     return data, M.indices.astype(np.int32), M.indptr.astype(np.int64), y
 
 
+@pytest.mark.parametrize("dtype,q", [("f64", 128), ("f32", 256), ("bf16", 512)])
+@pytest.mark.parametrize("density", [0.0, 0.02, 0.125, 1.0])
+def test_dense_atmul_sparse_coefficients(dtype, q, density):
+    """X^T (y .* z) where z is zero on most rows: the row kernel for rows of one
+    piece per lane skips every row whose coefficient is zero, so whole 64-row
+    chunks with no nonzero (density 0.02), chunks with about one batch of 8
+    (0.125), none at all and all of them are compared with the plain product
+    (n = 5003: a ragged last chunk)."""
+    n = 5003
+    rng = np.random.default_rng(q + int(1000 * density))
+    X64 = rng.standard_normal((n, q))
+    y = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    if dtype == "f64":
+        Xs, Xref, kw = X64, X64, {}
+    elif dtype == "f32":
+        Xs = X64.astype(np.float32)
+        Xref, kw = Xs.astype(np.float64), {}
+    else:
+        Xs = synth.to_bf16_bits(X64.astype(np.float32))
+        Xref, kw = synth.bf16_bits_to_f32(Xs).astype(np.float64), {"bf16": True}
+    z = rng.standard_normal(n) * (rng.random(n) < density)
+    with _solver(Xs, y, 1.0, **kw) as s:
+        r = _np(s.atmul(z))
+    r_ref = Xref.T @ (y * z)
+    bound = 1e-12 * (np.abs(Xref).T @ np.abs(z))
+    assert np.all(np.abs(r - r_ref) <= bound + 1e-300)
+
+
 @pytest.mark.parametrize("n,q,seed", [(1, 3, 1), (50, 20, 2), (3000, 500, 3), (20000, 3000, 4)])
 @pytest.mark.parametrize("f64", [False, True])
 def test_csr_matvec(n, q, seed, f64):
