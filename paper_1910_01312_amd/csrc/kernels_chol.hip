@@ -259,7 +259,10 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_panel(double* __restrict__ M
 // 64-long contraction in 16 steps of 4; lane l supplies row l % 16, column
 // l / 16 of the 16 x 4 operand from Li (rows of block ib) and likewise of the
 // 4 x 16 operand from Lj (rows of block jb, i.e. L_jb^T), and holds rows
-// 4 v + l / 16 (v = 0..3), column l % 16 of the 16 x 16 result.
+// 4 v + l / 16 (v = 0..3), column l % 16 of the 16 x 16 result.  The next
+// k-block's tiles are loaded while the current one's products run, and the
+// destination tile's entries at the start, so that no load is waited for at
+// the end.
 __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restrict__ M, int q, int k0,
                                                                 int k1, int j0) {
     __shared__ double Li[NB][NB + 1];
@@ -343,7 +346,8 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_chol_update_mfma(double* __restri
 // an XCD (dispatched round-robin) work on a contiguous run of tiles and share
 // their rows of the panel in that XCD's L2.  The contraction runs in chunks of
 // 32 columns staged in LDS (two tiles of 128 x 32, padded to an odd stride);
-// the next chunk's loads are issued before this chunk's products.  Eight
+// the next chunk's loads are issued before this chunk's products, and the
+// destination tile's entries at the start.  Eight
 // waves, each owning a 64 x 32 part (4 x 2 MFMA tiles of 16 x 16, 8
 // accumulators, so that two waves fit each SIMD), with the lane layout of the
 // kernel above.
