@@ -92,6 +92,7 @@ struct ssnalm_ctx {
     int device = 0;
     // sparse operator plans (forward on CSR rows, transpose on CSC columns)
     SegPlan fwd{}, tr{};
+    SellPlan sell{};                 // sliced-ELL rows for A v (fp32 values; nslice 0: none)
     int32_t* qperm = nullptr;        // CSR: internal index of each original column (null: identity)
     double *qin = nullptr, *qout = nullptr;   // q-vectors crossing the boundary, relabelled
     SegPlan trb{};                   // CSC cut into row blocks (segment = block * q + column)
@@ -351,6 +352,8 @@ static void op_amul(ssnalm_ctx* c, const double* v, double* t) {
         launch_svr_expand(t, c->nphys, c->st);
     } else if (c->kind == SSNALM_DENSE)
         launch_amul_dense(c->dtype, c->X, c->y, v, t, c->n, c->q, c->st);
+    else if (c->sell.nslice)
+        launch_sell_amul(c->sell, v, c->q, c->y, t, c->st);
     else
         launch_segsum(c->fwd, v, nullptr, nullptr, c->y, nullptr, t, c->st);
     prof_end(c, SSNALM_K_AMUL, bytes_amul(c), 2.0 * (c->kind == SSNALM_DENSE ? (double)c->n * c->q : (double)c->nnz));
@@ -1001,6 +1004,58 @@ static ssnalm_status build_plan(ssnalm_ctx* c, SegPlan* P, int64_t nseg, int64_t
     return SSNALM_OK;
 }
 
+// The sliced-ELL copy of the rows (fp32 values) for the forward product.  It
+// is built only when the padding stays within a quarter of the entries and no
+// row is longer than SELL_MAX_LEN (a wave walks its slice's longest row
+// alone); otherwise the merge-path plan serves A v.
+static ssnalm_status build_sell(ssnalm_ctx* c, int64_t n, const std::vector<int64_t>& rp,
+                                const std::vector<int32_t>& ci, const float* vals) {
+    const int64_t W = SELL_SLICE;
+    const int64_t nslice = (n + W - 1) / W;
+    const int64_t nnz = rp[n];
+    std::vector<int32_t> perm(nslice * W, -1);
+    for (int64_t w0 = 0; w0 < n; w0 += SELL_WINDOW) {
+        const int64_t w1 = std::min<int64_t>(n, w0 + SELL_WINDOW);
+        for (int64_t i = w0; i < w1; ++i) perm[i] = (int32_t)i;
+        std::stable_sort(perm.begin() + w0, perm.begin() + w1, [&](int32_t a, int32_t b) {
+            return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+        });
+    }
+    std::vector<int32_t> len(std::max<int64_t>(nslice, 1), 0);
+    std::vector<int64_t> ptr(std::max<int64_t>(nslice, 1), 0);
+    int64_t tot = 0;
+    for (int64_t s = 0; s < nslice; ++s) {
+        // windows are whole slices, sorted: the slice's first row is its longest
+        const int32_t r = perm[s * W];
+        const int64_t L = (rp[r + 1] - rp[r] + SELL_PAD - 1) / SELL_PAD * SELL_PAD;
+        if (L > SELL_MAX_LEN) return SSNALM_OK;
+        len[s] = (int32_t)L;
+        ptr[s] = tot;
+        tot += W * L;
+    }
+    if (tot > nnz + nnz / 4 + W * SELL_PAD * nslice) return SSNALM_OK;
+    std::vector<ColValF> cv(std::max<int64_t>(tot, 1), ColValF{0, 0.0f});
+    for (int64_t s = 0; s < nslice; ++s)
+        for (int64_t l = 0; l < W; ++l) {
+            const int32_t r = perm[s * W + l];
+            if (r < 0) continue;
+            for (int64_t k = rp[r]; k < rp[r + 1]; ++k)
+                cv[ptr[s] + (k - rp[r]) * W + l] = ColValF{ci[k], vals[k]};
+        }
+    SellPlan P{};
+    STCHK(dalloc(c, &P.ptr, std::max<int64_t>(nslice, 1)));
+    STCHK(dalloc(c, &P.len, std::max<int64_t>(nslice, 1)));
+    STCHK(dalloc(c, &P.perm, std::max<int64_t>(nslice * W, 1)));
+    STCHK(dalloc(c, &P.cv, std::max<int64_t>(tot, 1)));
+    HIPCHK(hipMemcpy(P.ptr, ptr.data(), sizeof(int64_t) * ptr.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(P.len, len.data(), sizeof(int32_t) * len.size(), hipMemcpyHostToDevice));
+    if (nslice) HIPCHK(hipMemcpy(P.perm, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(P.cv, cv.data(), sizeof(ColValF) * cv.size(), hipMemcpyHostToDevice));
+    P.nslice = nslice;
+    c->sell = P;
+    return SSNALM_OK;
+}
+
 // CSR input: validate, build the internal int32 CSR (rows) and the CSC copy
 // (columns, rows ascending inside each column: a stable counting sort).
 static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
@@ -1053,6 +1108,7 @@ static ssnalm_status setup_csr(ssnalm_ctx* c, const ssnalm_problem* pr) {
     std::vector<int32_t> rp32(n + 1);
     for (int64_t i = 0; i <= n; ++i) rp32[i] = (int32_t)rp[i];
     STCHK(build_plan(c, &c->fwd, n, nnz, rp32, ci, vals.data(), vb == 8));
+    if (vb == 4) STCHK(build_sell(c, n, rp, ci, (const float*)vals.data()));
     // CSC by a stable counting sort over rows
     std::vector<int32_t> cp(q + 1, 0);
     for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;

@@ -256,6 +256,25 @@ bool jcsc_bits_fit(int64_t n);
 // value type
 struct alignas(8) ColValF { int32_t col; float v; };
 struct alignas(16) ColValD { int32_t col; int32_t pad; double v; };
+// Sliced-ELL copy of the CSR rows (fp32 values) for the forward product:
+// rows sorted by decreasing length inside windows of SELL_WINDOW rows, 64
+// sorted rows per slice, slice s column-major from cv + ptr[s] (entry k of
+// its row l at ptr[s] + 64 k + l), len[s] its padded length (a multiple of
+// SELL_PAD), perm[64 s + l] the row's original index (-1 past n).
+constexpr int SELL_SLICE = 64;      // rows per slice: one wave, one lane per row
+constexpr int SELL_WINDOW = 1024;
+constexpr int SELL_PAD = 4;
+constexpr int SELL_MAX_LEN = 1024;   // longest row the copy is built for
+struct SellPlan {
+    int64_t  nslice;           // 0: no copy (the merge-path plan serves A v)
+    int64_t* ptr;              // nslice entry offsets (device)
+    int32_t* len;              // nslice padded lengths (device)
+    int32_t* perm;             // 64 * nslice original row indices (device)
+    ColValF* cv;               // padded entries (device)
+};
+// out[i] = y[i] * sum_k X_ik v[k] over the sliced-ELL copy
+void launch_sell_amul(const SellPlan& P, const double* v, int64_t q, const int8_t* y, double* out,
+                      hipStream_t s);
 void launch_jcsc_build(const SegPlan& T, const void* tcv, const uint8_t* mask, int64_t n,
                        uint32_t* bits,
                        const int32_t* rank, int* tcount, int* toff, long long* total, int32_t* jr,

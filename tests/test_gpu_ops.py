@@ -184,6 +184,35 @@ def test_csr_transpose_row_blocks(n, f64):
     np.testing.assert_array_equal(t, y * (Xref @ v))
 
 
+@pytest.mark.parametrize("case", ["ell", "long_row", "skewed"])
+def test_csr_matvec_row_layouts(case):
+    """A v over fp32 CSR rows in each row layout: rows of similar lengths (the
+    sliced-ELL copy; empty rows, n not a multiple of 64, several 1024-row
+    windows), one row past the copy's 1024-entry limit, and lengths so skewed
+    that the copy's padding would pass a quarter of the entries (both on the
+    merge-path plan).  Integer data, so every sum is exact."""
+    n, q = 5037, 3000
+    rng = np.random.default_rng({"ell": 1, "long_row": 2, "skewed": 3}[case])
+    if case == "skewed":
+        lens = np.where(rng.random(n) < 0.02, 600, 2)
+    else:
+        lens = rng.poisson(12, size=n)
+        lens[rng.random(n) < 0.05] = 0
+        if case == "long_row":
+            lens[1234] = 2000
+    rows = np.repeat(np.arange(n), lens)
+    cols = rng.integers(0, q, size=rows.size)
+    M = sp.csr_matrix((rng.integers(1, 4, size=rows.size).astype(np.float64), (rows, cols)), shape=(n, q))
+    M.sum_duplicates()
+    M.sort_indices()
+    data = M.data.astype(np.float32)
+    y = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    v = rng.integers(-4, 5, size=q).astype(np.float64)
+    with _solver(csr=(data, M.indices.astype(np.int32), M.indptr.astype(np.int64), n, q), y=y) as s:
+        t = _np(s.amul(v))
+    np.testing.assert_array_equal(t, y * (M @ v))
+
+
 def test_csr_text_like_sample():
     """Workload-shaped CSR (Zipf columns, L2-normalised rows), reduced n."""
     vals, ci, rp, y = synth.sparse_text(n=30000, q=8000, seed=11)
