@@ -80,8 +80,9 @@ TRAFFIC_KERNELS = {
     "atmul": (["k_mul_y", "k_segsum<float, 0>", "k_segsum_fix", "k_reduce_cols"],
               ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/kernels_vec.hip",
                "paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
-    "amul": (["k_segsum<float, 0>", "k_segsum_fix"],
-             ["paper_1910_01312_amd/csrc/kernels_sparse.hip", "paper_1910_01312_amd/csrc/dev_common.h"]),
+    "amul": (["k_sell_amul", "k_segsum<float, 0>", "k_segsum_fix"],
+             ["paper_1910_01312_amd/csrc/kernels_sell.hip", "paper_1910_01312_amd/csrc/kernels_sparse.hip",
+              "paper_1910_01312_amd/csrc/dev_common.h"]),
     "atmul-dense": (["k_atmul_rows", "k_reduce_cols"],
                     ["paper_1910_01312_amd/csrc/kernels_dense.hip", "paper_1910_01312_amd/csrc/lane_ops.h",
                      "paper_1910_01312_amd/csrc/dev_common.h"]),

@@ -618,7 +618,7 @@ static ssnalm_status newton_dir(ssnalm_ctx* c, const uint8_t* mask, int64_t p, c
         // decision inside; the kernels stop changing x once the tolerance is met).
         auto cg_iteration = [&](int par) {
             prof_begin(c, SSNALM_K_AMUL_J);
-            launch_cg_rows(c->fwd, c->jrow, p, c->cg_p, c->wJ, Pw, dsc(c), c->st);
+            launch_cg_rows(c->fwd, c->jrow, p, c->q, c->cg_p, c->wJ, Pw, dsc(c), c->st);
             prof_end(c, SSNALM_K_AMUL_J, (double)nnzj * (vb + 4.0) + 20.0 * p + 8.0 * c->q,
                      2.0 * (double)nnzj);
             prof_begin(c, SSNALM_K_ATMUL_J);

@@ -87,21 +87,46 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_init(const double* __restrict_
 // --------------------------------------------------------------- X_J v
 // w[k] = (X_J v)_k for the k-th row of the ordered J list; Pw[b] = sum w^2.
 // 16 lanes per row; each lane issues its loads four entries at a time, with no
-// load under a per-lane branch.
+// load under a per-lane branch.  Persistent workgroups keep v over the
+// CGR_HEAD most frequent columns in LDS: the random gathers of v, not the
+// stream of entries, are what a row product of a text-like X waits on.
+constexpr int CGR_THREADS = 1024;           // 16 waves per workgroup
+constexpr int CGR_WPB = CGR_THREADS / SSN_WAVE;
+constexpr int CGR_HEAD = 16384;             // columns of v in LDS (128 KB)
+static_assert(CGR_HEAD % CGR_THREADS == 0, "the head is copied in whole rounds");
+
 template <typename V>
-__global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ jrow,
-                                                       const int32_t* __restrict__ ci,
-                                                       const V* __restrict__ val, int64_t p,
-                                                       const double* __restrict__ v,
-                                                       double* __restrict__ w,
-                                                       double* __restrict__ Pw,
-                                                       const Scalars* __restrict__ sc) {
-    __shared__ double sh[SSN_WAVES_PER_BLOCK];
+__global__ __launch_bounds__(CGR_THREADS) void k_cg_rows(const int2* __restrict__ jrow,
+                                                         const int32_t* __restrict__ ci,
+                                                         const V* __restrict__ val, int64_t p,
+                                                         const double* __restrict__ v, int32_t H,
+                                                         double* __restrict__ w,
+                                                         double* __restrict__ Pw,
+                                                         const Scalars* __restrict__ sc) {
+    __shared__ double vh[CGR_HEAD];
+    __shared__ double sh[CGR_WPB];
     if (sc->cg_done) return;                   // converged: the step passes through
+    // v over the first H columns (the most frequent: columns are numbered by
+    // decreasing entry count) into LDS, every load issued before any store
+    {
+        constexpr int PER = CGR_HEAD / CGR_THREADS;
+        double t[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int j = (int)threadIdx.x + i * CGR_THREADS;
+            t[i] = v[j < H ? j : 0];
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int j = (int)threadIdx.x + i * CGR_THREADS;
+            if (j < H) vh[j] = t[i];
+        }
+    }
+    __syncthreads();
     const int lane = threadIdx.x & (SSN_WAVE - 1);
     const int grp = lane >> 4, sub = lane & 15;
-    const int64_t wave = (int64_t)blockIdx.x * SSN_WAVES_PER_BLOCK + threadIdx.x / SSN_WAVE;
-    const int64_t nwave = (int64_t)gridDim.x * SSN_WAVES_PER_BLOCK;
+    const int64_t wave = (int64_t)blockIdx.x * CGR_WPB + __builtin_amdgcn_readfirstlane(threadIdx.x / SSN_WAVE);
+    const int64_t nwave = (int64_t)gridDim.x * CGR_WPB;
     double ww = 0.0;
     for (int64_t base = wave * 4; base < p; base += nwave * 4) {
         const int64_t k = base + grp;
@@ -111,7 +136,9 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ 
             const int32_t e0 = er.x, e1 = er.y;
             // a lane's entries e0 + sub + 16 m, four at a time: the indices and
             // values of all four loaded at once (an entry past the row reads the
-            // row's first entry and is multiplied by 0), then the four gathers
+            // row's first entry and is multiplied by 0), then the four gathers,
+            // each issued to LDS and to global memory (the read not needed
+            // pointed at a fixed address)
             for (int32_t e = e0 + sub; e < e1; e += 64) {
                 int32_t cc[4];
                 double a[4];
@@ -123,11 +150,14 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ 
                     const double x = (double)val[ec];
                     a[m] = em < e1 ? x : 0.0;
                 }
-                double vv[4];
+                double gl[4], gg[4];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) vv[m] = v[cc[m]];
+                for (int m = 0; m < 4; ++m) {
+                    gl[m] = vh[cc[m] < H ? cc[m] : 0];
+                    gg[m] = v[cc[m] < H ? 0 : cc[m]];
+                }
 #pragma unroll
-                for (int m = 0; m < 4; ++m) acc = fma(a[m], vv[m], acc);
+                for (int m = 0; m < 4; ++m) acc = fma(a[m], cc[m] < H ? gl[m] : gg[m], acc);
             }
         }
         acc += __shfl_xor(acc, 8, SSN_WAVE);
@@ -139,26 +169,39 @@ __global__ __launch_bounds__(SSN_BLOCK) void k_cg_rows(const int2* __restrict__ 
             ww = fma(acc, acc, ww);
         }
     }
-    const double bs = block_sum(ww, sh);
-    if (threadIdx.x == 0) Pw[blockIdx.x] = bs;
+    // block sum of ww, waves in index order
+    ww = wave_sum(ww);
+    if (lane == 0) sh[threadIdx.x / SSN_WAVE] = ww;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < CGR_WPB; ++i) r += sh[i];
+        Pw[blockIdx.x] = r;
+    }
 }
 
+// one persistent workgroup per compute unit (the LDS copy of v takes 128 KB),
+// fewer when J is short
 unsigned cg_rows_grid(int64_t p) {
-    int64_t b = (p + 15) / 16;
-    if (b > 1024) b = 1024;
+    int64_t b = (p + 4 * CGR_WPB - 1) / (4 * CGR_WPB);
+    const int64_t ncu = device_cu_count();
+    if (b > ncu) b = ncu;
+    if (b > 1024) b = 1024;                  // the partials' buffer holds 1024
     if (b < 1) b = 1;
     return (unsigned)b;
 }
 
-void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double* v, double* w,
-                    double* Pw, const Scalars* sc, hipStream_t s) {
+void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, int64_t q, const double* v,
+                    double* w, double* Pw, const Scalars* sc, hipStream_t s) {
     const unsigned g = cg_rows_grid(p);
+    const int32_t H = (int32_t)(q < CGR_HEAD ? q : CGR_HEAD);
     if (F.val_f64)
-        SSN_LAUNCH((k_cg_rows<double>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
-                           (const double*)F.val, p, v, w, Pw, sc);
+        SSN_LAUNCH((k_cg_rows<double>), dim3(g), dim3(CGR_THREADS), 0, s, jrow, F.idx,
+                   (const double*)F.val, p, v, H, w, Pw, sc);
     else
-        SSN_LAUNCH((k_cg_rows<float>), dim3(g), dim3(SSN_BLOCK), 0, s, jrow, F.idx,
-                           (const float*)F.val, p, v, w, Pw, sc);
+        SSN_LAUNCH((k_cg_rows<float>), dim3(g), dim3(CGR_THREADS), 0, s, jrow, F.idx,
+                   (const float*)F.val, p, v, H, w, Pw, sc);
 }
 
 // --------------------------------------------------------------- X_J^T w

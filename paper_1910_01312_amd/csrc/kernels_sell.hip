@@ -98,17 +98,22 @@ __global__ __launch_bounds__(SELL_THREADS) void k_sell_amul(
     }
 }
 
+int device_cu_count() {
+    static int ncu_of[64];                       // per device, read once
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!ncu_of[dev]) {
+        int n = 0;
+        ncu_of[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0
+                          ? n : 256;
+    }
+    return ncu_of[dev];
+}
+
 void launch_sell_amul(const SellPlan& P, const double* v, int64_t q, const int8_t* y, double* out,
                       hipStream_t s) {
     if (P.nslice == 0) return;
-    static int ncu_of[64];                       // compute units per device, read once
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
-        if (!ncu_of[dev] &&
-            hipDeviceGetAttribute(&ncu_of[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            ncu_of[dev] = 256;
-        ncu = ncu_of[dev];
-    }
+    const int ncu = device_cu_count();
     const int per_cu = (160 * 1024) / (int)(SELL_HEAD * sizeof(double) + 1024);
     const int64_t want = (P.nslice + SELL_WPB - 1) / SELL_WPB;
     const int64_t nb = std::min<int64_t>(want, (int64_t)ncu * std::max(per_cu, 1));

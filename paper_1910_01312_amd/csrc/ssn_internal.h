@@ -282,13 +282,15 @@ void launch_jcsc_build(const SegPlan& T, const void* tcv, const uint8_t* mask, i
 
 // Fence-free CG on the compact X_J (kernels_cg.hip) ----------------------------
 unsigned cg_rows_grid(int64_t p);
+// compute units of the current device (read once per device)
+int device_cu_count();
 void launch_cg_init(const double* g, const double* diag, const double* sv, int64_t q, double* x,
                     double* r, double* z, double* pd, double* Pst, double* Pdir, hipStream_t s);
 void launch_cg_publish(const double* Pst, int64_t q, double tol2, Scalars* sc, hipStream_t s);
 // w[k] = (X_J v)_k for the k-th row of J (entry range jrow[k]); Pw: block sums of w^2
 // returns at once when sc->cg_done is set (the CG has converged)
-void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, const double* v, double* w,
-                    double* Pw, const Scalars* sc, hipStream_t s);
+void launch_cg_rows(const SegPlan& F, const int2* jrow, int64_t p, int64_t q, const double* v,
+                    double* w, double* Pw, const Scalars* sc, hipStream_t s);
 // The runs of equal column that cross chunk borders of a compact copy:
 // their first chunks (ascending), last chunks and columns; nfix on the host.
 struct KeyedFix {
