@@ -46,11 +46,11 @@ MEASURED_TRAFFIC = {
     # timed solve, divided by the 2 x 1328 CG iterations that did work
     # (profiles/sparse_text_atmul_J_hbm_traffic.md)
     ("sparse-text", "atmul_J"): {
-        "fetch_kib": 52681276.875 + 1168507.875, "write_kib": 2634982.9375 + 299527.5, "calls": 2656,
+        "fetch_kib": 52682109.125 + 1168507.875, "write_kib": 2634972.875 + 299527.5, "calls": 2656,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "files": {
             "paper_1910_01312_amd/csrc/kernels_cg.hip":
-                "6881fe425f87833c5d58404cce8bb89a812758589d7512533a90fc3dfdd60519",
+                "8e85f733a7420d47c946802ee1dfa72364236f54a1c9160ddcf75daaca924fd8",
             "paper_1910_01312_amd/csrc/dev_common.h":
                 "a34ef9e72788212b20fbb624e54dbe54c03922933c400472c434eed96aacfd9e",
         },
