@@ -184,15 +184,16 @@ def test_csr_transpose_row_blocks(n, f64):
     np.testing.assert_array_equal(t, y * (Xref @ v))
 
 
-@pytest.mark.parametrize("case", ["ell", "long_row", "skewed"])
+@pytest.mark.parametrize("case", ["ell", "ell_wide", "long_row", "skewed"])
 def test_csr_matvec_row_layouts(case):
     """A v over fp32 CSR rows in each row layout: rows of similar lengths (the
     sliced-ELL copy; empty rows, n not a multiple of 64, several 1024-row
-    windows), one row past the copy's 1024-entry limit, and lengths so skewed
-    that the copy's padding would pass a quarter of the entries (both on the
+    windows; with q = 40 000 also columns past the 16 384 whose v is read from
+    LDS), one row past the copy's 1024-entry limit, and lengths so skewed that
+    the copy's padding would pass a quarter of the entries (both on the
     merge-path plan).  Integer data, so every sum is exact."""
-    n, q = 5037, 3000
-    rng = np.random.default_rng({"ell": 1, "long_row": 2, "skewed": 3}[case])
+    n, q = 5037, (40000 if case == "ell_wide" else 3000)
+    rng = np.random.default_rng({"ell": 1, "ell_wide": 4, "long_row": 2, "skewed": 3}[case])
     if case == "skewed":
         lens = np.where(rng.random(n) < 0.02, 600, 2)
     else:
@@ -327,12 +328,16 @@ def test_newton_empty_free_set():
     np.testing.assert_array_equal(_np(d), -g)
 
 
+@pytest.mark.parametrize("q", [3000, 40000])
 @pytest.mark.parametrize("f64", [False, True])
-def test_newton_pcg_csr(f64):
-    vals, ci, rp, y = synth.sparse_text(n=20000, q=3000, seed=12)
+def test_newton_pcg_csr(f64, q):
+    """The Newton direction by PCG on a CSR X_J; at q = 40 000 the CG's row
+    product reads v for the 16 384 most frequent columns from LDS and for the
+    rest from global memory."""
+    vals, ci, rp, y = synth.sparse_text(n=20000, q=q, seed=12)
     if f64:
         vals = vals.astype(np.float64)
-    n, q = rp.size - 1, 3000
+    n = rp.size - 1
     Xr = sp.csr_matrix((vals.astype(np.float64), ci, rp), shape=(n, q))
     sigma = 25.0
     u, lam, free, g, _, _ = _newton_state(Xr, y, 1.0, sigma, 2)
