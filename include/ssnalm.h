@@ -19,7 +19,7 @@
  *    unchanged until ssnalm_destroy.  The library allocates and owns its
  *    own workspace (n-vectors, index lists, q x q blocks, the internal row
  *    and column copies of a CSR matrix, with fp32 values also a sliced-ELL
- *    row copy for A v: about 4 x 8 bytes per nonzero in all) and frees it in
+ *    row copy for A v: up to about 40 bytes per nonzero in all) and frees it in
  *    ssnalm_destroy.
  *  - All GPU work is enqueued on the stream given to ssnalm_create (NULL =
  *    the null stream).  Every entry point returns after that stream has
