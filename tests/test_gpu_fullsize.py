@@ -12,8 +12,11 @@ library primitive) and against oracle reference solves stored by
 tests/golden/make_refs.py (inputs regenerated here and matched by checksum):
   * every element of A v and A^T z within 1e-12 relative to |X||v|, |X|^T|z|;
   * R_KKT <= 1e-6 (eq. Def_Rkkt) as the oracle computes it from the returned
-    x, agreeing with the library's own R_KKT, feasibility, w = A^T x;
-  * |f - f*| / max(1, |f*|) <= 1e-8 with f* the oracle's, on the same
+    x, agreeing with the library's own R_KKT, feasibility, w = A^T x, the
+    duality gap at the returned bias;
+  * where a reference is stored (the dense C = 0.1 one is not yet: its oracle
+    solve runs for many hours), |f - f*| / max(1, |f*|) <= 1e-8 with f* the
+    oracle's, on the same
     solution as the R_KKT bar: the tol-1e-6 solve when it meets 1e-8, else
     a tol-1e-8 solve (the tol-1e-6 error is printed).
 """
@@ -127,10 +130,39 @@ def dense_bf16():
     return bits, y, Xr
 
 
-@pytest.mark.parametrize("C", [0.1, 1.0])
-def test_fullsize_dense_bf16_mixed(dense_bf16, C):
+def _bf16_solve(dense_bf16, C, tol):
     from paper_1910_01312_amd.solver import Solver
-    bits, y, Xr = dense_bf16
+    bits, y, _ = dense_bf16
+    bd = torch.from_numpy(bits.view(np.int16)).cuda()
+    with Solver(bd, y, C, tol=tol, bf16=True, precision="mixed") as s:
+        x, w, info = s.solve()
+    assert info["status_name"] == "OK"
+    return x.cpu().numpy(), w.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("C", [0.1, 1.0])
+def test_fullsize_dense_bf16_mixed_kkt(dense_bf16, C):
+    """The checks that need no stored reference: R_KKT as the oracle computes
+    it from the returned x (and agreeing with the library's), feasibility,
+    w = A^T x element by element, and the library's duality gap against the
+    oracle's at the returned bias."""
+    _, y, Xr = dense_bf16
+    xh, w, info = _bf16_solve(dense_bf16, C, 1e-6)
+    assert np.all(xh >= 0.0) and np.all(xh <= C)
+    R, _ = ssnal.rkkt(Xr, y, C, xh)
+    assert R <= 1e-6 * 1.0001
+    assert abs(R - info["rkkt"]) <= 1e-3 * R + 1e-12
+    w_ref = ssnal.atmul(Xr, y, xh)
+    assert np.all(np.abs(w - w_ref) <= 1e-12 * (np.abs(Xr).T @ xh) + 1e-300)
+    g_at, _, _ = ssnal.duality_gap_at(Xr, y, C, xh, info["b"])
+    assert info["gap"] == pytest.approx(g_at, rel=1e-6, abs=1e-12)
+
+
+@pytest.mark.parametrize("C", [0.1, 1.0])
+def test_fullsize_dense_bf16_mixed_objective(dense_bf16, C):
+    """The objective against the oracle's f* (tol-1e-8 oracle solve stored by
+    tests/golden/make_refs.py)."""
+    _, y, Xr = dense_bf16
     name = "dense_bf16_full_C" + ("0.1" if C == 0.1 else "1")
     refs = _refs()
     if name not in refs:
@@ -140,23 +172,10 @@ def test_fullsize_dense_bf16_mixed(dense_bf16, C):
     ref = refs[name]
     assert ref["status"] == "OK" and ref["C"] == C
     assert float(np.sum(Xr, dtype=np.float64)) == ref["inputs"]["sum_x"]
-    bd = torch.from_numpy(bits.view(np.int16)).cuda()
-    with Solver(bd, y, C, tol=1e-6, bf16=True, precision="mixed") as s:
-        x, w, info = s.solve()
-    assert info["status_name"] == "OK"
-    xh = x.cpu().numpy()
-    assert np.all(xh >= 0.0) and np.all(xh <= C)
-    R, _ = ssnal.rkkt(Xr, y, C, xh)
-    assert R <= 1e-6 * 1.0001
-    assert abs(R - info["rkkt"]) <= 1e-3 * R + 1e-12
-    w_ref = ssnal.atmul(Xr, y, xh)
-    assert np.all(np.abs(w.cpu().numpy() - w_ref) <= 1e-12 * (np.abs(Xr).T @ xh) + 1e-300)
+    xh, _, _ = _bf16_solve(dense_bf16, C, 1e-6)
 
     def rerun():
-        with Solver(bd, y, C, tol=1e-8, bf16=True, precision="mixed") as s8:
-            x8, _, i8 = s8.solve()
-        assert i8["status_name"] == "OK"
-        x8 = x8.cpu().numpy()
+        x8, _, _ = _bf16_solve(dense_bf16, C, 1e-8)
         return ssnal.dual_objective(Xr, y, x8), ssnal.rkkt(Xr, y, C, x8)[0]
 
     _objective_bar(ssnal.dual_objective(Xr, y, xh), ref["f_star"], rerun)
