@@ -489,7 +489,68 @@ def run_kernel(args):
     print(json.dumps(out), flush=True)
 
 
+# the other configurations, run after the headline one (each in a child
+# process: one warm-up and one timed step, no CPU baseline) and summarised in
+# the headline line; skipped once the run has taken OTHER_BUDGET_S
+OTHER_WORKLOADS = [
+    ("dense-bf16 C=1", ["--workload", "dense-bf16"]),
+    ("dense-bf16 C=0.1", ["--workload", "dense-bf16", "--C", "0.1"]),
+    ("batch", ["--workload", "batch", "--no-seq"]),
+    ("warmstart", ["--workload", "warmstart"]),
+    ("rbf-kernel", ["--workload", "rbf-kernel"]),
+]
+OTHER_BUDGET_S = 300.0
+OTHER_TIMEOUT_S = 150.0
+
+
+def _summary(d):
+    r = d.get("roofline") or {}
+    out = {"value": d["value"], "unit": d["unit"], "workload": d["config"]["workload"],
+           "dtype": d.get("dtype")}
+    if r:
+        out["roofline"] = {k: r.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
+    sv = d.get("solve")
+    if sv:
+        out["solve"] = {k: sv.get(k) for k in ("status", "rkkt", "rkkt_oracle", "outer", "newton")}
+    if "batch" in d:
+        b = d["batch"]
+        out["batch"] = {k: b.get(k) for k in ("seconds_per_batch", "ok", "newton_max", "oracle_checks")}
+    if "warmstart" in d:
+        w = d["warmstart"]
+        out["warmstart"] = {k: w.get(k) for k in ("speedup", "cold_s_per_qp", "warm_s_per_qp")}
+    return out
+
+
+def other_workloads(t0):
+    import subprocess
+    res = {}
+    for name, extra in OTHER_WORKLOADS:
+        if time.perf_counter() - t0 > OTHER_BUDGET_S:
+            res[name] = {"skipped": f"the run had passed {OTHER_BUDGET_S:.0f} s"}
+            continue
+        cmd = [sys.executable, os.path.abspath(__file__), *extra, "--steps", "1", "--warmup", "1",
+               "--no-cpu-baseline", "--no-other-workloads"]
+        log(f"[bench] other workload: {name}")
+        t = time.perf_counter()
+        try:
+            p = subprocess.run(cmd, capture_output=True, text=True, timeout=OTHER_TIMEOUT_S)
+        except subprocess.TimeoutExpired:
+            res[name] = {"skipped": f"no result within {OTHER_TIMEOUT_S:.0f} s"}
+            log(f"[bench]   {name}: no result within {OTHER_TIMEOUT_S:.0f} s")
+            continue
+        lines = [ln for ln in p.stdout.splitlines() if ln.startswith("{")]
+        if p.returncode != 0 or not lines:
+            res[name] = {"error": f"exit status {p.returncode}", "stderr_tail": p.stderr[-400:]}
+            log(f"[bench]   {name}: exit status {p.returncode}")
+            continue
+        res[name] = _summary(json.loads(lines[-1]))
+        log(f"[bench]   {name}: {res[name]['value']:.4g} {res[name]['unit']} "
+            f"({time.perf_counter() - t:.0f} s)")
+    return res
+
+
 def main():
+    t0 = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -497,6 +558,8 @@ def main():
     ap.add_argument("--workload", default="sparse-text")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="headline workload: leave out the summaries of the other configurations")
     ap.add_argument("--C", type=float, default=None)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--count", type=int, default=256, help="batched workload: number of QPs")
@@ -688,6 +751,8 @@ def main():
                     for k, v in ks_all.items() if v["launches"]},
     }
     s.close()
+    if args.workload == "sparse-text" and not args.no_other_workloads and not args.calib_copy_mb:
+        out["other_workloads"] = other_workloads(t0)
     print(json.dumps(out), flush=True)
     calib(args)
 
